@@ -1,0 +1,145 @@
+/*
+ * sfr.h -- C ABI of the MI355X (gfx950) sparse fixed-rank decomposition
+ * library: M = L + S with rank(L) = r and L kept as U B V^T (U in St_{m,r},
+ * B in SPD_r, V in St_{n,r}), computed by FR-ADM (Alg. 1) with the
+ * FixedRankOptStep L-step (Alg. 2) and its Nystrom variant FR-Nys (Alg. 3)
+ * of Ros et al., "Fast and Robust Fixed-Rank Matrix Recovery".
+ *
+ * The problem solved is eq. (1), min ||S||_1 s.t. M = L + S, rank(L) = r,
+ * through the augmented Lagrangian of eq. (4) with an l1 weight lambda
+ * (lambda = 1 is the paper's literal form; lambda only rescales the penalty
+ * mu, the minimisers of eq. (1) do not depend on it).
+ *
+ * Conventions for every entry point:
+ *  - Matrices are dense, row-major.  "Device" pointers address GPU memory
+ *    of the current HIP device (e.g. a torch CUDA tensor's data_ptr());
+ *    "host" pointers address ordinary CPU memory.
+ *  - The caller owns every buffer it passes; the library never frees or
+ *    retains them after the call returns.  The handle owns its workspace
+ *    (allocated in sfr_create, freed in sfr_destroy).
+ *  - Calls are synchronous with respect to `hip_stream` (a hipStream_t,
+ *    NULL for the legacy default stream): they enqueue their kernels on it
+ *    and return after the outputs are written.
+ *  - Return value: SFR_OK (0), an error (< 0: outputs left untouched) or a
+ *    warning (> 0: outputs valid).  Arguments are validated on the host
+ *    before any device work.
+ *  - A handle serves one solve at a time; distinct handles are independent.
+ */
+#ifndef SFR_H
+#define SFR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfr_ctx* sfr_handle;
+
+typedef enum {
+    SFR_OK = 0,
+    SFR_ERR_ARG = -1,        /* invalid argument (sizes, NULL pointers, ranges) */
+    SFR_ERR_NOMEM = -2,      /* device workspace allocation failed */
+    SFR_ERR_DEVICE = -3,     /* HIP runtime error or device-side wait bound hit */
+    SFR_ERR_RANK = -4,       /* rank(X V B) < r: P_O of eq. (7) is not unique */
+    SFR_ERR_NONFINITE = -5,  /* NaN/Inf in M or in the iteration */
+    SFR_ERR_HANDLE = -6,     /* NULL or wrong-kind handle */
+    SFR_WARN_MAXITER = 1,    /* max_iter reached before the tolerance */
+    SFR_WARN_NOT_SPD = 2     /* returned B has a non-positive eigenvalue (eq. (8) is
+                                not guaranteed SPD away from the optimum, Appendix) */
+} sfr_status;
+
+typedef enum {
+    SFR_F64 = 0,             /* M, S, U, V are double; all arithmetic in FP64 */
+    SFR_F32 = 1              /* M, S, U, V are float; r x r algebra stays FP64 */
+} sfr_precision;
+
+/*
+ * Options.  Zero-filled fields select the defaults; set struct_size to
+ * sizeof(sfr_options).
+ */
+typedef struct {
+    uint32_t struct_size;
+    int32_t precision;       /* sfr_precision, default SFR_F64 */
+    double rho;              /* continuation factor rho > 1 (Alg. 1), default 1.5 */
+    double mu_bar;           /* penalty cap (Alg. 1), default 1e9 */
+    int32_t max_iter;        /* iteration cap, default 300 */
+    int32_t fixed_iters;     /* > 0: run exactly this many iterations, no tolerance test */
+    int32_t nystrom_l;       /* > 0: FR-Nys handle with l sampled rows/columns (Alg. 3) */
+    int32_t reserved0;
+    double mu_left;          /* FR-Nys: initial penalty of the m x l sub-solve (> 0) */
+    double mu_top;           /* FR-Nys: initial penalty of the l x n sub-solve (> 0) */
+} sfr_options;
+
+/* Per-solve report. */
+typedef struct {
+    int32_t iters;           /* iterations of Alg. 1 performed (FR-Nys: of the m x l block) */
+    int32_t iters_top;       /* FR-Nys: iterations of the l x n block; else 0 */
+    int32_t converged;       /* 1 if the tolerance was met (or fixed_iters ran) */
+    int32_t reserved0;
+    double rel_residual;     /* ||M - L - S||_F / ||M||_F after the last iteration */
+    double min_eig_B;        /* smallest eigenvalue of the returned B */
+    double mu_final;         /* penalty used by the last iteration */
+} sfr_info;
+
+/*
+ * Create a solver for m x n inputs and rank r.
+ *   m, n >= 1, 1 <= r <= min(m, n, 32).
+ *   lambda > 0: weight of ||S||_1; the S-step threshold is lambda/mu_k.
+ *   mu > 0: initial penalty mu_0 of Alg. 1 (finite).
+ *   tol >= 0: stop at the first iteration k with
+ *       ||M - L_{k+1} - S_{k+1}||_F / ||M||_F <= tol
+ *     (Alg. 1 leaves "converged" unspecified; this is the reading taken).
+ *   opt: NULL or options (see sfr_options).
+ * FR-Nys handles (opt->nystrom_l = l > 0) need r <= l <= min(m, n) and
+ * positive mu_left, mu_top; the argument mu is then unused.
+ * Allocates the whole device workspace on the current HIP device; returns
+ * SFR_ERR_NOMEM if it does not fit.
+ */
+sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double lambda, double mu,
+                      double tol, const sfr_options* opt);
+
+/*
+ * FR-ADM (Alg. 1).
+ *   M (device, m x ldm, ldm >= n): the data; read only.
+ *   U (device, m x r), V (device, n x r), element type of the precision:
+ *     the Stiefel factors of the returned L = U B V^T.
+ *   B (device, r x r, double): the symmetric factor (Sym of eq. (8)).
+ *   S (device, m x lds, lds >= n, or NULL): the returned sparse part
+ *     S_{k+1} = P_ST_{lambda/mu_k}(M - L_{k+1} + Y_k/mu_k) of the last
+ *     iteration.
+ *   info (host, may be NULL): report.
+ * Errors: SFR_ERR_HANDLE (NULL or FR-Nys handle), SFR_ERR_ARG (NULL M/U/B/V,
+ * ldm < n, lds < n), SFR_ERR_NONFINITE, SFR_ERR_RANK, SFR_ERR_DEVICE.
+ */
+sfr_status sfr_solve(sfr_handle h, const void* M, int64_t ldm, void* U, double* B, void* V, void* S,
+                     int64_t lds, sfr_info* info, void* hip_stream);
+
+/*
+ * FR-Nys (Alg. 3) on a handle created with nystrom_l = l.
+ *   perm (host, m entries): the random row shuffle; row i of the shuffled
+ *     matrix is row perm[i] of M.  Must be a permutation of 0..m-1.
+ *   Outputs as for sfr_solve, with L = U B V^T the Nystrom combination
+ *   L_L (L_L[1:l,1:l])^+ L_T of the two sub-solves, rows in M's own order;
+ *   B is diagonal positive (singular values of the r x r core).  S = M - L.
+ */
+sfr_status sfr_solve_nys(sfr_handle h, const void* M, int64_t ldm, const int64_t* perm, void* U, double* B,
+                         void* V, void* S, int64_t lds, sfr_info* info, void* hip_stream);
+
+/* Release the handle and its workspace.  NULL is accepted. */
+sfr_status sfr_destroy(sfr_handle h);
+
+/* Device workspace owned by the handle, in bytes. */
+sfr_status sfr_workspace_bytes(sfr_handle h, uint64_t* bytes);
+
+/* Static description of a status code. */
+const char* sfr_status_string(sfr_status s);
+
+/* Library version as "major.minor.patch". */
+const char* sfr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFR_H */

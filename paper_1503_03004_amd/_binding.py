@@ -1,0 +1,250 @@
+"""ctypes binding of libsfr.so (argument marshalling only).
+
+Every step of the decomposition runs in the HIP library; PyTorch only
+provides device memory and the stream.  The binding refuses to run if the
+library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsfr.so")
+
+SFR_OK = 0
+SFR_ERR_ARG = -1
+SFR_ERR_NOMEM = -2
+SFR_ERR_DEVICE = -3
+SFR_ERR_RANK = -4
+SFR_ERR_NONFINITE = -5
+SFR_ERR_HANDLE = -6
+SFR_WARN_MAXITER = 1
+SFR_WARN_NOT_SPD = 2
+
+SFR_F64 = 0
+SFR_F32 = 1
+
+
+class sfr_options(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("precision", ctypes.c_int32),
+        ("rho", ctypes.c_double),
+        ("mu_bar", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("fixed_iters", ctypes.c_int32),
+        ("nystrom_l", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("mu_left", ctypes.c_double),
+        ("mu_top", ctypes.c_double),
+    ]
+
+
+class sfr_info(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("iters_top", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("rel_residual", ctypes.c_double),
+        ("min_eig_B", ctypes.c_double),
+        ("mu_final", ctypes.c_double),
+    ]
+
+
+class SFRError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {status_string(code)} (status {code})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libsfr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        # torch first: the library then binds to the HIP runtime torch loaded
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.sfr_create.argtypes = [ctypes.POINTER(vp), i64, i64, i32, d, d, d, ctypes.POINTER(sfr_options)]
+        L.sfr_create.restype = ctypes.c_int
+        L.sfr_solve.argtypes = [vp, vp, i64, vp, vp, vp, vp, i64, ctypes.POINTER(sfr_info), vp]
+        L.sfr_solve.restype = ctypes.c_int
+        L.sfr_solve_nys.argtypes = [vp, vp, i64, ctypes.POINTER(ctypes.c_int64), vp, vp, vp, vp, i64,
+                                    ctypes.POINTER(sfr_info), vp]
+        L.sfr_solve_nys.restype = ctypes.c_int
+        L.sfr_destroy.argtypes = [vp]
+        L.sfr_destroy.restype = ctypes.c_int
+        L.sfr_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.sfr_workspace_bytes.restype = ctypes.c_int
+        L.sfr_status_string.argtypes = [ctypes.c_int]
+        L.sfr_status_string.restype = ctypes.c_char_p
+        L.sfr_version.argtypes = []
+        L.sfr_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    try:
+        return lib().sfr_status_string(int(code)).decode()
+    except ImportError:
+        return f"status {code}"
+
+
+@dataclass
+class Info:
+    status: int
+    iters: int
+    iters_top: int
+    converged: bool
+    rel_residual: float
+    min_eig_B: float
+    mu_final: float
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Solver:
+    """A handle of the C ABI (sfr_create ... sfr_destroy).
+
+    precision: "f64" (SFR_F64) or "f32" (SFR_F32).  mu is mu_0 of Alg. 1.
+    nystrom_l > 0 makes an FR-Nys handle (Alg. 3) that needs mu_left/mu_top.
+    """
+
+    def __init__(self, m, n, r, lam, mu, tol=1e-7, *, precision="f64", rho=1.5, mu_bar=1e9,
+                 max_iter=300, fixed_iters=0, nystrom_l=0, mu_left=0.0, mu_top=0.0):
+        self.m, self.n, self.r = int(m), int(n), int(r)
+        self.precision = precision
+        o = sfr_options()
+        o.struct_size = ctypes.sizeof(sfr_options)
+        o.precision = SFR_F64 if precision == "f64" else SFR_F32
+        if precision not in ("f64", "f32"):
+            raise ValueError(precision)
+        o.rho, o.mu_bar = float(rho), float(mu_bar)
+        o.max_iter, o.fixed_iters = int(max_iter), int(fixed_iters)
+        o.nystrom_l = int(nystrom_l)
+        o.mu_left, o.mu_top = float(mu_left), float(mu_top)
+        self.nystrom_l = int(nystrom_l)
+        self._h = ctypes.c_void_p(None)
+        rc = lib().sfr_create(ctypes.byref(self._h), self.m, self.n, self.r, float(lam), float(mu), float(tol),
+                              ctypes.byref(o))
+        if rc != SFR_OK:
+            self._h = ctypes.c_void_p(None)
+            raise SFRError(rc, "sfr_create")
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float64 if self.precision == "f64" else torch.float32
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_uint64(0)
+        rc = lib().sfr_workspace_bytes(self._h, ctypes.byref(b))
+        if rc != SFR_OK:
+            raise SFRError(rc, "sfr_workspace_bytes")
+        return int(b.value)
+
+    def _check_M(self, M):
+        import torch
+        if not (isinstance(M, torch.Tensor) and M.is_cuda):
+            raise TypeError("M must be a CUDA (HIP) torch tensor")
+        if M.dtype != self.dtype or M.dim() != 2 or tuple(M.shape) != (self.m, self.n):
+            raise ValueError(f"M must be {self.m}x{self.n} {self.dtype}")
+        if M.stride(1) != 1:
+            raise ValueError("M must be row-major (unit column stride)")
+
+    def _outputs(self, M, want_S, out):
+        import torch
+        dev = M.device
+        if out is None:
+            U = torch.empty((self.m, self.r), dtype=self.dtype, device=dev)
+            B = torch.empty((self.r, self.r), dtype=torch.float64, device=dev)
+            V = torch.empty((self.n, self.r), dtype=self.dtype, device=dev)
+            S = torch.empty((self.m, self.n), dtype=self.dtype, device=dev) if want_S else None
+        else:
+            U, B, V, S = out
+        return U, B, V, S
+
+    def solve(self, M, *, want_S=True, out=None, stream=None, raise_on_error=True):
+        """FR-ADM.  Returns (U, B, V, S, Info); S is None if want_S is False."""
+        self._check_M(M)
+        U, B, V, S = self._outputs(M, want_S, out)
+        info = sfr_info()
+        rc = lib().sfr_solve(self._h, ctypes.c_void_p(M.data_ptr()), M.stride(0), ctypes.c_void_p(U.data_ptr()),
+                             ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(V.data_ptr()),
+                             ctypes.c_void_p(S.data_ptr()) if S is not None else None,
+                             S.stride(0) if S is not None else 0, ctypes.byref(info), _stream_handle(stream))
+        if rc < 0 and raise_on_error:
+            raise SFRError(rc, "sfr_solve")
+        return U, B, V, S, _info(rc, info)
+
+    def solve_nys(self, M, perm, *, want_S=True, out=None, stream=None, raise_on_error=True):
+        """FR-Nys with row shuffle `perm` (host int64 array of length m)."""
+        import numpy as np
+        self._check_M(M)
+        U, B, V, S = self._outputs(M, want_S, out)
+        p = np.ascontiguousarray(perm, dtype=np.int64)
+        if p.shape != (self.m,):
+            raise ValueError("perm must have m entries")
+        info = sfr_info()
+        rc = lib().sfr_solve_nys(self._h, ctypes.c_void_p(M.data_ptr()), M.stride(0),
+                                 p.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.c_void_p(U.data_ptr()),
+                                 ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(V.data_ptr()),
+                                 ctypes.c_void_p(S.data_ptr()) if S is not None else None,
+                                 S.stride(0) if S is not None else 0, ctypes.byref(info), _stream_handle(stream))
+        if rc < 0 and raise_on_error:
+            raise SFRError(rc, "sfr_solve_nys")
+        return U, B, V, S, _info(rc, info)
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().sfr_destroy(self._h)
+        self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _info(rc, info):
+    return Info(status=int(rc), iters=info.iters, iters_top=info.iters_top, converged=bool(info.converged),
+                rel_residual=info.rel_residual, min_eig_B=info.min_eig_B, mu_final=info.mu_final)
+
+
+def solve(M, r, lam, mu, tol=1e-7, **opts):
+    """One-shot FR-ADM on a CUDA tensor M: returns (U, B, V, S, Info)."""
+    import torch
+    precision = "f64" if M.dtype == torch.float64 else "f32"
+    with Solver(M.shape[0], M.shape[1], r, lam, mu, tol, precision=precision, **opts) as s:
+        return s.solve(M)
+
+
+def solve_nys(M, perm, r, lam, l, mu_left, mu_top, tol=1e-7, **opts):
+    """One-shot FR-Nys on a CUDA tensor M: returns (U, B, V, S, Info)."""
+    import torch
+    precision = "f64" if M.dtype == torch.float64 else "f32"
+    with Solver(M.shape[0], M.shape[1], r, lam, 1.0, tol, precision=precision, nystrom_l=l,
+                mu_left=mu_left, mu_top=mu_top, **opts) as s:
+        return s.solve_nys(M, perm)

@@ -1,0 +1,434 @@
+// Host side of the C ABI declared in include/sfr.h.
+//
+// One Engine owns the device workspace of one m x n FR-ADM solve shape and
+// drives the device-resident iteration: per iteration k it enqueues
+//   sweep(k)  fused pass over M / Y                       (sweep.hip)
+//   gram(k)   Q = sum of column partials, G_Q, G_P         (sweep.hip)
+//   step(k)   FP64 r x r projectors, mu, convergence test  (small.hip)
+// in batches; every kernel returns at once after the step kernel has set
+// the device `done` flag, so the host only reads the flag between batches
+// and the stopping iteration equals the one the test selects.
+#include "engine.hpp"
+
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+namespace sfr {
+
+bool dev_alloc(std::vector<void*>& list, size_t& bytes, void** p, size_t sz)
+{
+    *p = nullptr;
+    if (sz == 0) sz = 16;
+    if (hipMalloc(p, sz) != hipSuccess) { *p = nullptr; return false; }
+    list.push_back(*p);
+    bytes += sz;
+    return true;
+}
+
+void free_all(std::vector<void*>& list)
+{
+    for (void* p : list) (void)hipFree(p);
+    list.clear();
+}
+
+static int bucket_rank(int r)
+{
+    static const int Rs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32};
+    for (int R : Rs)
+        if (R >= r) return R;
+    return -1;
+}
+
+template <typename T>
+static size_t lds_of(int R, int lpr, int W, int c) { return sweep_lds_bytes_c<T>(R, lpr, W, c); }
+
+// Pick the row-pass shape (lanes per row, vectors per lane), the cluster
+// size and the grid for an m x ne problem.
+static sfr_status configure(Engine& e)
+{
+    const int vec = e.vec;
+    const int nvec = (e.ne + vec - 1) / vec;
+    const size_t ldsmax = 160 * 1024;
+    int best_lpr = -1, best_nv = -1;
+    long best_waste = -1;
+    // single-slice shapes (c = 1): choose the least lane waste
+    for (int lpr = 4; lpr <= 64; lpr *= 2) {
+        const int nv = (nvec + lpr - 1) / lpr;
+        if (nv > 4) continue;
+        const int W = lpr * vec * nv;
+        const size_t L = e.f64 ? lds_of<double>(e.R, lpr, W, 1) : lds_of<float>(e.R, lpr, W, 1);
+        if (L > ldsmax / 2) continue;
+        const long waste = (long)lpr * nv - nvec;
+        if (best_waste < 0 || waste < best_waste || (waste == best_waste && lpr > best_lpr)) {
+            best_waste = waste; best_lpr = lpr; best_nv = nv;
+        }
+    }
+    if (best_lpr > 0) {
+        e.lpr = best_lpr; e.nv = best_nv; e.c = 1;
+    } else {
+        // wide rows: one row per wave, slices of W columns exchanged in clusters
+        e.lpr = 64;
+        e.nv = 4;
+        for (;;) {
+            const int W = 64 * vec * e.nv;
+            const size_t L = e.f64 ? lds_of<double>(e.R, 64, W, 2) : lds_of<float>(e.R, 64, W, 2);
+            if (L <= ldsmax / 2 || e.nv == 1) break;
+            --e.nv;
+        }
+        e.c = (e.ne + 64 * vec * e.nv - 1) / (64 * vec * e.nv);
+    }
+    e.W = e.lpr * vec * e.nv;
+    e.H = 4 * (64 / e.lpr);
+    e.nbands = (e.m + e.H - 1) / e.H;
+    e.lds = e.f64 ? lds_of<double>(e.R, e.lpr, e.W, e.c) : lds_of<float>(e.R, e.lpr, e.W, e.c);
+
+    int bpc = 0;
+    hipError_t herr = e.f64 ? sweep_prepare<double>(e.R, e.lds, &bpc) : sweep_prepare<float>(e.R, e.lds, &bpc);
+    if (herr != hipSuccess || bpc < 1) return SFR_ERR_DEVICE;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SFR_ERR_DEVICE;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return SFR_ERR_DEVICE;
+    bpc = std::min(bpc, 2);
+    const int maxres = cus * bpc;
+    if (e.c == 1) {
+        int want = std::min(((e.nbands + kXCD - 1) / kXCD) * kXCD, (maxres / kXCD) * kXCD);
+        if (want < kXCD) want = kXCD;
+        e.cpx = want / kXCD;
+    } else {
+        e.cpx = std::max(1, maxres / (kXCD * e.c));
+        if (kXCD * e.cpx * e.c > maxres) return SFR_ERR_ARG;  // columns beyond what one wave of clusters covers
+        // no more clusters than bands
+        while (e.cpx > 1 && kXCD * (e.cpx - 1) >= e.nbands) --e.cpx;
+    }
+    e.ncl = kXCD * e.cpx;
+    e.grid = e.ncl * e.c;
+    e.nbl_max = (e.nbands + e.ncl - 1) / e.ncl;
+    // Gram launch shape
+    const int rows = kTPB / e.R;
+    e.nqb = std::max(1, std::min((e.ne + rows - 1) / rows, 256));
+    e.rows_q = (e.ne + e.nqb - 1) / e.nqb;
+    e.npb = std::max(1, std::min((e.m + rows - 1) / rows, 256));
+    e.rows_p = (e.m + e.npb - 1) / e.npb;
+    e.E = e.R * (e.R + 1) / 2;
+    return SFR_OK;
+}
+
+sfr_status engine_create(Engine& e, int m, int n, int r, bool f64, int hist_len)
+{
+    e.m = m; e.n = n; e.r = r; e.f64 = f64;
+    e.esz = f64 ? 8 : 4;
+    e.vec = f64 ? 2 : 4;
+    e.ne = ((n + e.vec - 1) / e.vec) * e.vec;
+    e.R = bucket_rank(r);
+    if (e.R < 0) return SFR_ERR_ARG;
+    e.hist_len = hist_len;
+    sfr_status cs = configure(e);
+    if (cs != SFR_OK) return cs;
+    e.ldy = e.ne;
+    const size_t mn = (size_t)e.m * (size_t)e.ldy;
+    bool ok = true;
+    for (int b = 0; b < 2 && ok; ++b) ok = dev_alloc(e.allocs, e.bytes, &e.Y[b], mn * e.esz);
+    for (int b = 0; b < 2 && ok; ++b) ok = dev_alloc(e.allocs, e.bytes, &e.P[b], (size_t)e.m * e.R * e.esz);
+    for (int b = 0; b < 2 && ok; ++b) ok = dev_alloc(e.allocs, e.bytes, &e.Q[b], (size_t)e.ne * e.R * e.esz);
+    if (ok) ok = dev_alloc(e.allocs, e.bytes, &e.Qpart, (size_t)e.ncl * e.ne * e.R * e.esz);
+    if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.dy2part, sizeof(double) * (size_t)e.grid);
+    e.exch_words = (e.c > 1) ? (size_t)e.ncl * 4 * e.c * e.H * e.R * (e.esz / 4) : 0;
+    if (ok && e.exch_words) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.exch, 8 * e.exch_words);
+    if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.GQpart, sizeof(double) * (size_t)e.nqb * e.E);
+    if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.GPpart, sizeof(double) * (size_t)e.npb * e.E);
+    if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.st, sizeof(DevState));
+    if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.res_hist, sizeof(double) * (size_t)(hist_len + 2));
+    if (ok && e.ne != e.n) {
+        e.ldmpad = e.ne;
+        ok = dev_alloc(e.allocs, e.bytes, &e.Mpad, (size_t)e.m * e.ldmpad * e.esz);
+    }
+    if (ok && hipHostMalloc((void**)&e.host_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+        e.host_state = nullptr;
+        ok = false;
+    }
+    if (!ok) {
+        free_all(e.allocs);
+        if (e.host_state) { (void)hipHostFree(e.host_state); e.host_state = nullptr; }
+        (void)hipGetLastError();
+        return SFR_ERR_NOMEM;
+    }
+    return SFR_OK;
+}
+
+void engine_destroy(Engine& e)
+{
+    free_all(e.allocs);
+    if (e.host_state) { (void)hipHostFree(e.host_state); e.host_state = nullptr; }
+}
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        if ((x) != hipSuccess) {                   \
+            (void)hipGetLastError();               \
+            return SFR_ERR_DEVICE;                 \
+        }                                          \
+    } while (0)
+
+// Iterate Alg. 1 on the engine's shape.  M: device, row-major, ldm.  On
+// success the engine's state holds the factors of the returned iterate.
+template <typename T>
+sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, int64_t ldm, hipStream_t s)
+{
+    const bool aligned = ((uintptr_t)M % 16 == 0) && (ldm % e.vec == 0) && (e.ne == e.n);
+    const T* Mk = M;
+    int64_t ldk = ldm;
+    if (!aligned) {
+        if (!e.Mpad) {
+            e.ldmpad = e.ne;
+            void* q = nullptr;
+            if (hipMalloc(&q, (size_t)e.m * e.ldmpad * e.esz) != hipSuccess) { (void)hipGetLastError(); return SFR_ERR_NOMEM; }
+            e.allocs.push_back(q);
+            e.bytes += (size_t)e.m * e.ldmpad * e.esz;
+            e.Mpad = q;
+        }
+        HIPCHK(launch_copy_pad<T>(M, ldm, static_cast<T*>(e.Mpad), e.ldmpad, e.m, e.n, s));
+        Mk = static_cast<const T*>(e.Mpad);
+        ldk = e.ldmpad;
+    }
+    DevState& h = *e.host_state;
+    memset(&h, 0, sizeof(DevState));
+    h.m = e.m; h.n = e.ne; h.r = e.r; h.R = e.R;
+    h.max_iter = p.max_iter; h.fixed_iters = p.fixed_iters;
+    h.lambda = p.lambda; h.rho = p.rho; h.mu_bar = p.mu_bar; h.tol = p.tol;
+    h.M = Mk; h.ldm = ldk;
+    h.k = 1; h.done = 0; h.status = 0;
+    h.mu = mu0; h.mu_prev = mu0;
+    for (int i = 0; i < e.r; ++i) {
+        h.B[i * kMaxR + i] = 1.0;
+        h.TV[i * kMaxR + i] = 1.0;
+        h.TVf[i * kMaxR + i] = 1.0f;
+    }
+    HIPCHK(hipMemcpyAsync(e.st, &h, sizeof(DevState), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_init_q<T>(static_cast<T*>(e.Q[0]), e.ne, e.r, e.R, s));
+    if (e.exch_words) HIPCHK(launch_fill_u64(e.exch, e.exch_words, s));
+
+    const int limit = (p.fixed_iters > 0 ? p.fixed_iters : p.max_iter) + 1;
+    const int batch = 8;
+    int k = 1;
+    bool done = false;
+    while (!done) {
+        for (int b = 0; b < batch && k <= limit; ++b, ++k) {
+            SweepArgs<T> a;
+            a.st = e.st;
+            a.Yprev = static_cast<const T*>(e.Y[(k - 1) & 1]);
+            a.Ynext = static_cast<T*>(e.Y[k & 1]);
+            a.ldy = e.ldy;
+            a.Pprev = static_cast<const T*>(e.P[(k - 1) & 1]);
+            a.Pnext = static_cast<T*>(e.P[k & 1]);
+            a.Qprev = static_cast<const T*>(e.Q[(k - 1) & 1]);
+            a.Qpart = static_cast<T*>(e.Qpart);
+            a.dy2part = e.dy2part;
+            a.exch = e.exch;
+            a.m = e.m; a.n = e.ne;
+            a.mode = (k == 1) ? 0 : (k == 2 ? 1 : 2);
+            a.lpr = e.lpr; a.nv = e.nv; a.W = e.W; a.c = e.c; a.cpx = e.cpx; a.ncl = e.ncl;
+            a.nbands = e.nbands; a.nbl_max = e.nbl_max;
+            HIPCHK(launch_sweep<T>(a, e.R, e.grid, e.lds, s));
+            GramArgs<T> g;
+            g.st = e.st;
+            g.Qpart = static_cast<const T*>(e.Qpart);
+            g.Qnext = static_cast<T*>(e.Q[k & 1]);
+            g.Pnext = static_cast<const T*>(e.P[k & 1]);
+            g.GQpart = e.GQpart; g.GPpart = e.GPpart;
+            g.m = e.m; g.n = e.ne; g.ncl = e.ncl;
+            g.rows_q = e.rows_q; g.nqb = e.nqb; g.rows_p = e.rows_p; g.npb = e.npb;
+            HIPCHK(launch_gram<T>(g, e.R, s));
+            StepArgs sa;
+            sa.st = e.st;
+            sa.GPpart = e.GPpart; sa.npb = e.npb;
+            sa.GQpart = e.GQpart; sa.nqb = e.nqb;
+            sa.dy2part = e.dy2part; sa.ndy = e.grid;
+            sa.res_hist = e.res_hist;
+            HIPCHK(launch_step(sa, s));
+        }
+        HIPCHK(hipMemcpyAsync(&h, e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (h.done || h.exch_timeout) done = true;
+        else if (k > limit) return SFR_ERR_DEVICE;  // the step kernel always stops by `limit`
+    }
+    if (h.exch_timeout) return SFR_ERR_DEVICE;
+    if (h.status < 0) return (sfr_status)h.status;
+    return SFR_OK;
+}
+
+// Write U, B, V (and S) of the returned iterate; A/Vt scratch reuse the
+// spare ping-pong buffers of P and Q.
+template <typename T>
+static sfr_status engine_outputs(Engine& e, const Params& p, const T* M, int64_t ldm, T* U, double* B, T* V,
+                                 T* S, int64_t lds, hipStream_t s)
+{
+    const DevState& h = *e.host_state;
+    const int K = h.iters;
+    T* A = static_cast<T*>(e.P[(K + 1) & 1]);
+    T* Vt = static_cast<T*>(e.Q[(K + 1) & 1]);
+    HIPCHK(launch_factors<T>(e.st, static_cast<const T*>(e.P[K & 1]), static_cast<const T*>(e.Q[K & 1]), e.m, e.n,
+                             e.r, e.R, U, V, B, A, Vt, s));
+    if (S) {
+        const T* Yk = (K >= 2) ? static_cast<const T*>(e.Y[K & 1]) : nullptr;
+        HIPCHK(launch_lowrank_pass<T>(M, ldm, Yk, e.ldy, A, Vt, e.m, e.n, e.R, S, lds, 0, p.lambda, h.mu_prev, s));
+    }
+    HIPCHK(launch_final_small(e.st, s));
+    HIPCHK(hipMemcpyAsync(e.host_state, e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return SFR_OK;
+}
+
+template sfr_status engine_iterate<float>(Engine&, const Params&, double, const float*, int64_t, hipStream_t);
+template sfr_status engine_iterate<double>(Engine&, const Params&, double, const double*, int64_t, hipStream_t);
+
+}  // namespace sfr
+
+using namespace sfr;
+
+static sfr_status fill_info(const Engine& e, sfr_info* info, sfr_status st)
+{
+    const DevState& h = *e.host_state;
+    if (info) {
+        info->iters = h.iters;
+        info->iters_top = 0;
+        info->converged = (h.status == kOK) ? 1 : 0;
+        info->rel_residual = h.res;
+        info->min_eig_B = h.min_eig_B;
+        info->mu_final = h.mu_prev;
+    }
+    if (st != SFR_OK) return st;
+    if (h.status == kWarnMaxIter) return SFR_WARN_MAXITER;
+    if (!(h.min_eig_B > 0.0)) return SFR_WARN_NOT_SPD;
+    return SFR_OK;
+}
+
+extern "C" {
+
+const char* sfr_version(void) { return "0.1.0"; }
+
+const char* sfr_status_string(sfr_status s)
+{
+    switch (s) {
+    case SFR_OK: return "ok";
+    case SFR_ERR_ARG: return "invalid argument";
+    case SFR_ERR_NOMEM: return "device workspace allocation failed";
+    case SFR_ERR_DEVICE: return "HIP runtime error or device wait bound reached";
+    case SFR_ERR_RANK: return "rank(X V B) < r: Stiefel projector not unique";
+    case SFR_ERR_NONFINITE: return "non-finite value in M or in the iteration";
+    case SFR_ERR_HANDLE: return "invalid handle for this call";
+    case SFR_WARN_MAXITER: return "max_iter reached before the tolerance";
+    case SFR_WARN_NOT_SPD: return "returned B is not positive definite";
+    }
+    return "unknown status";
+}
+
+sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double lambda, double mu, double tol,
+                      const sfr_options* opt)
+{
+    if (!out) return SFR_ERR_ARG;
+    *out = nullptr;
+    sfr_options o;
+    memset(&o, 0, sizeof(o));
+    if (opt) {
+        if (opt->struct_size != sizeof(sfr_options)) return SFR_ERR_ARG;
+        o = *opt;
+    }
+    if (m < 1 || n < 1 || r < 1 || r > kMaxR || r > m || r > n) return SFR_ERR_ARG;
+    if (m > (int64_t)1 << 30 || n > (int64_t)1 << 30) return SFR_ERR_ARG;
+    if (!(lambda > 0.0) || !(tol >= 0.0) || lambda > 1e300 || tol > 1e300) return SFR_ERR_ARG;
+    if (o.precision != SFR_F64 && o.precision != SFR_F32) return SFR_ERR_ARG;
+    if (o.rho == 0.0) o.rho = 1.5;
+    if (o.mu_bar == 0.0) o.mu_bar = 1e9;
+    if (o.max_iter == 0) o.max_iter = 300;
+    if (!(o.rho > 1.0) || !(o.mu_bar > 0.0) || o.rho > 1e300 || o.mu_bar > 1e300) return SFR_ERR_ARG;
+    if (o.max_iter < 1 || o.max_iter > 100000 || o.fixed_iters < 0 || o.fixed_iters > 100000) return SFR_ERR_ARG;
+    const bool nys = o.nystrom_l > 0;
+    if (o.nystrom_l < 0) return SFR_ERR_ARG;
+    if (nys) {
+        if (o.nystrom_l < r || o.nystrom_l > m || o.nystrom_l > n) return SFR_ERR_ARG;
+        if (!(o.mu_left > 0.0) || !(o.mu_top > 0.0) || o.mu_left > 1e300 || o.mu_top > 1e300) return SFR_ERR_ARG;
+    } else {
+        if (!(mu > 0.0) || mu > 1e300) return SFR_ERR_ARG;
+    }
+    sfr_ctx* h = new (std::nothrow) sfr_ctx();
+    if (!h) return SFR_ERR_NOMEM;
+    h->m = m; h->n = n; h->r = r;
+    h->f64 = (o.precision == SFR_F64);
+    h->nys = nys;
+    h->l = o.nystrom_l;
+    h->prm.lambda = lambda; h->prm.mu0 = mu; h->prm.tol = tol;
+    h->prm.rho = o.rho; h->prm.mu_bar = o.mu_bar;
+    h->prm.max_iter = o.max_iter; h->prm.fixed_iters = o.fixed_iters;
+    h->mu_left = o.mu_left; h->mu_top = o.mu_top;
+    const int hist = std::max(o.max_iter, o.fixed_iters);
+    sfr_status st;
+    if (!nys) {
+        st = engine_create(h->main, (int)m, (int)n, r, h->f64, hist);
+    } else {
+        st = nys_setup(h);
+    }
+    if (st != SFR_OK) {
+        engine_destroy(h->main);
+        engine_destroy(h->left);
+        engine_destroy(h->top);
+        free_all(h->allocs);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return SFR_OK;
+}
+
+sfr_status sfr_destroy(sfr_handle h)
+{
+    if (!h) return SFR_OK;
+    if (h->magic != 0x53465221u) return SFR_ERR_HANDLE;
+    engine_destroy(h->main);
+    engine_destroy(h->left);
+    engine_destroy(h->top);
+    free_all(h->allocs);
+    h->magic = 0;
+    delete h;
+    return SFR_OK;
+}
+
+sfr_status sfr_workspace_bytes(sfr_handle h, uint64_t* bytes)
+{
+    if (!h || h->magic != 0x53465221u) return SFR_ERR_HANDLE;
+    if (!bytes) return SFR_ERR_ARG;
+    size_t b = h->main.bytes + h->left.bytes + h->top.bytes;
+    *bytes = (uint64_t)b;
+    return SFR_OK;
+}
+
+sfr_status sfr_solve(sfr_handle h, const void* M, int64_t ldm, void* U, double* B, void* V, void* S, int64_t lds,
+                     sfr_info* info, void* hip_stream)
+{
+    if (!h || h->magic != 0x53465221u || h->nys) return SFR_ERR_HANDLE;
+    if (!M || !U || !B || !V) return SFR_ERR_ARG;
+    if (ldm < h->n || (S && lds < h->n)) return SFR_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Engine& e = h->main;
+    sfr_status st;
+    if (h->f64) {
+        st = engine_iterate<double>(e, h->prm, h->prm.mu0, static_cast<const double*>(M), ldm, s);
+        if (st == SFR_OK)
+            st = engine_outputs<double>(e, h->prm, static_cast<const double*>(M), ldm, static_cast<double*>(U), B,
+                                        static_cast<double*>(V), static_cast<double*>(S), lds, s);
+    } else {
+        st = engine_iterate<float>(e, h->prm, h->prm.mu0, static_cast<const float*>(M), ldm, s);
+        if (st == SFR_OK)
+            st = engine_outputs<float>(e, h->prm, static_cast<const float*>(M), ldm, static_cast<float*>(U), B,
+                                       static_cast<float*>(V), static_cast<float*>(S), lds, s);
+    }
+    if (st < 0) {
+        if (info) memset(info, 0, sizeof(*info));
+        return st;
+    }
+    return fill_info(e, info, st);
+}
+
+}  // extern "C"

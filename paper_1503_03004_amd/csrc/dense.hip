@@ -1,0 +1,191 @@
+// Once-per-solve kernels: initial factors, returned factors, the returned S
+// of Alg. 1 (soft threshold of the last residual), the gather of the two
+// Nystrom blocks of Alg. 3, and the dense S = M - L of its combine.
+#include "sfr_internal.hpp"
+
+namespace sfr {
+
+template <typename T>
+__global__ void init_q_kernel(T* Q, int n, int r, int R)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * R) return;
+    const int j = (int)(e / R), k = (int)(e % R);
+    Q[e] = (j == k && k < r) ? T(1) : T(0);
+}
+
+template <typename T>
+hipError_t launch_init_q(T* Q, int n, int r, int R, hipStream_t s)
+{
+    const int64_t cnt = (int64_t)n * R;
+    hipLaunchKernelGGL(init_q_kernel<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, Q, n, r, R);
+    return hipGetLastError();
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, size_t count)
+{
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (size_t)gridDim.x * blockDim.x)
+        p[e] = 0ull;
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, size_t count, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    unsigned grid = (unsigned)((count + 255) / 256);
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void copy_pad_kernel(const T* src, int64_t lds, T* dst, int64_t ldd, int m, int n)
+{
+    const int i = blockIdx.y;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ldd; j += gridDim.x * blockDim.x)
+        dst[(int64_t)i * ldd + j] = (j < n) ? src[(int64_t)i * lds + j] : T(0);
+}
+
+template <typename T>
+hipError_t launch_copy_pad(const T* src, int64_t lds, T* dst, int64_t ldd, int m, int n, hipStream_t s)
+{
+    unsigned gx = (unsigned)((ldd + 255) / 256);
+    if (gx > 64) gx = 64;
+    hipLaunchKernelGGL(copy_pad_kernel<T>, dim3(gx, m), dim3(256), 0, s, src, lds, dst, ldd, m, n);
+    return hipGetLastError();
+}
+
+// Returned factors: U = P TUbar (m x r), V = Q TV (n x r), B; and the row
+// factors A = P TU, Vt = Q TV (R wide, zero padded) used by the S pass.
+template <typename T>
+__global__ void factors_kernel(const DevState* st, const T* P, const T* Q, int m, int n, int r, int R,
+                               T* U, T* V, double* B, T* A, T* Vt)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nu = (int64_t)m * R, nvv = (int64_t)n * R;
+    if (e < nu) {
+        const int i = (int)(e / R), k = (int)(e % R);
+        double su = 0.0, sa = 0.0;
+        for (int t = 0; t < R; ++t) {
+            const double pt = (double)P[(int64_t)i * R + t];
+            su = fma(pt, st->TUbar[t * kMaxR + k], su);
+            sa = fma(pt, st->TU[t * kMaxR + k], sa);
+        }
+        if (k < r) U[(int64_t)i * r + k] = (T)su;
+        A[e] = (T)sa;
+    } else if (e < nu + nvv) {
+        const int64_t f = e - nu;
+        const int j = (int)(f / R), k = (int)(f % R);
+        double sv = 0.0;
+        for (int t = 0; t < R; ++t) sv = fma((double)Q[(int64_t)j * R + t], st->TV[t * kMaxR + k], sv);
+        if (k < r) V[(int64_t)j * r + k] = (T)sv;
+        Vt[f] = (T)sv;
+    } else if (e < nu + nvv + (int64_t)r * r) {
+        const int64_t f = e - nu - nvv;
+        const int i = (int)(f / r), j = (int)(f % r);
+        B[f] = st->B[i * kMaxR + j];
+    }
+}
+
+// Dense pass over an m x n matrix with the rank-R term l_ij = A_i . Vt_j:
+//   mode 0 (FR-ADM S):  S = P_ST_{lambda/mu}(M - l + Y/mu), Y may be NULL
+//   mode 1 (FR-Nys S):  S = M - l
+// The workgroup stages a column tile of Vt in LDS and walks a band of rows.
+template <typename T>
+__global__ void __launch_bounds__(256) lowrank_pass_kernel(const T* M, int64_t ldm, const T* Y, int64_t ldy,
+                                                           const T* A, const T* Vt, int m, int n, int R,
+                                                           T* S, int64_t lds, int mode, double lam, double mu,
+                                                           int rows_per_blk)
+{
+    extern __shared__ __align__(16) unsigned char smem_lr[];
+    T* Vs = reinterpret_cast<T*>(smem_lr);  // R x 256
+    const int tid = threadIdx.x;
+    const int j = blockIdx.x * 256 + tid;
+    for (int k = 0; k < R; ++k) Vs[k * 256 + tid] = (j < n) ? Vt[(int64_t)j * R + k] : T(0);
+    __syncthreads();
+    const T t = (T)(lam / mu), imu = (T)(1.0 / mu);
+    const int i0 = blockIdx.y * rows_per_blk;
+    const int i1 = min(m, i0 + rows_per_blk);
+    if (j >= n) return;
+    for (int i = i0; i < i1; ++i) {
+        T l = 0;
+        for (int k = 0; k < R; ++k) l = fma(A[(int64_t)i * R + k], Vs[k * 256 + tid], l);
+        const T mv = M[(int64_t)i * ldm + j];
+        T out;
+        if (mode == 0) {
+            const T yv = Y ? Y[(int64_t)i * ldy + j] : T(0);
+            const T Rr = mv - l + yv * imu;
+            const T a = Rr - t, b = Rr + t;
+            out = (a > T(0) ? a : T(0)) + (b < T(0) ? b : T(0));
+        } else {
+            out = mv - l;
+        }
+        S[(int64_t)i * lds + j] = out;
+    }
+}
+
+template <typename T>
+hipError_t launch_factors(const DevState* st, const T* P, const T* Q, int m, int n, int r, int R,
+                          T* U, T* V, double* B, T* A, T* Vt, hipStream_t s)
+{
+    const int64_t cnt = (int64_t)m * R + (int64_t)n * R + (int64_t)r * r;
+    hipLaunchKernelGGL(factors_kernel<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, st, P, Q,
+                       m, n, r, R, U, V, B, A, Vt);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_lowrank_pass(const T* M, int64_t ldm, const T* Y, int64_t ldy, const T* A, const T* Vt,
+                               int m, int n, int R, T* S, int64_t lds, int mode, double lam, double mu,
+                               hipStream_t s)
+{
+    const int rows = 32;
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)((m + rows - 1) / rows));
+    const size_t shm = sizeof(T) * (size_t)R * 256;
+    hipLaunchKernelGGL(lowrank_pass_kernel<T>, grid, dim3(256), shm, s, M, ldm, Y, ldy, A, Vt, m, n, R, S,
+                       lds, mode, lam, mu, rows);
+    return hipGetLastError();
+}
+
+// Alg. 3: C = Mt[:, 0:l] (m x l), Rb = Mt[0:l, :] (l x n) with row i of the
+// shuffled matrix Mt being row perm[i] of M.
+template <typename T>
+__global__ void nys_gather_kernel(const T* M, int64_t ldm, const int64_t* perm, int m, int n, int l,
+                                  T* C, T* Rb)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nc = (int64_t)m * l, nr = (int64_t)l * n;
+    if (e < nc) {
+        const int i = (int)(e / l), j = (int)(e % l);
+        C[e] = M[perm[i] * ldm + j];
+    } else if (e < nc + nr) {
+        const int64_t f = e - nc;
+        const int i = (int)(f / n), j = (int)(f % n);
+        Rb[f] = M[perm[i] * ldm + j];
+    }
+}
+
+template <typename T>
+hipError_t launch_nys_gather(const T* M, int64_t ldm, const int64_t* perm, int m, int n, int l, T* C, T* Rb,
+                             hipStream_t s)
+{
+    const int64_t cnt = (int64_t)m * l + (int64_t)l * n;
+    hipLaunchKernelGGL(nys_gather_kernel<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, M, ldm, perm,
+                       m, n, l, C, Rb);
+    return hipGetLastError();
+}
+
+#define INST(T)                                                                                              \
+    template hipError_t launch_init_q<T>(T*, int, int, int, hipStream_t);                                    \
+    template hipError_t launch_copy_pad<T>(const T*, int64_t, T*, int64_t, int, int, hipStream_t);          \
+    template hipError_t launch_factors<T>(const DevState*, const T*, const T*, int, int, int, int, T*, T*,    \
+                                          double*, T*, T*, hipStream_t);                                     \
+    template hipError_t launch_lowrank_pass<T>(const T*, int64_t, const T*, int64_t, const T*, const T*, int, \
+                                               int, int, T*, int64_t, int, double, double, hipStream_t);     \
+    template hipError_t launch_nys_gather<T>(const T*, int64_t, const int64_t*, int, int, int, T*, T*,       \
+                                             hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace sfr

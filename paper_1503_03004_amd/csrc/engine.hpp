@@ -1,0 +1,82 @@
+// Host-side engine and handle layout shared by api.hip and nys.hip.
+#pragma once
+
+#include "sfr_internal.hpp"
+#include "sfr.h"
+
+#include <vector>
+
+namespace sfr {
+
+struct Engine {
+    int m = 0, n = 0, ne = 0, r = 0, R = 0;   // ne: column count the kernels see (padded)
+    bool f64 = false;
+    size_t esz = 4;
+    int vec = 4;
+    // launch configuration
+    int lpr = 64, nv = 1, W = 0, c = 1, cpx = 1, ncl = 8, grid = 8, H = 4, nbands = 0, nbl_max = 0;
+    size_t lds = 0;
+    int rows_q = 0, nqb = 0, rows_p = 0, npb = 0, E = 0;
+    int hist_len = 0;
+    // workspace
+    void* Y[2] = {nullptr, nullptr};
+    int64_t ldy = 0;
+    void* P[2] = {nullptr, nullptr};
+    void* Q[2] = {nullptr, nullptr};
+    void* Qpart = nullptr;
+    double* dy2part = nullptr;
+    unsigned long long* exch = nullptr;
+    size_t exch_words = 0;
+    double* GQpart = nullptr;
+    double* GPpart = nullptr;
+    DevState* st = nullptr;
+    double* res_hist = nullptr;
+    void* Mpad = nullptr;             // padded copy of M when the kernels need it
+    int64_t ldmpad = 0;
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+    DevState* host_state = nullptr;   // pinned mirror used for init / readback
+};
+
+struct Params {
+    double lambda = 0, mu0 = 0, tol = 0, rho = 1.5, mu_bar = 1e9;
+    int max_iter = 300, fixed_iters = 0;
+};
+
+}  // namespace sfr
+
+struct sfr_ctx {
+    uint32_t magic = 0x53465221u;
+    int64_t m = 0, n = 0;
+    int32_t r = 0;
+    bool f64 = false;
+    bool nys = false;
+    int32_t l = 0;
+    sfr::Params prm;
+    double mu_left = 0, mu_top = 0;
+    sfr::Engine main;       // FR-ADM engine (m x n)
+    sfr::Engine left, top;  // FR-Nys sub-engines (m x l, l x n)
+    // FR-Nys workspace
+    void* C = nullptr;
+    void* Rb = nullptr;
+    int64_t* perm_d = nullptr;
+    void* UL = nullptr; double* BL = nullptr; void* VL = nullptr;
+    void* UT = nullptr; double* BT = nullptr; void* VT = nullptr;
+    double* core = nullptr;  // r x r workspace of the combine (several blocks)
+    void* Ucomb = nullptr;   // m x R combined row factor
+    void* Vcomb = nullptr;   // n x R combined column factor
+    std::vector<void*> allocs;
+};
+
+
+namespace sfr {
+sfr_status engine_create(Engine& e, int m, int n, int r, bool f64, int hist_len);
+void engine_destroy(Engine& e);
+bool dev_alloc(std::vector<void*>& list, size_t& bytes, void** p, size_t sz);
+void free_all(std::vector<void*>& list);
+template <typename T>
+sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, int64_t ldm, hipStream_t s);
+template <typename T>
+sfr_status engine_factors(Engine& e, T* U, double* B, T* V, hipStream_t s);
+sfr_status nys_setup(sfr_ctx* h);
+}  // namespace sfr

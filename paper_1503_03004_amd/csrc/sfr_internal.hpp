@@ -1,0 +1,161 @@
+// Internal declarations of the S-FR HIP library (gfx950).
+//
+// Device-resident solver state and kernel argument blocks for the FR-ADM
+// iteration (Alg. 1) with its L-step FixedRankOptStep (Alg. 2) evaluated in
+// one pass over the data per iteration:
+//
+//   X_k = M - S_k + Y_k/mu_k             formed in registers, never stored
+//   P   = X_k V_k          (m x r)       row-owned dot products
+//   Q   = X_k^T P          (n x r)       = X^T X V, column partials
+//   U   = P B C1,          C1 = (B G_P B)^{-1/2},   G_P = P^T P
+//   V   = Q K C2,          K  = B C1 B,  C2 = (K G_Q K)^{-1/2},  G_Q = Q^T Q
+//   B   = Sym(C1 B G_Q K C2)
+//
+// The first two lines are the two Stiefel projections of eq. (7) in their
+// A (A^T A)^{-1/2} form (A = X V B and A = X^T U B); the last is the SPD
+// step of eq. (8), using U^T X V = C1 B P^T X V = C1 B Q^T V.  The small
+// r x r algebra runs in FP64 in one workgroup; the m x n work runs in the
+// storage precision T (float or double).
+//
+// Within a sweep, the S- and dual steps of the previous iteration are fused
+// in front of the L-step input: with R = M - L_k + Y_{k-1}/mu_{k-1},
+//   Y_k = clamp(mu_{k-1} R, -lambda, lambda)
+//   S_k = R - Y_k / mu_{k-1}           (soft threshold, notation section)
+//   X_k = L_k + (Y_k - Y_{k-1})/mu_{k-1} + Y_k/mu_k
+// so each sweep reads M and Y_{k-1} and writes Y_k: 3 words per element.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfr {
+
+constexpr int kMaxR = 32;
+constexpr int kTPB = 256;            // threads per workgroup of the streaming kernels
+constexpr int kXCD = 8;              // accelerator complex dies on MI355X
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+// Status codes mirrored from the public header (kept numerically equal).
+enum : int32_t {
+    kOK = 0, kErrArg = -1, kErrNoMem = -2, kErrDevice = -3, kErrRank = -4,
+    kErrNonFinite = -5, kErrHandle = -6,
+    kWarnMaxIter = 1, kWarnNotSPD = 2
+};
+
+// Solver state kept in device memory for one solve.  Written by the FP64
+// step kernel, read by the streaming kernels.
+struct DevState {
+    // problem (fixed during a solve)
+    int32_t m, n, r, R;
+    int32_t max_iter, fixed_iters;
+    double lambda, rho, mu_bar, tol;
+    const void* M;      // caller's data, row-major
+    int64_t ldm;        // leading dimension of M (elements)
+    // progress
+    int32_t k;          // index of the next sweep (1-based)
+    int32_t done;       // 1 once the iteration has stopped
+    int32_t status;     // kOK or a negative error code, or kWarnMaxIter
+    int32_t iters;      // completed iterations once done
+    int32_t exch_timeout;  // set if a cluster exchange wait hit its bound
+    int32_t pad0;
+    double nrmM;        // ||M||_F
+    double mu;          // mu_k used by the next sweep's L-step input
+    double mu_prev;     // mu_{k-1} used by the next sweep's S/Y step
+    double res;         // last residual ||M - L - S||_F / ||M||_F
+    double min_eig_B;   // filled by the finalize step
+    double B[kMaxR * kMaxR];
+    double TU[kMaxR * kMaxR];     // a_i = P_i TU gives L rows (L = A V^T)
+    double TUbar[kMaxR * kMaxR];  // U = P TUbar
+    double TV[kMaxR * kMaxR];     // V = Q TV
+    float TUf[kMaxR * kMaxR];
+    float TVf[kMaxR * kMaxR];
+};
+
+template <typename T> __host__ __device__ inline const T* st_TU(const DevState* s);
+template <> __host__ __device__ inline const float* st_TU<float>(const DevState* s) { return s->TUf; }
+template <> __host__ __device__ inline const double* st_TU<double>(const DevState* s) { return s->TU; }
+template <typename T> __host__ __device__ inline const T* st_TV(const DevState* s);
+template <> __host__ __device__ inline const float* st_TV<float>(const DevState* s) { return s->TVf; }
+template <> __host__ __device__ inline const double* st_TV<double>(const DevState* s) { return s->TV; }
+
+// Arguments of one sweep launch.  Parities of the ping-pong buffers are
+// fixed per launch (sweep k reads buffer (k-1)&1 and writes buffer k&1).
+template <typename T>
+struct SweepArgs {
+    const DevState* st;
+    const T* Yprev;      // Y_{k-1}, m x ldy (mode 2 only)
+    T* Ynext;            // Y_k (modes 1, 2)
+    int64_t ldy;
+    const T* Pprev;      // P from sweep k-1, m x R (modes 1, 2)
+    T* Pnext;            // P of sweep k, m x R
+    const T* Qprev;      // Q from sweep k-1 (or V_1 = I), n x R
+    T* Qpart;            // per-cluster column partials, ncl x n x R
+    double* dy2part;     // per-workgroup ||Y_k - Y_{k-1}||^2 (mode 0: ||M||^2)
+    unsigned long long* exch;  // cluster exchange slots (tagged words)
+    int32_t m, n;
+    int32_t mode;        // 0: X = M (k = 1); 1: Y_{k-1} = 0 (k = 2); 2: general
+    int32_t lpr;         // lanes per row in the row pass (4..64)
+    int32_t nv;          // vectors per lane per row
+    int32_t W;           // columns per member slice = lpr * VEC * nv
+    int32_t c;           // members per cluster (column slices)
+    int32_t cpx;         // clusters per XCD
+    int32_t ncl;         // clusters
+    int32_t nbands;      // ceil(m / H)
+    int32_t nbl_max;     // max bands per cluster (tag stride)
+};
+
+// Column-partial reduction and Gram partials (one launch per iteration).
+template <typename T>
+struct GramArgs {
+    const DevState* st;
+    const T* Qpart;      // ncl x n x R
+    T* Qnext;            // n x R
+    const T* Pnext;      // m x R
+    double* GQpart;      // nqb x E
+    double* GPpart;      // npb x E
+    int32_t m, n, ncl;
+    int32_t rows_q;      // Q rows per workgroup
+    int32_t nqb;         // workgroups for Q
+    int32_t rows_p;      // P rows per workgroup
+    int32_t npb;         // workgroups for P
+};
+
+// FP64 r x r step (one workgroup).
+struct StepArgs {
+    DevState* st;
+    const double* GPpart; int32_t npb;
+    const double* GQpart; int32_t nqb;
+    const double* dy2part; int32_t ndy;
+    double* res_hist;     // res_hist[k-1] = residual of iteration k
+};
+
+// Host-side launchers (sweep.hip / small.hip / dense.hip).
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T>& a, int R, int grid, size_t lds, hipStream_t s);
+template <typename T>
+hipError_t launch_gram(const GramArgs<T>& a, int R, hipStream_t s);
+template <typename T>
+size_t sweep_lds_bytes_c(int R, int lpr, int W, int c);
+template <typename T>
+hipError_t sweep_prepare(int R, size_t lds, int* blocks_per_cu);
+
+hipError_t launch_step(const StepArgs& a, hipStream_t s);
+hipError_t launch_final_small(DevState* st, hipStream_t s);
+
+template <typename T>
+hipError_t launch_init_q(T* Q, int n, int r, int R, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, size_t count, hipStream_t s);
+template <typename T>
+hipError_t launch_copy_pad(const T* src, int64_t lds, T* dst, int64_t ldd, int m, int n, hipStream_t s);
+template <typename T>
+hipError_t launch_factors(const DevState* st, const T* P, const T* Q, int m, int n, int r, int R,
+                          T* U, T* V, double* B, T* A, T* Vt, hipStream_t s);
+template <typename T>
+hipError_t launch_lowrank_pass(const T* M, int64_t ldm, const T* Y, int64_t ldy, const T* A, const T* Vt,
+                               int m, int n, int R, T* S, int64_t lds, int mode, double lam, double mu,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_nys_gather(const T* M, int64_t ldm, const int64_t* perm, int m, int n, int l,
+                             T* C, T* Rb, hipStream_t s);
+
+}  // namespace sfr

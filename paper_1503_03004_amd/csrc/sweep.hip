@@ -1,0 +1,529 @@
+// One fused pass over the data per FR-ADM iteration (Alg. 1 with the
+// L-step of Alg. 2), gfx950.
+//
+// Work decomposition
+//   * Rows are cut into bands of H rows.  Each band is owned by a cluster of
+//     c workgroups; member q of a cluster covers the column slice
+//     [q W, (q+1) W).  Clusters are formed from workgroups of one XCD
+//     (workgroup g runs on XCD g % 8), so their exchange stays in one L2.
+//   * Row pass (phase 1): a group of `lpr` lanes owns one row of the band;
+//     each lane streams `nv` 16-byte vectors of M and Y_{k-1}, rebuilds
+//     l_ij = a_i . V_j (r FMAs, V slice staged in LDS), applies the S- and
+//     dual steps, writes Y_k, forms x_ij and accumulates p_i = sum_j x_ij V_j.
+//     x goes to LDS for phase 2.
+//   * If c > 1 the members add their partial p_i through tagged 64-bit
+//     words in global memory (value | tag << 32, so no fences are needed),
+//     one band behind the row pass so the wait overlaps streaming.
+//   * Column pass (phase 2): thread-owned columns accumulate
+//     Q_j += x_ij p_i from the LDS copy of x: Q = X^T X V with no second
+//     read of the data.
+// HBM traffic per element: read M, read Y_{k-1}, write Y_k.
+#include "sfr_internal.hpp"
+
+namespace sfr {
+
+template <typename T> struct Vec;
+template <> struct Vec<float> { using t = float4; static constexpr int N = 4; };
+template <> struct Vec<double> { using t = double2; static constexpr int N = 2; };
+
+template <typename T>
+__device__ __forceinline__ void load_vec(const T* p, T (&v)[Vec<T>::N])
+{
+    typename Vec<T>::t x = *reinterpret_cast<const typename Vec<T>::t*>(p);
+    __builtin_memcpy(v, &x, sizeof(x));
+}
+
+template <typename T>
+__device__ __forceinline__ void store_vec(T* p, const T (&v)[Vec<T>::N])
+{
+    typename Vec<T>::t x;
+    __builtin_memcpy(&x, v, sizeof(x));
+    *reinterpret_cast<typename Vec<T>::t*>(p) = x;
+}
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T v, int width)
+{
+    for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Number of 32-bit halves per exchanged value.
+template <typename T> struct Words { static constexpr int N = sizeof(T) / 4; };
+
+__device__ __forceinline__ unsigned long long spin_word(const unsigned long long* p, uint32_t tag,
+                                                        int32_t* timeout_flag)
+{
+    unsigned long long w = 0;
+    uint32_t n = 0;
+    for (;;) {
+        w = __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(w >> 32) == tag) break;
+        if (((++n) & 1023u) == 0) {
+            if (__hip_atomic_load(timeout_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (n >= kSpinLimit) {
+                __hip_atomic_store(timeout_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return w;
+}
+
+template <typename T>
+__device__ __forceinline__ void publish(unsigned long long* dst, T v, uint32_t tag)
+{
+    if constexpr (sizeof(T) == 4) {
+        unsigned long long w = ((unsigned long long)tag << 32) | (unsigned long long)__float_as_uint(v);
+        __hip_atomic_store(dst, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+        unsigned long long lo = ((unsigned long long)tag << 32) | (bits & 0xffffffffull);
+        unsigned long long hi = ((unsigned long long)tag << 32) | (bits >> 32);
+        __hip_atomic_store(dst, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(dst + 1, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T fetch(const unsigned long long* src, uint32_t tag, int32_t* timeout_flag)
+{
+    if constexpr (sizeof(T) == 4) {
+        unsigned long long w = spin_word(src, tag, timeout_flag);
+        return __uint_as_float((uint32_t)(w & 0xffffffffull));
+    } else {
+        unsigned long long lo = spin_word(src, tag, timeout_flag);
+        unsigned long long hi = spin_word(src + 1, tag, timeout_flag);
+        return __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
+    }
+}
+
+// Byte offsets of the dynamic LDS regions of one sweep workgroup.
+struct SweepLds {
+    size_t tu, tv, vs, xs, ps, gx, qred, red, total;
+};
+
+__host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
+
+template <typename T>
+__host__ __device__ inline SweepLds sweep_lds(int R, int lpr, int W, int c)
+{
+    const int H = 4 * (64 / lpr);
+    const int HG = (W >= kTPB) ? 1 : kTPB / W;
+    SweepLds L;
+    size_t o = 0;
+    L.tu = o; o = al16(o + sizeof(T) * R * R);
+    L.tv = o; o = al16(o + sizeof(T) * R * R);
+    L.vs = o; o = al16(o + sizeof(T) * (size_t)R * W);
+    L.xs = o; o = al16(o + sizeof(T) * 2 * (size_t)H * W);
+    L.ps = o; o = al16(o + sizeof(T) * 2 * (size_t)H * R);
+    L.gx = o; o = al16(o + (c > 1 ? sizeof(T) * 4 * (size_t)c * R : 0));
+    L.qred = o; o = al16(o + (W < kTPB ? sizeof(T) * (size_t)HG * W * R : 0));
+    L.red = o; o = al16(o + sizeof(double) * 4);
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+size_t sweep_lds_bytes_c(int R, int lpr, int W, int c)
+{
+    return sweep_lds<T>(R, lpr, W, c).total;
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kTPB, 2) sweep_kernel(SweepArgs<T> a)
+{
+    DevState* st = const_cast<DevState*>(a.st);
+    if (st->done) return;
+    constexpr int VEC = Vec<T>::N;
+    constexpr int WD = Words<T>::N;
+    constexpr int CPT2MAX = (R > 16) ? 2 : 4;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lpr = a.lpr, nv = a.nv, W = a.W, c = a.c;
+    const int rpw = 64 / lpr, H = 4 * rpw;
+    const int li = lane % lpr, rg = lane / lpr, gbase = lane - li;
+    const int g = blockIdx.x;
+    const int xcd = g % kXCD, loc = g / kXCD;
+    const int q = loc % c;
+    const int cl = xcd * a.cpx + loc / c;
+    const int c0 = q * W;
+    const int m = a.m, n = a.n;
+    const int64_t ldm = st->ldm, ldy = a.ldy;
+    const T* __restrict__ M = static_cast<const T*>(st->M);
+    const int mode = a.mode;
+    const T lam = (T)st->lambda;
+    const T mu_prev = (T)st->mu_prev;
+    const T imu_prev = (mode != 0) ? (T)(1.0 / st->mu_prev) : T(0);
+    const T imu_cur = (T)(1.0 / st->mu);
+    const uint32_t kiter = (uint32_t)st->k;
+    int32_t* tflag = &st->exch_timeout;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SweepLds L = sweep_lds<T>(R, lpr, W, c);
+    T* TUs = reinterpret_cast<T*>(smem + L.tu);
+    T* TVs = reinterpret_cast<T*>(smem + L.tv);
+    T* Vs = reinterpret_cast<T*>(smem + L.vs);
+    T* Xs = reinterpret_cast<T*>(smem + L.xs);
+    T* Ps = reinterpret_cast<T*>(smem + L.ps);
+    T* Gx = reinterpret_cast<T*>(smem + L.gx);
+    T* Qred = reinterpret_cast<T*>(smem + L.qred);
+    double* red = reinterpret_cast<double*>(smem + L.red);
+
+    {
+        const T* tu = st_TU<T>(st);
+        const T* tv = st_TV<T>(st);
+        for (int e = tid; e < R * R; e += kTPB) {
+            const int r0 = e / R, r1 = e % R;
+            TUs[e] = tu[r0 * kMaxR + r1];
+            TVs[e] = tv[r0 * kMaxR + r1];
+        }
+    }
+    __syncthreads();
+    // V slice of this member: V_j = Q_j TV, stored k-major (Vs[k][jj]).
+    for (int jj = tid; jj < W; jj += kTPB) {
+        const int j = c0 + jj;
+        T qrow[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) qrow[t] = (j < n) ? a.Qprev[(int64_t)j * R + t] : T(0);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            T s = 0;
+#pragma unroll
+            for (int t = 0; t < R; ++t) s = fma(qrow[t], TVs[t * R + k], s);
+            Vs[k * W + jj] = s;
+        }
+    }
+    __syncthreads();
+
+    const int nbands = a.nbands, ncl = a.ncl;
+    const int nbl = (cl < nbands) ? (nbands - 1 - cl) / ncl + 1 : 0;
+    const int cpt2 = (W >= kTPB) ? (W + kTPB - 1) / kTPB : 1;
+    const int HG = (W >= kTPB) ? 1 : kTPB / W;
+    double acc2 = 0.0;
+    T Qacc[CPT2MAX][R];
+#pragma unroll
+    for (int e = 0; e < CPT2MAX; ++e)
+#pragma unroll
+        for (int k = 0; k < R; ++k) Qacc[e][k] = T(0);
+
+    for (int j = 0; j <= nbl; ++j) {
+        if (j < nbl) {
+            // ---------------- phase 1: row pass over band b ----------------
+            const int b = cl + j * ncl;
+            const int buf = j & 1;
+            const int h = wave * rpw + rg;
+            const int i = b * H + h;
+            const bool row_ok = i < m;
+            T av[R];
+            if (mode != 0) {
+                T prow[R];
+#pragma unroll
+                for (int t = 0; t < R; ++t) prow[t] = row_ok ? a.Pprev[(int64_t)i * R + t] : T(0);
+                if (lpr >= R) {
+                    T s = 0;
+                    if (li < R) {
+#pragma unroll
+                        for (int t = 0; t < R; ++t) s = fma(prow[t], TUs[t * R + li], s);
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < R; ++kk) av[kk] = __shfl(s, gbase + kk, 64);
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < R; ++kk) {
+                        T s = 0;
+#pragma unroll
+                        for (int t = 0; t < R; ++t) s = fma(prow[t], TUs[t * R + kk], s);
+                        av[kk] = s;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < R; ++kk) av[kk] = T(0);
+            }
+            T p[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) p[k] = T(0);
+            T rowacc = 0;
+            for (int v = 0; v < nv; ++v) {
+                const int jj = (li + lpr * v) * VEC;
+                const int col = c0 + jj;
+                const bool ok = row_ok && (col < n);
+                T mv[VEC], yp[VEC], x[VEC];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) { mv[e] = T(0); yp[e] = T(0); }
+                if (ok) load_vec<T>(M + (int64_t)i * ldm + col, mv);
+                if (mode == 2 && ok) load_vec<T>(a.Yprev + (int64_t)i * ldy + col, yp);
+                T vk[R][VEC];
+#pragma unroll
+                for (int k = 0; k < R; ++k) load_vec<T>(Vs + k * W + jj, vk[k]);
+                if (mode == 0) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) { x[e] = mv[e]; rowacc = fma(mv[e], mv[e], rowacc); }
+                } else {
+                    T yn[VEC];
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        T l = 0;
+#pragma unroll
+                        for (int k = 0; k < R; ++k) l = fma(av[k], vk[k][e], l);
+                        const T Rr = mv[e] - l + yp[e] * imu_prev;
+                        const T y = fmin(fmax(mu_prev * Rr, -lam), lam);
+                        const T dy = y - yp[e];
+                        rowacc = fma(dy, dy, rowacc);
+                        x[e] = l + dy * imu_prev + y * imu_cur;
+                        yn[e] = y;
+                    }
+                    if (ok) store_vec<T>(a.Ynext + (int64_t)i * ldy + col, yn);
+                }
+                if (!ok) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) x[e] = T(0);
+                }
+                store_vec<T>(Xs + ((size_t)buf * H + h) * W + jj, x);
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) p[k] = fma(x[e], vk[k][e], p[k]);
+            }
+            acc2 += (double)rowacc;
+#pragma unroll
+            for (int k = 0; k < R; ++k) p[k] = group_sum(p[k], lpr);
+            if (c == 1) {
+                if (li == 0) {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) Ps[((size_t)buf * H + h) * R + k] = p[k];
+                }
+            } else if (li < R) {
+                // c > 1 only with lpr == 64 (one row per wave)
+                T mine = 0;
+#pragma unroll
+                for (int kk = 0; kk < R; ++kk) mine = (kk == li) ? p[kk] : mine;
+                const uint32_t tag = kiter * (uint32_t)a.nbl_max + (uint32_t)j + 1u;
+                const int slot = j & 3;
+                unsigned long long* dst =
+                    a.exch + (((((size_t)cl * 4 + slot) * c + q) * H + h) * R + li) * WD;
+                publish<T>(dst, mine, tag);
+            }
+        }
+        if (j >= 1) {
+            const int jb = j - 1;
+            const int b = cl + jb * ncl;
+            const int buf = jb & 1;
+            if (c > 1) {
+                // gather the c partials of this wave's row of band jb
+                const int h = wave;
+                const uint32_t tag = kiter * (uint32_t)a.nbl_max + (uint32_t)jb + 1u;
+                const int slot = jb & 3;
+                T* gx = Gx + (size_t)wave * c * R;
+                for (int e = lane; e < c * R; e += 64) {
+                    const int qq = e / R, k = e % R;
+                    const unsigned long long* src =
+                        a.exch + (((((size_t)cl * 4 + slot) * c + qq) * H + h) * R + k) * WD;
+                    gx[e] = fetch<T>(src, tag, tflag);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane < R) {
+                    T s = 0;
+                    for (int qq = 0; qq < c; ++qq) s += gx[qq * R + lane];
+                    Ps[((size_t)buf * H + h) * R + lane] = s;
+                }
+            }
+            __syncthreads();
+            if (q == 0) {
+                for (int e = tid; e < H * R; e += kTPB) {
+                    const int hh = e / R, k = e % R;
+                    const int i = b * H + hh;
+                    if (i < m) a.Pnext[(int64_t)i * R + k] = Ps[((size_t)buf * H + hh) * R + k];
+                }
+            }
+            // ---------------- phase 2: column pass, Q += X^T p --------------
+            if (W >= kTPB) {
+                for (int hh = 0; hh < H; ++hh) {
+                    const T* xr = Xs + ((size_t)buf * H + hh) * W;
+                    T pk[R];
+#pragma unroll
+                    for (int k = 0; k < R; ++k) pk[k] = Ps[((size_t)buf * H + hh) * R + k];
+#pragma unroll
+                    for (int e = 0; e < CPT2MAX; ++e) {
+                        const int col = tid + e * kTPB;
+                        if (e < cpt2 && col < W) {
+                            const T xv = xr[col];
+#pragma unroll
+                            for (int k = 0; k < R; ++k) Qacc[e][k] = fma(xv, pk[k], Qacc[e][k]);
+                        }
+                    }
+                }
+            } else {
+                const int col = tid % W, grp = tid / W;
+                if (grp < HG) {
+                    for (int hh = grp; hh < H; hh += HG) {
+                        const T xv = Xs[((size_t)buf * H + hh) * W + col];
+#pragma unroll
+                        for (int k = 0; k < R; ++k)
+                            Qacc[0][k] = fma(xv, Ps[((size_t)buf * H + hh) * R + k], Qacc[0][k]);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---------------- write the column partials of this cluster -----------
+    if (W >= kTPB) {
+#pragma unroll
+        for (int e = 0; e < CPT2MAX; ++e) {
+            const int col = tid + e * kTPB;
+            const int jcol = c0 + col;
+            if (e < cpt2 && col < W && jcol < n) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) a.Qpart[((size_t)cl * n + jcol) * R + k] = Qacc[e][k];
+            }
+        }
+    } else {
+        const int col = tid % W, grp = tid / W;
+        if (grp < HG) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) Qred[((size_t)grp * W + col) * R + k] = Qacc[0][k];
+        }
+        __syncthreads();
+        for (int e = tid; e < W * R; e += kTPB) {
+            const int colx = e / R, k = e % R;
+            T s = 0;
+            for (int gg = 0; gg < HG; ++gg) s += Qred[((size_t)gg * W + colx) * R + k];
+            const int jcol = c0 + colx;
+            if (jcol < n) a.Qpart[((size_t)cl * n + jcol) * R + k] = s;
+        }
+    }
+    // ---------------- ||Y_k - Y_{k-1}||^2 (or ||M||^2) partial ------------
+    acc2 = group_sum(acc2, 64);
+    if (lane == 0) red[wave] = acc2;
+    __syncthreads();
+    if (tid == 0) a.dy2part[g] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Sum the cluster partials of Q (fixed order), write Q, and form the
+// upper triangles of G_Q = Q^T Q and G_P = P^T P in FP64 per workgroup.
+template <typename T, int R>
+__global__ void __launch_bounds__(kTPB) gram_kernel(GramArgs<T> a)
+{
+    if (a.st->done) return;
+    constexpr int E = R * (R + 1) / 2;
+    constexpr int ROWS = kTPB / R;
+    __shared__ double tile[ROWS * R];
+    const int tid = threadIdx.x;
+    const int blk = blockIdx.x;
+    double acc[(E + kTPB - 1) / kTPB];
+#pragma unroll
+    for (int u = 0; u < (E + kTPB - 1) / kTPB; ++u) acc[u] = 0.0;
+    const bool isq = blk < a.nqb;
+    const int nrows = isq ? a.n : a.m;
+    const int per = isq ? a.rows_q : a.rows_p;
+    const int r0 = (isq ? blk : blk - a.nqb) * per;
+    const int r1 = min(nrows, r0 + per);
+    for (int base = r0; base < r1; base += ROWS) {
+        if (tid < ROWS * R) {
+            const int jl = tid / R, k = tid % R;
+            const int j = base + jl;
+            double v = 0.0;
+            if (j < r1) {
+                if (isq) {
+                    T s = 0;
+                    for (int cl = 0; cl < a.ncl; ++cl) s += a.Qpart[((size_t)cl * a.n + j) * R + k];
+                    a.Qnext[(int64_t)j * R + k] = s;
+                    v = (double)s;
+                } else {
+                    v = (double)a.Pnext[(int64_t)j * R + k];
+                }
+            }
+            tile[tid] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < (E + kTPB - 1) / kTPB; ++u) {
+            int e = tid + u * kTPB;
+            if (e < E) {
+                int x = 0, rem = e;
+                while (rem >= R - x) { rem -= R - x; ++x; }
+                const int y = x + rem;
+                double s = 0.0;
+                for (int jl = 0; jl < ROWS; ++jl) s = fma(tile[jl * R + x], tile[jl * R + y], s);
+                acc[u] += s;
+            }
+        }
+        __syncthreads();
+    }
+    double* out = isq ? (a.GQpart + (size_t)blk * E) : (a.GPpart + (size_t)(blk - a.nqb) * E);
+#pragma unroll
+    for (int u = 0; u < (E + kTPB - 1) / kTPB; ++u) {
+        int e = tid + u * kTPB;
+        if (e < E) out[e] = acc[u];
+    }
+}
+
+#define SFR_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
+
+template <typename T>
+static void* sweep_fn(int R)
+{
+    switch (R) {
+#define CASE(r) case r: return reinterpret_cast<void*>(&sweep_kernel<T, r>);
+        SFR_R_LIST(CASE)
+#undef CASE
+    default: return nullptr;
+    }
+}
+
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T>& a, int R, int grid, size_t lds, hipStream_t s)
+{
+    switch (R) {
+#define CASE(r)                                                                       \
+    case r:                                                                           \
+        hipLaunchKernelGGL((sweep_kernel<T, r>), dim3(grid), dim3(kTPB), lds, s, a); \
+        return hipGetLastError();
+        SFR_R_LIST(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t sweep_prepare(int R, size_t lds, int* blocks_per_cu)
+{
+    void* fn = sweep_fn<T>(R);
+    if (!fn) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kTPB, lds);
+}
+
+template <typename T>
+hipError_t launch_gram(const GramArgs<T>& a, int R, hipStream_t s)
+{
+    const int grid = a.nqb + a.npb;
+    switch (R) {
+#define CASE(r)                                                                     \
+    case r:                                                                         \
+        hipLaunchKernelGGL((gram_kernel<T, r>), dim3(grid), dim3(kTPB), 0, s, a); \
+        return hipGetLastError();
+        SFR_R_LIST(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_sweep<float>(const SweepArgs<float>&, int, int, size_t, hipStream_t);
+template hipError_t launch_sweep<double>(const SweepArgs<double>&, int, int, size_t, hipStream_t);
+template hipError_t launch_gram<float>(const GramArgs<float>&, int, hipStream_t);
+template hipError_t launch_gram<double>(const GramArgs<double>&, int, hipStream_t);
+template size_t sweep_lds_bytes_c<float>(int, int, int, int);
+template size_t sweep_lds_bytes_c<double>(int, int, int, int);
+template hipError_t sweep_prepare<float>(int, size_t, int*);
+template hipError_t sweep_prepare<double>(int, size_t, int*);
+
+}  // namespace sfr

@@ -1,0 +1,125 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point of include/sfr.h, and rejects invalid arguments on the host before
+any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1503_03004_amd as sfr
+from paper_1503_03004_amd import _binding as B
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "sfr.h")
+
+
+def declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sfr_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared()
+    for want in ("sfr_create", "sfr_solve", "sfr_solve_nys", "sfr_destroy", "sfr_status_string",
+                 "sfr_version", "sfr_workspace_bytes"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(sfr.LIB_PATH)
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structs have the C compiler's size and offsets."""
+    import subprocess
+    fields = {"sfr_options": [f for f, _ in B.sfr_options._fields_],
+              "sfr_info": [f for f, _ in B.sfr_info._fields_]}
+    lines = ['#include "sfr.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void) {"]
+    for st, fs in fields.items():
+        lines.append(f'printf("%zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'printf("%zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.dirname(HDR), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = []
+    for cls in (B.sfr_options, B.sfr_info):
+        want.append(ctypes.sizeof(cls))
+        want += [getattr(cls, f).offset for f, _ in cls._fields_]
+    assert got == want
+
+
+def test_status_strings_and_version():
+    L = sfr.lib()
+    assert L.sfr_version().decode().count(".") == 2
+    for code in (0, -1, -2, -3, -4, -5, -6, 1, 2):
+        s = L.sfr_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert L.sfr_status_string(99).decode() == "unknown status"
+
+
+def _create(m, n, r, lam, mu, tol, **kw):
+    o = B.sfr_options()
+    o.struct_size = ctypes.sizeof(B.sfr_options)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p(None)
+    rc = sfr.lib().sfr_create(ctypes.byref(h), m, n, r, lam, mu, tol, ctypes.byref(o))
+    return rc, h
+
+
+@pytest.mark.parametrize("args,kw", [
+    ((0, 10, 1, 0.1, 1.0, 1e-7), {}),            # m < 1
+    ((10, 0, 1, 0.1, 1.0, 1e-7), {}),            # n < 1
+    ((10, 10, 0, 0.1, 1.0, 1e-7), {}),           # r < 1
+    ((10, 5, 6, 0.1, 1.0, 1e-7), {}),            # r > min(m, n)
+    ((100, 100, 33, 0.1, 1.0, 1e-7), {}),        # r above the supported 32
+    ((10, 10, 2, 0.0, 1.0, 1e-7), {}),           # lambda <= 0
+    ((10, 10, 2, float("nan"), 1.0, 1e-7), {}),  # lambda NaN
+    ((10, 10, 2, 0.1, 0.0, 1e-7), {}),           # mu <= 0
+    ((10, 10, 2, 0.1, float("inf"), 1e-7), {}),  # mu infinite
+    ((10, 10, 2, 0.1, 1.0, -1.0), {}),           # tol < 0
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"precision": 7}),
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"rho": 0.9}),       # rho must exceed 1 (Alg. 1)
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"max_iter": -3}),
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"fixed_iters": -1}),
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"nystrom_l": 1}),   # l < r
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"nystrom_l": 11}),  # l > min(m, n)
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"nystrom_l": 4}),   # missing mu_left / mu_top
+])
+def test_create_rejects_invalid_arguments(args, kw):
+    rc, h = _create(*args, **kw)
+    assert rc == B.SFR_ERR_ARG
+    assert not h.value
+
+
+def test_create_rejects_wrong_struct_size():
+    o = B.sfr_options()
+    o.struct_size = 12
+    h = ctypes.c_void_p(None)
+    assert sfr.lib().sfr_create(ctypes.byref(h), 10, 10, 2, 0.1, 1.0, 1e-7, ctypes.byref(o)) == B.SFR_ERR_ARG
+    assert sfr.lib().sfr_create(None, 10, 10, 2, 0.1, 1.0, 1e-7, None) == B.SFR_ERR_ARG
+
+
+def test_null_handle_paths():
+    L = sfr.lib()
+    info = B.sfr_info()
+    assert L.sfr_solve(None, None, 0, None, None, None, None, 0, ctypes.byref(info), None) == B.SFR_ERR_HANDLE
+    assert L.sfr_solve_nys(None, None, 0, None, None, None, None, None, 0, ctypes.byref(info),
+                           None) == B.SFR_ERR_HANDLE
+    assert L.sfr_destroy(None) == B.SFR_OK
+    b = ctypes.c_uint64(0)
+    assert L.sfr_workspace_bytes(None, ctypes.byref(b)) == B.SFR_ERR_HANDLE
+
+
+def test_binding_refuses_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(ImportError):
+        B.lib()

@@ -1,0 +1,229 @@
+"""GPU parity of FR-ADM (Alg. 1 with the Alg. 2 L-step) against the FP64
+oracle, through the C ABI (Python binding = argument marshalling only).
+
+Tolerances (relative Frobenius error against the oracle at the same
+iteration count):
+  FP64: 1e-9.  The GPU forms the Stiefel projections of eq. (7) through the
+        Gram inverse square root and the oracle through a Jacobi thin SVD;
+        both are exact in real arithmetic, so only rounding differs
+        (observed ~1e-14; the margin covers the conditioning of the r x r
+        Grams, which squares kappa(X V)).
+  FP32: 1e-5, the target accuracy of the FP32 solve; FP32 rounding of the
+        m x n work sets a floor of a few 1e-7.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_1503_03004_amd as sfr
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-9, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    sfr.lib()
+    yield
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def gpu_solve(M, r, lam, mu0, precision, **opts):
+    dt = torch.float64 if precision == "f64" else torch.float32
+    Mt = torch.from_numpy(np.ascontiguousarray(M)).to(device="cuda", dtype=dt)
+    with sfr.Solver(M.shape[0], M.shape[1], r, lam, mu0, opts.pop("tol", 1e-7), precision=precision,
+                    **opts) as s:
+        U, B, V, S, info = s.solve(Mt)
+        torch.cuda.synchronize()
+        return dict(U=U.double().cpu().numpy(), B=B.cpu().numpy(), V=V.double().cpu().numpy(),
+                    S=S.double().cpu().numpy(), info=info)
+
+
+def compare(g, o, precision, what=""):
+    Lg = g["U"] @ g["B"] @ g["V"].T
+    Lo = o["U"] @ o["B"] @ o["V"].T
+    eL, eS = rel(Lg, Lo), rel(g["S"], o["S"])
+    tol = TOL[precision]
+    print(f"{what}: iters gpu {g['info'].iters} oracle {o['iters']}  errL {eL:.2e}  errS {eS:.2e}")
+    assert eL <= tol, (what, eL)
+    assert eS <= tol, (what, eS)
+    return eL, eS
+
+
+def case(inst, precision, fixed, **extra):
+    M = inst.M.astype(np.float64 if precision == "f64" else np.float32)
+    Md = M.astype(np.float64)
+    mu0 = workloads.default_mu0(Md)
+    o = oracle.fradm(Md, inst.r, inst.lam, mu0, fixed_iters=fixed, **extra)
+    g = gpu_solve(M, inst.r, inst.lam, mu0, precision, fixed_iters=fixed, **extra)
+    assert g["info"].iters == o["iters"]
+    return g, o
+
+
+# ---------------------------------------------------------------------------
+
+
+def test_plain_fp64_tolerance_driven_same_stop():
+    """400 x 400, r = 5, FP64 workload: the tolerance test stops at the same
+    iteration as the oracle and the results agree."""
+    inst = workloads.plain_fp64(seed=0)
+    mu0 = workloads.default_mu0(inst.M)
+    o = oracle.fradm(inst.M, inst.r, inst.lam, mu0, tol=1e-7, max_iter=300)
+    g = gpu_solve(inst.M, inst.r, inst.lam, mu0, "f64", tol=1e-7, max_iter=300)
+    assert g["info"].status == sfr.SFR_OK
+    assert g["info"].iters == o["iters"]
+    assert abs(g["info"].rel_residual - o["res"]) <= 1e-6 * o["res"] + 1e-15
+    compare(g, o, "f64", "plain_fp64")
+    # invariants of the returned factors (FP64)
+    r = inst.r
+    np.testing.assert_allclose(g["U"].T @ g["U"], np.eye(r), atol=1e-12)
+    np.testing.assert_allclose(g["V"].T @ g["V"], np.eye(r), atol=1e-12)
+    np.testing.assert_allclose(g["B"], g["B"].T, atol=0)
+    assert np.linalg.eigvalsh(g["B"]).min() > 0
+    assert abs(g["info"].min_eig_B - np.linalg.eigvalsh(g["B"]).min()) <= 1e-9 * np.abs(g["B"]).max()
+    assert np.linalg.matrix_rank(g["U"] @ g["B"] @ g["V"].T) == r
+    # planted recovery
+    assert rel(g["U"] @ g["B"] @ g["V"].T, inst.L0) <= 1e-5
+
+
+@pytest.mark.parametrize("fixed", [1, 2, 3, 8])
+def test_fp64_each_sweep_mode(fixed):
+    """Iteration 1 (X = M), 2 (Y_1 = 0) and the general sweep."""
+    inst = workloads.plain_fp64(seed=3, m=150, n=110, r=4)
+    g, o = case(inst, "f64", fixed)
+    compare(g, o, "f64", f"fixed{fixed}")
+    np.testing.assert_allclose(g["U"], o["U"], atol=1e-8)
+    np.testing.assert_allclose(g["V"], o["V"], atol=1e-8)
+    np.testing.assert_allclose(g["B"], o["B"], rtol=1e-9, atol=1e-9 * np.abs(o["B"]).max())
+
+
+@pytest.mark.parametrize("m,n,r,precision", [
+    (301, 203, 3, "f32"),     # ragged rows and columns
+    (1037, 77, 4, "f32"),     # narrow rows: several rows per wavefront
+    (257, 130, 5, "f32"),     # n not a multiple of the vector width (padded copy)
+    (211, 77, 3, "f64"),      # odd n in FP64
+    (600, 3000, 6, "f32"),    # wide rows: clusters of 3 column slices
+    (300, 1500, 4, "f64"),    # wide rows in FP64
+    (97, 2500, 12, "f32"),    # few rows, wide
+    (3, 50, 2, "f64"),        # fewer rows than one band
+    (200, 150, 1, "f64"),     # rank one
+    (64, 64, 16, "f32"),
+    (500, 64, 20, "f32"),     # r = 20 bucket
+    (400, 300, 32, "f64"),    # largest supported rank
+])
+def test_shapes(m, n, r, precision):
+    inst = workloads.planted(m, n, r, seed=m + n + r, frac=0.05, kind="uniform", scale=20.0,
+                             dtype=np.float64)
+    g, o = case(inst, precision, 10)
+    compare(g, o, precision, f"{m}x{n} r{r} {precision}")
+
+
+def test_fp32_large_shape_parity():
+    """2000 x 2000, r = 10, 10 % outliers U[-100, 100] in FP32 (the shape of
+    the 8000^2 workload at a size the oracle solves in seconds), at the
+    oracle's own stopping iteration."""
+    inst = workloads.large_fp32(seed=1, m=2000, n=2000, r=10)
+    Md = inst.M.astype(np.float64)
+    mu0 = workloads.default_mu0(Md)
+    o = oracle.fradm(Md, 10, inst.lam, mu0, tol=1e-7)
+    g = gpu_solve(inst.M, 10, inst.lam, mu0, "f32", fixed_iters=o["iters"])
+    compare(g, o, "f32", "2000^2 r10")
+    assert rel(g["U"] @ g["B"] @ g["V"].T, inst.L0.astype(np.float64)) <= 1e-5
+
+
+def test_rank_equals_min_dim_exact_in_one_iteration():
+    rng = np.random.default_rng(5)
+    M = rng.standard_normal((40, 12))
+    g = gpu_solve(M, 12, 0.1, 0.5, "f64", tol=1e-10)
+    assert g["info"].iters == 1
+    assert rel(g["U"] @ g["B"] @ g["V"].T, M) <= 1e-12
+    assert np.abs(g["S"]).max() <= 1e-10
+
+
+def test_no_outliers_exact_in_one_iteration_f32():
+    rng = np.random.default_rng(6)
+    M = (rng.standard_normal((500, 4)) @ rng.standard_normal((4, 300))).astype(np.float32)
+    g = gpu_solve(M, 4, 0.05, 0.1, "f32", tol=1e-5)
+    assert g["info"].iters == 1
+    assert rel(g["U"] @ g["B"] @ g["V"].T, M.astype(np.float64)) <= 1e-6
+
+
+def test_error_paths():
+    rng = np.random.default_rng(7)
+    M = rng.standard_normal((50, 40))
+    Mn = M.copy(); Mn[3, 7] = np.nan
+    g = gpu_solve_status(Mn, 3)
+    assert g == sfr.SFR_ERR_NONFINITE
+    Mz = M.copy(); Mz[:, :3] = 0.0   # X V_0 = 0 for V_0 = I_{n x r}: P_O undefined
+    assert gpu_solve_status(Mz, 3) == sfr.SFR_ERR_RANK
+    # max_iter reached
+    Mt = torch.from_numpy(M).cuda()
+    with sfr.Solver(50, 40, 3, 0.1, 0.05, 0.0, precision="f64", max_iter=2) as s:
+        U, B, V, S, info = s.solve(Mt)
+        assert info.status == sfr.SFR_WARN_MAXITER and info.iters == 2
+
+
+def gpu_solve_status(M, r):
+    Mt = torch.from_numpy(M).cuda()
+    with sfr.Solver(M.shape[0], M.shape[1], r, 0.1, 0.05, 1e-7, precision="f64") as s:
+        out = s.solve(Mt, raise_on_error=False)
+        return out[4].status
+
+
+def test_outputs_untouched_on_error():
+    M = np.full((30, 20), np.inf)
+    Mt = torch.from_numpy(M).cuda()
+    with sfr.Solver(30, 20, 2, 0.1, 0.1, 1e-7, precision="f64") as s:
+        U = torch.full((30, 2), 7.0, dtype=torch.float64, device="cuda")
+        B = torch.full((2, 2), 7.0, dtype=torch.float64, device="cuda")
+        V = torch.full((20, 2), 7.0, dtype=torch.float64, device="cuda")
+        S = torch.full((30, 20), 7.0, dtype=torch.float64, device="cuda")
+        out = s.solve(Mt, out=(U, B, V, S), raise_on_error=False)
+        assert out[4].status == sfr.SFR_ERR_NONFINITE
+        for t in (U, B, V, S):
+            assert bool((t == 7.0).all())
+
+
+def test_deterministic_and_handle_reuse():
+    """Two solves on one handle: bitwise equal on equal input (fixed-order
+    reductions, no float atomics), and a different input in between gives
+    its own oracle answer (state and exchange slots are reset)."""
+    a = workloads.planted(500, 3000, 5, seed=11, frac=0.08, kind="uniform", scale=30.0)
+    b = workloads.planted(500, 3000, 5, seed=12, frac=0.08, kind="uniform", scale=30.0)
+    mu_a = workloads.default_mu0(a.M); mu_b = workloads.default_mu0(b.M)
+    Ma = torch.from_numpy(a.M.astype(np.float32)).cuda()
+    Mb = torch.from_numpy(b.M.astype(np.float32)).cuda()
+    with sfr.Solver(500, 3000, 5, a.lam, mu_a, 1e-7, precision="f32", fixed_iters=9) as s:
+        r1 = [t.clone() for t in s.solve(Ma)[:4]]
+        s.solve(Mb)
+        r2 = [t.clone() for t in s.solve(Ma)[:4]]
+    for x, y in zip(r1, r2):
+        assert torch.equal(x, y)
+    o = oracle.fradm(b.M.astype(np.float32).astype(np.float64), 5, b.lam, mu_b, fixed_iters=9)
+    g = gpu_solve(b.M.astype(np.float32), 5, b.lam, mu_b, "f32", fixed_iters=9)
+    compare(g, o, "f32", "reuse")
+
+
+def test_full_size_8000_fp32_first_iterations():
+    """The 8000 x 8000, r = 10 FP32 workload in the launch configuration the
+    benchmark times: three iterations (all three sweep modes) against the
+    FP64 oracle, L and S compared on every entry of 64 sampled rows."""
+    inst = workloads.large_fp32(seed=0)
+    Md = inst.M.astype(np.float64)
+    mu0 = workloads.default_mu0(inst.M)
+    o = oracle.fradm(Md, 10, inst.lam, mu0, fixed_iters=3)
+    g = gpu_solve(inst.M, 10, inst.lam, mu0, "f32", fixed_iters=3)
+    rows = np.random.default_rng(0).choice(8000, 64, replace=False)
+    Lg = g["U"][rows] @ g["B"] @ g["V"].T
+    Lo = o["U"][rows] @ o["B"] @ o["V"].T
+    assert rel(Lg, Lo) <= 1e-5
+    assert rel(g["S"][rows], o["S"][rows]) <= 1e-5
+    assert rel(g["S"], o["S"]) <= 1e-5
