@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of the S-FR hot path on one MI355X.
+
+A step is one FR-ADM iteration (Alg. 1 with the Alg. 2 L-step): the fused
+sweep over M and Y, the column-partial/Gram reduction and the FP64 r x r
+step.  The timed region runs exactly --steps iterations through the C ABI
+(sfr_solve with fixed_iters = steps, which also writes U, B, V and S once
+at the end), with the input already resident in HBM.
+
+Default workload: m = n = 8000, r = 10, FP32 storage, L0 = A B^T with
+N(0,1) factors, 10 % Bernoulli outliers U[-100, 100] (seeded synthetic).
+
+Printed: one JSON line with the iteration rate, the fused sweep's HBM
+roofline fraction (HIP events on the solve stream around every sweep
+launch), a full tolerance-driven solve rate with p50/p99 latency, the
+relative error against the FP64 oracle on the same input, and the oracle's
+own rate on the host (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sweep.hip", "sfr_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1503_03004_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter
+    summary, if it was taken on the current sweep source."""
+    path = os.path.join(ROOT, "profiles", f"sweep_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("sweep_source_sha") != sweep_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def rel(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", default="large_fp32", choices=["large_fp32", "plain_fp64", "photometric"])
+    ap.add_argument("--solves", type=int, default=5, help="tolerance-driven solves timed for solves/s")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-iters", type=int, default=2, help="oracle iterations timed on the host")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the row-sharded multi-GPU form is a design note only).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    import paper_1503_03004_amd as sfr
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    if args.workload == "large_fp32":
+        inst = workloads.large_fp32(seed=args.seed)
+        precision, esz, tol = "f32", 4, 1e-6
+        desc = "FR-ADM, m=n=8000, r=10, FP32, 10% outliers U[-100,100]"
+    elif args.workload == "plain_fp64":
+        inst = workloads.plain_fp64(seed=args.seed)
+        precision, esz, tol = "f64", 8, 1e-7
+        desc = "FR-ADM, m=n=400, r=5, FP64, 5% outliers U[-50,50]"
+    else:
+        inst = workloads.photometric(seed=args.seed)
+        precision, esz, tol = "f32", 4, 1e-6
+        desc = "FR-ADM, photometric stereo shape m=262144 x n=48, r=3, FP32"
+    m, n = inst.M.shape
+    r = inst.r
+    mu0 = workloads.default_mu0(inst.M)
+    tdt = torch.float64 if precision == "f64" else torch.float32
+    M = torch.from_numpy(np.ascontiguousarray(inst.M)).to(device=dev, dtype=tdt)
+    torch.cuda.synchronize()
+    print(f"[bench] workload {args.workload} {m}x{n} r={r} ready in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+
+    stream = torch.cuda.current_stream()
+    # ---- warmup: W untimed iterations
+    if args.warmup > 0:
+        with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=args.warmup) as w:
+            w.solve(M)
+    torch.cuda.synchronize()
+
+    # ---- timed: exactly K iterations
+    K = args.steps
+    solver = sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K, profile=True)
+    U = torch.empty((m, r), dtype=tdt, device=dev)
+    Bm = torch.empty((r, r), dtype=torch.float64, device=dev)
+    V = torch.empty((n, r), dtype=tdt, device=dev)
+    S = torch.empty((m, n), dtype=tdt, device=dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    _, _, _, _, info = solver.solve(M, out=(U, Bm, V, S), stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    assert info.iters == K, info
+    value = K / (ms / 1e3)
+    sweep_ms = info.sweep_ms
+    print(f"[bench] {K} iterations in {ms:.3f} ms; sweep {sweep_ms * 1e3:.1f} us avg over {info.sweeps_timed}",
+          file=sys.stderr, flush=True)
+
+    bytes_per_el = 3 * esz  # read M, read Y_{k-1}, write Y_k
+    alg_bytes = bytes_per_el * m * n
+    achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
+    traffic = measured_traffic(args.workload)
+
+    # ---- full tolerance-driven solves: solves/s and latency percentiles
+    lat = []
+    solve_iters = None
+    Ls = None
+    with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, max_iter=300) as s2:
+        for i in range(max(1, args.solves)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            U2, B2, V2, S2, inf2 = s2.solve(M, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            lat.append(e0.elapsed_time(e1))
+            solve_iters = inf2.iters
+        rec_err = None
+        if inst.L0 is not None:
+            rows = np.random.default_rng(1).choice(m, min(m, 256), replace=False)
+            Lr = (U2.double()[rows] @ B2 @ V2.double().T).cpu().numpy()
+            rec_err = rel(Lr, inst.L0[rows].astype(np.float64))
+    lat = np.array(lat)
+    print(f"[bench] tolerance-driven solve: {solve_iters} iterations, p50 {np.percentile(lat, 50):.2f} ms",
+          file=sys.stderr, flush=True)
+
+    # ---- FP64 oracle on the same input: host rate and parity of the first iterations
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        Md = inst.M.astype(np.float64)
+        oi = args.oracle_iters
+        t1 = time.perf_counter()
+        o = oracle.fradm(Md, r, inst.lam, mu0, fixed_iters=oi)
+        tc = time.perf_counter() - t1
+        cpu = {"value": oi / tc, "unit": "iters/s", "cores": 1, "kind": "oracle",
+               "sample": f"{oi} FR-ADM iterations of the same {m}x{n} r={r} input, FP64, one thread "
+                         f"({tc:.1f} s)"}
+        with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=oi) as s3:
+            U3, B3, V3, S3, _ = s3.solve(M)
+        torch.cuda.synchronize()
+        rows = np.random.default_rng(2).choice(m, min(m, 128), replace=False)
+        Lg = (U3.double()[rows] @ B3 @ V3.double().T).cpu().numpy()
+        Lo = o["U"][rows] @ o["B"] @ o["V"].T
+        parity = {"iterations": oi, "rel_err_L": rel(Lg, Lo),
+                  "rel_err_S": rel(S3.double()[rows].cpu().numpy(), o["S"][rows]),
+                  "rows_sampled": int(rows.size)}
+        print(f"[bench] oracle {oi} iterations in {tc:.1f} s; parity {parity}", file=sys.stderr, flush=True)
+    solver.close()
+
+    out = {
+        "metric": "iters/s & solves/s at rel-err<=1e-5 vs FP64 oracle; %HBM roofline; p50/p99",
+        "value": value,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": precision,
+        "data": "synthetic",
+        "config": {"workload": desc, "m": m, "n": n, "r": r, "lambda": inst.lam, "mu0": mu0,
+                   "rho": 1.5, "mu_bar": 1e9, "seed": args.seed},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "sweep_kernel", "sweep_us": sweep_ms * 1e3,
+                     "alg_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+        "solves_per_s": 1e3 / float(np.mean(lat)),
+        "solve_iters": solve_iters,
+        "solve_tol": tol,
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "parity_vs_oracle": parity,
+        "recovery_rel_err_L": rec_err,
+        "paper_context": "Table 1, FR-ADM 8000^2 r=10 (outliers in [-1,1]): 28 iterations in 27.42 s "
+                         "(~1.0 it/s) on a 3.2 GHz desktop CPU; not the same workload",
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -66,7 +66,8 @@ typedef struct {
     int32_t max_iter;        /* iteration cap, default 300 */
     int32_t fixed_iters;     /* > 0: run exactly this many iterations, no tolerance test */
     int32_t nystrom_l;       /* > 0: FR-Nys handle with l sampled rows/columns (Alg. 3) */
-    int32_t reserved0;
+    int32_t profile;         /* nonzero: time every general sweep launch with HIP events on
+                                the solve stream and report the mean in sfr_info.sweep_ms */
     double mu_left;          /* FR-Nys: initial penalty of the m x l sub-solve (> 0) */
     double mu_top;           /* FR-Nys: initial penalty of the l x n sub-solve (> 0) */
 } sfr_options;
@@ -80,6 +81,10 @@ typedef struct {
     double rel_residual;     /* ||M - L - S||_F / ||M||_F after the last iteration */
     double min_eig_B;        /* smallest eigenvalue of the returned B */
     double mu_final;         /* penalty used by the last iteration */
+    double sweep_ms;         /* profile != 0: mean duration of the fused sweep kernel over the
+                                iterations 2..K (ms); else 0 */
+    int32_t sweeps_timed;    /* number of launches averaged in sweep_ms */
+    int32_t reserved1;
 } sfr_info;
 
 /*

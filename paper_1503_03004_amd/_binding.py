@@ -36,7 +36,7 @@ class sfr_options(ctypes.Structure):
         ("max_iter", ctypes.c_int32),
         ("fixed_iters", ctypes.c_int32),
         ("nystrom_l", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
         ("mu_left", ctypes.c_double),
         ("mu_top", ctypes.c_double),
     ]
@@ -51,6 +51,9 @@ class sfr_info(ctypes.Structure):
         ("rel_residual", ctypes.c_double),
         ("min_eig_B", ctypes.c_double),
         ("mu_final", ctypes.c_double),
+        ("sweep_ms", ctypes.c_double),
+        ("sweeps_timed", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
     ]
 
 
@@ -109,6 +112,8 @@ class Info:
     rel_residual: float
     min_eig_B: float
     mu_final: float
+    sweep_ms: float
+    sweeps_timed: int
 
 
 def _stream_handle(stream):
@@ -126,7 +131,7 @@ class Solver:
     """
 
     def __init__(self, m, n, r, lam, mu, tol=1e-7, *, precision="f64", rho=1.5, mu_bar=1e9,
-                 max_iter=300, fixed_iters=0, nystrom_l=0, mu_left=0.0, mu_top=0.0):
+                 max_iter=300, fixed_iters=0, nystrom_l=0, mu_left=0.0, mu_top=0.0, profile=False):
         self.m, self.n, self.r = int(m), int(n), int(r)
         self.precision = precision
         o = sfr_options()
@@ -137,6 +142,7 @@ class Solver:
         o.rho, o.mu_bar = float(rho), float(mu_bar)
         o.max_iter, o.fixed_iters = int(max_iter), int(fixed_iters)
         o.nystrom_l = int(nystrom_l)
+        o.profile = 1 if profile else 0
         o.mu_left, o.mu_top = float(mu_left), float(mu_top)
         self.nystrom_l = int(nystrom_l)
         self._h = ctypes.c_void_p(None)
@@ -230,7 +236,8 @@ class Solver:
 
 def _info(rc, info):
     return Info(status=int(rc), iters=info.iters, iters_top=info.iters_top, converged=bool(info.converged),
-                rel_residual=info.rel_residual, min_eig_B=info.min_eig_B, mu_final=info.mu_final)
+                rel_residual=info.rel_residual, min_eig_B=info.min_eig_B, mu_final=info.mu_final,
+                sweep_ms=info.sweep_ms, sweeps_timed=info.sweeps_timed)
 
 
 def solve(M, r, lam, mu, tol=1e-7, **opts):

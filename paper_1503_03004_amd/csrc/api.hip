@@ -93,17 +93,26 @@ static sfr_status configure(Engine& e)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return SFR_ERR_DEVICE;
     bpc = std::min(bpc, 2);
     const int maxres = cus * bpc;
+    // Every member of a cluster must be resident at once (they wait on each
+    // other), so the grid never exceeds what the device holds in one wave.
     if (e.c == 1) {
         int want = std::min(((e.nbands + kXCD - 1) / kXCD) * kXCD, (maxres / kXCD) * kXCD);
         if (want < kXCD) want = kXCD;
         e.cpx = want / kXCD;
-    } else {
+        e.xcd_local = 1;
+        e.ncl = kXCD * e.cpx;
+    } else if (kXCD * e.c <= maxres) {
         e.cpx = std::max(1, maxres / (kXCD * e.c));
-        if (kXCD * e.cpx * e.c > maxres) return SFR_ERR_ARG;  // columns beyond what one wave of clusters covers
-        // no more clusters than bands
-        while (e.cpx > 1 && kXCD * (e.cpx - 1) >= e.nbands) --e.cpx;
+        while (e.cpx > 1 && kXCD * (e.cpx - 1) >= e.nbands) --e.cpx;  // no more clusters than bands
+        e.xcd_local = 1;
+        e.ncl = kXCD * e.cpx;
+    } else if (e.c <= maxres) {
+        e.xcd_local = 0;
+        e.cpx = 0;
+        e.ncl = std::max(1, std::min(maxres / e.c, e.nbands));
+    } else {
+        return SFR_ERR_ARG;  // more column slices than resident workgroups
     }
-    e.ncl = kXCD * e.cpx;
     e.grid = e.ncl * e.c;
     e.nbl_max = (e.nbands + e.ncl - 1) / e.ncl;
     // Gram launch shape
@@ -149,9 +158,17 @@ sfr_status engine_create(Engine& e, int m, int n, int r, bool f64, int hist_len)
         e.host_state = nullptr;
         ok = false;
     }
+    if (ok && hipHostMalloc((void**)&e.host_poll, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+        e.host_poll = nullptr;
+        ok = false;
+    }
+    for (int b = 0; b < 2 && ok; ++b)
+        if (hipEventCreateWithFlags(&e.poll_ev[b], hipEventDisableTiming) != hipSuccess) {
+            e.poll_ev[b] = nullptr;
+            ok = false;
+        }
     if (!ok) {
-        free_all(e.allocs);
-        if (e.host_state) { (void)hipHostFree(e.host_state); e.host_state = nullptr; }
+        engine_destroy(e);
         (void)hipGetLastError();
         return SFR_ERR_NOMEM;
     }
@@ -162,6 +179,11 @@ void engine_destroy(Engine& e)
 {
     free_all(e.allocs);
     if (e.host_state) { (void)hipHostFree(e.host_state); e.host_state = nullptr; }
+    if (e.host_poll) { (void)hipHostFree(e.host_poll); e.host_poll = nullptr; }
+    for (int b = 0; b < 2; ++b)
+        if (e.poll_ev[b]) { (void)hipEventDestroy(e.poll_ev[b]); e.poll_ev[b] = nullptr; }
+    for (hipEvent_t ev : e.prof_ev) (void)hipEventDestroy(ev);
+    e.prof_ev.clear();
 }
 
 #define HIPCHK(x)                                  \
@@ -202,6 +224,8 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
     h.k = 1; h.done = 0; h.status = 0;
     h.mu = mu0; h.mu_prev = mu0;
     for (int i = 0; i < e.r; ++i) {
+        h.E1[i * kMaxR + i] = 1.0;
+        h.E2[i * kMaxR + i] = 1.0;
         h.B[i * kMaxR + i] = 1.0;
         h.TV[i * kMaxR + i] = 1.0;
         h.TVf[i * kMaxR + i] = 1.0f;
@@ -212,9 +236,19 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
 
     const int limit = (p.fixed_iters > 0 ? p.fixed_iters : p.max_iter) + 1;
     const int batch = 8;
+    // Profiling: a start/stop event pair around every general sweep (k >= 3).
+    if (p.profile) {
+        const size_t need = 2 * (size_t)std::max(0, limit - 2);
+        while (e.prof_ev.size() < need) {
+            hipEvent_t ev;
+            HIPCHK(hipEventCreate(&ev));
+            e.prof_ev.push_back(ev);
+        }
+    }
     int k = 1;
+    int launched_batches = 0, checked_batches = 0;
     bool done = false;
-    while (!done) {
+    auto enqueue_batch = [&](void) -> sfr_status {
         for (int b = 0; b < batch && k <= limit; ++b, ++k) {
             SweepArgs<T> a;
             a.st = e.st;
@@ -229,9 +263,12 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
             a.exch = e.exch;
             a.m = e.m; a.n = e.ne;
             a.mode = (k == 1) ? 0 : (k == 2 ? 1 : 2);
-            a.lpr = e.lpr; a.nv = e.nv; a.W = e.W; a.c = e.c; a.cpx = e.cpx; a.ncl = e.ncl;
+            a.lpr = e.lpr; a.nv = e.nv; a.W = e.W; a.c = e.c; a.cpx = e.cpx; a.xcd_local = e.xcd_local; a.ncl = e.ncl;
             a.nbands = e.nbands; a.nbl_max = e.nbl_max;
+            const bool timed = p.profile && k >= 3;
+            if (timed) HIPCHK(hipEventRecord(e.prof_ev[2 * (k - 3)], s));
             HIPCHK(launch_sweep<T>(a, e.R, e.grid, e.lds, s));
+            if (timed) HIPCHK(hipEventRecord(e.prof_ev[2 * (k - 3) + 1], s));
             GramArgs<T> g;
             g.st = e.st;
             g.Qpart = static_cast<const T*>(e.Qpart);
@@ -249,10 +286,44 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
             sa.res_hist = e.res_hist;
             HIPCHK(launch_step(sa, s));
         }
-        HIPCHK(hipMemcpyAsync(&h, e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (h.done || h.exch_timeout) done = true;
-        else if (k > limit) return SFR_ERR_DEVICE;  // the step kernel always stops by `limit`
+        const int slot = launched_batches & 1;
+        HIPCHK(hipMemcpyAsync(&e.host_poll[slot], e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(e.poll_ev[slot], s));
+        ++launched_batches;
+        return SFR_OK;
+    };
+    // Keep one batch queued behind the one being checked: kernels of a
+    // finished solve return at once, so running ahead costs only launches.
+    sfr_status es = enqueue_batch();
+    if (es != SFR_OK) return es;
+    while (!done) {
+        if (k <= limit) {
+            es = enqueue_batch();
+            if (es != SFR_OK) return es;
+        }
+        const int slot = checked_batches & 1;
+        HIPCHK(hipEventSynchronize(e.poll_ev[slot]));
+        const DevState& ph = e.host_poll[slot];
+        ++checked_batches;
+        if (ph.done || ph.exch_timeout) done = true;
+        else if (checked_batches == launched_batches && k > limit) {
+            HIPCHK(hipStreamSynchronize(s));
+            return SFR_ERR_DEVICE;  // the step kernel always stops by `limit`
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(&h, e.st, offsetof(DevState, B), hipMemcpyDeviceToHost));
+    e.sweep_ms = 0.0;
+    e.sweeps_timed = 0;
+    if (p.profile && h.done) {
+        const int last = std::min(h.iters + 1, limit);  // sweeps 3..K+1 did work
+        for (int kk = 3; kk <= last; ++kk) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e.prof_ev[2 * (kk - 3)], e.prof_ev[2 * (kk - 3) + 1]));
+            e.sweep_ms += ms;
+            ++e.sweeps_timed;
+        }
+        if (e.sweeps_timed) e.sweep_ms /= e.sweeps_timed;
     }
     if (h.exch_timeout) return SFR_ERR_DEVICE;
     if (h.status < 0) return (sfr_status)h.status;
@@ -298,6 +369,8 @@ static sfr_status fill_info(const Engine& e, sfr_info* info, sfr_status st)
         info->rel_residual = h.res;
         info->min_eig_B = h.min_eig_B;
         info->mu_final = h.mu_prev;
+        info->sweep_ms = e.sweep_ms;
+        info->sweeps_timed = e.sweeps_timed;
     }
     if (st != SFR_OK) return st;
     if (h.status == kWarnMaxIter) return SFR_WARN_MAXITER;
@@ -362,6 +435,7 @@ sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double l
     h->prm.lambda = lambda; h->prm.mu0 = mu; h->prm.tol = tol;
     h->prm.rho = o.rho; h->prm.mu_bar = o.mu_bar;
     h->prm.max_iter = o.max_iter; h->prm.fixed_iters = o.fixed_iters;
+    h->prm.profile = o.profile != 0;
     h->mu_left = o.mu_left; h->mu_top = o.mu_top;
     const int hist = std::max(o.max_iter, o.fixed_iters);
     sfr_status st;

@@ -14,7 +14,7 @@ struct Engine {
     size_t esz = 4;
     int vec = 4;
     // launch configuration
-    int lpr = 64, nv = 1, W = 0, c = 1, cpx = 1, ncl = 8, grid = 8, H = 4, nbands = 0, nbl_max = 0;
+    int lpr = 64, nv = 1, W = 0, c = 1, cpx = 1, xcd_local = 1, ncl = 8, grid = 8, H = 4, nbands = 0, nbl_max = 0;
     size_t lds = 0;
     int rows_q = 0, nqb = 0, rows_p = 0, npb = 0, E = 0;
     int hist_len = 0;
@@ -36,11 +36,17 @@ struct Engine {
     std::vector<void*> allocs;
     size_t bytes = 0;
     DevState* host_state = nullptr;   // pinned mirror used for init / readback
+    DevState* host_poll = nullptr;    // pinned: two header snapshots, one per batch in flight
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> prof_ev;  // start/stop pairs of timed sweeps
+    double sweep_ms = 0.0;
+    int sweeps_timed = 0;
 };
 
 struct Params {
     double lambda = 0, mu0 = 0, tol = 0, rho = 1.5, mu_bar = 1e9;
     int max_iter = 300, fixed_iters = 0;
+    bool profile = false;
 };
 
 }  // namespace sfr

@@ -69,6 +69,10 @@ struct DevState {
     double TV[kMaxR * kMaxR];     // V = Q TV
     float TUf[kMaxR * kMaxR];
     float TVf[kMaxR * kMaxR];
+    // eigenbases of the two Grams of the previous step (warm start of the
+    // next Jacobi eigendecompositions)
+    double E1[kMaxR * kMaxR];
+    double E2[kMaxR * kMaxR];
 };
 
 template <typename T> __host__ __device__ inline const T* st_TU(const DevState* s);
@@ -98,7 +102,8 @@ struct SweepArgs {
     int32_t nv;          // vectors per lane per row
     int32_t W;           // columns per member slice = lpr * VEC * nv
     int32_t c;           // members per cluster (column slices)
-    int32_t cpx;         // clusters per XCD
+    int32_t cpx;         // clusters per XCD (xcd_local layout)
+    int32_t xcd_local;   // 1: members of a cluster share an XCD; 0: contiguous workgroups
     int32_t ncl;         // clusters
     int32_t nbands;      // ceil(m / H)
     int32_t nbl_max;     // max bands per cluster (tag stride)

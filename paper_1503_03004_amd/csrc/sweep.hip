@@ -5,7 +5,8 @@
 //   * Rows are cut into bands of H rows.  Each band is owned by a cluster of
 //     c workgroups; member q of a cluster covers the column slice
 //     [q W, (q+1) W).  Clusters are formed from workgroups of one XCD
-//     (workgroup g runs on XCD g % 8), so their exchange stays in one L2.
+//     (workgroup g runs on XCD g % 8), so their exchange stays in one L2;
+//     clusters wider than one XCD's share of the grid span XCDs instead.
 //   * Row pass (phase 1): a group of `lpr` lanes owns one row of the band;
 //     each lane streams `nv` 16-byte vectors of M and Y_{k-1}, rebuilds
 //     l_ij = a_i . V_j (r FMAs, V slice staged in LDS), applies the S- and
@@ -132,23 +133,35 @@ size_t sweep_lds_bytes_c(int R, int lpr, int W, int c)
     return sweep_lds<T>(R, lpr, W, c).total;
 }
 
+// Two waves per SIMD while the per-lane register state fits in 256 VGPRs;
+// larger ranks take one wave per SIMD and the full register file.
 template <typename T, int R>
-__global__ void __launch_bounds__(kTPB, 2) sweep_kernel(SweepArgs<T> a)
+constexpr int sweep_waves_per_simd() { return (sizeof(T) * R <= 48) ? 2 : 1; }
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_kernel(SweepArgs<T> a)
 {
     DevState* st = const_cast<DevState*>(a.st);
     if (st->done) return;
     constexpr int VEC = Vec<T>::N;
     constexpr int WD = Words<T>::N;
     constexpr int CPT2MAX = (R > 16) ? 2 : 4;
+    constexpr int NVMAX = 4;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lpr = a.lpr, nv = a.nv, W = a.W, c = a.c;
     const int rpw = 64 / lpr, H = 4 * rpw;
     const int li = lane % lpr, rg = lane / lpr, gbase = lane - li;
     const int g = blockIdx.x;
-    const int xcd = g % kXCD, loc = g / kXCD;
-    const int q = loc % c;
-    const int cl = xcd * a.cpx + loc / c;
+    int q, cl;
+    if (a.xcd_local) {
+        const int xcd = g % kXCD, loc = g / kXCD;
+        q = loc % c;
+        cl = xcd * a.cpx + loc / c;
+    } else {
+        q = g % c;
+        cl = g / c;
+    }
     const int c0 = q * W;
     const int m = a.m, n = a.n;
     const int64_t ldm = st->ldm, ldy = a.ldy;
@@ -247,15 +260,29 @@ __global__ void __launch_bounds__(kTPB, 2) sweep_kernel(SweepArgs<T> a)
 #pragma unroll
             for (int k = 0; k < R; ++k) p[k] = T(0);
             T rowacc = 0;
-            for (int v = 0; v < nv; ++v) {
+            // Issue every load of this row before the first use, so a lane
+            // has all its 2 * nv vectors in flight at once.  Out-of-range
+            // vectors read a valid dummy address and are zeroed at use.
+            T mvv[NVMAX][VEC], ypv[NVMAX][VEC];
+#pragma unroll
+            for (int v = 0; v < NVMAX; ++v) {
+                const int col = c0 + (li + lpr * v) * VEC;
+                const bool ok = (v < nv) && row_ok && (col < n);
+                load_vec<T>(M + (ok ? (int64_t)i * ldm + col : 0), mvv[v]);
+                if (mode == 2) load_vec<T>(a.Yprev + (ok ? (int64_t)i * ldy + col : 0), ypv[v]);
+            }
+#pragma unroll
+            for (int v = 0; v < NVMAX; ++v) {
+                if (v >= nv) break;
                 const int jj = (li + lpr * v) * VEC;
                 const int col = c0 + jj;
                 const bool ok = row_ok && (col < n);
                 T mv[VEC], yp[VEC], x[VEC];
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) { mv[e] = T(0); yp[e] = T(0); }
-                if (ok) load_vec<T>(M + (int64_t)i * ldm + col, mv);
-                if (mode == 2 && ok) load_vec<T>(a.Yprev + (int64_t)i * ldy + col, yp);
+                for (int e = 0; e < VEC; ++e) {
+                    mv[e] = ok ? mvv[v][e] : T(0);
+                    yp[e] = (ok && mode == 2) ? ypv[v][e] : T(0);
+                }
                 T vk[R][VEC];
 #pragma unroll
                 for (int k = 0; k < R; ++k) load_vec<T>(Vs + k * W + jj, vk[k]);
@@ -433,6 +460,7 @@ __global__ void __launch_bounds__(kTPB) gram_kernel(GramArgs<T> a)
             if (j < r1) {
                 if (isq) {
                     T s = 0;
+#pragma unroll 8
                     for (int cl = 0; cl < a.ncl; ++cl) s += a.Qpart[((size_t)cl * a.n + j) * R + k];
                     a.Qnext[(int64_t)j * R + k] = s;
                     v = (double)s;

@@ -118,6 +118,7 @@ def test_fp64_each_sweep_mode(fixed):
     (64, 64, 16, "f32"),
     (500, 64, 20, "f32"),     # r = 20 bucket
     (400, 300, 32, "f64"),    # largest supported rank
+    (48, 36000, 20, "f32"),   # clusters wider than one XCD's share of the grid
 ])
 def test_shapes(m, n, r, precision):
     inst = workloads.planted(m, n, r, seed=m + n + r, frac=0.05, kind="uniform", scale=20.0,

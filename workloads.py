@@ -205,3 +205,28 @@ def default_mu0(M: np.ndarray) -> float:
     """Initial penalty mu_0 = 1.25 / ||M||_2 (the iALM scale the continuation
     scheme of Alg. 1 is taken from); passed explicitly to both sides."""
     return 1.25 / spectral_norm(M)
+
+
+def nystrom_large_device(seed: int = 0, m: int = 40000, n: int = 40000, r: int = 20, frac: float = 0.07,
+                         scale: float = 20.0, device="cuda"):
+    """The 40000 x 40000, r = 20 workload drawn directly in device memory
+    with torch's seeded generator (the host copy would be 6.4 GB): L0 =
+    A B^T with N(0,1) factors, a Bernoulli(frac) outlier mask and
+    Laplace(0, scale) outlier values (inverse-CDF draw).  Returns
+    (M, A, B, lam) with M float32 on `device`."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    A = torch.randn(m, r, generator=g, device=device, dtype=torch.float32)
+    B = torch.randn(n, r, generator=g, device=device, dtype=torch.float32)
+    M = A @ B.T
+    rows_per = max(1, (1 << 28) // n)
+    for i0 in range(0, m, rows_per):
+        i1 = min(m, i0 + rows_per)
+        u = torch.rand(i1 - i0, n, generator=g, device=device)
+        mask = u < frac
+        v = torch.rand(i1 - i0, n, generator=g, device=device) - 0.5
+        lap = -scale * torch.sign(v) * torch.log1p(-2.0 * v.abs())
+        M[i0:i1] += torch.where(mask, lap, torch.zeros_like(lap))
+        del u, mask, v, lap
+    return M, A, B, 1.0 / math.sqrt(max(m, n))
