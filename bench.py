@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--solves", type=int, default=5, help="tolerance-driven solves timed for solves/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-iters", type=int, default=2, help="oracle iterations timed on the host")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -108,6 +110,14 @@ def main():
           flush=True)
 
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        # a plain copy kernel of known size: reads and writes 256 MiB each
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # ---- warmup: W untimed iterations
     if args.warmup > 0:
         with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=args.warmup) as w:

@@ -223,10 +223,12 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
     h.M = Mk; h.ldm = ldk;
     h.k = 1; h.done = 0; h.status = 0;
     h.mu = mu0; h.mu_prev = mu0;
-    for (int i = 0; i < e.r; ++i) {
+    for (int i = 0; i < kMaxR; ++i) {
         h.E1[i * kMaxR + i] = 1.0;
         h.E2[i * kMaxR + i] = 1.0;
         h.B[i * kMaxR + i] = 1.0;
+    }
+    for (int i = 0; i < e.r; ++i) {
         h.TV[i * kMaxR + i] = 1.0;
         h.TVf[i * kMaxR + i] = 1.0f;
     }
@@ -284,7 +286,7 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
             sa.GQpart = e.GQpart; sa.nqb = e.nqb;
             sa.dy2part = e.dy2part; sa.ndy = e.grid;
             sa.res_hist = e.res_hist;
-            HIPCHK(launch_step(sa, s));
+            HIPCHK(launch_step(sa, e.R, s));
         }
         const int slot = launched_batches & 1;
         HIPCHK(hipMemcpyAsync(&e.host_poll[slot], e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
@@ -346,7 +348,7 @@ static sfr_status engine_outputs(Engine& e, const Params& p, const T* M, int64_t
         const T* Yk = (K >= 2) ? static_cast<const T*>(e.Y[K & 1]) : nullptr;
         HIPCHK(launch_lowrank_pass<T>(M, ldm, Yk, e.ldy, A, Vt, e.m, e.n, e.R, S, lds, 0, p.lambda, h.mu_prev, s));
     }
-    HIPCHK(launch_final_small(e.st, s));
+    HIPCHK(launch_final_small(e.st, e.R, s));
     HIPCHK(hipMemcpyAsync(e.host_state, e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return SFR_OK;

@@ -20,80 +20,89 @@
 namespace sfr {
 
 // One wavefront: from U_L (rows 0..l-1 used), B_L, U_T, B_T build G and its
-// SVD.  status: 0, or kErrRank if A^T A or G is singular.
-template <typename T>
+// SVD.  status: 0, or kErrRank if A^T A or G is singular.  The r x r
+// matrices are held R x R with an identity block on the padded indices.
+template <typename T, int R>
 __global__ void __launch_bounds__(64) nys_combine_kernel(const T* UL, const double* BL, const T* UT,
                                                          const double* BT, int l, int r, double* Wl,
                                                          double* Zr, double* sig, int32_t* status)
 {
-    __shared__ double H1[kMaxR * LDP], H2[kMaxR * LDP], Bl[kMaxR * LDP], Bt[kMaxR * LDP];
-    __shared__ double T1[kMaxR * LDP], T2[kMaxR * LDP], Ev[kMaxR * LDP], G[kMaxR * LDP];
-    __shared__ double cs[4 * 16];
+    __shared__ double H1[R * LDP], H2[R * LDP], Bl[R * LDP], Bt[R * LDP];
+    __shared__ double T1[R * LDP], T2[R * LDP], Ev[R * LDP], G[R * LDP];
+    __shared__ double cs[8 * 16];
     __shared__ double wbuf[kMaxR];
     const int lane = threadIdx.x & 63;
     // H1 = U_L[0:l]^T U_L[0:l], H2 = U_L[0:l]^T U_T
-    for (int e = lane; e < r * r; e += 64) {
-        const int a = e / r, b = e % r;
+    for (int e = lane; e < R * R; e += 64) {
+        const int a = e / R, b = e % R;
+        const bool pad = (a >= r) || (b >= r);
         double s1 = 0.0, s2 = 0.0;
-        for (int i = 0; i < l; ++i) {
-            const double ua = (double)UL[(int64_t)i * r + a];
-            s1 = fma(ua, (double)UL[(int64_t)i * r + b], s1);
-            s2 = fma(ua, (double)UT[(int64_t)i * r + b], s2);
+        if (!pad) {
+            for (int i = 0; i < l; ++i) {
+                const double ua = (double)UL[(int64_t)i * r + a];
+                s1 = fma(ua, (double)UL[(int64_t)i * r + b], s1);
+                s2 = fma(ua, (double)UT[(int64_t)i * r + b], s2);
+            }
         }
-        H1[a * LDP + b] = s1;
-        H2[a * LDP + b] = s2;
-        Bl[a * LDP + b] = BL[a * r + b];
-        Bt[a * LDP + b] = BT[a * r + b];
-        Ev[a * LDP + b] = (a == b) ? 1.0 : 0.0;
+        const double id = (a == b) ? 1.0 : 0.0;
+        H1[a * LDP + b] = pad ? id : s1;
+        H2[a * LDP + b] = pad ? id : s2;
+        Bl[a * LDP + b] = pad ? id : BL[a * r + b];
+        Bt[a * LDP + b] = pad ? id : BT[a * r + b];
+        Ev[a * LDP + b] = id;
     }
     wsync();
     // A^T A = B_L H1 B_L
-    wmm(T1, Bl, H1, r);
-    wmm(T2, T1, Bl, r);
-    wsym(T2, r);
-    wjacobi(T2, Ev, r, cs);
+    wmm<R>(T1, Bl, H1);
+    wmm<R>(T2, T1, Bl);
+    wsym<R>(T2);
+    wjacobi<R>(T2, Ev, cs);
     double wmax = -INFINITY, wmin = INFINITY;
-    for (int i = lane; i < r; i += 64) {
+    for (int i = lane; i < R; i += 64) {
         wbuf[i] = T2[i * LDP + i];
-        wmax = fmax(wmax, wbuf[i]);
-        wmin = fmin(wmin, wbuf[i]);
+        if (i < r) {
+            wmax = fmax(wmax, wbuf[i]);
+            wmin = fmin(wmin, wbuf[i]);
+        }
     }
     wmax = wave_max(wmax);
     wmin = wave_min(wmin);
     wsync();
     bool ok = (wmax > 0.0) && (wmin > (double)r * DBL_EPSILON * wmax) && isfinite(wmax);
     // T1 = (A^T A)^{-1}
-    for (int e = lane; e < r * r; e += 64) {
-        const int i = e / r, j = e % r;
+    for (int e = lane; e < R * R; e += 64) {
+        const int i = e / R, j = e % R;
         double s = 0.0;
-        for (int t = 0; t < r; ++t) s = fma(Ev[i * LDP + t] / wbuf[t], Ev[j * LDP + t], s);
+        for (int t = 0; t < R; ++t) s = fma(Ev[i * LDP + t] / wbuf[t], Ev[j * LDP + t], s);
         T1[i * LDP + j] = s;
     }
     wsync();
     // G = B_L (A^T A)^{-1} (B_L H2) B_T
-    wmm(T2, Bl, T1, r);      // B_L (A^T A)^{-1}
-    wmm(H1, Bl, H2, r);      // A^T U_T = B_L H2
-    wmm(T1, T2, H1, r);
-    wmm(G, T1, Bt, r);
+    wmm<R>(T2, Bl, T1);      // B_L (A^T A)^{-1}
+    wmm<R>(H1, Bl, H2);      // A^T U_T = B_L H2
+    wmm<R>(T1, T2, H1);
+    wmm<R>(G, T1, Bt);
     // SVD of G from the eigendecomposition of G^T G = Zr diag(sig^2) Zr^T
-    wmtm(T2, G, G, r);
-    wsym(T2, r);
-    for (int e = lane; e < r * r; e += 64) Ev[(e / r) * LDP + e % r] = ((e / r) == (e % r)) ? 1.0 : 0.0;
+    wmtm<R>(T2, G, G);
+    wsym<R>(T2);
+    for (int e = lane; e < R * R; e += 64) Ev[(e / R) * LDP + e % R] = ((e / R) == (e % R)) ? 1.0 : 0.0;
     wsync();
-    wjacobi(T2, Ev, r, cs);
+    wjacobi<R>(T2, Ev, cs);
     double smax = -INFINITY, smin = INFINITY;
-    for (int i = lane; i < r; i += 64) {
+    for (int i = lane; i < R; i += 64) {
         const double w = T2[i * LDP + i];
         wbuf[i] = w > 0.0 ? sqrt(w) : 0.0;
-        smax = fmax(smax, wbuf[i]);
-        smin = fmin(smin, wbuf[i]);
+        if (i < r) {
+            smax = fmax(smax, wbuf[i]);
+            smin = fmin(smin, wbuf[i]);
+        }
     }
     smax = wave_max(smax);
     smin = wave_min(smin);
     wsync();
     ok = ok && (smax > 0.0) && (smin > (double)r * DBL_EPSILON * smax) && isfinite(smax);
     // Wl = G Zr diag(1/sig)
-    wmm(T1, G, Ev, r);
+    wmm<R>(T1, G, Ev);
     for (int e = lane; e < r * r; e += 64) {
         const int i = e / r, j = e % r;
         Wl[i * r + j] = wbuf[j] > 0.0 ? T1[i * LDP + j] / wbuf[j] : 0.0;
@@ -101,6 +110,24 @@ __global__ void __launch_bounds__(64) nys_combine_kernel(const T* UL, const doub
     }
     for (int i = lane; i < r; i += 64) sig[i] = wbuf[i];
     if (lane == 0) *status = ok ? kOK : kErrRank;
+}
+
+template <typename T>
+static hipError_t launch_nys_combine(int R, const T* UL, const double* BL, const T* UT, const double* BT, int l,
+                                     int r, double* Wl, double* Zr, double* sig, int32_t* status, hipStream_t s)
+{
+    switch (R) {
+#define CASE(rr)                                                                                          \
+    case rr:                                                                                              \
+        hipLaunchKernelGGL((nys_combine_kernel<T, rr>), dim3(1), dim3(64), 0, s, UL, BL, UT, BT, l, r, Wl, \
+                           Zr, sig, status);                                                              \
+        break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(8) CASE(10) CASE(12) CASE(16) CASE(20) CASE(24)
+        CASE(32)
+#undef CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // U[perm[i]] = (U_L Wl)_i,  V = V_T Zr,  B = diag(sig), and the R-wide row
@@ -203,9 +230,8 @@ static sfr_status nys_run(sfr_ctx* h, const T* M, int64_t ldm, T* U, double* B, 
     double* Zr = Wl + r * r;
     double* sig = Zr + r * r;
     int32_t* status = reinterpret_cast<int32_t*>(sig + r);
-    hipLaunchKernelGGL(nys_combine_kernel<T>, dim3(1), dim3(64), 0, s, static_cast<const T*>(h->UL), h->BL,
-                       static_cast<const T*>(h->UT), h->BT, l, r, Wl, Zr, sig, status);
-    HIPCHK(hipGetLastError());
+    HIPCHK(launch_nys_combine<T>(R, static_cast<const T*>(h->UL), h->BL, static_cast<const T*>(h->UT), h->BT, l, r,
+                                 Wl, Zr, sig, status, s));
     double host_core[kMaxR + 2];
     HIPCHK(hipMemcpyAsync(host_core, sig, sizeof(double) * (size_t)(r + 1), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

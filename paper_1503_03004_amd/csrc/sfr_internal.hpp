@@ -144,8 +144,8 @@ size_t sweep_lds_bytes_c(int R, int lpr, int W, int c);
 template <typename T>
 hipError_t sweep_prepare(int R, size_t lds, int* blocks_per_cu);
 
-hipError_t launch_step(const StepArgs& a, hipStream_t s);
-hipError_t launch_final_small(DevState* st, hipStream_t s);
+hipError_t launch_step(const StepArgs& a, int R, hipStream_t s);
+hipError_t launch_final_small(DevState* st, int R, hipStream_t s);
 
 template <typename T>
 hipError_t launch_init_q(T* Q, int n, int r, int R, hipStream_t s);

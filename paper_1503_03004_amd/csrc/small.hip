@@ -16,42 +16,49 @@
 namespace sfr {
 
 // Sum of `count` FP64 partial vectors of length E (part[b * E + e]) in a
-// fixed order, spread over the workgroup: segment sums, then segments.
+// fixed order, spread over the workgroup: adjacent threads read adjacent
+// entries of one partial; segment sums first, then the segments.
 __device__ void sum_partials(double* out_lds, const double* part, int count, int E, double* seg)
 {
     const int tid = threadIdx.x;
     const int nseg = max(1, kTPB / E);
     for (int w = tid; w < E * nseg; w += kTPB) {
-        const int e = w / nseg, sg = w % nseg;
+        const int sg = w / E, e = w % E;
         double s = 0.0;
-#pragma unroll 8
+#pragma unroll 16
         for (int b = sg; b < count; b += nseg) s += part[(size_t)b * E + e];
         seg[w] = s;
     }
     __syncthreads();
     for (int e = tid; e < E; e += kTPB) {
         double s = 0.0;
-        for (int sg = 0; sg < nseg; ++sg) s += seg[e * nseg + sg];
+        for (int sg = 0; sg < nseg; ++sg) s += seg[sg * E + e];
         out_lds[e] = s;
     }
     __syncthreads();
 }
 
+// The r x r matrices are held R x R (R the rank bucket, a compile-time
+// size) with an identity block on the padded indices: every product and
+// inverse square root below is then block diagonal and exact on the
+// leading r x r block, and the padded block is dropped when the transforms
+// are stored.
+template <int R>
 __global__ void __launch_bounds__(kTPB) step_kernel(StepArgs a)
 {
     DevState* st = a.st;
     if (st->done) return;
-    __shared__ double Gp[kMaxR * LDP], Gq[kMaxR * LDP], Bm[kMaxR * LDP], C1[kMaxR * LDP];
-    __shared__ double C2[kMaxR * LDP], Km[kMaxR * LDP], T1[kMaxR * LDP], T2[kMaxR * LDP];
-    __shared__ double Ev[kMaxR * LDP], Ev2[kMaxR * LDP];
-    __shared__ double seg[2 * kMaxR * (kMaxR + 1) / 2 + kTPB];
-    __shared__ double tri[2][kMaxR * (kMaxR + 1) / 2];
+    constexpr int E = R * (R + 1) / 2;
+    __shared__ double Gp[R * LDP], Gq[R * LDP], Bm[R * LDP], C1[R * LDP];
+    __shared__ double C2[R * LDP], Km[R * LDP], T1[R * LDP], T2[R * LDP];
+    __shared__ double Ev[R * LDP], Ev2[R * LDP];
+    __shared__ double seg[E > kTPB ? E : kTPB];
+    __shared__ double tri[2][E];
     __shared__ double red[kTPB / 64];
-    __shared__ double cs[4 * 16];
+    __shared__ double cs[8 * 16];
     __shared__ double wbuf[kMaxR];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r = st->r, R = st->R, k = st->k;
-    const int E = R * (R + 1) / 2;
+    const int r = st->r, k = st->k;
 
     // ---- convergence test of iteration k-1 (or ||M||_F on the first pass)
     double part = 0.0;
@@ -92,17 +99,13 @@ __global__ void __launch_bounds__(kTPB) step_kernel(StepArgs a)
     if (wave != 0) return;
 
     // ---- the r x r algebra: one wavefront from here on
-    for (int e = lane; e < E; e += 64) {
-        int x = 0, rem = e;
-        while (rem >= R - x) { rem -= R - x; ++x; }
-        const int y = x + rem;
-        if (x < r && y < r) {
-            Gp[x * LDP + y] = tri[0][e]; Gp[y * LDP + x] = tri[0][e];
-            Gq[x * LDP + y] = tri[1][e]; Gq[y * LDP + x] = tri[1][e];
-        }
-    }
-    for (int e = lane; e < r * r; e += 64) {
-        const int i = e / r, j = e % r;
+    for (int e = lane; e < R * R; e += 64) {
+        const int i = e / R, j = e % R;
+        const int x = i < j ? i : j, y = i < j ? j : i;
+        const int t = x * R - x * (x - 1) / 2 + (y - x);   // upper-triangle index of (x, y)
+        const bool pad = (i >= r) || (j >= r);
+        Gp[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : tri[0][t];
+        Gq[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : tri[1][t];
         Bm[i * LDP + j] = st->B[i * kMaxR + j];
         Ev[i * LDP + j] = st->E1[i * kMaxR + j];
         Ev2[i * LDP + j] = st->E2[i * kMaxR + j];
@@ -110,44 +113,43 @@ __global__ void __launch_bounds__(kTPB) step_kernel(StepArgs a)
     wsync();
 
     // ---- U-step: C1 = (B0 G_P B0)^{-1/2}
-    wmm(T1, Bm, Gp, r);
-    wmm(T2, T1, Bm, r);
-    wsym(T2, r);
-    const bool ok1 = winv_sqrt(C1, T2, Ev, T1, r, cs, wbuf);
+    wmm<R>(T1, Bm, Gp);
+    wmm<R>(T2, T1, Bm);
+    wsym<R>(T2);
+    const bool ok1 = winv_sqrt<R>(C1, T2, Ev, T1, r, cs, wbuf);
     // ---- V-step: K = B0 C1 B0, C2 = (K G_Q K)^{-1/2}
-    wmm(T1, Bm, C1, r);          // T1 = B0 C1  (the U transform)
-    wmm(Km, T1, Bm, r);
-    wsym(Km, r);
-    wmm(T2, Km, Gq, r);
-    wmm(C2, T2, Km, r);          // K G_Q K (C2 as scratch)
-    wsym(C2, r);
-    wcopy(T2, C2, r);
-    const bool ok2 = winv_sqrt(C2, T2, Ev2, Gp, r, cs, wbuf);   // Gp free now
+    wmm<R>(T1, Bm, C1);          // T1 = B0 C1  (the U transform)
+    wmm<R>(Km, T1, Bm);
+    wsym<R>(Km);
+    wmm<R>(T2, Km, Gq);
+    wmm<R>(C2, T2, Km);          // K G_Q K (C2 as scratch)
+    wsym<R>(C2);
+    wcopy<R>(T2, C2);
+    const bool ok2 = winv_sqrt<R>(C2, T2, Ev2, Gp, r, cs, wbuf);   // Gp free now
     if (!ok1 || !ok2) {
         if (lane == 0) { st->status = kErrRank; st->iters = k - 1; st->done = 1; }
         return;
     }
     // TV = K C2 -> Gp ; B = Sym(C1 B0 G_Q K C2) -> T2 ; TU = B0 C1 B -> Km
-    wmm(Gp, Km, C2, r);               // TV
-    wmm(T2, C1, Bm, r);               // C1 B0
-    wmm(C2, T2, Gq, r);               // C1 B0 G_Q
-    wmm(T2, C2, Gp, r);               // C1 B0 G_Q K C2
-    wsym(T2, r);                      // new B
-    wmm(Km, T1, T2, r);               // TU
+    wmm<R>(Gp, Km, C2);               // TV
+    wmm<R>(T2, C1, Bm);               // C1 B0
+    wmm<R>(C2, T2, Gq);               // C1 B0 G_Q
+    wmm<R>(T2, C2, Gp);               // C1 B0 G_Q K C2
+    wsym<R>(T2);                      // new B
+    wmm<R>(Km, T1, T2);               // TU
     for (int e = lane; e < kMaxR * kMaxR; e += 64) {
         const int i = e / kMaxR, j = e % kMaxR;
         const bool in = (i < r) && (j < r);
-        const double b = in ? T2[i * LDP + j] : 0.0;
+        const bool blk = (i < R) && (j < R);
         const double tu = in ? Km[i * LDP + j] : 0.0;
-        const double tub = in ? T1[i * LDP + j] : 0.0;
         const double tv = in ? Gp[i * LDP + j] : 0.0;
-        st->B[e] = b;
+        st->B[e] = in ? T2[i * LDP + j] : (i == j ? 1.0 : 0.0);
         st->TU[e] = tu;
-        st->TUbar[e] = tub;
+        st->TUbar[e] = in ? T1[i * LDP + j] : 0.0;
         st->TV[e] = tv;
         st->TUf[e] = (float)tu;
         st->TVf[e] = (float)tv;
-        if (in) {
+        if (blk) {
             st->E1[e] = Ev[i * LDP + j];
             st->E2[e] = Ev2[i * LDP + j];
         }
@@ -162,34 +164,48 @@ __global__ void __launch_bounds__(kTPB) step_kernel(StepArgs a)
 }
 
 // Smallest eigenvalue of the returned B (is it in SPD_r?  Appendix, Lemma 2).
+template <int R>
 __global__ void __launch_bounds__(64) final_small_kernel(DevState* st)
 {
-    __shared__ double A[kMaxR * LDP], Ev[kMaxR * LDP];
-    __shared__ double cs[4 * 16];
+    __shared__ double A[R * LDP], Ev[R * LDP];
+    __shared__ double cs[8 * 16];
     const int r = st->r;
     const int lane = threadIdx.x & 63;
-    for (int e = lane; e < r * r; e += 64) {
-        const int i = e / r, j = e % r;
-        A[i * LDP + j] = st->B[i * kMaxR + j];
+    for (int e = lane; e < R * R; e += 64) {
+        const int i = e / R, j = e % R;
+        const bool pad = (i >= r) || (j >= r);
+        A[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : st->B[i * kMaxR + j];
         Ev[i * LDP + j] = (i == j) ? 1.0 : 0.0;
     }
     wsync();
-    wjacobi(A, Ev, r, cs);
+    wjacobi<R>(A, Ev, cs);
     double w = INFINITY;
     for (int i = lane; i < r; i += 64) w = fmin(w, A[i * LDP + i]);
     w = wave_min(w);
     if (lane == 0) st->min_eig_B = w;
 }
 
-hipError_t launch_step(const StepArgs& a, hipStream_t s)
+#define SFR_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
+
+hipError_t launch_step(const StepArgs& a, int R, hipStream_t s)
 {
-    hipLaunchKernelGGL(step_kernel, dim3(1), dim3(kTPB), 0, s, a);
+    switch (R) {
+#define CASE(rr) case rr: hipLaunchKernelGGL(step_kernel<rr>, dim3(1), dim3(kTPB), 0, s, a); break;
+        SFR_R_LIST(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_final_small(DevState* st, hipStream_t s)
+hipError_t launch_final_small(DevState* st, int R, hipStream_t s)
 {
-    hipLaunchKernelGGL(final_small_kernel, dim3(1), dim3(64), 0, s, st);
+    switch (R) {
+#define CASE(rr) case rr: hipLaunchKernelGGL(final_small_kernel<rr>, dim3(1), dim3(64), 0, s, st); break;
+        SFR_R_LIST(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
