@@ -49,6 +49,75 @@ __device__ __forceinline__ T group_sum(T v, int width)
     return v;
 }
 
+// DPP lane exchange within rows of 16 lanes (compile-time control word).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum each of the R values over aligned groups of `width` lanes (a power of
+// two, 2..64); every lane of a group receives its group's sums.  Steps
+// inside a row of 16 lanes use DPP (quad permutations, half-row and row
+// mirrors, each of which pairs lanes holding disjoint partial sums); the
+// 16- and 32-lane steps use one cross-lane permute per value, all issued
+// together.
+template <typename T, int R>
+__device__ __forceinline__ void group_sum_all(T (&p)[R], int width)
+{
+    if (width >= 2) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) p[k] += dpp<0xB1>(p[k]);   // quad_perm [1,0,3,2]
+    }
+    if (width >= 4) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) p[k] += dpp<0x4E>(p[k]);   // quad_perm [2,3,0,1]
+    }
+    if (width >= 8) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) p[k] += dpp<0x141>(p[k]);  // row_half_mirror
+    }
+    if (width >= 16) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) p[k] += dpp<0x140>(p[k]);  // row_mirror
+    }
+    if (width >= 32) {
+        T t[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) t[k] = __shfl_xor(p[k], 16, 64);
+#pragma unroll
+        for (int k = 0; k < R; ++k) p[k] += t[k];
+    }
+    if (width >= 64) {
+        T t[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) t[k] = __shfl_xor(p[k], 32, 64);
+#pragma unroll
+        for (int k = 0; k < R; ++k) p[k] += t[k];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T readlane(T v, int lane)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+    } else {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    }
+}
+
 // Number of 32-bit halves per exchanged value.
 template <typename T> struct Words { static constexpr int N = sizeof(T) / 4; };
 
@@ -235,7 +304,16 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
                 T prow[R];
 #pragma unroll
                 for (int t = 0; t < R; ++t) prow[t] = row_ok ? a.Pprev[(int64_t)i * R + t] : T(0);
-                if (lpr >= R) {
+                if (lpr == 64) {
+                    // one row per wavefront: a_i is uniform, broadcast by readlane
+                    T s = 0;
+                    if (li < R) {
+#pragma unroll
+                        for (int t = 0; t < R; ++t) s = fma(prow[t], TUs[t * R + li], s);
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < R; ++kk) av[kk] = readlane(s, kk);
+                } else if (lpr >= R) {
                     T s = 0;
                     if (li < R) {
 #pragma unroll
@@ -316,8 +394,7 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
                     for (int e = 0; e < VEC; ++e) p[k] = fma(x[e], vk[k][e], p[k]);
             }
             acc2 += (double)rowacc;
-#pragma unroll
-            for (int k = 0; k < R; ++k) p[k] = group_sum(p[k], lpr);
+            group_sum_all<T, R>(p, lpr);
             if (c == 1) {
                 if (li == 0) {
 #pragma unroll
