@@ -291,6 +291,24 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
 #pragma unroll
         for (int k = 0; k < R; ++k) Qacc[e][k] = T(0);
 
+    // Row-pass operands of the band being processed: all 2 * nv vectors of
+    // a lane are issued together, one band ahead of their use.  Vectors out
+    // of range read a valid dummy address and are zeroed at use.
+    T mvv[NVMAX][VEC], ypv[NVMAX][VEC];
+    auto issue_loads = [&](int jb) {
+        const int bb = cl + jb * ncl;
+        const int ii = bb * H + wave * rpw + rg;
+        const bool rok = ii < m;
+#pragma unroll
+        for (int v = 0; v < NVMAX; ++v) {
+            const int col = c0 + (li + lpr * v) * VEC;
+            const bool ok = (v < nv) && rok && (col < n);
+            load_vec<T>(M + (ok ? (int64_t)ii * ldm + col : 0), mvv[v]);
+            if (mode == 2) load_vec<T>(a.Yprev + (ok ? (int64_t)ii * ldy + col : 0), ypv[v]);
+        }
+    };
+    if (nbl > 0) issue_loads(0);
+
     for (int j = 0; j <= nbl; ++j) {
         if (j < nbl) {
             // ---------------- phase 1: row pass over band b ----------------
@@ -338,17 +356,6 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
 #pragma unroll
             for (int k = 0; k < R; ++k) p[k] = T(0);
             T rowacc = 0;
-            // Issue every load of this row before the first use, so a lane
-            // has all its 2 * nv vectors in flight at once.  Out-of-range
-            // vectors read a valid dummy address and are zeroed at use.
-            T mvv[NVMAX][VEC], ypv[NVMAX][VEC];
-#pragma unroll
-            for (int v = 0; v < NVMAX; ++v) {
-                const int col = c0 + (li + lpr * v) * VEC;
-                const bool ok = (v < nv) && row_ok && (col < n);
-                load_vec<T>(M + (ok ? (int64_t)i * ldm + col : 0), mvv[v]);
-                if (mode == 2) load_vec<T>(a.Yprev + (ok ? (int64_t)i * ldy + col : 0), ypv[v]);
-            }
 #pragma unroll
             for (int v = 0; v < NVMAX; ++v) {
                 if (v >= nv) break;
@@ -393,6 +400,9 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) p[k] = fma(x[e], vk[k][e], p[k]);
             }
+            // the next band's loads go out now and land during the
+            // reduction, the exchange and the column pass of this band
+            if (j + 1 < nbl) issue_loads(j + 1);
             acc2 += (double)rowacc;
             group_sum_all<T, R>(p, lpr);
             if (c == 1) {
