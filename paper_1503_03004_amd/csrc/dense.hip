@@ -87,40 +87,85 @@ __global__ void factors_kernel(const DevState* st, const T* P, const T* Q, int m
     }
 }
 
+// VEC consecutive elements; one 16-byte access when VEC * sizeof(T) == 16.
+template <typename T, int VEC>
+__device__ __forceinline__ void vload(const T* p, T (&v)[VEC])
+{
+    if constexpr (VEC * sizeof(T) == 16) {
+        const float4 x = *reinterpret_cast<const float4*>(p);
+        __builtin_memcpy(v, &x, 16);
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[e] = p[e];
+    }
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void vstore(T* p, const T (&v)[VEC])
+{
+    if constexpr (VEC * sizeof(T) == 16) {
+        float4 x;
+        __builtin_memcpy(&x, v, 16);
+        *reinterpret_cast<float4*>(p) = x;
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) p[e] = v[e];
+    }
+}
+
 // Dense pass over an m x n matrix with the rank-R term l_ij = A_i . Vt_j:
 //   mode 0 (FR-ADM S):  S = P_ST_{lambda/mu}(M - l + Y/mu), Y may be NULL
 //   mode 1 (FR-Nys S):  S = M - l
-// The workgroup stages a column tile of Vt in LDS and walks a band of rows.
-template <typename T>
+// A workgroup owns a column tile of 256 * VEC columns and a band of rows;
+// each thread keeps its VEC columns of Vt in registers and streams 16-byte
+// vectors down the band.  The row factor A_i is uniform over the
+// workgroup.  Vector paths need n, ldm, ldy, lds multiples of VEC and
+// 16-byte aligned bases; otherwise VEC = 1.
+template <typename T, int VEC, int R>
 __global__ void __launch_bounds__(256) lowrank_pass_kernel(const T* M, int64_t ldm, const T* Y, int64_t ldy,
-                                                           const T* A, const T* Vt, int m, int n, int R,
+                                                           const T* A, const T* Vt, int m, int n,
                                                            T* S, int64_t lds, int mode, double lam, double mu,
                                                            int rows_per_blk)
 {
-    extern __shared__ __align__(16) unsigned char smem_lr[];
-    T* Vs = reinterpret_cast<T*>(smem_lr);  // R x 256
     const int tid = threadIdx.x;
-    const int j = blockIdx.x * 256 + tid;
-    for (int k = 0; k < R; ++k) Vs[k * 256 + tid] = (j < n) ? Vt[(int64_t)j * R + k] : T(0);
-    __syncthreads();
+    const int j0 = blockIdx.x * 256 * VEC;
     const T t = (T)(lam / mu), imu = (T)(1.0 / mu);
     const int i0 = blockIdx.y * rows_per_blk;
     const int i1 = min(m, i0 + rows_per_blk);
+    const int jj = tid * VEC;
+    const int j = j0 + jj;
     if (j >= n) return;
+    // this thread's VEC columns of Vt stay in registers for the whole band
+    T vk[R][VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+#pragma unroll
+        for (int k = 0; k < R; ++k) vk[k][e] = (j + e < n) ? Vt[(int64_t)(j + e) * R + k] : T(0);
+    const bool full = (VEC == 1) || (j + VEC <= n);
     for (int i = i0; i < i1; ++i) {
-        T l = 0;
-        for (int k = 0; k < R; ++k) l = fma(A[(int64_t)i * R + k], Vs[k * 256 + tid], l);
-        const T mv = M[(int64_t)i * ldm + j];
-        T out;
-        if (mode == 0) {
-            const T yv = Y ? Y[(int64_t)i * ldy + j] : T(0);
-            const T Rr = mv - l + yv * imu;
-            const T a = Rr - t, b = Rr + t;
-            out = (a > T(0) ? a : T(0)) + (b < T(0) ? b : T(0));
-        } else {
-            out = mv - l;
+        T av[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) av[k] = A[(int64_t)i * R + k];
+        T mv[VEC], yv[VEC], out[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) { mv[e] = T(0); yv[e] = T(0); }
+        if (full) {
+            vload<T, VEC>(M + (int64_t)i * ldm + j, mv);
+            if (mode == 0 && Y) vload<T, VEC>(Y + (int64_t)i * ldy + j, yv);
         }
-        S[(int64_t)i * lds + j] = out;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            T l = 0;
+#pragma unroll
+            for (int k = 0; k < R; ++k) l = fma(av[k], vk[k][e], l);
+            if (mode == 0) {
+                const T Rr = mv[e] - l + yv[e] * imu;
+                const T a = Rr - t, b = Rr + t;
+                out[e] = (a > T(0) ? a : T(0)) + (b < T(0) ? b : T(0));
+            } else {
+                out[e] = mv[e] - l;
+            }
+        }
+        if (full) vstore<T, VEC>(S + (int64_t)i * lds + j, out);
     }
 }
 
@@ -134,17 +179,37 @@ hipError_t launch_factors(const DevState* st, const T* P, const T* Q, int m, int
     return hipGetLastError();
 }
 
+template <typename T, int VEC>
+static hipError_t lowrank_dispatch(const T* M, int64_t ldm, const T* Y, int64_t ldy, const T* A, const T* Vt,
+                                   int m, int n, int R, T* S, int64_t lds, int mode, double lam, double mu,
+                                   hipStream_t s)
+{
+    const int rows = 64;
+    dim3 grid((unsigned)((n + 256 * VEC - 1) / (256 * VEC)), (unsigned)((m + rows - 1) / rows));
+    switch (R) {
+#define CASE(rr)                                                                                        \
+    case rr:                                                                                            \
+        hipLaunchKernelGGL((lowrank_pass_kernel<T, VEC, rr>), grid, dim3(256), 0, s, M, ldm, Y, ldy, A, \
+                           Vt, m, n, S, lds, mode, lam, mu, rows);                                      \
+        break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(8) CASE(10) CASE(12) CASE(16) CASE(20) CASE(24)
+        CASE(32)
+#undef CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_lowrank_pass(const T* M, int64_t ldm, const T* Y, int64_t ldy, const T* A, const T* Vt,
                                int m, int n, int R, T* S, int64_t lds, int mode, double lam, double mu,
                                hipStream_t s)
 {
-    const int rows = 32;
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)((m + rows - 1) / rows));
-    const size_t shm = sizeof(T) * (size_t)R * 256;
-    hipLaunchKernelGGL(lowrank_pass_kernel<T>, grid, dim3(256), shm, s, M, ldm, Y, ldy, A, Vt, m, n, R, S,
-                       lds, mode, lam, mu, rows);
-    return hipGetLastError();
+    constexpr int V = 16 / sizeof(T);
+    const bool vec = (n % V == 0) && (ldm % V == 0) && (lds % V == 0) && ((uintptr_t)M % 16 == 0) &&
+                     ((uintptr_t)S % 16 == 0) && (!Y || ((ldy % V == 0) && ((uintptr_t)Y % 16 == 0)));
+    if (vec) return lowrank_dispatch<T, V>(M, ldm, Y, ldy, A, Vt, m, n, R, S, lds, mode, lam, mu, s);
+    return lowrank_dispatch<T, 1>(M, ldm, Y, ldy, A, Vt, m, n, R, S, lds, mode, lam, mu, s);
 }
 
 // Alg. 3: C = Mt[:, 0:l] (m x l), Rb = Mt[0:l, :] (l x n) with row i of the

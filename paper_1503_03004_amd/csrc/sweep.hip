@@ -170,6 +170,15 @@ __device__ __forceinline__ T fetch(const unsigned long long* src, uint32_t tag, 
     }
 }
 
+// Exchange words of one band are read ahead of use: a lane holds up to
+// kGatherAhead words, loaded before its row pass and checked after it.
+constexpr int kGatherAhead = 2;
+
+__device__ __forceinline__ unsigned long long peek_word(const unsigned long long* p)
+{
+    return __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Byte offsets of the dynamic LDS regions of one sweep workgroup.
 struct SweepLds {
     size_t tu, tv, vs, xs, ps, gx, qred, red, total;
@@ -205,7 +214,7 @@ size_t sweep_lds_bytes_c(int R, int lpr, int W, int c)
 // Two waves per SIMD while the per-lane register state fits in 256 VGPRs;
 // larger ranks take one wave per SIMD and the full register file.
 template <typename T, int R>
-constexpr int sweep_waves_per_simd() { return (sizeof(T) * R <= 48) ? 2 : 1; }
+constexpr int sweep_waves_per_simd() { return (sizeof(T) * R <= 40) ? 2 : 1; }
 
 template <typename T, int R>
 __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_kernel(SweepArgs<T> a)
@@ -310,6 +319,21 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
     if (nbl > 0) issue_loads(0);
 
     for (int j = 0; j <= nbl; ++j) {
+        // exchange words of the previous band (c > 1): issued now, consumed
+        // after this band's row pass
+        const int nwords = c * R * WD;
+        const bool ahead = (c > 1) && (j >= 1) && (nwords <= 64 * kGatherAhead);
+        unsigned long long gw[kGatherAhead];
+        if (ahead) {
+            const int slot = (j - 1) & 3;
+            const unsigned long long* base = a.exch + (((size_t)cl * 4 + slot) * c) * H * R * WD;
+#pragma unroll
+            for (int g = 0; g < kGatherAhead; ++g) {
+                const int e = lane + 64 * g;      // word index over (member, k, half)
+                const int qq = e / (R * WD), rem = e % (R * WD);
+                gw[g] = (e < nwords) ? peek_word(base + ((size_t)qq * H + wave) * R * WD + rem) : 0ull;
+            }
+        }
         if (j < nbl) {
             // ---------------- phase 1: row pass over band b ----------------
             const int b = cl + j * ncl;
@@ -432,11 +456,30 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
                 const uint32_t tag = kiter * (uint32_t)a.nbl_max + (uint32_t)jb + 1u;
                 const int slot = jb & 3;
                 T* gx = Gx + (size_t)wave * c * R;
-                for (int e = lane; e < c * R; e += 64) {
-                    const int qq = e / R, k = e % R;
-                    const unsigned long long* src =
-                        a.exch + (((((size_t)cl * 4 + slot) * c + qq) * H + h) * R + k) * WD;
-                    gx[e] = fetch<T>(src, tag, tflag);
+                if (ahead) {
+                    // words read before the row pass; re-poll only those whose
+                    // tag has not arrived yet
+                    uint32_t* gxw = reinterpret_cast<uint32_t*>(gx);
+                    const unsigned long long* base = a.exch + (((size_t)cl * 4 + slot) * c) * H * R * WD;
+#pragma unroll
+                    for (int g = 0; g < kGatherAhead; ++g) {
+                        const int e = lane + 64 * g;
+                        if (e < nwords) {
+                            unsigned long long w = gw[g];
+                            if ((uint32_t)(w >> 32) != tag) {
+                                const int qq = e / (R * WD), rem = e % (R * WD);
+                                w = spin_word(base + ((size_t)qq * H + h) * R * WD + rem, tag, tflag);
+                            }
+                            gxw[e] = (uint32_t)(w & 0xffffffffull);
+                        }
+                    }
+                } else {
+                    for (int e = lane; e < c * R; e += 64) {
+                        const int qq = e / R, k = e % R;
+                        const unsigned long long* src =
+                            a.exch + (((((size_t)cl * 4 + slot) * c + qq) * H + h) * R + k) * WD;
+                        gx[e] = fetch<T>(src, tag, tflag);
+                    }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
