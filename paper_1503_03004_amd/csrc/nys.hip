@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(64) nys_combine_kernel(const T* UL, const doub
 {
     __shared__ double H1[R * LDP], H2[R * LDP], Bl[R * LDP], Bt[R * LDP];
     __shared__ double T1[R * LDP], T2[R * LDP], Ev[R * LDP], G[R * LDP];
-    __shared__ double cs[8 * 16];
+    __shared__ __align__(16) double cs[2 * 16];
     __shared__ double wbuf[kMaxR];
     const int lane = threadIdx.x & 63;
     // H1 = U_L[0:l]^T U_L[0:l], H2 = U_L[0:l]^T U_T

@@ -15,14 +15,22 @@
 
 namespace sfr {
 
+// Workgroup size of the step kernel: the partial sums are latency bound,
+// so as many threads as the r x r algebra's register use allows (the
+// algebra itself runs on wave 0 only; 1024 threads leave 128 registers a
+// lane, which buckets 5 and 12 and up exceed).
+template <int R>
+constexpr int step_tpb() { return (R <= 10 && R != 5) ? 1024 : (R <= 20 ? 512 : 256); }
+
 // Sum of `count` FP64 partial vectors of length E (part[b * E + e]) in a
 // fixed order, spread over the workgroup: adjacent threads read adjacent
 // entries of one partial; segment sums first, then the segments.
+template <int TPB>
 __device__ void sum_partials(double* out_lds, const double* part, int count, int E, double* seg)
 {
     const int tid = threadIdx.x;
-    const int nseg = max(1, kTPB / E);
-    for (int w = tid; w < E * nseg; w += kTPB) {
+    const int nseg = max(1, TPB / E);
+    for (int w = tid; w < E * nseg; w += TPB) {
         const int sg = w / E, e = w % E;
         double s = 0.0;
 #pragma unroll 16
@@ -30,7 +38,7 @@ __device__ void sum_partials(double* out_lds, const double* part, int count, int
         seg[w] = s;
     }
     __syncthreads();
-    for (int e = tid; e < E; e += kTPB) {
+    for (int e = tid; e < E; e += TPB) {
         double s = 0.0;
         for (int sg = 0; sg < nseg; ++sg) s += seg[sg * E + e];
         out_lds[e] = s;
@@ -44,29 +52,32 @@ __device__ void sum_partials(double* out_lds, const double* part, int count, int
 // leading r x r block, and the padded block is dropped when the transforms
 // are stored.
 template <int R>
-__global__ void __launch_bounds__(kTPB) step_kernel(StepArgs a)
+__global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
 {
     DevState* st = a.st;
     if (st->done) return;
+    constexpr int TPB = step_tpb<R>();
     constexpr int E = R * (R + 1) / 2;
     __shared__ double Gp[R * LDP], Gq[R * LDP], Bm[R * LDP], C1[R * LDP];
     __shared__ double C2[R * LDP], Km[R * LDP], T1[R * LDP], T2[R * LDP];
     __shared__ double Ev[R * LDP], Ev2[R * LDP];
-    __shared__ double seg[E > kTPB ? E : kTPB];
+    __shared__ double seg[E > TPB ? E : TPB];
     __shared__ double tri[2][E];
-    __shared__ double red[kTPB / 64];
-    __shared__ double cs[8 * 16];
+    __shared__ double red[TPB / 64];
+    __shared__ __align__(16) double cs[2 * 16];
     __shared__ double wbuf[kMaxR];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = st->r, k = st->k;
 
     // ---- convergence test of iteration k-1 (or ||M||_F on the first pass)
     double part = 0.0;
-    for (int e = tid; e < a.ndy; e += kTPB) part += a.dy2part[e];
+    for (int e = tid; e < a.ndy; e += TPB) part += a.dy2part[e];
     part = wave_sum(part);
     if (lane == 0) red[wave] = part;
     __syncthreads();
-    const double total = (red[0] + red[1]) + (red[2] + red[3]);
+    double total = 0.0;
+#pragma unroll
+    for (int w = 0; w < TPB / 64; ++w) total += red[w];
     if (k == 1) {
         const double nrm = sqrt(total);
         if (!(nrm > 0.0) || !isfinite(nrm)) {
@@ -94,8 +105,8 @@ __global__ void __launch_bounds__(kTPB) step_kernel(StepArgs a)
     }
 
     // ---- Grams (upper triangles, fixed summation order)
-    sum_partials(tri[0], a.GPpart, a.npb, E, seg);
-    sum_partials(tri[1], a.GQpart, a.nqb, E, seg);
+    sum_partials<TPB>(tri[0], a.GPpart, a.npb, E, seg);
+    sum_partials<TPB>(tri[1], a.GQpart, a.nqb, E, seg);
     if (wave != 0) return;
 
     // ---- the r x r algebra: one wavefront from here on
@@ -168,7 +179,7 @@ template <int R>
 __global__ void __launch_bounds__(64) final_small_kernel(DevState* st)
 {
     __shared__ double A[R * LDP], Ev[R * LDP];
-    __shared__ double cs[8 * 16];
+    __shared__ __align__(16) double cs[2 * 16];
     const int r = st->r;
     const int lane = threadIdx.x & 63;
     for (int e = lane; e < R * R; e += 64) {
@@ -190,7 +201,7 @@ __global__ void __launch_bounds__(64) final_small_kernel(DevState* st)
 hipError_t launch_step(const StepArgs& a, int R, hipStream_t s)
 {
     switch (R) {
-#define CASE(rr) case rr: hipLaunchKernelGGL(step_kernel<rr>, dim3(1), dim3(kTPB), 0, s, a); break;
+#define CASE(rr) case rr: hipLaunchKernelGGL(step_kernel<rr>, dim3(1), dim3(step_tpb<rr>()), 0, s, a); break;
         SFR_R_LIST(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

@@ -107,86 +107,111 @@ __device__ inline int rr_player(int pos, int round, int N)
 // One wavefront.  A (r x r symmetric, LDS) -> diag(eigenvalues) in place;
 // E holds on entry an orthogonal starting basis E0 and on exit the
 // eigenvectors, with A_in = E diag E^T.  On entry A must already be
-// expressed in the basis E0 (A = E0^T A_in E0).  cs: LDS scratch 8 * 16.
+// expressed in the basis E0 (A = E0^T A_in E0).  cs: LDS scratch of 2 * 16
+// doubles, 16-byte aligned.
 //
-// Each rotation sets its pair exactly (a_pq = 0, a_pp -= t a_pq,
-// a_qq += t a_pq), so off-diagonal entries shrink without a rounding floor
-// and the relative test |a_pq| <= eps sqrt(|a_pp a_qq|) is reached also for
-// graded matrices; the test is made for all pairs before each sweep.
+// Cyclic Jacobi in the round-robin parallel order: each round rotates
+// N / 2 disjoint pairs at once.  Each rotation sets its pair exactly
+// (a_pq = 0, a_pp -= t a_pq, a_qq += t a_pq), so off-diagonal entries shrink
+// without a rounding floor and the relative test
+// |a_pq| <= eps sqrt(|a_pp a_qq|) is reached also for graded matrices; the
+// test is made for all pairs before each sweep.
+//
+// A round is two phases.  Pair phase: lane b < N / 2 computes the rotation
+// of pair b, t = sign(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)) with
+// d = a_qq - a_pp (the smaller root of t^2 + 2 tau t - 1 = 0, tau = d / 2a_pq),
+// c = 1 / sqrt(1 + t^2), s = t c, and writes the pair's own 2 x 2 block.
+// Update phase: one lane per 2 x 2 block (rows of pair i, columns of pair
+// j, i != j) applies J_i^T . J_j, and one lane per 2 x 2 block of E (two
+// rows, the columns of one pair) applies . J.  Pair indices are recomputed
+// from the round number, so the only data passed between the phases is
+// (c, s).  Squares of entries above ~1e150 would overflow d^2 + 4 a_pq^2.
 template <int r>
-__device__ inline void wjacobi(double* A, double* E, double* cs)
+__device__ inline void wjacobi(double* A, double* E, double* cs, double tau = 0.0)
 {
     const int lane = threadIdx.x & 63;
     if (r == 1) return;
     constexpr int N = r + (r & 1);
     constexpr int npair = N / 2;
+    constexpr int nrp = (r + 1) / 2;              // row pairs of E
+    constexpr int nblk = npair * npair;           // 2 x 2 blocks of A
+    constexpr int nitem = nblk + nrp * npair;     // + 2 x 2 blocks of E
     for (int sweep = 0; sweep < 16; ++sweep) {
-        int big = 0;
+        int big = 0, far = 0;
         for (int e = lane; e < r * r; e += 64) {
             const int i = e / r, j = e % r;
             if (i < j) {
                 const double apq = A[i * LDP + j];
-                if (fabs(apq) > DBL_EPSILON * sqrt(fabs(A[i * LDP + i] * A[j * LDP + j])) && apq != 0.0) big = 1;
+                const double app = A[i * LDP + i], aqq = A[j * LDP + j];
+                if (apq != 0.0 && apq * apq > DBL_EPSILON * DBL_EPSILON * fabs(app * aqq)) big = 1;
+                if (!(fabs(apq) <= tau * fmin(fabs(app), fabs(aqq)))) far = 1;
             }
         }
-        if (!__any(big)) break;
+        if (!__any(big) || !__any(far)) break;
         for (int round = 0; round < N - 1; ++round) {
             if (lane < npair) {
                 int p = rr_player(lane, round, N);
                 int q = rr_player(N - 1 - lane, round, N);
                 if (p > q) { int t = p; p = q; q = t; }
-                double c = 1.0, s = 0.0, t = 0.0, app = 0.0, aqq = 0.0, apq = 0.0;
+                double c = 1.0, s = 0.0;
                 if (q < r) {
-                    apq = A[p * LDP + q];
-                    app = A[p * LDP + p];
-                    aqq = A[q * LDP + q];
-                    if (fabs(apq) > DBL_EPSILON * sqrt(fabs(app * aqq)) && apq != 0.0) {
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
+                    const double apq = A[p * LDP + q];
+                    const double app = A[p * LDP + p];
+                    const double aqq = A[q * LDP + q];
+                    if (apq != 0.0 && apq * apq > DBL_EPSILON * DBL_EPSILON * fabs(app * aqq)) {
+                        const double d = aqq - app;
+                        const double h = sqrt(fma(d, d, 4.0 * apq * apq));
+                        const double t = (d >= 0.0 ? 2.0 * apq : -2.0 * apq) / (fabs(d) + h);
+                        c = rsqrt(fma(t, t, 1.0));
                         s = t * c;
+                        A[p * LDP + p] = fma(-t, apq, app);
+                        A[q * LDP + q] = fma(t, apq, aqq);
+                        A[p * LDP + q] = 0.0;
+                        A[q * LDP + p] = 0.0;
                     }
                 }
-                double* w = cs + 8 * lane;
-                w[0] = c; w[1] = s; w[2] = (double)p; w[3] = (double)q;
-                w[4] = app - t * apq;   // new a_pp
-                w[5] = aqq + t * apq;   // new a_qq
-                w[6] = (s != 0.0) ? 1.0 : 0.0;
+                cs[2 * lane] = c;
+                cs[2 * lane + 1] = s;
             }
             wsync();
-            // A <- A J and E <- E J  (columns p, q of every row)
-            for (int it = lane; it < npair * r; it += 64) {
-                const int pi = it / r, x = it % r;
-                const double* w = cs + 8 * pi;
-                if (w[6] == 0.0) continue;
-                const int p = (int)w[2], q = (int)w[3];
-                const double c = w[0], s = w[1];
-                const double ap = A[x * LDP + p], aq = A[x * LDP + q];
-                A[x * LDP + p] = c * ap - s * aq;
-                A[x * LDP + q] = s * ap + c * aq;
-                const double ep = E[x * LDP + p], eq = E[x * LDP + q];
-                E[x * LDP + p] = c * ep - s * eq;
-                E[x * LDP + q] = s * ep + c * eq;
-            }
-            wsync();
-            // A <- J^T A  (rows p, q of every column); the 2 x 2 block of
-            // the pair takes its exact rotated values
-            for (int it = lane; it < npair * r; it += 64) {
-                const int pi = it / r, x = it % r;
-                const double* w = cs + 8 * pi;
-                if (w[6] == 0.0) continue;
-                const int p = (int)w[2], q = (int)w[3];
-                const double c = w[0], s = w[1];
-                if (x == p) {
-                    A[p * LDP + p] = w[4];
-                    A[q * LDP + p] = 0.0;
-                } else if (x == q) {
-                    A[q * LDP + q] = w[5];
-                    A[p * LDP + q] = 0.0;
+            for (int it = lane; it < nitem; it += 64) {
+                if (it < nblk) {
+                    const int bi = it / npair, bj = it % npair;
+                    if (bi == bj) continue;
+                    int pi = rr_player(bi, round, N), qi = rr_player(N - 1 - bi, round, N);
+                    int pj = rr_player(bj, round, N), qj = rr_player(N - 1 - bj, round, N);
+                    if (pi > qi) { int t = pi; pi = qi; qi = t; }
+                    if (pj > qj) { int t = pj; pj = qj; qj = t; }
+                    const bool hq_i = qi < r, hq_j = qj < r;
+                    const double a00 = A[pi * LDP + pj];
+                    const double a01 = hq_j ? A[pi * LDP + qj] : 0.0;
+                    const double a10 = hq_i ? A[qi * LDP + pj] : 0.0;
+                    const double a11 = (hq_i && hq_j) ? A[qi * LDP + qj] : 0.0;
+                    const double ci = cs[2 * bi], si = cs[2 * bi + 1];
+                    const double cj = cs[2 * bj], sj = cs[2 * bj + 1];
+                    const double b00 = cj * a00 - sj * a01, b01 = sj * a00 + cj * a01;
+                    const double b10 = cj * a10 - sj * a11, b11 = sj * a10 + cj * a11;
+                    A[pi * LDP + pj] = ci * b00 - si * b10;
+                    if (hq_j) A[pi * LDP + qj] = ci * b01 - si * b11;
+                    if (hq_i) A[qi * LDP + pj] = si * b00 + ci * b10;
+                    if (hq_i && hq_j) A[qi * LDP + qj] = si * b01 + ci * b11;
                 } else {
-                    const double ap = A[p * LDP + x], aq = A[q * LDP + x];
-                    A[p * LDP + x] = c * ap - s * aq;
-                    A[q * LDP + x] = s * ap + c * aq;
+                    const int e2 = it - nblk;
+                    const int x = e2 / npair, bi = e2 % npair;
+                    int p = rr_player(bi, round, N), q = rr_player(N - 1 - bi, round, N);
+                    if (p > q) { int t = p; p = q; q = t; }
+                    if (q >= r) continue;                 // the idle pair of odd r
+                    const int x0 = 2 * x, x1 = 2 * x + 1;
+                    const bool h1 = x1 < r;
+                    const double e0p = E[x0 * LDP + p], e0q = E[x0 * LDP + q];
+                    const double e1p = h1 ? E[x1 * LDP + p] : 0.0, e1q = h1 ? E[x1 * LDP + q] : 0.0;
+                    const double c = cs[2 * bi], s = cs[2 * bi + 1];
+                    E[x0 * LDP + p] = c * e0p - s * e0q;
+                    E[x0 * LDP + q] = s * e0p + c * e0q;
+                    if (h1) {
+                        E[x1 * LDP + p] = c * e1p - s * e1q;
+                        E[x1 * LDP + q] = s * e1p + c * e1q;
+                    }
                 }
             }
             wsync();
@@ -194,11 +219,21 @@ __device__ inline void wjacobi(double* A, double* E, double* cs)
     }
 }
 
+// Relative off-diagonal size at which the Jacobi sweeps of winv_sqrt stop:
+// |a_ij| <= kDkTau min(a_ii, a_jj) in the current basis.  The rest of the
+// way is the second-order expansion of t^{-1/2} about the diagonal, whose
+// error is O(kDkTau^3) relative (about 1e-16 here).  Across FR-ADM
+// iterations the Grams move less and less, so the previous iteration's
+// basis soon meets this bound with no sweep at all.
+constexpr double kDkTau = 4e-6;
+
 // Out = A^{-1/2} for symmetric A (destroyed), one wavefront.  E: on entry
-// the warm-start basis, on exit the eigenvectors of A.  T: scratch.  Only
-// the leading `nreal` eigenvalues are tested (the rest belong to an
-// identity padding block).  Returns false if A is not positive definite to
-// working precision (the Stiefel projector of eq. (7) needs rank r).
+// the warm-start basis, on exit a basis in which A is diagonal to within
+// kDkTau (updated only by the sweeps that were needed).  T, cs, wbuf:
+// scratch.  Only the leading `nreal` eigenvalues are tested (the rest belong
+// to an identity padding block).  Returns false if A is not positive
+// definite to working precision (the Stiefel projector of eq. (7) needs
+// rank r).
 template <int N>
 __device__ inline bool winv_sqrt(double* Out, double* A, double* E, double* T, int nreal, double* cs, double* wbuf)
 {
@@ -207,19 +242,60 @@ __device__ inline bool winv_sqrt(double* Out, double* A, double* E, double* T, i
     wmm<N>(T, A, E);
     wmtm<N>(A, E, T);
     wsym<N>(A);
-    wjacobi<N>(A, E, cs);
+    wjacobi<N>(A, E, cs, kDkTau);
+    // A = D + F, D = diag(d), F off-diagonal with |F_ij| <= kDkTau min(d_i, d_j)
+    // (or at the strict Jacobi test).  x = sqrt(d) -> wbuf, y = 1 / x -> cs.
     double wmax = -INFINITY, wmin = INFINITY;
     for (int i = lane; i < N; i += 64) {
-        wbuf[i] = A[i * LDP + i];
+        const double d = A[i * LDP + i];
         if (i < nreal) {
-            wmax = fmax(wmax, wbuf[i]);
-            wmin = fmin(wmin, wbuf[i]);
+            wmax = fmax(wmax, d);
+            wmin = fmin(wmin, d);
         }
+        const double x = d > 0.0 ? sqrt(d) : 0.0;
+        wbuf[i] = x;
+        cs[i] = d > 0.0 ? 1.0 / x : 0.0;
     }
     wmax = wave_max(wmax);
     wmin = wave_min(wmin);
     wsync();
     const bool ok = (wmax > 0.0) && (wmin > (double)nreal * DBL_EPSILON * wmax) && isfinite(wmax);
+    // W_ij = 1 / (x_i + x_j) -> Out, Phi = F o W -> T
+    for (int e = lane; e < N * N; e += 64) {
+        const int i = e / N, j = e % N;
+        const double den = wbuf[i] + wbuf[j];
+        const double w = den > 0.0 ? 1.0 / den : 0.0;
+        Out[i * LDP + j] = w;
+        T[i * LDP + j] = (i == j) ? 0.0 : A[i * LDP + j] * w;
+    }
+    wsync();
+    // Z = f(D + F) to second order, f(t) = t^{-1/2}:
+    //   Z_ij = delta_ij y_i + F_ij f[d_i, d_j] + sum_k F_ik F_kj f[d_i, d_k, d_j],
+    //   f[d_i, d_j] = -W_ij y_i y_j,
+    //   f[d_i, d_k, d_j] = (x_i + x_k + x_j) y_i y_k y_j W_ik W_kj W_ij,
+    // so the sum is W_ij y_i y_j ((x_i + x_j) (Phi Y Phi)_ij + (Phi Phi)_ij).
+    // The dropped terms are O(|F|^3) relative.  Z -> A.
+#pragma unroll
+    for (int e0 = 0; e0 < N * N; e0 += 64) {
+        const int e = e0 + lane;
+        if (e >= N * N) break;
+        const int i = e / N, j = e % N;
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double pp = T[i * LDP + k] * T[k * LDP + j];
+            s1 = fma(pp, cs[k], s1);
+            s2 += pp;
+        }
+        const double yy = cs[i] * cs[j];
+        const double w = Out[i * LDP + j];
+        double z = yy * (w * fma(wbuf[i] + wbuf[j], s1, s2) - T[i * LDP + j]);
+        if (i == j) z += cs[i];
+        A[i * LDP + j] = z;
+    }
+    wsync();
+    // Out = E Z E^T
+    wmm<N>(T, E, A);
 #pragma unroll
     for (int e0 = 0; e0 < N * N; e0 += 64) {
         const int e = e0 + lane;
@@ -227,10 +303,7 @@ __device__ inline bool winv_sqrt(double* Out, double* A, double* E, double* T, i
         const int i = e / N, j = e % N;
         double s = 0.0;
 #pragma unroll
-        for (int t = 0; t < N; ++t) {
-            const double wt = wbuf[t] > 0.0 ? 1.0 / sqrt(wbuf[t]) : 0.0;
-            s = fma(E[i * LDP + t] * wt, E[j * LDP + t], s);
-        }
+        for (int k = 0; k < N; ++k) s = fma(T[i * LDP + k], E[j * LDP + k], s);
         Out[i * LDP + j] = s;
     }
     wsync();
