@@ -117,9 +117,9 @@ static sfr_status configure(Engine& e)
     e.nbl_max = (e.nbands + e.ncl - 1) / e.ncl;
     // Gram launch shape
     const int rows = kTPB / e.R;
-    e.nqb = std::max(1, std::min((e.ne + rows - 1) / rows, 256));
+    e.nqb = std::max(1, std::min((e.ne + rows - 1) / rows, kMaxGramPartials));
     e.rows_q = (e.ne + e.nqb - 1) / e.nqb;
-    e.npb = std::max(1, std::min((e.m + rows - 1) / rows, 256));
+    e.npb = std::max(1, std::min((e.m + rows - 1) / rows, kMaxGramPartials));
     e.rows_p = (e.m + e.npb - 1) / e.npb;
     e.E = e.R * (e.R + 1) / 2;
     return SFR_OK;

@@ -34,6 +34,11 @@ constexpr int kMaxR = 32;
 constexpr int kTPB = 256;            // threads per workgroup of the streaming kernels
 constexpr int kXCD = 8;              // accelerator complex dies on MI355X
 constexpr uint32_t kSpinLimit = 1u << 24;
+// Residual partials the step kernel loads in its first round (one per
+// sweep workgroup; more are summed by a tail loop).
+constexpr int kMaxDyPartials = 2048;
+// Upper bound on the Gram partials of one pass (one per Gram workgroup).
+constexpr int kMaxGramPartials = 256;
 
 // Status codes mirrored from the public header (kept numerically equal).
 enum : int32_t {

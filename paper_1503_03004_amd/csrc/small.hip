@@ -22,30 +22,6 @@ namespace sfr {
 template <int R>
 constexpr int step_tpb() { return (R <= 10 && R != 5) ? 1024 : (R <= 20 ? 512 : 256); }
 
-// Sum of `count` FP64 partial vectors of length E (part[b * E + e]) in a
-// fixed order, spread over the workgroup: adjacent threads read adjacent
-// entries of one partial; segment sums first, then the segments.
-template <int TPB>
-__device__ void sum_partials(double* out_lds, const double* part, int count, int E, double* seg)
-{
-    const int tid = threadIdx.x;
-    const int nseg = max(1, TPB / E);
-    for (int w = tid; w < E * nseg; w += TPB) {
-        const int sg = w / E, e = w % E;
-        double s = 0.0;
-#pragma unroll 16
-        for (int b = sg; b < count; b += nseg) s += part[(size_t)b * E + e];
-        seg[w] = s;
-    }
-    __syncthreads();
-    for (int e = tid; e < E; e += TPB) {
-        double s = 0.0;
-        for (int sg = 0; sg < nseg; ++sg) s += seg[sg * E + e];
-        out_lds[e] = s;
-    }
-    __syncthreads();
-}
-
 // The r x r matrices are held R x R (R the rank bucket, a compile-time
 // size) with an identity block on the padded indices: every product and
 // inverse square root below is then block diagonal and exact on the
@@ -61,7 +37,7 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
     __shared__ double Gp[R * LDP], Gq[R * LDP], Bm[R * LDP], C1[R * LDP];
     __shared__ double C2[R * LDP], Km[R * LDP], T1[R * LDP], T2[R * LDP];
     __shared__ double Ev[R * LDP], Ev2[R * LDP];
-    __shared__ double seg[E > TPB ? E : TPB];
+    __shared__ double seg[2 * E > TPB ? 2 * E : TPB];
     __shared__ double tri[2][E];
     __shared__ double red[TPB / 64];
     __shared__ __align__(16) double cs[2 * 16];
@@ -69,9 +45,54 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = st->r, k = st->k;
 
+    // ---- one round of loads: B0 and the two warm-start bases (wave 0, into
+    // registers), the residual partials and the Gram partials.  The Gram
+    // partials (upper triangles) are summed in a fixed order: thread w owns
+    // entry e of Gram g over the partials b = s, s + nseg, ... (segment s),
+    // then the nseg segment sums are added in order.
+    // Every load below is unconditional (indices are clamped into range and
+    // the surplus masked afterwards), so each thread has all of its loads in
+    // flight at once: one memory round trip for the lot.
+    constexpr int NPL = (R * R + 63) / 64;
+    double rb[NPL], re1[NPL], re2[NPL];
+    if (wave == 0) {
+#pragma unroll
+        for (int u = 0; u < NPL; ++u) {
+            const int e = min(lane + 64 * u, R * R - 1);
+            const int i = e / R, j = e % R;
+            rb[u] = st->B[i * kMaxR + j];
+            re1[u] = st->E1[i * kMaxR + j];
+            re2[u] = st->E2[i * kMaxR + j];
+        }
+    }
+    constexpr int DYU = (kMaxDyPartials + TPB - 1) / TPB;
+    double dyv[DYU];
+#pragma unroll
+    for (int u = 0; u < DYU; ++u) dyv[u] = a.dy2part[min(tid + u * TPB, a.ndy - 1)];
+    constexpr int nseg = (2 * E >= TPB) ? 1 : TPB / (2 * E);
+    constexpr int PER = (kMaxGramPartials + nseg - 1) / nseg;   // partials per segment
+    constexpr int CH = PER < 32 ? PER : 32;                      // loads in flight
+    for (int w = tid; w < 2 * E * nseg; w += TPB) {
+        const int g = w / (E * nseg), rem = w % (E * nseg);
+        const int sg = rem / E, e = rem % E;
+        const double* part = g ? a.GQpart : a.GPpart;
+        const int count = g ? a.nqb : a.npb;
+        double s = 0.0;
+        for (int u0 = 0; u0 < PER; u0 += CH) {
+            double v[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) v[u] = part[(size_t)min(sg + (u0 + u) * nseg, count - 1) * E + e];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) s += (sg + (u0 + u) * nseg < count) ? v[u] : 0.0;
+        }
+        seg[w] = s;
+    }
+
     // ---- convergence test of iteration k-1 (or ||M||_F on the first pass)
     double part = 0.0;
-    for (int e = tid; e < a.ndy; e += TPB) part += a.dy2part[e];
+#pragma unroll
+    for (int u = 0; u < DYU; ++u) part += (tid + u * TPB < a.ndy) ? dyv[u] : 0.0;
+    for (int e = tid + DYU * TPB; e < a.ndy; e += TPB) part += a.dy2part[e];
     part = wave_sum(part);
     if (lane == 0) red[wave] = part;
     __syncthreads();
@@ -104,22 +125,31 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
         }
     }
 
-    // ---- Grams (upper triangles, fixed summation order)
-    sum_partials<TPB>(tri[0], a.GPpart, a.npb, E, seg);
-    sum_partials<TPB>(tri[1], a.GQpart, a.nqb, E, seg);
+    // ---- Grams: add the segment sums
+    for (int w = tid; w < 2 * E; w += TPB) {
+        const int g = w / E, e = w % E;
+        double s = 0.0;
+#pragma unroll
+        for (int sg = 0; sg < nseg; ++sg) s += seg[(g * nseg + sg) * E + e];
+        tri[g][e] = s;
+    }
+    __syncthreads();
     if (wave != 0) return;
 
     // ---- the r x r algebra: one wavefront from here on
-    for (int e = lane; e < R * R; e += 64) {
+#pragma unroll
+    for (int u = 0; u < NPL; ++u) {
+        const int e = lane + 64 * u;
+        if (e >= R * R) break;
         const int i = e / R, j = e % R;
         const int x = i < j ? i : j, y = i < j ? j : i;
         const int t = x * R - x * (x - 1) / 2 + (y - x);   // upper-triangle index of (x, y)
         const bool pad = (i >= r) || (j >= r);
         Gp[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : tri[0][t];
         Gq[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : tri[1][t];
-        Bm[i * LDP + j] = st->B[i * kMaxR + j];
-        Ev[i * LDP + j] = st->E1[i * kMaxR + j];
-        Ev2[i * LDP + j] = st->E2[i * kMaxR + j];
+        Bm[i * LDP + j] = rb[u];
+        Ev[i * LDP + j] = re1[u];
+        Ev2[i * LDP + j] = re2[u];
     }
     wsync();
 
@@ -148,22 +178,25 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
     wmm<R>(T2, C2, Gp);               // C1 B0 G_Q K C2
     wsym<R>(T2);                      // new B
     wmm<R>(Km, T1, T2);               // TU
-    for (int e = lane; e < kMaxR * kMaxR; e += 64) {
-        const int i = e / kMaxR, j = e % kMaxR;
+    // only the R x R block changes; the rest keeps the values set at the
+    // start of the solve (zero, identity on the diagonal of B)
+#pragma unroll
+    for (int u = 0; u < NPL; ++u) {
+        const int e = lane + 64 * u;
+        if (e >= R * R) break;
+        const int i = e / R, j = e % R;
+        const int g = i * kMaxR + j;
         const bool in = (i < r) && (j < r);
-        const bool blk = (i < R) && (j < R);
         const double tu = in ? Km[i * LDP + j] : 0.0;
         const double tv = in ? Gp[i * LDP + j] : 0.0;
-        st->B[e] = in ? T2[i * LDP + j] : (i == j ? 1.0 : 0.0);
-        st->TU[e] = tu;
-        st->TUbar[e] = in ? T1[i * LDP + j] : 0.0;
-        st->TV[e] = tv;
-        st->TUf[e] = (float)tu;
-        st->TVf[e] = (float)tv;
-        if (blk) {
-            st->E1[e] = Ev[i * LDP + j];
-            st->E2[e] = Ev2[i * LDP + j];
-        }
+        st->B[g] = in ? T2[i * LDP + j] : (i == j ? 1.0 : 0.0);
+        st->TU[g] = tu;
+        st->TUbar[g] = in ? T1[i * LDP + j] : 0.0;
+        st->TV[g] = tv;
+        st->TUf[g] = (float)tu;
+        st->TVf[g] = (float)tv;
+        st->E1[g] = Ev[i * LDP + j];
+        st->E2[g] = Ev2[i * LDP + j];
     }
     if (lane == 0) {
         const double mu = st->mu;
