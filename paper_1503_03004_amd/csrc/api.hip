@@ -194,10 +194,15 @@ void engine_destroy(Engine& e)
         }                                          \
     } while (0)
 
-// Iterate Alg. 1 on the engine's shape.  M: device, row-major, ldm.  On
-// success the engine's state holds the factors of the returned iterate.
+// Iterate Alg. 1 on the engine's shape and write the outputs of the
+// returned iterate.  M: device, row-major, ldm.  A fixed iteration count is
+// queued in one go; a tolerance-driven solve is queued in batches of 8 with
+// one batch running ahead of the host's check of the previous one (kernels
+// of a finished solve return at once).  The output kernels follow the last
+// batch on the stream; the host waits once, at the end.
 template <typename T>
-sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, int64_t ldm, hipStream_t s)
+sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, int64_t ldm,
+                          const OutputSpec<T>& out, hipStream_t s)
 {
     const bool aligned = ((uintptr_t)M % 16 == 0) && (ldm % e.vec == 0) && (e.ne == e.n);
     const T* Mk = M;
@@ -237,8 +242,9 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
     if (e.exch_words) HIPCHK(launch_fill_u64(e.exch, e.exch_words, s));
 
     const int limit = (p.fixed_iters > 0 ? p.fixed_iters : p.max_iter) + 1;
+    const bool fixed = p.fixed_iters > 0;
     const int batch = 8;
-    // Profiling: a start/stop event pair around every general sweep (k >= 3).
+    // Profiling: start/stop events bound to every general sweep (k >= 3).
     if (p.profile) {
         const size_t need = 2 * (size_t)std::max(0, limit - 2);
         while (e.prof_ev.size() < need) {
@@ -249,7 +255,6 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
     }
     int k = 1;
     int launched_batches = 0, checked_batches = 0;
-    bool done = false;
     auto enqueue_batch = [&](void) -> sfr_status {
         for (int b = 0; b < batch && k <= limit; ++b, ++k) {
             SweepArgs<T> a;
@@ -268,9 +273,8 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
             a.lpr = e.lpr; a.nv = e.nv; a.W = e.W; a.c = e.c; a.cpx = e.cpx; a.xcd_local = e.xcd_local; a.ncl = e.ncl;
             a.nbands = e.nbands; a.nbl_max = e.nbl_max;
             const bool timed = p.profile && k >= 3;
-            if (timed) HIPCHK(hipEventRecord(e.prof_ev[2 * (k - 3)], s));
-            HIPCHK(launch_sweep<T>(a, e.R, e.grid, e.lds, s));
-            if (timed) HIPCHK(hipEventRecord(e.prof_ev[2 * (k - 3) + 1], s));
+            HIPCHK(launch_sweep<T>(a, e.R, e.grid, e.lds, s, timed ? e.prof_ev[2 * (k - 3)] : nullptr,
+                                   timed ? e.prof_ev[2 * (k - 3) + 1] : nullptr));
             GramArgs<T> g;
             g.st = e.st;
             g.Qpart = static_cast<const T*>(e.Qpart);
@@ -288,33 +292,65 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
             sa.res_hist = e.res_hist;
             HIPCHK(launch_step(sa, e.R, s));
         }
-        const int slot = launched_batches & 1;
-        HIPCHK(hipMemcpyAsync(&e.host_poll[slot], e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipEventRecord(e.poll_ev[slot], s));
+        if (!fixed) {
+            const int slot = launched_batches & 1;
+            HIPCHK(hipMemcpyAsync(&e.host_poll[slot], e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(e.poll_ev[slot], s));
+        }
         ++launched_batches;
         return SFR_OK;
     };
-    // Keep one batch queued behind the one being checked: kernels of a
-    // finished solve return at once, so running ahead costs only launches.
-    sfr_status es = enqueue_batch();
-    if (es != SFR_OK) return es;
-    while (!done) {
-        if (k <= limit) {
+    sfr_status es;
+    if (fixed) {
+        while (k <= limit) {
             es = enqueue_batch();
             if (es != SFR_OK) return es;
         }
-        const int slot = checked_batches & 1;
-        HIPCHK(hipEventSynchronize(e.poll_ev[slot]));
-        const DevState& ph = e.host_poll[slot];
-        ++checked_batches;
-        if (ph.done || ph.exch_timeout) done = true;
-        else if (checked_batches == launched_batches && k > limit) {
-            HIPCHK(hipStreamSynchronize(s));
-            return SFR_ERR_DEVICE;  // the step kernel always stops by `limit`
+    } else {
+        es = enqueue_batch();
+        if (es != SFR_OK) return es;
+        bool done = false;
+        while (!done) {
+            if (k <= limit) {
+                es = enqueue_batch();
+                if (es != SFR_OK) return es;
+            }
+            const int slot = checked_batches & 1;
+            HIPCHK(hipEventSynchronize(e.poll_ev[slot]));
+            const DevState& ph = e.host_poll[slot];
+            ++checked_batches;
+            if (ph.done || ph.exch_timeout) done = true;
+            else if (checked_batches == launched_batches && k > limit) break;  // reported below
         }
     }
+    // ---- outputs of the returned iterate, then one wait
+    PingPong<T> pp;
+    for (int b = 0; b < 2; ++b) {
+        pp.P[b] = static_cast<T*>(e.P[b]);
+        pp.Q[b] = static_cast<T*>(e.Q[b]);
+        pp.Y[b] = static_cast<const T*>(e.Y[b]);
+    }
+    HIPCHK(launch_factors<T>(e.st, pp, e.m, e.n, e.r, e.R, out.U, out.V, out.B, s));
+    if (out.S) {
+        LowrankArgs<T> la;
+        memset(&la, 0, sizeof(la));
+        la.st = e.st;
+        la.pp = pp;
+        la.M = out.M;
+        la.ldm = out.ldm;
+        la.ldy = e.ldy;
+        la.S = out.S;
+        la.lds = out.lds;
+        la.m = e.m;
+        la.n = e.n;
+        la.mode = 0;
+        la.lam = p.lambda;
+        la.mu = 1.0;
+        HIPCHK(launch_lowrank_pass<T>(la, e.R, s));
+    }
+    if (out.min_eig) HIPCHK(launch_final_small(e.st, e.R, s));
+    HIPCHK(hipMemcpyAsync(e.host_state, e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipMemcpy(&h, e.st, offsetof(DevState, B), hipMemcpyDeviceToHost));
     e.sweep_ms = 0.0;
     e.sweeps_timed = 0;
     if (p.profile && h.done) {
@@ -328,34 +364,15 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         if (e.sweeps_timed) e.sweep_ms /= e.sweeps_timed;
     }
     if (h.exch_timeout) return SFR_ERR_DEVICE;
+    if (!h.done) return SFR_ERR_DEVICE;  // the step kernel always stops by `limit`
     if (h.status < 0) return (sfr_status)h.status;
     return SFR_OK;
 }
 
-// Write U, B, V (and S) of the returned iterate; A/Vt scratch reuse the
-// spare ping-pong buffers of P and Q.
-template <typename T>
-static sfr_status engine_outputs(Engine& e, const Params& p, const T* M, int64_t ldm, T* U, double* B, T* V,
-                                 T* S, int64_t lds, hipStream_t s)
-{
-    const DevState& h = *e.host_state;
-    const int K = h.iters;
-    T* A = static_cast<T*>(e.P[(K + 1) & 1]);
-    T* Vt = static_cast<T*>(e.Q[(K + 1) & 1]);
-    HIPCHK(launch_factors<T>(e.st, static_cast<const T*>(e.P[K & 1]), static_cast<const T*>(e.Q[K & 1]), e.m, e.n,
-                             e.r, e.R, U, V, B, A, Vt, s));
-    if (S) {
-        const T* Yk = (K >= 2) ? static_cast<const T*>(e.Y[K & 1]) : nullptr;
-        HIPCHK(launch_lowrank_pass<T>(M, ldm, Yk, e.ldy, A, Vt, e.m, e.n, e.R, S, lds, 0, p.lambda, h.mu_prev, s));
-    }
-    HIPCHK(launch_final_small(e.st, e.R, s));
-    HIPCHK(hipMemcpyAsync(e.host_state, e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return SFR_OK;
-}
-
-template sfr_status engine_iterate<float>(Engine&, const Params&, double, const float*, int64_t, hipStream_t);
-template sfr_status engine_iterate<double>(Engine&, const Params&, double, const double*, int64_t, hipStream_t);
+template sfr_status engine_iterate<float>(Engine&, const Params&, double, const float*, int64_t,
+                                          const OutputSpec<float>&, hipStream_t);
+template sfr_status engine_iterate<double>(Engine&, const Params&, double, const double*, int64_t,
+                                           const OutputSpec<double>&, hipStream_t);
 
 }  // namespace sfr
 
@@ -490,15 +507,17 @@ sfr_status sfr_solve(sfr_handle h, const void* M, int64_t ldm, void* U, double* 
     Engine& e = h->main;
     sfr_status st;
     if (h->f64) {
-        st = engine_iterate<double>(e, h->prm, h->prm.mu0, static_cast<const double*>(M), ldm, s);
-        if (st == SFR_OK)
-            st = engine_outputs<double>(e, h->prm, static_cast<const double*>(M), ldm, static_cast<double*>(U), B,
-                                        static_cast<double*>(V), static_cast<double*>(S), lds, s);
+        OutputSpec<double> o;
+        o.U = static_cast<double*>(U); o.B = B; o.V = static_cast<double*>(V);
+        o.M = static_cast<const double*>(M); o.ldm = ldm; o.S = static_cast<double*>(S); o.lds = lds;
+        o.min_eig = true;
+        st = engine_iterate<double>(e, h->prm, h->prm.mu0, static_cast<const double*>(M), ldm, o, s);
     } else {
-        st = engine_iterate<float>(e, h->prm, h->prm.mu0, static_cast<const float*>(M), ldm, s);
-        if (st == SFR_OK)
-            st = engine_outputs<float>(e, h->prm, static_cast<const float*>(M), ldm, static_cast<float*>(U), B,
-                                       static_cast<float*>(V), static_cast<float*>(S), lds, s);
+        OutputSpec<float> o;
+        o.U = static_cast<float*>(U); o.B = B; o.V = static_cast<float*>(V);
+        o.M = static_cast<const float*>(M); o.ldm = ldm; o.S = static_cast<float*>(S); o.lds = lds;
+        o.min_eig = true;
+        st = engine_iterate<float>(e, h->prm, h->prm.mu0, static_cast<const float*>(M), ldm, o, s);
     }
     if (st < 0) {
         if (info) memset(info, 0, sizeof(*info));

@@ -57,10 +57,19 @@ hipError_t launch_copy_pad(const T* src, int64_t lds, T* dst, int64_t ldd, int m
 
 // Returned factors: U = P TUbar (m x r), V = Q TV (n x r), B; and the row
 // factors A = P TU, Vt = Q TV (R wide, zero padded) used by the S pass.
+// P and Q are the ping-pong buffers of the iteration: the returned iterate
+// K = st->iters reads P[K & 1], Q[K & 1] and writes A, Vt into the other
+// pair.  Nothing is written unless the solve finished without error.
 template <typename T>
-__global__ void factors_kernel(const DevState* st, const T* P, const T* Q, int m, int n, int r, int R,
-                               T* U, T* V, double* B, T* A, T* Vt)
+__global__ void factors_kernel(const DevState* st, PingPong<T> pp, int m, int n, int r, int R, T* U, T* V,
+                               double* B)
 {
+    if (!st->done || st->status < 0 || st->exch_timeout) return;
+    const int K = st->iters;
+    const T* P = pp.P[K & 1];
+    const T* Q = pp.Q[K & 1];
+    T* A = pp.P[(K + 1) & 1];
+    T* Vt = pp.Q[(K + 1) & 1];
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nu = (int64_t)m * R, nvv = (int64_t)n * R;
     if (e < nu) {
@@ -121,11 +130,27 @@ __device__ __forceinline__ void vstore(T* p, const T (&v)[VEC])
 // workgroup.  Vector paths need n, ldm, ldy, lds multiples of VEC and
 // 16-byte aligned bases; otherwise VEC = 1.
 template <typename T, int VEC, int R>
-__global__ void __launch_bounds__(256) lowrank_pass_kernel(const T* M, int64_t ldm, const T* Y, int64_t ldy,
-                                                           const T* A, const T* Vt, int m, int n,
-                                                           T* S, int64_t lds, int mode, double lam, double mu,
-                                                           int rows_per_blk)
+__global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
 {
+    const T* M = a.M;
+    const int64_t ldm = a.ldm, ldy = a.ldy, lds = a.lds;
+    const int m = a.m, n = a.n, mode = a.mode, rows_per_blk = a.rows_per_blk;
+    T* S = a.S;
+    const T* Y = a.Y;
+    const T* A = a.A;
+    const T* Vt = a.Vt;
+    double mu = a.mu;
+    const double lam = a.lam;
+    if (a.st) {
+        // FR-ADM: the returned iterate K picks the buffers (see factors_kernel)
+        const DevState* st = a.st;
+        if (!st->done || st->status < 0 || st->exch_timeout) return;
+        const int K = st->iters;
+        Y = (K >= 2) ? a.pp.Y[K & 1] : nullptr;
+        A = a.pp.P[(K + 1) & 1];
+        Vt = a.pp.Q[(K + 1) & 1];
+        mu = st->mu_prev;
+    }
     const int tid = threadIdx.x;
     const int j0 = blockIdx.x * 256 * VEC;
     const T t = (T)(lam / mu), imu = (T)(1.0 / mu);
@@ -170,27 +195,22 @@ __global__ void __launch_bounds__(256) lowrank_pass_kernel(const T* M, int64_t l
 }
 
 template <typename T>
-hipError_t launch_factors(const DevState* st, const T* P, const T* Q, int m, int n, int r, int R,
-                          T* U, T* V, double* B, T* A, T* Vt, hipStream_t s)
+hipError_t launch_factors(const DevState* st, const PingPong<T>& pp, int m, int n, int r, int R, T* U, T* V,
+                          double* B, hipStream_t s)
 {
     const int64_t cnt = (int64_t)m * R + (int64_t)n * R + (int64_t)r * r;
-    hipLaunchKernelGGL(factors_kernel<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, st, P, Q,
-                       m, n, r, R, U, V, B, A, Vt);
+    hipLaunchKernelGGL(factors_kernel<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, st, pp, m, n, r,
+                       R, U, V, B);
     return hipGetLastError();
 }
 
 template <typename T, int VEC>
-static hipError_t lowrank_dispatch(const T* M, int64_t ldm, const T* Y, int64_t ldy, const T* A, const T* Vt,
-                                   int m, int n, int R, T* S, int64_t lds, int mode, double lam, double mu,
-                                   hipStream_t s)
+static hipError_t lowrank_dispatch(const LowrankArgs<T>& a, int R, hipStream_t s)
 {
-    const int rows = 64;
-    dim3 grid((unsigned)((n + 256 * VEC - 1) / (256 * VEC)), (unsigned)((m + rows - 1) / rows));
+    dim3 grid((unsigned)((a.n + 256 * VEC - 1) / (256 * VEC)), (unsigned)((a.m + a.rows_per_blk - 1) / a.rows_per_blk));
     switch (R) {
-#define CASE(rr)                                                                                        \
-    case rr:                                                                                            \
-        hipLaunchKernelGGL((lowrank_pass_kernel<T, VEC, rr>), grid, dim3(256), 0, s, M, ldm, Y, ldy, A, \
-                           Vt, m, n, S, lds, mode, lam, mu, rows);                                      \
+#define CASE(rr)                                                                               \
+    case rr: hipLaunchKernelGGL((lowrank_pass_kernel<T, VEC, rr>), grid, dim3(256), 0, s, a); \
         break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(8) CASE(10) CASE(12) CASE(16) CASE(20) CASE(24)
         CASE(32)
@@ -200,16 +220,19 @@ static hipError_t lowrank_dispatch(const T* M, int64_t ldm, const T* Y, int64_t 
     return hipGetLastError();
 }
 
+// Vector paths need n, ldm, ldy, lds multiples of VEC and 16-byte aligned
+// bases (both Y buffers when they are picked on the device).
 template <typename T>
-hipError_t launch_lowrank_pass(const T* M, int64_t ldm, const T* Y, int64_t ldy, const T* A, const T* Vt,
-                               int m, int n, int R, T* S, int64_t lds, int mode, double lam, double mu,
-                               hipStream_t s)
+hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s)
 {
     constexpr int V = 16 / sizeof(T);
-    const bool vec = (n % V == 0) && (ldm % V == 0) && (lds % V == 0) && ((uintptr_t)M % 16 == 0) &&
-                     ((uintptr_t)S % 16 == 0) && (!Y || ((ldy % V == 0) && ((uintptr_t)Y % 16 == 0)));
-    if (vec) return lowrank_dispatch<T, V>(M, ldm, Y, ldy, A, Vt, m, n, R, S, lds, mode, lam, mu, s);
-    return lowrank_dispatch<T, 1>(M, ldm, Y, ldy, A, Vt, m, n, R, S, lds, mode, lam, mu, s);
+    a.rows_per_blk = 64;
+    auto al = [](const void* p) { return ((uintptr_t)p % 16) == 0; };
+    bool ys = a.st ? (al(a.pp.Y[0]) && al(a.pp.Y[1])) : (!a.Y || al(a.Y));
+    const bool vec = (a.n % V == 0) && (a.ldm % V == 0) && (a.lds % V == 0) && al(a.M) && al(a.S) &&
+                     (a.ldy % V == 0) && ys;
+    if (vec) return lowrank_dispatch<T, V>(a, R, s);
+    return lowrank_dispatch<T, 1>(a, R, s);
 }
 
 // Alg. 3: C = Mt[:, 0:l] (m x l), Rb = Mt[0:l, :] (l x n) with row i of the
@@ -243,10 +266,9 @@ hipError_t launch_nys_gather(const T* M, int64_t ldm, const int64_t* perm, int m
 #define INST(T)                                                                                              \
     template hipError_t launch_init_q<T>(T*, int, int, int, hipStream_t);                                    \
     template hipError_t launch_copy_pad<T>(const T*, int64_t, T*, int64_t, int, int, hipStream_t);          \
-    template hipError_t launch_factors<T>(const DevState*, const T*, const T*, int, int, int, int, T*, T*,    \
-                                          double*, T*, T*, hipStream_t);                                     \
-    template hipError_t launch_lowrank_pass<T>(const T*, int64_t, const T*, int64_t, const T*, const T*, int, \
-                                               int, int, T*, int64_t, int, double, double, hipStream_t);     \
+    template hipError_t launch_factors<T>(const DevState*, const PingPong<T>&, int, int, int, int, T*, T*,    \
+                                          double*, hipStream_t);                                             \
+    template hipError_t launch_lowrank_pass<T>(LowrankArgs<T>, int, hipStream_t);                            \
     template hipError_t launch_nys_gather<T>(const T*, int64_t, const int64_t*, int, int, int, T*, T*,       \
                                              hipStream_t);
 INST(float)

@@ -49,6 +49,22 @@ struct Params {
     bool profile = false;
 };
 
+// What a solve writes once the iteration has stopped: the factors U, B, V
+// (always), the sparse part S of M (optional) and the smallest eigenvalue
+// of B (into the state).  The kernels are queued behind the iteration and
+// write nothing if it ended with an error.
+template <typename T>
+struct OutputSpec {
+    T* U = nullptr;
+    double* B = nullptr;
+    T* V = nullptr;
+    const T* M = nullptr;
+    int64_t ldm = 0;
+    T* S = nullptr;
+    int64_t lds = 0;
+    bool min_eig = false;
+};
+
 }  // namespace sfr
 
 struct sfr_ctx {
@@ -81,8 +97,7 @@ void engine_destroy(Engine& e);
 bool dev_alloc(std::vector<void*>& list, size_t& bytes, void** p, size_t sz);
 void free_all(std::vector<void*>& list);
 template <typename T>
-sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, int64_t ldm, hipStream_t s);
-template <typename T>
-sfr_status engine_factors(Engine& e, T* U, double* B, T* V, hipStream_t s);
+sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, int64_t ldm,
+                          const OutputSpec<T>& out, hipStream_t s);
 sfr_status nys_setup(sfr_ctx* h);
 }  // namespace sfr

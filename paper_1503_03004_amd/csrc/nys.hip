@@ -202,29 +202,19 @@ sfr_status nys_setup(sfr_ctx* h)
 }
 
 template <typename T>
-static sfr_status sub_factors(Engine& e, T* U, double* B, T* V, hipStream_t s)
-{
-    const int K = e.host_state->iters;
-    HIPCHK(launch_factors<T>(e.st, static_cast<const T*>(e.P[K & 1]), static_cast<const T*>(e.Q[K & 1]), e.m, e.n,
-                             e.r, e.R, U, V, B, static_cast<T*>(e.P[(K + 1) & 1]),
-                             static_cast<T*>(e.Q[(K + 1) & 1]), s));
-    return SFR_OK;
-}
-
-template <typename T>
 static sfr_status nys_run(sfr_ctx* h, const T* M, int64_t ldm, T* U, double* B, T* V, T* S, int64_t lds,
                           double* min_sig, hipStream_t s)
 {
     const int m = (int)h->m, n = (int)h->n, r = h->r, l = h->l;
     const int R = h->left.R;
     HIPCHK(launch_nys_gather<T>(M, ldm, h->perm_d, m, n, l, static_cast<T*>(h->C), static_cast<T*>(h->Rb), s));
-    sfr_status st = engine_iterate<T>(h->left, h->prm, h->mu_left, static_cast<const T*>(h->C), l, s);
+    OutputSpec<T> ol;
+    ol.U = static_cast<T*>(h->UL); ol.B = h->BL; ol.V = static_cast<T*>(h->VL);
+    sfr_status st = engine_iterate<T>(h->left, h->prm, h->mu_left, static_cast<const T*>(h->C), l, ol, s);
     if (st != SFR_OK) return st;
-    st = sub_factors<T>(h->left, static_cast<T*>(h->UL), h->BL, static_cast<T*>(h->VL), s);
-    if (st != SFR_OK) return st;
-    st = engine_iterate<T>(h->top, h->prm, h->mu_top, static_cast<const T*>(h->Rb), n, s);
-    if (st != SFR_OK) return st;
-    st = sub_factors<T>(h->top, static_cast<T*>(h->UT), h->BT, static_cast<T*>(h->VT), s);
+    OutputSpec<T> ot;
+    ot.U = static_cast<T*>(h->UT); ot.B = h->BT; ot.V = static_cast<T*>(h->VT);
+    st = engine_iterate<T>(h->top, h->prm, h->mu_top, static_cast<const T*>(h->Rb), n, ot, s);
     if (st != SFR_OK) return st;
     double* Wl = h->core;
     double* Zr = Wl + r * r;
@@ -246,9 +236,22 @@ static sfr_status nys_run(sfr_ctx* h, const T* M, int64_t ldm, T* U, double* B, 
                        static_cast<const T*>(h->UL), static_cast<const T*>(h->VT), h->perm_d, Wl, Zr, sig, m, n,
                        r, R, U, V, B, static_cast<T*>(h->Ucomb), static_cast<T*>(h->Vcomb));
     HIPCHK(hipGetLastError());
-    if (S)
-        HIPCHK(launch_lowrank_pass<T>(M, ldm, nullptr, 0, static_cast<const T*>(h->Ucomb),
-                                      static_cast<const T*>(h->Vcomb), m, n, R, S, lds, 1, 0.0, 1.0, s));
+    if (S) {
+        LowrankArgs<T> la;
+        memset(&la, 0, sizeof(la));
+        la.M = M;
+        la.ldm = ldm;
+        la.A = static_cast<const T*>(h->Ucomb);
+        la.Vt = static_cast<const T*>(h->Vcomb);
+        la.S = S;
+        la.lds = lds;
+        la.m = m;
+        la.n = n;
+        la.mode = 1;
+        la.lam = 0.0;
+        la.mu = 1.0;
+        HIPCHK(launch_lowrank_pass<T>(la, R, s));
+    }
     HIPCHK(hipStreamSynchronize(s));
     return SFR_OK;
 }

@@ -139,9 +139,40 @@ struct StepArgs {
     double* res_hist;     // res_hist[k-1] = residual of iteration k
 };
 
-// Host-side launchers (sweep.hip / small.hip / dense.hip).
+// The ping-pong buffers of one solve (P, Q: m x R, n x R; Y: m x n with
+// leading dimension ldy).  Kernels that run after the iteration pick the
+// returned iterate's buffers from the iteration count in DevState.
 template <typename T>
-hipError_t launch_sweep(const SweepArgs<T>& a, int R, int grid, size_t lds, hipStream_t s);
+struct PingPong {
+    T* P[2];
+    T* Q[2];
+    const T* Y[2];
+};
+
+// Arguments of the dense S pass.  With st set (FR-ADM), Y, A, Vt and mu are
+// taken from the ping-pong buffers and the state of the returned iterate;
+// otherwise the explicit pointers and mu are used.
+template <typename T>
+struct LowrankArgs {
+    const DevState* st;
+    PingPong<T> pp;
+    const T* M;
+    int64_t ldm;
+    const T* Y;
+    int64_t ldy;
+    const T* A;
+    const T* Vt;
+    T* S;
+    int64_t lds;
+    int m, n, mode, rows_per_blk;
+    double lam, mu;
+};
+
+// Host-side launchers (sweep.hip / small.hip / dense.hip).  The sweep takes
+// an optional start/stop event pair bound to its dispatch.
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T>& a, int R, int grid, size_t lds, hipStream_t s,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 hipError_t launch_gram(const GramArgs<T>& a, int R, hipStream_t s);
 template <typename T>
@@ -158,12 +189,10 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t count, hipStream_t s);
 template <typename T>
 hipError_t launch_copy_pad(const T* src, int64_t lds, T* dst, int64_t ldd, int m, int n, hipStream_t s);
 template <typename T>
-hipError_t launch_factors(const DevState* st, const T* P, const T* Q, int m, int n, int r, int R,
-                          T* U, T* V, double* B, T* A, T* Vt, hipStream_t s);
+hipError_t launch_factors(const DevState* st, const PingPong<T>& pp, int m, int n, int r, int R, T* U, T* V,
+                          double* B, hipStream_t s);
 template <typename T>
-hipError_t launch_lowrank_pass(const T* M, int64_t ldm, const T* Y, int64_t ldy, const T* A, const T* Vt,
-                               int m, int n, int R, T* S, int64_t lds, int mode, double lam, double mu,
-                               hipStream_t s);
+hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s);
 template <typename T>
 hipError_t launch_nys_gather(const T* M, int64_t ldm, const int64_t* perm, int m, int n, int l,
                              T* C, T* Rb, hipStream_t s);

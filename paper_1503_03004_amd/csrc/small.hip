@@ -32,6 +32,10 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
 {
     DevState* st = a.st;
     if (st->done) return;
+    if (st->exch_timeout) {   // a sweep hit its wait bound: stop the solve
+        if (threadIdx.x == 0) st->done = 1;
+        return;
+    }
     constexpr int TPB = step_tpb<R>();
     constexpr int E = R * (R + 1) / 2;
     __shared__ double Gp[R * LDP], Gq[R * LDP], Bm[R * LDP], C1[R * LDP];

@@ -21,6 +21,8 @@
 // HBM traffic per element: read M, read Y_{k-1}, write Y_k.
 #include "sfr_internal.hpp"
 
+#include <hip/hip_ext.h>
+
 namespace sfr {
 
 template <typename T> struct Vec;
@@ -637,12 +639,17 @@ static void* sweep_fn(int R)
 }
 
 template <typename T>
-hipError_t launch_sweep(const SweepArgs<T>& a, int R, int grid, size_t lds, hipStream_t s)
+hipError_t launch_sweep(const SweepArgs<T>& a, int R, int grid, size_t lds, hipStream_t s, hipEvent_t ev0,
+                        hipEvent_t ev1)
 {
     switch (R) {
-#define CASE(r)                                                                       \
-    case r:                                                                           \
-        hipLaunchKernelGGL((sweep_kernel<T, r>), dim3(grid), dim3(kTPB), lds, s, a); \
+#define CASE(r)                                                                                            \
+    case r:                                                                                                \
+        if (ev0)                                                                                           \
+            hipExtLaunchKernelGGL((sweep_kernel<T, r>), dim3(grid), dim3(kTPB), (uint32_t)lds, s, ev0, ev1, \
+                                  0u, a);                                                                  \
+        else                                                                                               \
+            hipLaunchKernelGGL((sweep_kernel<T, r>), dim3(grid), dim3(kTPB), lds, s, a);                  \
         return hipGetLastError();
         SFR_R_LIST(CASE)
 #undef CASE
@@ -675,8 +682,10 @@ hipError_t launch_gram(const GramArgs<T>& a, int R, hipStream_t s)
     }
 }
 
-template hipError_t launch_sweep<float>(const SweepArgs<float>&, int, int, size_t, hipStream_t);
-template hipError_t launch_sweep<double>(const SweepArgs<double>&, int, int, size_t, hipStream_t);
+template hipError_t launch_sweep<float>(const SweepArgs<float>&, int, int, size_t, hipStream_t, hipEvent_t,
+                                        hipEvent_t);
+template hipError_t launch_sweep<double>(const SweepArgs<double>&, int, int, size_t, hipStream_t, hipEvent_t,
+                                         hipEvent_t);
 template hipError_t launch_gram<float>(const GramArgs<float>&, int, hipStream_t);
 template hipError_t launch_gram<double>(const GramArgs<double>&, int, hipStream_t);
 template size_t sweep_lds_bytes_c<float>(int, int, int, int);
