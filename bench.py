@@ -11,8 +11,9 @@ Default workload: m = n = 8000, r = 10, FP32 storage, L0 = A B^T with
 N(0,1) factors, 10 % Bernoulli outliers U[-100, 100] (seeded synthetic).
 
 Printed: one JSON line with the iteration rate, the fused sweep's HBM
-roofline fraction (HIP events on the solve stream around every sweep
-launch), a full tolerance-driven solve rate with p50/p99 latency, the
+roofline fraction (HIP start/stop events bound to every sweep dispatch,
+taken in a second run of the same K iterations), a full
+tolerance-driven solve rate with p50/p99 latency, the
 relative error against the FP64 oracle on the same input, and the oracle's
 own rate on the host (cpu_baseline).
 """
@@ -124,9 +125,9 @@ def main():
             w.solve(M)
     torch.cuda.synchronize()
 
-    # ---- timed: exactly K iterations
+    # ---- timed: exactly K iterations (plus the output pass writing U, B, V, S)
     K = args.steps
-    solver = sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K, profile=True)
+    solver = sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K)
     U = torch.empty((m, r), dtype=tdt, device=dev)
     Bm = torch.empty((r, r), dtype=torch.float64, device=dev)
     V = torch.empty((n, r), dtype=tdt, device=dev)
@@ -141,8 +142,14 @@ def main():
     ms = ev0.elapsed_time(ev1)
     assert info.iters == K, info
     value = K / (ms / 1e3)
-    sweep_ms = info.sweep_ms
-    print(f"[bench] {K} iterations in {ms:.3f} ms; sweep {sweep_ms * 1e3:.1f} us avg over {info.sweeps_timed}",
+    solver.close()
+    # ---- the same K iterations again with HIP events bound to every sweep
+    # dispatch (kept out of the run above: the events cost a few us a launch)
+    with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K, profile=True) as sp:
+        _, _, _, _, pinfo = sp.solve(M, out=(U, Bm, V, S), stream=stream)
+    torch.cuda.synchronize()
+    sweep_ms = pinfo.sweep_ms
+    print(f"[bench] {K} iterations in {ms:.3f} ms; sweep {sweep_ms * 1e3:.1f} us avg over {pinfo.sweeps_timed}",
           file=sys.stderr, flush=True)
 
     bytes_per_el = 3 * esz  # read M, read Y_{k-1}, write Y_k
@@ -196,7 +203,6 @@ def main():
                   "rel_err_S": rel(S3.double()[rows].cpu().numpy(), o["S"][rows]),
                   "rows_sampled": int(rows.size)}
         print(f"[bench] oracle {oi} iterations in {tc:.1f} s; parity {parity}", file=sys.stderr, flush=True)
-    solver.close()
 
     out = {
         "metric": "iters/s & solves/s at rel-err<=1e-5 vs FP64 oracle; %HBM roofline; p50/p99",
