@@ -306,19 +306,18 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
     // a lane are issued together, one band ahead of their use.  Vectors out
     // of range read a valid dummy address and are zeroed at use.
     T mvv[NVMAX][VEC], ypv[NVMAX][VEC];
-    auto issue_loads = [&](int jb) {
+    auto issue_load = [&](int jb, int v) {
         const int bb = cl + jb * ncl;
         const int ii = bb * H + wave * rpw + rg;
-        const bool rok = ii < m;
-#pragma unroll
-        for (int v = 0; v < NVMAX; ++v) {
-            const int col = c0 + (li + lpr * v) * VEC;
-            const bool ok = (v < nv) && rok && (col < n);
-            load_vec<T>(M + (ok ? (int64_t)ii * ldm + col : 0), mvv[v]);
-            if (mode == 2) load_vec<T>(a.Yprev + (ok ? (int64_t)ii * ldy + col : 0), ypv[v]);
-        }
+        const int col = c0 + (li + lpr * v) * VEC;
+        const bool ok = (v < nv) && (ii < m) && (col < n);
+        load_vec<T>(M + (ok ? (int64_t)ii * ldm + col : 0), mvv[v]);
+        if (mode == 2) load_vec<T>(a.Yprev + (ok ? (int64_t)ii * ldy + col : 0), ypv[v]);
     };
-    if (nbl > 0) issue_loads(0);
+    if (nbl > 0) {
+#pragma unroll
+        for (int v = 0; v < NVMAX; ++v) issue_load(0, v);
+    }
 
     for (int j = 0; j <= nbl; ++j) {
         // exchange words of the previous band (c > 1): issued now, consumed
@@ -425,10 +424,11 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
                 for (int k = 0; k < R; ++k)
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) p[k] = fma(x[e], vk[k][e], p[k]);
+                // this vector's registers are free: the next band's load
+                // goes out now and lands during the rest of this row pass,
+                // the reduction, the exchange and the column pass
+                if (j + 1 < nbl) issue_load(j + 1, v);
             }
-            // the next band's loads go out now and land during the
-            // reduction, the exchange and the column pass of this band
-            if (j + 1 < nbl) issue_loads(j + 1);
             acc2 += (double)rowacc;
             group_sum_all<T, R>(p, lpr);
             if (c == 1) {
