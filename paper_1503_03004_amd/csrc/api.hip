@@ -346,9 +346,11 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         la.mode = 0;
         la.lam = p.lambda;
         la.mu = 1.0;
+        la.min_eig = out.min_eig ? 1 : 0;
         HIPCHK(launch_lowrank_pass<T>(la, e.R, s));
+    } else if (out.min_eig) {
+        HIPCHK(launch_final_small(e.st, e.R, s));
     }
-    if (out.min_eig) HIPCHK(launch_final_small(e.st, e.R, s));
     HIPCHK(hipMemcpyAsync(e.host_state, e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     e.sweep_ms = 0.0;

@@ -2,6 +2,7 @@
 // of Alg. 1 (soft threshold of the last residual), the gather of the two
 // Nystrom blocks of Alg. 3, and the dense S = M - L of its combine.
 #include "sfr_internal.hpp"
+#include "small_la.hpp"
 
 namespace sfr {
 
@@ -122,7 +123,8 @@ __device__ __forceinline__ void vstore(T* p, const T (&v)[VEC])
 }
 
 // Dense pass over an m x n matrix with the rank-R term l_ij = A_i . Vt_j:
-//   mode 0 (FR-ADM S):  S = P_ST_{lambda/mu}(M - l + Y/mu), Y may be NULL
+//   mode 0 (FR-ADM S):  S = P_ST_{lambda/mu}(M - l + Y/mu), Y may be NULL;
+//                       optionally also min eig(B) into the state
 //   mode 1 (FR-Nys S):  S = M - l
 // A workgroup owns a column tile of 256 * VEC columns and a band of rows;
 // each thread keeps its VEC columns of Vt in registers and streams 16-byte
@@ -150,6 +152,14 @@ __global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
         A = a.pp.P[(K + 1) & 1];
         Vt = a.pp.Q[(K + 1) & 1];
         mu = st->mu_prev;
+        if (a.min_eig && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 64) {
+            // smallest eigenvalue of the returned B (Appendix, Lemma 2): one
+            // wavefront of the first workgroup, before its share of the pass
+            __shared__ double Aw[R * LDP], Ew[R * LDP];
+            __shared__ __align__(16) double csw[2 * 16];
+            const double w = wmin_eig<R>(st->B, st->r, Aw, Ew, csw);
+            if (threadIdx.x == 0) a.st->min_eig_B = w;
+        }
     }
     const int tid = threadIdx.x;
     const int j0 = blockIdx.x * 256 * VEC;

@@ -154,7 +154,7 @@ struct PingPong {
 // otherwise the explicit pointers and mu are used.
 template <typename T>
 struct LowrankArgs {
-    const DevState* st;
+    DevState* st;
     PingPong<T> pp;
     const T* M;
     int64_t ldm;
@@ -165,6 +165,7 @@ struct LowrankArgs {
     T* S;
     int64_t lds;
     int m, n, mode, rows_per_blk;
+    int min_eig;   // with st: also write min eig(B) into the state
     double lam, mu;
 };
 

@@ -217,20 +217,8 @@ __global__ void __launch_bounds__(64) final_small_kernel(DevState* st)
 {
     __shared__ double A[R * LDP], Ev[R * LDP];
     __shared__ __align__(16) double cs[2 * 16];
-    const int r = st->r;
-    const int lane = threadIdx.x & 63;
-    for (int e = lane; e < R * R; e += 64) {
-        const int i = e / R, j = e % R;
-        const bool pad = (i >= r) || (j >= r);
-        A[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : st->B[i * kMaxR + j];
-        Ev[i * LDP + j] = (i == j) ? 1.0 : 0.0;
-    }
-    wsync();
-    wjacobi<R>(A, Ev, cs);
-    double w = INFINITY;
-    for (int i = lane; i < r; i += 64) w = fmin(w, A[i * LDP + i]);
-    w = wave_min(w);
-    if (lane == 0) st->min_eig_B = w;
+    const double w = wmin_eig<R>(st->B, st->r, A, Ev, cs);
+    if (threadIdx.x == 0) st->min_eig_B = w;
 }
 
 #define SFR_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)

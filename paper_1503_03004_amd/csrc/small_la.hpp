@@ -310,4 +310,24 @@ __device__ inline bool winv_sqrt(double* Out, double* A, double* E, double* T, i
     return ok;
 }
 
+// Smallest eigenvalue of the leading r x r block of B (row pitch kMaxR),
+// one wavefront; A, Ev: LDS scratch R x LDP, cs: 2 * 16.  Full Jacobi
+// convergence from the identity basis.
+template <int R>
+__device__ inline double wmin_eig(const double* B, int r, double* A, double* Ev, double* cs)
+{
+    const int lane = threadIdx.x & 63;
+    for (int e = lane; e < R * R; e += 64) {
+        const int i = e / R, j = e % R;
+        const bool pad = (i >= r) || (j >= r);
+        A[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : B[i * kMaxR + j];
+        Ev[i * LDP + j] = (i == j) ? 1.0 : 0.0;
+    }
+    wsync();
+    wjacobi<R>(A, Ev, cs);
+    double w = INFINITY;
+    for (int i = lane; i < r; i += 64) w = fmin(w, A[i * LDP + i]);
+    return wave_min(w);
+}
+
 }  // namespace sfr

@@ -591,9 +591,19 @@ __global__ void __launch_bounds__(kTPB) gram_kernel(GramArgs<T> a)
             double v = 0.0;
             if (j < r1) {
                 if (isq) {
+                    // all cluster partials of (j, k) in flight at once, in
+                    // batches of 32 unconditional (clamped) loads; summed in
+                    // cluster order
+                    constexpr int CH = 32;
                     T s = 0;
-#pragma unroll 8
-                    for (int cl = 0; cl < a.ncl; ++cl) s += a.Qpart[((size_t)cl * a.n + j) * R + k];
+                    for (int c0 = 0; c0 < a.ncl; c0 += CH) {
+                        T w[CH];
+#pragma unroll
+                        for (int u = 0; u < CH; ++u)
+                            w[u] = a.Qpart[((size_t)min(c0 + u, a.ncl - 1) * a.n + j) * R + k];
+#pragma unroll
+                        for (int u = 0; u < CH; ++u) s += (c0 + u < a.ncl) ? w[u] : T(0);
+                    }
                     a.Qnext[(int64_t)j * R + k] = s;
                     v = (double)s;
                 } else {
