@@ -55,12 +55,14 @@ static sfr_status configure(Engine& e)
     int best_lpr = -1, best_nv = -1;
     long best_waste = -1;
     // single-slice shapes (c = 1): choose the least lane waste
+    const int wmax = e.f64 ? sweep_max_width<double>(e.R) : sweep_max_width<float>(e.R);
     for (int lpr = 4; lpr <= 64; lpr *= 2) {
         const int nv = (nvec + lpr - 1) / lpr;
         if (nv > 4) continue;
         const int W = lpr * vec * nv;
+        if (W > wmax) continue;
         const size_t L = e.f64 ? lds_of<double>(e.R, lpr, W, 1) : lds_of<float>(e.R, lpr, W, 1);
-        if (L > ldsmax / 2) continue;
+        if (L > ldsmax) continue;
         const long waste = (long)lpr * nv - nvec;
         if (best_waste < 0 || waste < best_waste || (waste == best_waste && lpr > best_lpr)) {
             best_waste = waste; best_lpr = lpr; best_nv = nv;
@@ -72,16 +74,18 @@ static sfr_status configure(Engine& e)
         // wide rows: one row per wave, slices of W columns exchanged in clusters
         e.lpr = 64;
         e.nv = 4;
+        while (e.nv > 1 && 64 * vec * e.nv > wmax) --e.nv;
         for (;;) {
             const int W = 64 * vec * e.nv;
             const size_t L = e.f64 ? lds_of<double>(e.R, 64, W, 2) : lds_of<float>(e.R, 64, W, 2);
-            if (L <= ldsmax / 2 || e.nv == 1) break;
+            if (L <= ldsmax || e.nv == 1) break;
             --e.nv;
         }
         e.c = (e.ne + 64 * vec * e.nv - 1) / (64 * vec * e.nv);
     }
     e.W = e.lpr * vec * e.nv;
-    e.H = 4 * (64 / e.lpr);
+    const int tpb = e.f64 ? sweep_threads<double>(e.R) : sweep_threads<float>(e.R);
+    e.H = (tpb / 64) * (64 / e.lpr);
     e.nbands = (e.m + e.H - 1) / e.H;
     e.lds = e.f64 ? lds_of<double>(e.R, e.lpr, e.W, e.c) : lds_of<float>(e.R, e.lpr, e.W, e.c);
 
@@ -144,7 +148,7 @@ sfr_status engine_create(Engine& e, int m, int n, int r, bool f64, int hist_len)
     for (int b = 0; b < 2 && ok; ++b) ok = dev_alloc(e.allocs, e.bytes, &e.Q[b], (size_t)e.ne * e.R * e.esz);
     if (ok) ok = dev_alloc(e.allocs, e.bytes, &e.Qpart, (size_t)e.ncl * e.ne * e.R * e.esz);
     if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.dy2part, sizeof(double) * (size_t)e.grid);
-    e.exch_words = (e.c > 1) ? (size_t)e.ncl * 4 * e.c * e.H * e.R * (e.esz / 4) : 0;
+    e.exch_words = (e.c > 1) ? (size_t)e.ncl * kExchSlots * e.c * e.H * e.R * (e.esz / 4) : 0;
     if (ok && e.exch_words) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.exch, 8 * e.exch_words);
     if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.GQpart, sizeof(double) * (size_t)e.nqb * e.E);
     if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.GPpart, sizeof(double) * (size_t)e.npb * e.E);

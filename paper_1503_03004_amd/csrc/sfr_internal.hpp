@@ -179,6 +179,12 @@ hipError_t launch_gram(const GramArgs<T>& a, int R, hipStream_t s);
 template <typename T>
 size_t sweep_lds_bytes_c(int R, int lpr, int W, int c);
 template <typename T>
+int sweep_threads(int R);     // workgroup size of the sweep for rank bucket R
+template <typename T>
+int sweep_max_width(int R);   // widest column slice the sweep's column pass holds
+// Exchange slots cycled by a cluster (bands in flight between its members).
+constexpr int kExchSlots = 8;
+template <typename T>
 hipError_t sweep_prepare(int R, size_t lds, int* blocks_per_cu);
 
 hipError_t launch_step(const StepArgs& a, int R, hipStream_t s);

@@ -2,11 +2,13 @@
 // L-step of Alg. 2), gfx950.
 //
 // Work decomposition
-//   * Rows are cut into bands of H rows.  Each band is owned by a cluster of
-//     c workgroups; member q of a cluster covers the column slice
-//     [q W, (q+1) W).  Clusters are formed from workgroups of one XCD
-//     (workgroup g runs on XCD g % 8), so their exchange stays in one L2;
-//     clusters wider than one XCD's share of the grid span XCDs instead.
+//   * Rows are cut into bands of H rows (one or more per wavefront).  Each
+//     band is owned by a cluster of c workgroups; member q of a cluster
+//     covers the column slice [q W, (q+1) W).  Clusters are formed from
+//     workgroups of one XCD (workgroup g runs on XCD g % 8), so their
+//     exchange stays in one L2; clusters wider than one XCD's share of the
+//     grid span XCDs instead.  A workgroup is 8 wavefronts (one per CU)
+//     while two wavefronts fit a SIMD, else 4.
 //   * Row pass (phase 1): a group of `lpr` lanes owns one row of the band;
 //     each lane streams `nv` 16-byte vectors of M and Y_{k-1}, rebuilds
 //     l_ij = a_i . V_j (r FMAs, V slice staged in LDS), applies the S- and
@@ -14,7 +16,10 @@
 //     x goes to LDS for phase 2.
 //   * If c > 1 the members add their partial p_i through tagged 64-bit
 //     words in global memory (value | tag << 32, so no fences are needed),
-//     one band behind the row pass so the wait overlaps streaming.
+//     two bands behind the row pass (three band buffers of x and p in LDS),
+//     so a member may run up to two bands ahead of the slowest one before
+//     it waits.  A member can then publish at most five bands ahead of one
+//     still reading, so eight exchange slots are cycled.
 //   * Column pass (phase 2): thread-owned columns accumulate
 //     Q_j += x_ij p_i from the LDS copy of x: Q = X^T X V with no second
 //     read of the data.
@@ -188,49 +193,61 @@ struct SweepLds {
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
 
+// Gather lag (bands between a row pass and the column pass that uses it)
+// and the number of band buffers of x and p.
+__host__ __device__ inline int sweep_lag(int c) { return c > 1 ? 2 : 1; }
+
 template <typename T>
-__host__ __device__ inline SweepLds sweep_lds(int R, int lpr, int W, int c)
+__host__ __device__ inline SweepLds sweep_lds(int R, int lpr, int W, int c, int tpb)
 {
-    const int H = 4 * (64 / lpr);
-    const int HG = (W >= kTPB) ? 1 : kTPB / W;
+    const int H = (tpb / 64) * (64 / lpr);
+    const int HG = (W >= tpb) ? 1 : tpb / W;
+    const int nbuf = sweep_lag(c) + 1;
     SweepLds L;
     size_t o = 0;
     L.tu = o; o = al16(o + sizeof(T) * R * R);
     L.tv = o; o = al16(o + sizeof(T) * R * R);
     L.vs = o; o = al16(o + sizeof(T) * (size_t)R * W);
-    L.xs = o; o = al16(o + sizeof(T) * 2 * (size_t)H * W);
-    L.ps = o; o = al16(o + sizeof(T) * 2 * (size_t)H * R);
-    L.gx = o; o = al16(o + (c > 1 ? sizeof(T) * 4 * (size_t)c * R : 0));
-    L.qred = o; o = al16(o + (W < kTPB ? sizeof(T) * (size_t)HG * W * R : 0));
-    L.red = o; o = al16(o + sizeof(double) * 4);
+    L.xs = o; o = al16(o + sizeof(T) * nbuf * (size_t)H * W);
+    L.ps = o; o = al16(o + sizeof(T) * nbuf * (size_t)H * R);
+    L.gx = o; o = al16(o + (c > 1 ? sizeof(T) * (tpb / 64) * (size_t)c * R : 0));
+    L.qred = o; o = al16(o + (W < tpb ? sizeof(T) * (size_t)HG * W * R : 0));
+    L.red = o; o = al16(o + sizeof(double) * (tpb / 64));
     L.total = o;
     return L;
 }
 
-template <typename T>
-size_t sweep_lds_bytes_c(int R, int lpr, int W, int c)
-{
-    return sweep_lds<T>(R, lpr, W, c).total;
-}
-
-// Two waves per SIMD while the per-lane register state fits in 256 VGPRs;
-// larger ranks take one wave per SIMD and the full register file.
+// Two waves per SIMD while the per-lane register state fits in 256 VGPRs
+// (workgroups of 8 waves); larger ranks take one wave per SIMD and the full
+// register file (workgroups of 4 waves).
 template <typename T, int R>
 constexpr int sweep_waves_per_simd() { return (sizeof(T) * R <= 40) ? 2 : 1; }
+template <typename T, int R>
+constexpr int sweep_tpb() { return sweep_waves_per_simd<T, R>() == 2 ? 512 : 256; }
+// Columns a thread accumulates in the column pass (bounds the slice width
+// W <= cpt2 * threads); two for the widest ranks to keep Q in registers.
+template <typename T, int R>
+constexpr int sweep_cpt2()
+{
+    return (R > 16) ? 2 : (64 * 4 * Vec<T>::N + sweep_tpb<T, R>() - 1) / sweep_tpb<T, R>();
+}
 
 template <typename T, int R>
-__global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_kernel(SweepArgs<T> a)
+__global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs<T> a)
 {
     DevState* st = const_cast<DevState*>(a.st);
     if (st->done) return;
+    constexpr int TPB = sweep_tpb<T, R>();
+    constexpr int NW = TPB / 64;
     constexpr int VEC = Vec<T>::N;
     constexpr int WD = Words<T>::N;
-    constexpr int CPT2MAX = (R > 16) ? 2 : 4;
     constexpr int NVMAX = 4;
+    constexpr int CPT2MAX = sweep_cpt2<T, R>();   // columns per thread, column pass
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lpr = a.lpr, nv = a.nv, W = a.W, c = a.c;
-    const int rpw = 64 / lpr, H = 4 * rpw;
+    const int rpw = 64 / lpr, H = NW * rpw;
+    const int lag = sweep_lag(c), nbuf = lag + 1;
     const int li = lane % lpr, rg = lane / lpr, gbase = lane - li;
     const int g = blockIdx.x;
     int q, cl;
@@ -255,7 +272,7 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
     int32_t* tflag = &st->exch_timeout;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    const SweepLds L = sweep_lds<T>(R, lpr, W, c);
+    const SweepLds L = sweep_lds<T>(R, lpr, W, c, TPB);
     T* TUs = reinterpret_cast<T*>(smem + L.tu);
     T* TVs = reinterpret_cast<T*>(smem + L.tv);
     T* Vs = reinterpret_cast<T*>(smem + L.vs);
@@ -268,7 +285,7 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
     {
         const T* tu = st_TU<T>(st);
         const T* tv = st_TV<T>(st);
-        for (int e = tid; e < R * R; e += kTPB) {
+        for (int e = tid; e < R * R; e += TPB) {
             const int r0 = e / R, r1 = e % R;
             TUs[e] = tu[r0 * kMaxR + r1];
             TVs[e] = tv[r0 * kMaxR + r1];
@@ -276,7 +293,7 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
     }
     __syncthreads();
     // V slice of this member: V_j = Q_j TV, stored k-major (Vs[k][jj]).
-    for (int jj = tid; jj < W; jj += kTPB) {
+    for (int jj = tid; jj < W; jj += TPB) {
         const int j = c0 + jj;
         T qrow[R];
 #pragma unroll
@@ -293,8 +310,8 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
 
     const int nbands = a.nbands, ncl = a.ncl;
     const int nbl = (cl < nbands) ? (nbands - 1 - cl) / ncl + 1 : 0;
-    const int cpt2 = (W >= kTPB) ? (W + kTPB - 1) / kTPB : 1;
-    const int HG = (W >= kTPB) ? 1 : kTPB / W;
+    const int cpt2 = (W >= TPB) ? (W + TPB - 1) / TPB : 1;
+    const int HG = (W >= TPB) ? 1 : TPB / W;
     double acc2 = 0.0;
     T Qacc[CPT2MAX][R];
 #pragma unroll
@@ -319,15 +336,15 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
         for (int v = 0; v < NVMAX; ++v) issue_load(0, v);
     }
 
-    for (int j = 0; j <= nbl; ++j) {
-        // exchange words of the previous band (c > 1): issued now, consumed
-        // after this band's row pass
+    for (int j = 0; j < nbl + lag; ++j) {
+        // exchange words of band j - lag (c > 1): issued now, consumed after
+        // this band's row pass
         const int nwords = c * R * WD;
-        const bool ahead = (c > 1) && (j >= 1) && (nwords <= 64 * kGatherAhead);
+        const bool ahead = (c > 1) && (j >= lag) && (nwords <= 64 * kGatherAhead);
         unsigned long long gw[kGatherAhead];
         if (ahead) {
-            const int slot = (j - 1) & 3;
-            const unsigned long long* base = a.exch + (((size_t)cl * 4 + slot) * c) * H * R * WD;
+            const int slot = (j - lag) & (kExchSlots - 1);
+            const unsigned long long* base = a.exch + (((size_t)cl * kExchSlots + slot) * c) * H * R * WD;
 #pragma unroll
             for (int g = 0; g < kGatherAhead; ++g) {
                 const int e = lane + 64 * g;      // word index over (member, k, half)
@@ -338,7 +355,7 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
         if (j < nbl) {
             // ---------------- phase 1: row pass over band b ----------------
             const int b = cl + j * ncl;
-            const int buf = j & 1;
+            const int buf = j % nbuf;
             const int h = wave * rpw + rg;
             const int i = b * H + h;
             const bool row_ok = i < m;
@@ -442,27 +459,27 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
 #pragma unroll
                 for (int kk = 0; kk < R; ++kk) mine = (kk == li) ? p[kk] : mine;
                 const uint32_t tag = kiter * (uint32_t)a.nbl_max + (uint32_t)j + 1u;
-                const int slot = j & 3;
+                const int slot = j & (kExchSlots - 1);
                 unsigned long long* dst =
-                    a.exch + (((((size_t)cl * 4 + slot) * c + q) * H + h) * R + li) * WD;
+                    a.exch + (((((size_t)cl * kExchSlots + slot) * c + q) * H + h) * R + li) * WD;
                 publish<T>(dst, mine, tag);
             }
         }
-        if (j >= 1) {
-            const int jb = j - 1;
+        if (j >= lag) {
+            const int jb = j - lag;
             const int b = cl + jb * ncl;
-            const int buf = jb & 1;
+            const int buf = jb % nbuf;
             if (c > 1) {
                 // gather the c partials of this wave's row of band jb
                 const int h = wave;
                 const uint32_t tag = kiter * (uint32_t)a.nbl_max + (uint32_t)jb + 1u;
-                const int slot = jb & 3;
+                const int slot = jb & (kExchSlots - 1);
                 T* gx = Gx + (size_t)wave * c * R;
                 if (ahead) {
                     // words read before the row pass; re-poll only those whose
                     // tag has not arrived yet
                     uint32_t* gxw = reinterpret_cast<uint32_t*>(gx);
-                    const unsigned long long* base = a.exch + (((size_t)cl * 4 + slot) * c) * H * R * WD;
+                    const unsigned long long* base = a.exch + (((size_t)cl * kExchSlots + slot) * c) * H * R * WD;
 #pragma unroll
                     for (int g = 0; g < kGatherAhead; ++g) {
                         const int e = lane + 64 * g;
@@ -479,7 +496,7 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
                     for (int e = lane; e < c * R; e += 64) {
                         const int qq = e / R, k = e % R;
                         const unsigned long long* src =
-                            a.exch + (((((size_t)cl * 4 + slot) * c + qq) * H + h) * R + k) * WD;
+                            a.exch + (((((size_t)cl * kExchSlots + slot) * c + qq) * H + h) * R + k) * WD;
                         gx[e] = fetch<T>(src, tag, tflag);
                     }
                 }
@@ -494,14 +511,14 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
             }
             __syncthreads();
             if (q == 0) {
-                for (int e = tid; e < H * R; e += kTPB) {
+                for (int e = tid; e < H * R; e += TPB) {
                     const int hh = e / R, k = e % R;
                     const int i = b * H + hh;
                     if (i < m) a.Pnext[(int64_t)i * R + k] = Ps[((size_t)buf * H + hh) * R + k];
                 }
             }
             // ---------------- phase 2: column pass, Q += X^T p --------------
-            if (W >= kTPB) {
+            if (W >= TPB) {
                 for (int hh = 0; hh < H; ++hh) {
                     const T* xr = Xs + ((size_t)buf * H + hh) * W;
                     T pk[R];
@@ -509,7 +526,7 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
                     for (int k = 0; k < R; ++k) pk[k] = Ps[((size_t)buf * H + hh) * R + k];
 #pragma unroll
                     for (int e = 0; e < CPT2MAX; ++e) {
-                        const int col = tid + e * kTPB;
+                        const int col = tid + e * TPB;
                         if (e < cpt2 && col < W) {
                             const T xv = xr[col];
 #pragma unroll
@@ -533,10 +550,10 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
     }
 
     // ---------------- write the column partials of this cluster -----------
-    if (W >= kTPB) {
+    if (W >= TPB) {
 #pragma unroll
         for (int e = 0; e < CPT2MAX; ++e) {
-            const int col = tid + e * kTPB;
+            const int col = tid + e * TPB;
             const int jcol = c0 + col;
             if (e < cpt2 && col < W && jcol < n) {
 #pragma unroll
@@ -550,7 +567,7 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
             for (int k = 0; k < R; ++k) Qred[((size_t)grp * W + col) * R + k] = Qacc[0][k];
         }
         __syncthreads();
-        for (int e = tid; e < W * R; e += kTPB) {
+        for (int e = tid; e < W * R; e += TPB) {
             const int colx = e / R, k = e % R;
             T s = 0;
             for (int gg = 0; gg < HG; ++gg) s += Qred[((size_t)gg * W + colx) * R + k];
@@ -562,7 +579,12 @@ __global__ void __launch_bounds__(kTPB, (sweep_waves_per_simd<T, R>())) sweep_ke
     acc2 = group_sum(acc2, 64);
     if (lane == 0) red[wave] = acc2;
     __syncthreads();
-    if (tid == 0) a.dy2part[g] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (tid == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += red[w];
+        a.dy2part[g] = t;
+    }
 }
 
 // Sum the cluster partials of Q (fixed order), write Q, and form the
@@ -638,6 +660,34 @@ __global__ void __launch_bounds__(kTPB) gram_kernel(GramArgs<T> a)
 #define SFR_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
 
 template <typename T>
+size_t sweep_lds_bytes_c(int R, int lpr, int W, int c)
+{
+    return sweep_lds<T>(R, lpr, W, c, sweep_threads<T>(R)).total;
+}
+
+template <typename T>
+int sweep_threads(int R)
+{
+    switch (R) {
+#define CASE(r) case r: return sweep_tpb<T, r>();
+        SFR_R_LIST(CASE)
+#undef CASE
+    default: return 0;
+    }
+}
+
+template <typename T>
+int sweep_max_width(int R)
+{
+    switch (R) {
+#define CASE(r) case r: return sweep_cpt2<T, r>() * sweep_tpb<T, r>();
+        SFR_R_LIST(CASE)
+#undef CASE
+    default: return 0;
+    }
+}
+
+template <typename T>
 static void* sweep_fn(int R)
 {
     switch (R) {
@@ -655,11 +705,11 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int R, int grid, size_t lds, hipS
     switch (R) {
 #define CASE(r)                                                                                            \
     case r:                                                                                                \
-        if (ev0)                                                                                           \
-            hipExtLaunchKernelGGL((sweep_kernel<T, r>), dim3(grid), dim3(kTPB), (uint32_t)lds, s, ev0, ev1, \
-                                  0u, a);                                                                  \
-        else                                                                                               \
-            hipLaunchKernelGGL((sweep_kernel<T, r>), dim3(grid), dim3(kTPB), lds, s, a);                  \
+        if (ev0)                                                                                         \
+            hipExtLaunchKernelGGL((sweep_kernel<T, r>), dim3(grid), dim3(sweep_tpb<T, r>()), (uint32_t)lds, \
+                                  s, ev0, ev1, 0u, a);                                                   \
+        else                                                                                             \
+            hipLaunchKernelGGL((sweep_kernel<T, r>), dim3(grid), dim3(sweep_tpb<T, r>()), lds, s, a);   \
         return hipGetLastError();
         SFR_R_LIST(CASE)
 #undef CASE
@@ -674,7 +724,7 @@ hipError_t sweep_prepare(int R, size_t lds, int* blocks_per_cu)
     if (!fn) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kTPB, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, sweep_threads<T>(R), lds);
 }
 
 template <typename T>
@@ -700,6 +750,10 @@ template hipError_t launch_gram<float>(const GramArgs<float>&, int, hipStream_t)
 template hipError_t launch_gram<double>(const GramArgs<double>&, int, hipStream_t);
 template size_t sweep_lds_bytes_c<float>(int, int, int, int);
 template size_t sweep_lds_bytes_c<double>(int, int, int, int);
+template int sweep_threads<float>(int);
+template int sweep_threads<double>(int);
+template int sweep_max_width<float>(int);
+template int sweep_max_width<double>(int);
 template hipError_t sweep_prepare<float>(int, size_t, int*);
 template hipError_t sweep_prepare<double>(int, size_t, int*);
 
