@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--workload", default="large_fp32", choices=["large_fp32", "plain_fp64", "photometric"])
     ap.add_argument("--solves", type=int, default=5, help="tolerance-driven solves timed for solves/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--oracle-iters", type=int, default=2, help="oracle iterations timed on the host")
+    ap.add_argument("--oracle-iters", type=int, default=12, help="oracle iterations timed on the host (about 1 s each)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
