@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="large_fp32", choices=["large_fp32", "plain_fp64", "photometric"])
+    ap.add_argument("--workload", default="large_fp32", choices=["large_fp32", "plain_fp64", "photometric", "tsvd_fp32"])
     ap.add_argument("--solves", type=int, default=5, help="tolerance-driven solves timed for solves/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-iters", type=int, default=12, help="oracle iterations timed on the host (about 1 s each)")
@@ -89,10 +89,14 @@ def main():
     torch.cuda.set_device(dev)
 
     t0 = time.time()
-    if args.workload == "large_fp32":
+    tsvd = args.workload == "tsvd_fp32"
+    if args.workload in ("large_fp32", "tsvd_fp32"):
         inst = workloads.large_fp32(seed=args.seed)
         precision, esz, tol = "f32", 4, 1e-6
         desc = "FR-ADM, m=n=8000, r=10, FP32, 10% outliers U[-100,100]"
+        if tsvd:
+            tol = 1e-6
+            desc = "FixedRankOptFull (Alg. 4) rank-10 TSVD of the same 8000x8000 FP32 matrix"
     elif args.workload == "plain_fp64":
         inst = workloads.plain_fp64(seed=args.seed)
         precision, esz, tol = "f64", 8, 1e-7
@@ -119,10 +123,17 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    def run(solver, out=None, stream=None):
+        """One solve: FR-ADM (U, B, V, S, info) or Alg. 4 (U, B, V, None, info)."""
+        if tsvd:
+            U_, B_, V_, inf_ = solver.tsvd(M, out=None if out is None else out[:3], stream=stream)
+            return U_, B_, V_, None, inf_
+        return solver.solve(M, out=out, stream=stream)
+
     # ---- warmup: W untimed iterations
     if args.warmup > 0:
         with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=args.warmup) as w:
-            w.solve(M)
+            run(w)
     torch.cuda.synchronize()
 
     # ---- timed: exactly K iterations (plus the output pass writing U, B, V, S)
@@ -136,7 +147,7 @@ def main():
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
-    _, _, _, _, info = solver.solve(M, out=(U, Bm, V, S), stream=stream)
+    _, _, _, _, info = run(solver, out=(U, Bm, V, S), stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
@@ -146,13 +157,13 @@ def main():
     # ---- the same K iterations again with HIP events bound to every sweep
     # dispatch (kept out of the run above: the events cost a few us a launch)
     with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K, profile=True) as sp:
-        _, _, _, _, pinfo = sp.solve(M, out=(U, Bm, V, S), stream=stream)
+        _, _, _, _, pinfo = run(sp, out=(U, Bm, V, S), stream=stream)
     torch.cuda.synchronize()
     sweep_ms = pinfo.sweep_ms
     print(f"[bench] {K} iterations in {ms:.3f} ms; sweep {sweep_ms * 1e3:.1f} us avg over {pinfo.sweeps_timed}",
           file=sys.stderr, flush=True)
 
-    bytes_per_el = 3 * esz  # read M, read Y_{k-1}, write Y_k
+    bytes_per_el = (1 if tsvd else 3) * esz  # read M (, read Y_{k-1}, write Y_k)
     alg_bytes = bytes_per_el * m * n
     achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
     traffic = measured_traffic(args.workload)
@@ -166,13 +177,13 @@ def main():
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            U2, B2, V2, S2, inf2 = s2.solve(M, stream=stream)
+            U2, B2, V2, S2, inf2 = run(s2, stream=stream)
             e1.record(stream)
             torch.cuda.synchronize()
             lat.append(e0.elapsed_time(e1))
             solve_iters = inf2.iters
         rec_err = None
-        if inst.L0 is not None:
+        if inst.L0 is not None and not tsvd:
             rows = np.random.default_rng(1).choice(m, min(m, 256), replace=False)
             Lr = (U2.double()[rows] @ B2 @ V2.double().T).cpu().numpy()
             rec_err = rel(Lr, inst.L0[rows].astype(np.float64))
@@ -188,19 +199,23 @@ def main():
         Md = inst.M.astype(np.float64)
         oi = args.oracle_iters
         t1 = time.perf_counter()
-        o = oracle.fradm(Md, r, inst.lam, mu0, fixed_iters=oi)
+        if tsvd:
+            Uo, Bo, Vo, _ = oracle.fr_full(Md, np.eye(m, r), np.eye(r), np.eye(n, r), oi)
+            o = {"U": Uo, "B": Bo, "V": Vo, "S": None}
+        else:
+            o = oracle.fradm(Md, r, inst.lam, mu0, fixed_iters=oi)
         tc = time.perf_counter() - t1
         cpu = {"value": oi / tc, "unit": "iters/s", "cores": 1, "kind": "oracle",
-               "sample": f"{oi} FR-ADM iterations of the same {m}x{n} r={r} input, FP64, one thread "
-                         f"({tc:.1f} s)"}
+               "sample": f"{oi} {'Alg. 4 steps' if tsvd else 'FR-ADM iterations'} of the same {m}x{n} r={r} "
+                         f"input, FP64, one thread ({tc:.1f} s)"}
         with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=oi) as s3:
-            U3, B3, V3, S3, _ = s3.solve(M)
+            U3, B3, V3, S3, _ = run(s3)
         torch.cuda.synchronize()
         rows = np.random.default_rng(2).choice(m, min(m, 128), replace=False)
         Lg = (U3.double()[rows] @ B3 @ V3.double().T).cpu().numpy()
         Lo = o["U"][rows] @ o["B"] @ o["V"].T
         parity = {"iterations": oi, "rel_err_L": rel(Lg, Lo),
-                  "rel_err_S": rel(S3.double()[rows].cpu().numpy(), o["S"][rows]),
+                  "rel_err_S": None if tsvd else rel(S3.double()[rows].cpu().numpy(), o["S"][rows]),
                   "rows_sampled": int(rows.size)}
         print(f"[bench] oracle {oi} iterations in {tc:.1f} s; parity {parity}", file=sys.stderr, flush=True)
 
@@ -231,8 +246,10 @@ def main():
         "p99_ms": float(np.percentile(lat, 99)),
         "parity_vs_oracle": parity,
         "recovery_rel_err_L": rec_err,
-        "paper_context": "Table 1, FR-ADM 8000^2 r=10 (outliers in [-1,1]): 28 iterations in 27.42 s "
-                         "(~1.0 it/s) on a 3.2 GHz desktop CPU; not the same workload",
+        "paper_context": ("Appendix, Alg. 4 (FixedRankOptFull): Q-linear convergence to the TSVD; the paper "
+                          "prints no timing for this shape") if tsvd else
+                         ("Table 1, FR-ADM 8000^2 r=10 (outliers in [-1,1]): 28 iterations in 27.42 s "
+                          "(~1.0 it/s) on a 3.2 GHz desktop CPU; not the same workload"),
     }
     print(json.dumps(out), flush=True)
 

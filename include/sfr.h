@@ -66,8 +66,9 @@ typedef struct {
     int32_t max_iter;        /* iteration cap, default 300 */
     int32_t fixed_iters;     /* > 0: run exactly this many iterations, no tolerance test */
     int32_t nystrom_l;       /* > 0: FR-Nys handle with l sampled rows/columns (Alg. 3) */
-    int32_t profile;         /* nonzero: time every general sweep launch with HIP events on
-                                the solve stream and report the mean in sfr_info.sweep_ms */
+    int32_t profile;         /* nonzero: time every general sweep launch with HIP start/stop
+                                events bound to its dispatch and report the mean in
+                                sfr_info.sweep_ms (the events add a few us per launch) */
     double mu_left;          /* FR-Nys: initial penalty of the m x l sub-solve (> 0) */
     double mu_top;           /* FR-Nys: initial penalty of the l x n sub-solve (> 0) */
 } sfr_options;
@@ -78,7 +79,8 @@ typedef struct {
     int32_t iters_top;       /* FR-Nys: iterations of the l x n block; else 0 */
     int32_t converged;       /* 1 if the tolerance was met (or fixed_iters ran) */
     int32_t reserved0;
-    double rel_residual;     /* ||M - L - S||_F / ||M||_F after the last iteration */
+    double rel_residual;     /* ||M - L - S||_F / ||M||_F after the last iteration
+                                (sfr_tsvd: ||B_k - B_{k-1}||_F / ||B_k||_F) */
     double min_eig_B;        /* smallest eigenvalue of the returned B */
     double mu_final;         /* penalty used by the last iteration */
     double sweep_ms;         /* profile != 0: mean duration of the fused sweep kernel over the
@@ -130,6 +132,29 @@ sfr_status sfr_solve(sfr_handle h, const void* M, int64_t ldm, void* U, double* 
  */
 sfr_status sfr_solve_nys(sfr_handle h, const void* M, int64_t ldm, const int64_t* perm, void* U, double* B,
                          void* V, void* S, int64_t lds, sfr_info* info, void* hip_stream);
+
+/*
+ * FixedRankOptFull (Appendix, Alg. 4): FixedRankOptStep (Alg. 2) repeated
+ * on the fixed matrix M from B_0 = I_r, V_0 = I_{n x r}; the iterates
+ * converge Q-linearly, at the rate (sigma_{r+1} / sigma_r)^2, to the rank-r
+ * truncated SVD L = U B V^T of M (Eckart-Young, eq. (5); Appendix,
+ * Theorem 2), provided rank(M V_0) = r.
+ *   Uses an FR-ADM handle (sfr_create): its precision, tol, max_iter and
+ *   fixed_iters apply; lambda and mu are not used.  Alg. 4 leaves
+ *   "converged" unspecified; the reading taken is to stop after the first
+ *   step k with ||B_k - B_{k-1}||_F <= tol ||B_k||_F (fixed_iters > 0:
+ *   after exactly that many steps; max_iter reached: SFR_WARN_MAXITER).
+ *   M (device, m x ldm, ldm >= n): read only.
+ *   U (device, m x r), V (device, n x r), element type of the precision;
+ *   B (device, r x r, double): the factors of the returned L = U B V^T.
+ *   info (host, may be NULL): iters = steps performed, rel_residual = the
+ *   last relative change of B, min_eig_B.
+ * Errors: SFR_ERR_HANDLE (NULL or FR-Nys handle), SFR_ERR_ARG (NULL M/U/B/V,
+ * ldm < n), SFR_ERR_NONFINITE, SFR_ERR_RANK (rank(M V_i) < r), SFR_ERR_DEVICE.
+ * On an error the outputs are left untouched.
+ */
+sfr_status sfr_tsvd(sfr_handle h, const void* M, int64_t ldm, void* U, double* B, void* V, sfr_info* info,
+                    void* hip_stream);
 
 /* Release the handle and its workspace.  NULL is accepted. */
 sfr_status sfr_destroy(sfr_handle h);

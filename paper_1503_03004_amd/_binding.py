@@ -84,6 +84,8 @@ def lib():
         L.sfr_solve_nys.argtypes = [vp, vp, i64, ctypes.POINTER(ctypes.c_int64), vp, vp, vp, vp, i64,
                                     ctypes.POINTER(sfr_info), vp]
         L.sfr_solve_nys.restype = ctypes.c_int
+        L.sfr_tsvd.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.POINTER(sfr_info), vp]
+        L.sfr_tsvd.restype = ctypes.c_int
         L.sfr_destroy.argtypes = [vp]
         L.sfr_destroy.restype = ctypes.c_int
         L.sfr_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
@@ -216,6 +218,19 @@ class Solver:
             raise SFRError(rc, "sfr_solve_nys")
         return U, B, V, S, _info(rc, info)
 
+    def tsvd(self, M, *, out=None, stream=None, raise_on_error=True):
+        """FixedRankOptFull (Alg. 4) on M: the rank-r truncated SVD as
+        (U, B, V, Info); lambda and mu of the handle are not used."""
+        self._check_M(M)
+        U, B, V, _ = self._outputs(M, False, None if out is None else (*out, None))
+        info = sfr_info()
+        rc = lib().sfr_tsvd(self._h, ctypes.c_void_p(M.data_ptr()), M.stride(0), ctypes.c_void_p(U.data_ptr()),
+                            ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(V.data_ptr()), ctypes.byref(info),
+                            _stream_handle(stream))
+        if rc < 0 and raise_on_error:
+            raise SFRError(rc, "sfr_tsvd")
+        return U, B, V, _info(rc, info)
+
     def close(self):
         if self._h and self._h.value:
             lib().sfr_destroy(self._h)
@@ -255,3 +270,12 @@ def solve_nys(M, perm, r, lam, l, mu_left, mu_top, tol=1e-7, **opts):
     with Solver(M.shape[0], M.shape[1], r, lam, 1.0, tol, precision=precision, nystrom_l=l,
                 mu_left=mu_left, mu_top=mu_top, **opts) as s:
         return s.solve_nys(M, perm)
+
+
+def tsvd(M, r, tol=1e-12, **opts):
+    """One-shot FixedRankOptFull (Alg. 4) on a CUDA tensor M: the rank-r
+    truncated SVD as (U, B, V, Info)."""
+    import torch
+    precision = "f64" if M.dtype == torch.float64 else "f32"
+    with Solver(M.shape[0], M.shape[1], r, 1.0, 1.0, tol, precision=precision, **opts) as s:
+        return s.tsvd(M)

@@ -206,7 +206,7 @@ void engine_destroy(Engine& e)
 // batch on the stream; the host waits once, at the end.
 template <typename T>
 sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, int64_t ldm,
-                          const OutputSpec<T>& out, hipStream_t s)
+                          const OutputSpec<T>& out, hipStream_t s, bool tsvd)
 {
     const bool aligned = ((uintptr_t)M % 16 == 0) && (ldm % e.vec == 0) && (e.ne == e.n);
     const T* Mk = M;
@@ -232,6 +232,7 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
     h.M = Mk; h.ldm = ldk;
     h.k = 1; h.done = 0; h.status = 0;
     h.mu = mu0; h.mu_prev = mu0;
+    h.tsvd = tsvd ? 1 : 0;
     for (int i = 0; i < kMaxR; ++i) {
         h.E1[i * kMaxR + i] = 1.0;
         h.E2[i * kMaxR + i] = 1.0;
@@ -245,7 +246,9 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
     HIPCHK(launch_init_q<T>(static_cast<T*>(e.Q[0]), e.ne, e.r, e.R, s));
     if (e.exch_words) HIPCHK(launch_fill_u64(e.exch, e.exch_words, s));
 
-    const int limit = (p.fixed_iters > 0 ? p.fixed_iters : p.max_iter) + 1;
+    // FR-ADM stops at the start of a step (iteration k - 1 converged), Alg. 4
+    // at the end of one, so FR-ADM launches one more sweep/step pair.
+    const int limit = (p.fixed_iters > 0 ? p.fixed_iters : p.max_iter) + (tsvd ? 0 : 1);
     const bool fixed = p.fixed_iters > 0;
     const int batch = 8;
     // Profiling: start/stop events bound to every general sweep (k >= 3).
@@ -273,7 +276,7 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
             a.dy2part = e.dy2part;
             a.exch = e.exch;
             a.m = e.m; a.n = e.ne;
-            a.mode = (k == 1) ? 0 : (k == 2 ? 1 : 2);
+            a.mode = (k == 1 || tsvd) ? 0 : (k == 2 ? 1 : 2);
             a.lpr = e.lpr; a.nv = e.nv; a.W = e.W; a.c = e.c; a.cpx = e.cpx; a.xcd_local = e.xcd_local; a.ncl = e.ncl;
             a.nbands = e.nbands; a.nbl_max = e.nbl_max;
             const bool timed = p.profile && k >= 3;
@@ -360,7 +363,7 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
     e.sweep_ms = 0.0;
     e.sweeps_timed = 0;
     if (p.profile && h.done) {
-        const int last = std::min(h.iters + 1, limit);  // sweeps 3..K+1 did work
+        const int last = std::min(h.iters + (tsvd ? 0 : 1), limit);  // sweeps that did work
         for (int kk = 3; kk <= last; ++kk) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, e.prof_ev[2 * (kk - 3)], e.prof_ev[2 * (kk - 3) + 1]));
@@ -376,9 +379,9 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
 }
 
 template sfr_status engine_iterate<float>(Engine&, const Params&, double, const float*, int64_t,
-                                          const OutputSpec<float>&, hipStream_t);
+                                          const OutputSpec<float>&, hipStream_t, bool);
 template sfr_status engine_iterate<double>(Engine&, const Params&, double, const double*, int64_t,
-                                           const OutputSpec<double>&, hipStream_t);
+                                           const OutputSpec<double>&, hipStream_t, bool);
 
 }  // namespace sfr
 
@@ -524,6 +527,33 @@ sfr_status sfr_solve(sfr_handle h, const void* M, int64_t ldm, void* U, double* 
         o.M = static_cast<const float*>(M); o.ldm = ldm; o.S = static_cast<float*>(S); o.lds = lds;
         o.min_eig = true;
         st = engine_iterate<float>(e, h->prm, h->prm.mu0, static_cast<const float*>(M), ldm, o, s);
+    }
+    if (st < 0) {
+        if (info) memset(info, 0, sizeof(*info));
+        return st;
+    }
+    return fill_info(e, info, st);
+}
+
+sfr_status sfr_tsvd(sfr_handle h, const void* M, int64_t ldm, void* U, double* B, void* V, sfr_info* info,
+                    void* hip_stream)
+{
+    if (!h || h->magic != 0x53465221u || h->nys) return SFR_ERR_HANDLE;
+    if (!M || !U || !B || !V) return SFR_ERR_ARG;
+    if (ldm < h->n) return SFR_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Engine& e = h->main;
+    sfr_status st;
+    if (h->f64) {
+        OutputSpec<double> o;
+        o.U = static_cast<double*>(U); o.B = B; o.V = static_cast<double*>(V);
+        o.min_eig = true;
+        st = engine_iterate<double>(e, h->prm, h->prm.mu0, static_cast<const double*>(M), ldm, o, s, true);
+    } else {
+        OutputSpec<float> o;
+        o.U = static_cast<float*>(U); o.B = B; o.V = static_cast<float*>(V);
+        o.min_eig = true;
+        st = engine_iterate<float>(e, h->prm, h->prm.mu0, static_cast<const float*>(M), ldm, o, s, true);
     }
     if (st < 0) {
         if (info) memset(info, 0, sizeof(*info));

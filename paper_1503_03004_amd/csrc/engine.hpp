@@ -96,8 +96,9 @@ sfr_status engine_create(Engine& e, int m, int n, int r, bool f64, int hist_len)
 void engine_destroy(Engine& e);
 bool dev_alloc(std::vector<void*>& list, size_t& bytes, void** p, size_t sz);
 void free_all(std::vector<void*>& list);
+// tsvd: FixedRankOptFull (Alg. 4) on X = M instead of FR-ADM.
 template <typename T>
 sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, int64_t ldm,
-                          const OutputSpec<T>& out, hipStream_t s);
+                          const OutputSpec<T>& out, hipStream_t s, bool tsvd = false);
 sfr_status nys_setup(sfr_ctx* h);
 }  // namespace sfr

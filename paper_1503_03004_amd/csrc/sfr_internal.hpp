@@ -62,7 +62,7 @@ struct DevState {
     int32_t status;     // kOK or a negative error code, or kWarnMaxIter
     int32_t iters;      // completed iterations once done
     int32_t exch_timeout;  // set if a cluster exchange wait hit its bound
-    int32_t pad0;
+    int32_t tsvd;       // 1: FixedRankOptFull (Alg. 4) on X = M, stop on the change of B
     double nrmM;        // ||M||_F
     double mu;          // mu_k used by the next sweep's L-step input
     double mu_prev;     // mu_{k-1} used by the next sweep's S/Y step

@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
             return;
         }
         if (tid == 0) st->nrmM = nrm;
-    } else {
+    } else if (!st->tsvd) {
         const double res = sqrt(total) / (st->mu_prev * st->nrmM);
         const int kdone = k - 1;
         bool stop = false;
@@ -201,6 +201,37 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
         st->TVf[g] = (float)tv;
         st->E1[g] = Ev[i * LDP + j];
         st->E2[g] = Ev2[i * LDP + j];
+    }
+    if (st->tsvd) {
+        // Alg. 4 stops after this step once B has settled:
+        // ||B_k - B_{k-1}||_F <= tol ||B_k||_F (or after fixed_iters steps)
+        double d2 = 0.0, n2 = 0.0;
+#pragma unroll
+        for (int u = 0; u < NPL; ++u) {
+            const int e = lane + 64 * u;
+            const int i = e / R, j = e % R;
+            if (e < R * R && i < r && j < r) {
+                const double bn = T2[i * LDP + j], bo = Bm[i * LDP + j];
+                d2 = fma(bn - bo, bn - bo, d2);
+                n2 = fma(bn, bn, n2);
+            }
+        }
+        d2 = wave_sum(d2);
+        n2 = wave_sum(n2);
+        const double res = sqrt(d2 / n2);
+        bool stop = false;
+        int32_t status = kOK;
+        if (!isfinite(res)) { stop = true; status = kErrNonFinite; }
+        else if (st->fixed_iters > 0) { stop = k >= st->fixed_iters; }
+        else if (res <= st->tol) { stop = true; }
+        else if (k >= st->max_iter) { stop = true; status = kWarnMaxIter; }
+        if (lane == 0) {
+            a.res_hist[k - 1] = res;
+            st->res = res;
+            st->k = k + 1;
+            if (stop) { st->status = status; st->iters = k; st->done = 1; }
+        }
+        return;
     }
     if (lane == 0) {
         const double mu = st->mu;

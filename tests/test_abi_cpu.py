@@ -21,7 +21,7 @@ def declared():
 
 def test_header_declares_the_entry_points():
     names = declared()
-    for want in ("sfr_create", "sfr_solve", "sfr_solve_nys", "sfr_destroy", "sfr_status_string",
+    for want in ("sfr_create", "sfr_solve", "sfr_solve_nys", "sfr_tsvd", "sfr_destroy", "sfr_status_string",
                  "sfr_version", "sfr_workspace_bytes"):
         assert want in names
 
@@ -113,6 +113,7 @@ def test_null_handle_paths():
     assert L.sfr_solve(None, None, 0, None, None, None, None, 0, ctypes.byref(info), None) == B.SFR_ERR_HANDLE
     assert L.sfr_solve_nys(None, None, 0, None, None, None, None, None, 0, ctypes.byref(info),
                            None) == B.SFR_ERR_HANDLE
+    assert L.sfr_tsvd(None, None, 0, None, None, None, ctypes.byref(info), None) == B.SFR_ERR_HANDLE
     assert L.sfr_destroy(None) == B.SFR_OK
     b = ctypes.c_uint64(0)
     assert L.sfr_workspace_bytes(None, ctypes.byref(b)) == B.SFR_ERR_HANDLE
