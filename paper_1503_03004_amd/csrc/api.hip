@@ -46,10 +46,11 @@ template <typename T>
 static size_t lds_of(int R, int lpr, int W, int c) { return sweep_lds_bytes_c<T>(R, lpr, W, c); }
 
 // Pick the row-pass shape (lanes per row, vectors per lane), the cluster
-// size and the grid for an m x ne problem.
-static sfr_status configure(Engine& e)
+// size and the grid of one sweep kernel for an m x ne problem.
+static sfr_status configure_sweep(const Engine& e, SweepCfg& sc, bool mfma)
 {
     const int vec = e.vec;
+    sc.mfma = mfma ? 1 : 0;
     const int nvec = (e.ne + vec - 1) / vec;
     const size_t ldsmax = 160 * 1024;
     int best_lpr = -1, best_nv = -1;
@@ -68,29 +69,33 @@ static sfr_status configure(Engine& e)
             best_waste = waste; best_lpr = lpr; best_nv = nv;
         }
     }
-    if (best_lpr > 0) {
-        e.lpr = best_lpr; e.nv = best_nv; e.c = 1;
+    if (sc.mfma) {
+        sc.lpr = 64; sc.nv = 4; sc.c = (e.ne + 1023) / 1024;
+    } else if (best_lpr > 0) {
+        sc.lpr = best_lpr; sc.nv = best_nv; sc.c = 1;
     } else {
         // wide rows: one row per wave, slices of W columns exchanged in clusters
-        e.lpr = 64;
-        e.nv = 4;
-        while (e.nv > 1 && 64 * vec * e.nv > wmax) --e.nv;
+        sc.lpr = 64;
+        sc.nv = 4;
+        while (sc.nv > 1 && 64 * vec * sc.nv > wmax) --sc.nv;
         for (;;) {
-            const int W = 64 * vec * e.nv;
+            const int W = 64 * vec * sc.nv;
             const size_t L = e.f64 ? lds_of<double>(e.R, 64, W, 2) : lds_of<float>(e.R, 64, W, 2);
-            if (L <= ldsmax || e.nv == 1) break;
-            --e.nv;
+            if (L <= ldsmax || sc.nv == 1) break;
+            --sc.nv;
         }
-        e.c = (e.ne + 64 * vec * e.nv - 1) / (64 * vec * e.nv);
+        sc.c = (e.ne + 64 * vec * sc.nv - 1) / (64 * vec * sc.nv);
     }
-    e.W = e.lpr * vec * e.nv;
+    sc.W = sc.lpr * vec * sc.nv;
     const int tpb = e.f64 ? sweep_threads<double>(e.R) : sweep_threads<float>(e.R);
-    e.H = (tpb / 64) * (64 / e.lpr);
-    e.nbands = (e.m + e.H - 1) / e.H;
-    e.lds = e.f64 ? lds_of<double>(e.R, e.lpr, e.W, e.c) : lds_of<float>(e.R, e.lpr, e.W, e.c);
+    sc.H = sc.mfma ? 16 : (tpb / 64) * (64 / sc.lpr);
+    sc.nbands = (e.m + sc.H - 1) / sc.H;
+    if (sc.mfma) sc.lds = sweep_mfma_lds_bytes(e.R);
+    else sc.lds = e.f64 ? lds_of<double>(e.R, sc.lpr, sc.W, sc.c) : lds_of<float>(e.R, sc.lpr, sc.W, sc.c);
 
     int bpc = 0;
-    hipError_t herr = e.f64 ? sweep_prepare<double>(e.R, e.lds, &bpc) : sweep_prepare<float>(e.R, e.lds, &bpc);
+    hipError_t herr = sc.mfma ? sweep_mfma_prepare(e.R, sc.lds, &bpc)
+                              : (e.f64 ? sweep_prepare<double>(e.R, sc.lds, &bpc) : sweep_prepare<float>(e.R, sc.lds, &bpc));
     if (herr != hipSuccess || bpc < 1) return SFR_ERR_DEVICE;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SFR_ERR_DEVICE;
@@ -99,26 +104,54 @@ static sfr_status configure(Engine& e)
     const int maxres = cus * bpc;
     // Every member of a cluster must be resident at once (they wait on each
     // other), so the grid never exceeds what the device holds in one wave.
-    if (e.c == 1) {
-        int want = std::min(((e.nbands + kXCD - 1) / kXCD) * kXCD, (maxres / kXCD) * kXCD);
+    if (sc.c == 1) {
+        int want = std::min(((sc.nbands + kXCD - 1) / kXCD) * kXCD, (maxres / kXCD) * kXCD);
         if (want < kXCD) want = kXCD;
-        e.cpx = want / kXCD;
-        e.xcd_local = 1;
-        e.ncl = kXCD * e.cpx;
-    } else if (kXCD * e.c <= maxres) {
-        e.cpx = std::max(1, maxres / (kXCD * e.c));
-        while (e.cpx > 1 && kXCD * (e.cpx - 1) >= e.nbands) --e.cpx;  // no more clusters than bands
-        e.xcd_local = 1;
-        e.ncl = kXCD * e.cpx;
-    } else if (e.c <= maxres) {
-        e.xcd_local = 0;
-        e.cpx = 0;
-        e.ncl = std::max(1, std::min(maxres / e.c, e.nbands));
+        sc.cpx = want / kXCD;
+        sc.xcd_local = 1;
+        sc.ncl = kXCD * sc.cpx;
+    } else if (kXCD * sc.c <= maxres) {
+        sc.cpx = std::max(1, maxres / (kXCD * sc.c));
+        while (sc.cpx > 1 && kXCD * (sc.cpx - 1) >= sc.nbands) --sc.cpx;  // no more clusters than bands
+        sc.xcd_local = 1;
+        sc.ncl = kXCD * sc.cpx;
+    } else if (sc.c <= maxres) {
+        sc.xcd_local = 0;
+        sc.cpx = 0;
+        sc.ncl = std::max(1, std::min(maxres / sc.c, sc.nbands));
     } else {
         return SFR_ERR_ARG;  // more column slices than resident workgroups
     }
-    e.grid = e.ncl * e.c;
-    e.nbl_max = (e.nbands + e.ncl - 1) / e.ncl;
+    sc.grid = sc.ncl * sc.c;
+    sc.nbl_max = (sc.nbands + sc.ncl - 1) / sc.ncl;
+    return SFR_OK;
+}
+
+static size_t exch_words_of(const Engine& e, const SweepCfg& sc)
+{
+    return (sc.c > 1) ? (size_t)sc.ncl * kExchSlots * sc.c * sc.H * e.R * (e.esz / 4) : 0;
+}
+
+// The matrix-core sweep takes FP32 problems with R <= 12 and at least one
+// full 1024-column slice.  It runs the sweeps of mode 0 (X = M: the first
+// FR-ADM sweep and every Alg. 4 step), where it is faster; the FR-ADM general
+// sweeps stay on the vector kernel, whose row-contiguous loads stream better.
+// SFR_SWEEP=vector or =mfma in the environment forces one kernel for every
+// sweep (both are exact; used to test both).
+static sfr_status configure(Engine& e)
+{
+    const char* pick = getenv("SFR_SWEEP");
+    const bool want_vector = pick && strcmp(pick, "vector") == 0;
+    const bool want_mfma = pick && strcmp(pick, "mfma") == 0;
+    const bool mfma_ok = !e.f64 && sweep_mfma_supported(e.R) && e.ne >= 1024;
+    sfr_status st = configure_sweep(e, e.cfg[0], mfma_ok && want_mfma);
+    if (st != SFR_OK) return st;
+    st = configure_sweep(e, e.cfg[1], mfma_ok && !want_vector);
+    if (st != SFR_OK) return st;
+    e.tag_stride = std::max(e.cfg[0].nbl_max, e.cfg[1].nbl_max);
+    e.max_grid = std::max(e.cfg[0].grid, e.cfg[1].grid);
+    e.max_ncl = std::max(e.cfg[0].ncl, e.cfg[1].ncl);
+    e.exch_words = std::max(exch_words_of(e, e.cfg[0]), exch_words_of(e, e.cfg[1]));
     // Gram launch shape
     const int rows = kTPB / e.R;
     e.nqb = std::max(1, std::min((e.ne + rows - 1) / rows, kMaxGramPartials));
@@ -146,9 +179,8 @@ sfr_status engine_create(Engine& e, int m, int n, int r, bool f64, int hist_len)
     for (int b = 0; b < 2 && ok; ++b) ok = dev_alloc(e.allocs, e.bytes, &e.Y[b], mn * e.esz);
     for (int b = 0; b < 2 && ok; ++b) ok = dev_alloc(e.allocs, e.bytes, &e.P[b], (size_t)e.m * e.R * e.esz);
     for (int b = 0; b < 2 && ok; ++b) ok = dev_alloc(e.allocs, e.bytes, &e.Q[b], (size_t)e.ne * e.R * e.esz);
-    if (ok) ok = dev_alloc(e.allocs, e.bytes, &e.Qpart, (size_t)e.ncl * e.ne * e.R * e.esz);
-    if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.dy2part, sizeof(double) * (size_t)e.grid);
-    e.exch_words = (e.c > 1) ? (size_t)e.ncl * kExchSlots * e.c * e.H * e.R * (e.esz / 4) : 0;
+    if (ok) ok = dev_alloc(e.allocs, e.bytes, &e.Qpart, (size_t)e.max_ncl * e.ne * e.R * e.esz);
+    if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.dy2part, sizeof(double) * (size_t)e.max_grid);
     if (ok && e.exch_words) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.exch, 8 * e.exch_words);
     if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.GQpart, sizeof(double) * (size_t)e.nqb * e.E);
     if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.GPpart, sizeof(double) * (size_t)e.npb * e.E);
@@ -277,25 +309,32 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
             a.exch = e.exch;
             a.m = e.m; a.n = e.ne;
             a.mode = (k == 1 || tsvd) ? 0 : (k == 2 ? 1 : 2);
-            a.lpr = e.lpr; a.nv = e.nv; a.W = e.W; a.c = e.c; a.cpx = e.cpx; a.xcd_local = e.xcd_local; a.ncl = e.ncl;
-            a.nbands = e.nbands; a.nbl_max = e.nbl_max;
+            const SweepCfg& sc = e.cfg[a.mode == 0 ? 1 : 0];
+            a.lpr = sc.lpr; a.nv = sc.nv; a.W = sc.W; a.c = sc.c; a.cpx = sc.cpx; a.xcd_local = sc.xcd_local;
+            a.ncl = sc.ncl; a.nbands = sc.nbands; a.nbl_max = e.tag_stride;
             const bool timed = p.profile && k >= 3;
-            HIPCHK(launch_sweep<T>(a, e.R, e.grid, e.lds, s, timed ? e.prof_ev[2 * (k - 3)] : nullptr,
-                                   timed ? e.prof_ev[2 * (k - 3) + 1] : nullptr));
+            hipEvent_t ev0 = timed ? e.prof_ev[2 * (k - 3)] : nullptr;
+            hipEvent_t ev1 = timed ? e.prof_ev[2 * (k - 3) + 1] : nullptr;
+            if constexpr (sizeof(T) == 4) {
+                if (sc.mfma) HIPCHK(launch_sweep_mfma(a, e.R, sc.grid, sc.lds, s, ev0, ev1));
+                else HIPCHK(launch_sweep<T>(a, e.R, sc.grid, sc.lds, s, ev0, ev1));
+            } else {
+                HIPCHK(launch_sweep<T>(a, e.R, sc.grid, sc.lds, s, ev0, ev1));
+            }
             GramArgs<T> g;
             g.st = e.st;
             g.Qpart = static_cast<const T*>(e.Qpart);
             g.Qnext = static_cast<T*>(e.Q[k & 1]);
             g.Pnext = static_cast<const T*>(e.P[k & 1]);
             g.GQpart = e.GQpart; g.GPpart = e.GPpart;
-            g.m = e.m; g.n = e.ne; g.ncl = e.ncl;
+            g.m = e.m; g.n = e.ne; g.ncl = sc.ncl;
             g.rows_q = e.rows_q; g.nqb = e.nqb; g.rows_p = e.rows_p; g.npb = e.npb;
             HIPCHK(launch_gram<T>(g, e.R, s));
             StepArgs sa;
             sa.st = e.st;
             sa.GPpart = e.GPpart; sa.npb = e.npb;
             sa.GQpart = e.GQpart; sa.nqb = e.nqb;
-            sa.dy2part = e.dy2part; sa.ndy = e.grid;
+            sa.dy2part = e.dy2part; sa.ndy = sc.grid;
             sa.res_hist = e.res_hist;
             HIPCHK(launch_step(sa, e.R, s));
         }

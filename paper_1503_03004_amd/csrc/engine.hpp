@@ -8,14 +8,24 @@
 
 namespace sfr {
 
+// Launch shape of one sweep kernel on the engine's problem.
+struct SweepCfg {
+    int mfma = 0;   // 1: the matrix-core sweep (sweep_mfma.hip), else sweep.hip
+    int lpr = 64, nv = 1, W = 0, c = 1, cpx = 1, xcd_local = 1, ncl = 8, grid = 8, H = 4, nbands = 0, nbl_max = 0;
+    size_t lds = 0;
+};
+
 struct Engine {
     int m = 0, n = 0, ne = 0, r = 0, R = 0;   // ne: column count the kernels see (padded)
     bool f64 = false;
     size_t esz = 4;
     int vec = 4;
-    // launch configuration
-    int lpr = 64, nv = 1, W = 0, c = 1, cpx = 1, xcd_local = 1, ncl = 8, grid = 8, H = 4, nbands = 0, nbl_max = 0;
-    size_t lds = 0;
+    // launch configurations: cfg[0] for the FR-ADM general sweeps (modes 1,
+    // 2), cfg[1] for the sweeps on X = M (mode 0); tag_stride, the larger
+    // band count per cluster, keeps exchange tags increasing across sweeps
+    SweepCfg cfg[2];
+    int tag_stride = 0;
+    int max_grid = 0, max_ncl = 0;
     int rows_q = 0, nqb = 0, rows_p = 0, npb = 0, E = 0;
     int hist_len = 0;
     // workspace

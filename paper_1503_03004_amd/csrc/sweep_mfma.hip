@@ -1,0 +1,378 @@
+// The fused FR-ADM sweep on the matrix cores (FP32, R <= 12, wide rows).
+//
+// Same iteration as sweep.hip (Alg. 1 with the Alg. 2 L-step; one pass
+// over M and Y per iteration), with its three contractions on
+// v_mfma_f32_16x16x4_f32 (exact FP32 products, FP32 accumulation):
+//   l  (16 rows x 16 columns)  = A_band (16 x R) . V_tile^T        K = R
+//   p  (16 rows x R)          += X_tile (16 x 16) . V_tile (16 x R) K = 16 columns
+//   Q  (16 columns x R)       += X_tile^T (16 x 16) . P_band        K = 16 rows
+// Lane layout of the instruction (lane l, lr = l % 16, lq = l / 16): it
+// supplies A[lr][lq] and B[lq][lr] and receives D[4 lq + e][lr], e = 0..3.
+// With l computed as D[column][row], lane l holds row lr, columns
+// 4 lq .. 4 lq + 3 of a 16 x 16 tile: exactly one 16-byte vector of M and
+// Y.  The p product takes that lane's own x values as its B operand; the Q
+// product needs x transposed, which goes through a wave-private LDS tile.
+//
+// Work decomposition
+//   * A band is 16 rows.  A workgroup is 8 wavefronts; wave w owns the 128
+//     columns [w 128, (w+1) 128) of its member's 1024-column slice, as
+//     eight 16-column tiles, for every band.  The V values a lane needs for
+//     its tiles (56 of them for R <= 12) are loaded into registers once.
+//   * Row pass: per tile, l (ceil(R/4) MFMA), the S/dual step, Y_k, x, the
+//     wave's p partial (4 MFMA); each 16-byte load of the next band goes
+//     out as soon as its tile has been consumed.
+//   * The 8 waves' p partials are added in LDS; with c > 1 members of a
+//     cluster exchange them through tagged words (exchange.hpp), one band
+//     behind the row pass.
+//   * Column pass: Q += X^T P from the wave's own x tile (4 MFMA per tile);
+//     Q stays in registers until the end.
+// HBM traffic per element: read M, read Y_{k-1}, write Y_k.
+#include "exchange.hpp"
+#include "sfr_internal.hpp"
+
+#include <hip/hip_ext.h>
+
+namespace sfr {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMW8 = 8;                  // wavefronts per workgroup
+constexpr int kMTPB = 64 * kMW8;         // threads per workgroup
+constexpr int kMTiles = 8;               // 16-column tiles per wavefront
+constexpr int kMCols = 16 * kMTiles;     // columns per wavefront
+constexpr int kMWidth = kMW8 * kMCols;   // columns per member slice (1024)
+constexpr int kMH = 16;                  // rows per band
+constexpr int kMXP = kMCols + 16;        // LDS pitch of a row of a wave's x tile (floats)
+
+struct MfmaLds {
+    size_t tu, xw, pw, ps, red, total;
+};
+
+__host__ __device__ inline MfmaLds mfma_lds(int R)
+{
+    auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
+    MfmaLds L;
+    size_t o = 0;
+    L.tu = o; o = al(o + sizeof(float) * R * R);
+    // x tiles: per wave, two band buffers of 16 rows; the V slice is staged
+    // here during the prologue (kMWidth x R floats fit)
+    L.xw = o; o = al(o + sizeof(float) * (size_t)kMW8 * 2 * kMH * kMXP);
+    L.pw = o; o = al(o + sizeof(float) * kMW8 * 256);
+    L.ps = o; o = al(o + sizeof(float) * 2 * 256);
+    L.red = o; o = al(o + sizeof(double) * kMW8);
+    L.total = o;
+    return L;
+}
+
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int R>
+__global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a)
+{
+    static_assert(R <= 16, "matrix-core sweep: ranks fill at most one 16-wide operand");
+    constexpr int S1 = (R + 3) / 4;   // K steps of the l product
+    DevState* st = const_cast<DevState*>(a.st);
+    if (st->done) return;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int c = a.c;
+    const int g = blockIdx.x;
+    int q, cl;
+    if (a.xcd_local) {
+        const int xcd = g % kXCD, loc = g / kXCD;
+        q = loc % c;
+        cl = xcd * a.cpx + loc / c;
+    } else {
+        q = g % c;
+        cl = g / c;
+    }
+    const int c0 = q * kMWidth;                 // first column of this member
+    const int cw = c0 + wave * kMCols;          // first column of this wave
+    const int m = a.m, n = a.n;
+    const int64_t ldm = st->ldm, ldy = a.ldy;
+    const float* __restrict__ M = static_cast<const float*>(st->M);
+    const int mode = a.mode;
+    const float lam = (float)st->lambda;
+    const float mu_prev = (float)st->mu_prev;
+    const float imu_prev = (mode != 0) ? (float)(1.0 / st->mu_prev) : 0.f;
+    const float imu_cur = (float)(1.0 / st->mu);
+    const uint32_t kiter = (uint32_t)st->k;
+    int32_t* tflag = &st->exch_timeout;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    const MfmaLds L = mfma_lds(R);
+    float* TUs = reinterpret_cast<float*>(smem + L.tu);
+    float* Xall = reinterpret_cast<float*>(smem + L.xw);
+    float* Xw = Xall + (size_t)wave * 2 * kMH * kMXP;
+    float* PW = reinterpret_cast<float*>(smem + L.pw);
+    float* PS = reinterpret_cast<float*>(smem + L.ps);
+    double* red = reinterpret_cast<double*>(smem + L.red);
+
+    // ---- prologue: TU, and V_j = Q_j TV for this member's columns
+    float* Vst = Xall;   // kMWidth x R, row j - c0
+    {
+        const float* tu = st->TUf;
+        const float* tv = st->TVf;
+        for (int e = tid; e < R * R; e += kMTPB) TUs[e] = tu[(e / R) * kMaxR + e % R];
+        for (int jj = tid; jj < kMWidth; jj += kMTPB) {
+            const int j = c0 + jj;
+            float qrow[R];
+#pragma unroll
+            for (int t = 0; t < R; ++t) qrow[t] = (j < n) ? a.Qprev[(int64_t)j * R + t] : 0.f;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                float s = 0.f;
+#pragma unroll
+                for (int t = 0; t < R; ++t) s = fmaf(qrow[t], tv[t * kMaxR + k], s);
+                Vst[(size_t)jj * R + k] = s;
+            }
+        }
+    }
+    __syncthreads();
+    // this lane's V operands: l product A[lr][lq] = V[col 16t + lr][rank 4s + lq],
+    // p product A[lr][lq] = V[col 16t + 4 lq + u][rank lr]
+    float va1[kMTiles][S1], va2[kMTiles][4];
+#pragma unroll
+    for (int t = 0; t < kMTiles; ++t) {
+        const int jl = wave * kMCols + 16 * t;
+#pragma unroll
+        for (int s = 0; s < S1; ++s) {
+            const int k = 4 * s + lq;
+            va1[t][s] = (k < R) ? Vst[(size_t)(jl + lr) * R + k] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) va2[t][u] = (lr < R) ? Vst[(size_t)(jl + 4 * lq + u) * R + lr] : 0.f;
+    }
+    __syncthreads();   // the staging area becomes the x tiles
+
+    const int nbands = a.nbands, ncl = a.ncl;
+    const int nbl = (cl < nbands) ? (nbands - 1 - cl) / ncl + 1 : 0;
+    double acc2 = 0.0;
+    f32x4 qacc[kMTiles];
+#pragma unroll
+    for (int t = 0; t < kMTiles; ++t) qacc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // the row-pass operands of one band: tile t of row lr, columns
+    // cw + 16 t + 4 lq .. + 3 (out-of-range vectors read a valid dummy
+    // address and are zeroed at use)
+    float4 mv[kMTiles], yv[kMTiles];
+    auto issue_load = [&](int jb, int t) {
+        const int i = (cl + jb * ncl) * kMH + lr;
+        const int col = cw + 16 * t + 4 * lq;
+        const bool ok = (i < m) && (col < n);
+        mv[t] = *reinterpret_cast<const float4*>(M + (ok ? (int64_t)i * ldm + col : 0));
+        if (mode == 2) yv[t] = *reinterpret_cast<const float4*>(a.Yprev + (ok ? (int64_t)i * ldy + col : 0));
+    };
+    if (nbl > 0) {
+#pragma unroll
+        for (int t = 0; t < kMTiles; ++t) issue_load(0, t);
+    }
+
+    for (int j = 0; j <= nbl; ++j) {
+        const int buf = j & 1;
+        if (j < nbl) {
+            // ---------------- row pass over band j ----------------
+            const int i = (cl + j * ncl) * kMH + lr;
+            const bool row_ok = i < m;
+            float aop[S1];
+            if (mode != 0) {
+                float prow[R];
+#pragma unroll
+                for (int t = 0; t < R; ++t) prow[t] = row_ok ? a.Pprev[(int64_t)i * R + t] : 0.f;
+#pragma unroll
+                for (int s = 0; s < S1; ++s) {
+                    const int k = 4 * s + lq;
+                    float v = 0.f;
+                    if (k < R) {
+#pragma unroll
+                        for (int t = 0; t < R; ++t) v = fmaf(prow[t], TUs[t * R + k], v);
+                    }
+                    aop[s] = v;
+                }
+            }
+            f32x4 pacc = {0.f, 0.f, 0.f, 0.f};
+            float rowacc = 0.f;
+#pragma unroll
+            for (int t = 0; t < kMTiles; ++t) {
+                const int col = cw + 16 * t + 4 * lq;
+                const bool ok = row_ok && (col < n);
+                float x[4];
+                const float mvv[4] = {mv[t].x, mv[t].y, mv[t].z, mv[t].w};
+                if (mode == 0) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        x[e] = ok ? mvv[e] : 0.f;
+                        rowacc = fmaf(x[e], x[e], rowacc);
+                    }
+                } else {
+                    f32x4 lv = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int s = 0; s < S1; ++s) lv = mfma4(va1[t][s], aop[s], lv);
+                    float ypv[4] = {0.f, 0.f, 0.f, 0.f};
+                    if (mode == 2) {
+                        ypv[0] = yv[t].x; ypv[1] = yv[t].y; ypv[2] = yv[t].z; ypv[3] = yv[t].w;
+                    }
+                    float yn[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float yp = ok ? ypv[e] : 0.f;
+                        const float mm = ok ? mvv[e] : 0.f;
+                        const float l = lv[e];
+                        const float Rr = mm - l + yp * imu_prev;
+                        const float y = fminf(fmaxf(mu_prev * Rr, -lam), lam);
+                        const float dy = y - yp;
+                        rowacc = fmaf(dy, dy, rowacc);
+                        x[e] = ok ? (l + dy * imu_prev + y * imu_cur) : 0.f;
+                        yn[e] = y;
+                    }
+                    if (ok) *reinterpret_cast<float4*>(a.Ynext + (int64_t)i * ldy + col) = make_float4(yn[0], yn[1], yn[2], yn[3]);
+                }
+                *reinterpret_cast<float4*>(Xw + ((size_t)buf * kMH + lr) * kMXP + 16 * t + 4 * lq) =
+                    make_float4(x[0], x[1], x[2], x[3]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) pacc = mfma4(va2[t][u], x[u], pacc);
+                if (j + 1 < nbl) issue_load(j + 1, t);
+            }
+            acc2 += (double)rowacc;
+            // lane l holds p[row lr][rank 4 lq + e] of this wave's 128 columns
+#pragma unroll
+            for (int e = 0; e < 4; ++e) PW[wave * 256 + lr * 16 + 4 * lq + e] = pacc[e];
+        }
+        __syncthreads();
+        const int prow_ = tid >> 4, prk = tid & 15;   // (row, rank) owned by threads 0..255
+        if (j < nbl && tid < 256) {
+            float s = 0.f;
+#pragma unroll
+            for (int w = 0; w < kMW8; ++w) s += PW[w * 256 + tid];
+            if (c == 1) {
+                PS[buf * 256 + tid] = s;
+            } else if (prk < R) {
+                const uint32_t tag = kiter * (uint32_t)a.nbl_max + (uint32_t)j + 1u;
+                const int slot = j & (kExchSlots - 1);
+                publish<float>(a.exch + ((((size_t)cl * kExchSlots + slot) * c + q) * kMH + prow_) * R + prk, s, tag);
+            }
+        }
+        if (j >= 1 && c > 1 && tid < 256) {
+            // gather the members' partials of band j - 1, added in member order
+            const int jb = j - 1;
+            const uint32_t tag = kiter * (uint32_t)a.nbl_max + (uint32_t)jb + 1u;
+            const int slot = jb & (kExchSlots - 1);
+            float s = 0.f;
+            if (prk < R) {
+                const unsigned long long* base = a.exch + (((size_t)cl * kExchSlots + slot) * c) * kMH * R;
+                for (int qq = 0; qq < c; ++qq) {
+                    const unsigned long long* src = base + ((size_t)qq * kMH + prow_) * R + prk;
+                    unsigned long long w = peek_word(src);
+                    if ((uint32_t)(w >> 32) != tag) w = spin_word(src, tag, tflag);
+                    s += __uint_as_float((uint32_t)(w & 0xffffffffull));
+                }
+            }
+            PS[(jb & 1) * 256 + tid] = s;
+        }
+        __syncthreads();
+        if (j >= 1) {
+            // ---------------- column pass over band j - 1 ----------------
+            const int jb = j - 1;
+            const int bb = jb & 1;
+            const int i0 = (cl + jb * ncl) * kMH;
+            if (q == 0) {
+                for (int e = tid; e < kMH * R; e += kMTPB) {
+                    const int hh = e / R, k = e % R;
+                    if (i0 + hh < m) a.Pnext[(int64_t)(i0 + hh) * R + k] = PS[bb * 256 + hh * 16 + k];
+                }
+            }
+            // B operand: p[row 4 s + lq][rank lr]; A operand: x[row 4 s + lq][column 16 t + lr]
+            float b3[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) b3[s] = PS[bb * 256 + (4 * s + lq) * 16 + lr];
+#pragma unroll
+            for (int t = 0; t < kMTiles; ++t) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float a3 = Xw[((size_t)bb * kMH + 4 * s + lq) * kMXP + 16 * t + lr];
+                    qacc[t] = mfma4(a3, b3[s], qacc[t]);
+                }
+            }
+        }
+    }
+
+    // ---------------- write the column partials of this cluster -----------
+    // lane l holds Q[column 16 t + 4 lq + e][rank lr]
+    if (lr < R) {
+#pragma unroll
+        for (int t = 0; t < kMTiles; ++t) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int col = cw + 16 * t + 4 * lq + e;
+                if (col < n) a.Qpart[((size_t)cl * n + col) * R + lr] = qacc[t][e];
+            }
+        }
+    }
+    // ---------------- ||Y_k - Y_{k-1}||^2 (or ||M||^2) partial ------------
+    for (int off = 32; off > 0; off >>= 1) acc2 += __shfl_xor(acc2, off, 64);
+    if (lane == 0) red[wave] = acc2;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kMW8; ++w) t += red[w];
+        a.dy2part[g] = t;
+    }
+}
+
+#define SFR_MFMA_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12)
+
+bool sweep_mfma_supported(int R)
+{
+    switch (R) {
+#define CASE(r) case r: return true;
+        SFR_MFMA_R_LIST(CASE)
+#undef CASE
+    default: return false;
+    }
+}
+
+size_t sweep_mfma_lds_bytes(int R) { return mfma_lds(R).total; }
+
+static void* sweep_mfma_fn(int R)
+{
+    switch (R) {
+#define CASE(r) case r: return reinterpret_cast<void*>(&sweep_mfma_kernel<r>);
+        SFR_MFMA_R_LIST(CASE)
+#undef CASE
+    default: return nullptr;
+    }
+}
+
+hipError_t sweep_mfma_prepare(int R, size_t lds, int* blocks_per_cu)
+{
+    void* fn = sweep_mfma_fn(R);
+    if (!fn) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kMTPB, lds);
+}
+
+hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int grid, size_t lds, hipStream_t s,
+                             hipEvent_t ev0, hipEvent_t ev1)
+{
+    switch (R) {
+#define CASE(r)                                                                                         \
+    case r:                                                                                             \
+        if (ev0)                                                                                        \
+            hipExtLaunchKernelGGL((sweep_mfma_kernel<r>), dim3(grid), dim3(kMTPB), (uint32_t)lds, s, ev0, \
+                                  ev1, 0u, a);                                                          \
+        else                                                                                            \
+            hipLaunchKernelGGL((sweep_mfma_kernel<r>), dim3(grid), dim3(kMTPB), lds, s, a);            \
+        return hipGetLastError();
+        SFR_MFMA_R_LIST(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace sfr

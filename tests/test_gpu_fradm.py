@@ -228,3 +228,14 @@ def test_full_size_8000_fp32_first_iterations():
     assert rel(Lg, Lo) <= 1e-5
     assert rel(g["S"][rows], o["S"][rows]) <= 1e-5
     assert rel(g["S"], o["S"]) <= 1e-5
+
+
+@pytest.mark.parametrize("sweep", ["mfma", "vector"])
+@pytest.mark.parametrize("m,n,r", [(300, 1100, 10), (1037, 2048, 4), (64, 5000, 12), (2100, 1024, 1)])
+def test_both_fp32_sweeps(monkeypatch, sweep, m, n, r):
+    """FP32, R <= 12, n >= 1024: the matrix-core sweep and the vector sweep
+    (SFR_SWEEP selects) each against the oracle."""
+    monkeypatch.setenv("SFR_SWEEP", sweep)
+    inst = workloads.planted(m, n, r, seed=m + n + r, frac=0.08, kind="uniform", scale=30.0, dtype=np.float32)
+    g, o = case(inst, "f32", 4)
+    compare(g, o, "f32", f"{sweep} {m}x{n} r={r}")
