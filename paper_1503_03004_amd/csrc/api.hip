@@ -70,7 +70,8 @@ static sfr_status configure_sweep(const Engine& e, SweepCfg& sc, bool mfma)
         }
     }
     if (sc.mfma) {
-        sc.lpr = 64; sc.nv = 4; sc.c = (e.ne + 1023) / 1024;
+        const int mw = sweep_mfma_width(e.R);
+        sc.lpr = 64; sc.nv = 4; sc.c = (e.ne + mw - 1) / mw;
     } else if (best_lpr > 0) {
         sc.lpr = best_lpr; sc.nv = best_nv; sc.c = 1;
     } else {
@@ -86,7 +87,7 @@ static sfr_status configure_sweep(const Engine& e, SweepCfg& sc, bool mfma)
         }
         sc.c = (e.ne + 64 * vec * sc.nv - 1) / (64 * vec * sc.nv);
     }
-    sc.W = sc.lpr * vec * sc.nv;
+    sc.W = sc.mfma ? sweep_mfma_width(e.R) : sc.lpr * vec * sc.nv;
     const int tpb = e.f64 ? sweep_threads<double>(e.R) : sweep_threads<float>(e.R);
     sc.H = sc.mfma ? 16 : (tpb / 64) * (64 / sc.lpr);
     sc.nbands = (e.m + sc.H - 1) / sc.H;
@@ -132,9 +133,10 @@ static size_t exch_words_of(const Engine& e, const SweepCfg& sc)
     return (sc.c > 1) ? (size_t)sc.ncl * kExchSlots * sc.c * sc.H * e.R * (e.esz / 4) : 0;
 }
 
-// The matrix-core sweep takes FP32 problems with R <= 12 and at least one
-// full 1024-column slice.  It runs the sweeps of mode 0 (X = M: the first
-// FR-ADM sweep and every Alg. 4 step), where it is faster; the FR-ADM general
+// The matrix-core sweep takes FP32 problems with at least one full member
+// slice (1024 columns for R <= 12, 512 above).  It runs the sweeps of mode 0
+// (X = M: the first FR-ADM sweep and every Alg. 4 step) and, for R >= 16,
+// every sweep: there it is the faster kernel.  For R <= 12 the FR-ADM general
 // sweeps stay on the vector kernel, whose row-contiguous loads stream better.
 // SFR_SWEEP=vector or =mfma in the environment forces one kernel for every
 // sweep (both are exact; used to test both).
@@ -143,8 +145,9 @@ static sfr_status configure(Engine& e)
     const char* pick = getenv("SFR_SWEEP");
     const bool want_vector = pick && strcmp(pick, "vector") == 0;
     const bool want_mfma = pick && strcmp(pick, "mfma") == 0;
-    const bool mfma_ok = !e.f64 && sweep_mfma_supported(e.R) && e.ne >= 1024;
-    sfr_status st = configure_sweep(e, e.cfg[0], mfma_ok && want_mfma);
+    const bool mfma_ok = !e.f64 && sweep_mfma_supported(e.R) && e.ne >= sweep_mfma_width(e.R);
+    const bool general_mfma = mfma_ok && !want_vector && (want_mfma || e.R >= 16);
+    sfr_status st = configure_sweep(e, e.cfg[0], general_mfma);
     if (st != SFR_OK) return st;
     st = configure_sweep(e, e.cfg[1], mfma_ok && !want_vector);
     if (st != SFR_OK) return st;

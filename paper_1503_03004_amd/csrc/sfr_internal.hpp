@@ -187,10 +187,11 @@ constexpr int kExchSlots = 8;
 template <typename T>
 hipError_t sweep_prepare(int R, size_t lds, int* blocks_per_cu);
 
-// Matrix-core sweep (sweep_mfma.hip): FP32, R <= 12, 1024-column member
-// slices, 16-row bands, 512-thread workgroups.
+// Matrix-core sweep (sweep_mfma.hip): FP32, R <= 32, member slices of
+// sweep_mfma_width(R) columns, 16-row bands, 512-thread workgroups.
 bool sweep_mfma_supported(int R);
 size_t sweep_mfma_lds_bytes(int R);
+int sweep_mfma_width(int R);
 hipError_t sweep_mfma_prepare(int R, size_t lds, int* blocks_per_cu);
 hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int grid, size_t lds, hipStream_t s,
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

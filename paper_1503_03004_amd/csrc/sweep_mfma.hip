@@ -1,4 +1,4 @@
-// The fused FR-ADM sweep on the matrix cores (FP32, R <= 12, wide rows).
+// The fused FR-ADM sweep on the matrix cores (FP32, R <= 32, wide rows).
 //
 // Same iteration as sweep.hip (Alg. 1 with the Alg. 2 L-step; one pass
 // over M and Y per iteration), with its three contractions on
@@ -14,10 +14,11 @@
 // product needs x transposed, which goes through a wave-private LDS tile.
 //
 // Work decomposition
-//   * A band is 16 rows.  A workgroup is 8 wavefronts; wave w owns the 128
-//     columns [w 128, (w+1) 128) of its member's 1024-column slice, as
-//     eight 16-column tiles, for every band.  The V values a lane needs for
-//     its tiles (56 of them for R <= 12) are loaded into registers once.
+//   * A band is 16 rows.  A workgroup is 8 wavefronts; wave w owns 16 TPW
+//     consecutive columns of its member's slice (TPW = 8 tiles of 16 columns
+//     for R <= 12, 4 above), for every band.  Ranks are padded to 16-wide
+//     tiles (one, or two for R > 16).  The V values a lane needs for its
+//     tiles are loaded into registers once.
 //   * Row pass: per tile, l (ceil(R/4) MFMA), the S/dual step, Y_k, x, the
 //     wave's p partial (4 MFMA); each 16-byte load of the next band goes
 //     out as soon as its tile has been consumed.
@@ -38,27 +39,38 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMW8 = 8;                  // wavefronts per workgroup
 constexpr int kMTPB = 64 * kMW8;         // threads per workgroup
-constexpr int kMTiles = 8;               // 16-column tiles per wavefront
-constexpr int kMCols = 16 * kMTiles;     // columns per wavefront
-constexpr int kMWidth = kMW8 * kMCols;   // columns per member slice (1024)
 constexpr int kMH = 16;                  // rows per band
-constexpr int kMXP = kMCols + 16;        // LDS pitch of a row of a wave's x tile (floats)
+
+// Compile-time shape for rank bucket R.
+template <int R>
+struct MShape {
+    static constexpr int RT = (R + 15) / 16;          // 16-wide rank tiles (p, Q)
+    static constexpr int S1 = (R + 3) / 4;            // K steps of the l product
+    static constexpr int TPW = (R <= 12) ? 8 : 4;     // 16-column tiles per wavefront
+    static constexpr int COLS = 16 * TPW;             // columns per wavefront
+    static constexpr int WIDTH = kMW8 * COLS;         // columns per member slice
+    static constexpr int XP = COLS + 16;              // LDS pitch of a row of a wave's x tile (floats)
+};
 
 struct MfmaLds {
     size_t tu, xw, pw, ps, red, total;
 };
 
-__host__ __device__ inline MfmaLds mfma_lds(int R)
+template <int R>
+__host__ __device__ inline MfmaLds mfma_lds()
 {
+    using S = MShape<R>;
     auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
     MfmaLds L;
     size_t o = 0;
     L.tu = o; o = al(o + sizeof(float) * R * R);
-    // x tiles: per wave, two band buffers of 16 rows; the V slice is staged
-    // here during the prologue (kMWidth x R floats fit)
-    L.xw = o; o = al(o + sizeof(float) * (size_t)kMW8 * 2 * kMH * kMXP);
-    L.pw = o; o = al(o + sizeof(float) * kMW8 * 256);
-    L.ps = o; o = al(o + sizeof(float) * 2 * 256);
+    // x tiles: per wave, two band buffers of 16 rows; the V slice
+    // (WIDTH x R floats) is staged here during the prologue
+    size_t xw = sizeof(float) * (size_t)kMW8 * 2 * kMH * S::XP;
+    const size_t vst = sizeof(float) * (size_t)S::WIDTH * R;
+    L.xw = o; o = al(o + (xw > vst ? xw : vst));
+    L.pw = o; o = al(o + sizeof(float) * kMW8 * 256 * S::RT);
+    L.ps = o; o = al(o + sizeof(float) * 2 * 256 * S::RT);
     L.red = o; o = al(o + sizeof(double) * kMW8);
     L.total = o;
     return L;
@@ -72,8 +84,10 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c)
 template <int R>
 __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a)
 {
-    static_assert(R <= 16, "matrix-core sweep: ranks fill at most one 16-wide operand");
-    constexpr int S1 = (R + 3) / 4;   // K steps of the l product
+    using SH = MShape<R>;
+    constexpr int RT = SH::RT, S1 = SH::S1, kMTiles = SH::TPW, kMCols = SH::COLS;
+    constexpr int kMWidth = SH::WIDTH, kMXP = SH::XP;
+    constexpr int PT = 256 * RT;      // (row, padded rank) entries of one band
     DevState* st = const_cast<DevState*>(a.st);
     if (st->done) return;
 
@@ -104,7 +118,7 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
     int32_t* tflag = &st->exch_timeout;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    const MfmaLds L = mfma_lds(R);
+    const MfmaLds L = mfma_lds<R>();
     float* TUs = reinterpret_cast<float*>(smem + L.tu);
     float* Xall = reinterpret_cast<float*>(smem + L.xw);
     float* Xw = Xall + (size_t)wave * 2 * kMH * kMXP;
@@ -134,8 +148,8 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
     }
     __syncthreads();
     // this lane's V operands: l product A[lr][lq] = V[col 16t + lr][rank 4s + lq],
-    // p product A[lr][lq] = V[col 16t + 4 lq + u][rank lr]
-    float va1[kMTiles][S1], va2[kMTiles][4];
+    // p product A[lr][lq] = V[col 16t + 4 lq + u][rank 16 rt + lr]
+    float va1[kMTiles][S1], va2[kMTiles][RT][4];
 #pragma unroll
     for (int t = 0; t < kMTiles; ++t) {
         const int jl = wave * kMCols + 16 * t;
@@ -145,16 +159,22 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
             va1[t][s] = (k < R) ? Vst[(size_t)(jl + lr) * R + k] : 0.f;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) va2[t][u] = (lr < R) ? Vst[(size_t)(jl + 4 * lq + u) * R + lr] : 0.f;
+        for (int rt = 0; rt < RT; ++rt) {
+            const int k = 16 * rt + lr;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) va2[t][rt][u] = (k < R) ? Vst[(size_t)(jl + 4 * lq + u) * R + k] : 0.f;
+        }
     }
     __syncthreads();   // the staging area becomes the x tiles
 
     const int nbands = a.nbands, ncl = a.ncl;
     const int nbl = (cl < nbands) ? (nbands - 1 - cl) / ncl + 1 : 0;
     double acc2 = 0.0;
-    f32x4 qacc[kMTiles];
+    f32x4 qacc[kMTiles][RT];
 #pragma unroll
-    for (int t = 0; t < kMTiles; ++t) qacc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < kMTiles; ++t)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) qacc[t][rt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // the row-pass operands of one band: tile t of row lr, columns
     // cw + 16 t + 4 lq .. + 3 (out-of-range vectors read a valid dummy
@@ -194,7 +214,9 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
                     aop[s] = v;
                 }
             }
-            f32x4 pacc = {0.f, 0.f, 0.f, 0.f};
+            f32x4 pacc[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) pacc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
             float rowacc = 0.f;
 #pragma unroll
             for (int t = 0; t < kMTiles; ++t) {
@@ -234,29 +256,34 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
                 *reinterpret_cast<float4*>(Xw + ((size_t)buf * kMH + lr) * kMXP + 16 * t + 4 * lq) =
                     make_float4(x[0], x[1], x[2], x[3]);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) pacc = mfma4(va2[t][u], x[u], pacc);
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) pacc[rt] = mfma4(va2[t][rt][u], x[u], pacc[rt]);
                 if (j + 1 < nbl) issue_load(j + 1, t);
             }
             acc2 += (double)rowacc;
-            // lane l holds p[row lr][rank 4 lq + e] of this wave's 128 columns
+            // lane l holds p[row lr][rank 16 rt + 4 lq + e] of this wave's columns
 #pragma unroll
-            for (int e = 0; e < 4; ++e) PW[wave * 256 + lr * 16 + 4 * lq + e] = pacc[e];
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) PW[wave * PT + rt * 256 + lr * 16 + 4 * lq + e] = pacc[rt][e];
         }
         __syncthreads();
-        const int prow_ = tid >> 4, prk = tid & 15;   // (row, rank) owned by threads 0..255
-        if (j < nbl && tid < 256) {
+        // (row, rank) owned by threads 0..PT-1: tid = 256 rt + 16 row + rank % 16
+        const int prow_ = (tid & 255) >> 4, prk = 16 * (tid >> 8) + (tid & 15);
+        if (j < nbl && tid < PT) {
             float s = 0.f;
 #pragma unroll
-            for (int w = 0; w < kMW8; ++w) s += PW[w * 256 + tid];
+            for (int w = 0; w < kMW8; ++w) s += PW[w * PT + tid];
             if (c == 1) {
-                PS[buf * 256 + tid] = s;
+                PS[buf * PT + tid] = s;
             } else if (prk < R) {
                 const uint32_t tag = kiter * (uint32_t)a.nbl_max + (uint32_t)j + 1u;
                 const int slot = j & (kExchSlots - 1);
                 publish<float>(a.exch + ((((size_t)cl * kExchSlots + slot) * c + q) * kMH + prow_) * R + prk, s, tag);
             }
         }
-        if (j >= 1 && c > 1 && tid < 256) {
+        if (j >= 1 && c > 1 && tid < PT) {
             // gather the members' partials of band j - 1, added in member order
             const int jb = j - 1;
             const uint32_t tag = kiter * (uint32_t)a.nbl_max + (uint32_t)jb + 1u;
@@ -271,7 +298,7 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
                     s += __uint_as_float((uint32_t)(w & 0xffffffffull));
                 }
             }
-            PS[(jb & 1) * 256 + tid] = s;
+            PS[(jb & 1) * PT + tid] = s;
         }
         __syncthreads();
         if (j >= 1) {
@@ -282,33 +309,41 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
             if (q == 0) {
                 for (int e = tid; e < kMH * R; e += kMTPB) {
                     const int hh = e / R, k = e % R;
-                    if (i0 + hh < m) a.Pnext[(int64_t)(i0 + hh) * R + k] = PS[bb * 256 + hh * 16 + k];
+                    if (i0 + hh < m)
+                        a.Pnext[(int64_t)(i0 + hh) * R + k] = PS[bb * PT + (k >> 4) * 256 + hh * 16 + (k & 15)];
                 }
             }
-            // B operand: p[row 4 s + lq][rank lr]; A operand: x[row 4 s + lq][column 16 t + lr]
-            float b3[4];
+            // B operand: p[row 4 s + lq][rank 16 rt + lr]; A operand: x[row 4 s + lq][column 16 t + lr]
+            float b3[RT][4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) b3[s] = PS[bb * 256 + (4 * s + lq) * 16 + lr];
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) b3[rt][s] = PS[bb * PT + rt * 256 + (4 * s + lq) * 16 + lr];
 #pragma unroll
             for (int t = 0; t < kMTiles; ++t) {
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const float a3 = Xw[((size_t)bb * kMH + 4 * s + lq) * kMXP + 16 * t + lr];
-                    qacc[t] = mfma4(a3, b3[s], qacc[t]);
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt) qacc[t][rt] = mfma4(a3, b3[rt][s], qacc[t][rt]);
                 }
             }
         }
     }
 
     // ---------------- write the column partials of this cluster -----------
-    // lane l holds Q[column 16 t + 4 lq + e][rank lr]
-    if (lr < R) {
+    // lane l holds Q[column 16 t + 4 lq + e][rank 16 rt + lr]
 #pragma unroll
-        for (int t = 0; t < kMTiles; ++t) {
+    for (int rt = 0; rt < RT; ++rt) {
+        const int k = 16 * rt + lr;
+        if (k < R) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int col = cw + 16 * t + 4 * lq + e;
-                if (col < n) a.Qpart[((size_t)cl * n + col) * R + lr] = qacc[t][e];
+            for (int t = 0; t < kMTiles; ++t) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int col = cw + 16 * t + 4 * lq + e;
+                    if (col < n) a.Qpart[((size_t)cl * n + col) * R + k] = qacc[t][rt][e];
+                }
             }
         }
     }
@@ -324,7 +359,7 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
     }
 }
 
-#define SFR_MFMA_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12)
+#define SFR_MFMA_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
 
 bool sweep_mfma_supported(int R)
 {
@@ -336,7 +371,25 @@ bool sweep_mfma_supported(int R)
     }
 }
 
-size_t sweep_mfma_lds_bytes(int R) { return mfma_lds(R).total; }
+size_t sweep_mfma_lds_bytes(int R)
+{
+    switch (R) {
+#define CASE(r) case r: return mfma_lds<r>().total;
+        SFR_MFMA_R_LIST(CASE)
+#undef CASE
+    default: return 0;
+    }
+}
+
+int sweep_mfma_width(int R)
+{
+    switch (R) {
+#define CASE(r) case r: return MShape<r>::WIDTH;
+        SFR_MFMA_R_LIST(CASE)
+#undef CASE
+    default: return 0;
+    }
+}
 
 static void* sweep_mfma_fn(int R)
 {

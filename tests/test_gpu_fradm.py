@@ -231,10 +231,11 @@ def test_full_size_8000_fp32_first_iterations():
 
 
 @pytest.mark.parametrize("sweep", ["mfma", "vector"])
-@pytest.mark.parametrize("m,n,r", [(300, 1100, 10), (1037, 2048, 4), (64, 5000, 12), (2100, 1024, 1)])
+@pytest.mark.parametrize("m,n,r", [(300, 1100, 10), (1037, 2048, 4), (64, 5000, 12), (2100, 1024, 1),
+                                   (300, 1100, 16), (200, 2000, 20), (1037, 700, 24), (150, 1500, 32)])
 def test_both_fp32_sweeps(monkeypatch, sweep, m, n, r):
-    """FP32, R <= 12, n >= 1024: the matrix-core sweep and the vector sweep
-    (SFR_SWEEP selects) each against the oracle."""
+    """FP32 shapes that both sweeps take: the matrix-core sweep and the vector
+    sweep (SFR_SWEEP selects) each against the oracle."""
     monkeypatch.setenv("SFR_SWEEP", sweep)
     inst = workloads.planted(m, n, r, seed=m + n + r, frac=0.08, kind="uniform", scale=30.0, dtype=np.float32)
     g, o = case(inst, "f32", 4)
