@@ -16,11 +16,10 @@
 namespace sfr {
 
 // Workgroup size of the step kernel: the partial sums are latency bound,
-// so as many threads as the r x r algebra's register use allows (the
-// algebra itself runs on wave 0 only; 1024 threads leave 128 registers a
-// lane, which buckets 5 and 12 and up exceed).
+// so as many threads as the r x r algebra's register use allows (1024
+// threads leave 128 registers a lane, which buckets 5 and 12 and up exceed).
 template <int R>
-constexpr int step_tpb() { return (R <= 10 && R != 5) ? 1024 : (R <= 20 ? 512 : 256); }
+constexpr int step_tpb() { return (R <= 10 && R != 5) ? 1024 : 512; }
 
 // The r x r matrices are held R x R (R the rank bucket, a compile-time
 // size) with an identity block on the padded indices: every product and
@@ -37,6 +36,9 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
         return;
     }
     constexpr int TPB = step_tpb<R>();
+    // threads of the r x r algebra: one wavefront up to R = 12, the whole
+    // workgroup above (each Jacobi round then has >= 128 2x2 blocks)
+    constexpr int NT = (R >= 16) ? TPB : 64;
     constexpr int E = R * (R + 1) / 2;
     __shared__ double Gp[R * LDP], Gq[R * LDP], Bm[R * LDP], C1[R * LDP];
     __shared__ double C2[R * LDP], Km[R * LDP], T1[R * LDP], T2[R * LDP];
@@ -57,12 +59,12 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
     // Every load below is unconditional (indices are clamped into range and
     // the surplus masked afterwards), so each thread has all of its loads in
     // flight at once: one memory round trip for the lot.
-    constexpr int NPL = (R * R + 63) / 64;
+    constexpr int NPL = (R * R + NT - 1) / NT;
     double rb[NPL], re1[NPL], re2[NPL];
-    if (wave == 0) {
+    if (tid < NT) {
 #pragma unroll
         for (int u = 0; u < NPL; ++u) {
-            const int e = min(lane + 64 * u, R * R - 1);
+            const int e = min(tid + NT * u, R * R - 1);
             const int i = e / R, j = e % R;
             rb[u] = st->B[i * kMaxR + j];
             re1[u] = st->E1[i * kMaxR + j];
@@ -138,12 +140,12 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
         tri[g][e] = s;
     }
     __syncthreads();
-    if (wave != 0) return;
+    if (tid >= NT) return;
 
-    // ---- the r x r algebra: one wavefront from here on
+    // ---- the r x r algebra: NT threads from here on
 #pragma unroll
     for (int u = 0; u < NPL; ++u) {
-        const int e = lane + 64 * u;
+        const int e = tid + NT * u;
         if (e >= R * R) break;
         const int i = e / R, j = e % R;
         const int x = i < j ? i : j, y = i < j ? j : i;
@@ -155,38 +157,38 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
         Ev[i * LDP + j] = re1[u];
         Ev2[i * LDP + j] = re2[u];
     }
-    wsync();
+    lsync<NT>();
 
     // ---- U-step: C1 = (B0 G_P B0)^{-1/2}
-    wmm<R>(T1, Bm, Gp);
-    wmm<R>(T2, T1, Bm);
-    wsym<R>(T2);
-    const bool ok1 = winv_sqrt<R>(C1, T2, Ev, T1, r, cs, wbuf);
+    wmm<R, NT>(T1, Bm, Gp);
+    wmm<R, NT>(T2, T1, Bm);
+    wsym<R, NT>(T2);
+    const bool ok1 = winv_sqrt<R, NT>(C1, T2, Ev, T1, r, cs, wbuf);
     // ---- V-step: K = B0 C1 B0, C2 = (K G_Q K)^{-1/2}
-    wmm<R>(T1, Bm, C1);          // T1 = B0 C1  (the U transform)
-    wmm<R>(Km, T1, Bm);
-    wsym<R>(Km);
-    wmm<R>(T2, Km, Gq);
-    wmm<R>(C2, T2, Km);          // K G_Q K (C2 as scratch)
-    wsym<R>(C2);
-    wcopy<R>(T2, C2);
-    const bool ok2 = winv_sqrt<R>(C2, T2, Ev2, Gp, r, cs, wbuf);   // Gp free now
+    wmm<R, NT>(T1, Bm, C1);          // T1 = B0 C1  (the U transform)
+    wmm<R, NT>(Km, T1, Bm);
+    wsym<R, NT>(Km);
+    wmm<R, NT>(T2, Km, Gq);
+    wmm<R, NT>(C2, T2, Km);          // K G_Q K (C2 as scratch)
+    wsym<R, NT>(C2);
+    wcopy<R, NT>(T2, C2);
+    const bool ok2 = winv_sqrt<R, NT>(C2, T2, Ev2, Gp, r, cs, wbuf);   // Gp free now
     if (!ok1 || !ok2) {
-        if (lane == 0) { st->status = kErrRank; st->iters = k - 1; st->done = 1; }
+        if (tid == 0) { st->status = kErrRank; st->iters = k - 1; st->done = 1; }
         return;
     }
     // TV = K C2 -> Gp ; B = Sym(C1 B0 G_Q K C2) -> T2 ; TU = B0 C1 B -> Km
-    wmm<R>(Gp, Km, C2);               // TV
-    wmm<R>(T2, C1, Bm);               // C1 B0
-    wmm<R>(C2, T2, Gq);               // C1 B0 G_Q
-    wmm<R>(T2, C2, Gp);               // C1 B0 G_Q K C2
-    wsym<R>(T2);                      // new B
-    wmm<R>(Km, T1, T2);               // TU
+    wmm<R, NT>(Gp, Km, C2);               // TV
+    wmm<R, NT>(T2, C1, Bm);               // C1 B0
+    wmm<R, NT>(C2, T2, Gq);               // C1 B0 G_Q
+    wmm<R, NT>(T2, C2, Gp);               // C1 B0 G_Q K C2
+    wsym<R, NT>(T2);                      // new B
+    wmm<R, NT>(Km, T1, T2);               // TU
     // only the R x R block changes; the rest keeps the values set at the
     // start of the solve (zero, identity on the diagonal of B)
 #pragma unroll
     for (int u = 0; u < NPL; ++u) {
-        const int e = lane + 64 * u;
+        const int e = tid + NT * u;
         if (e >= R * R) break;
         const int i = e / R, j = e % R;
         const int g = i * kMaxR + j;
@@ -208,7 +210,7 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
         double d2 = 0.0, n2 = 0.0;
 #pragma unroll
         for (int u = 0; u < NPL; ++u) {
-            const int e = lane + 64 * u;
+            const int e = tid + NT * u;
             const int i = e / R, j = e % R;
             if (e < R * R && i < r && j < r) {
                 const double bn = T2[i * LDP + j], bo = Bm[i * LDP + j];
@@ -218,6 +220,14 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
         }
         d2 = wave_sum(d2);
         n2 = wave_sum(n2);
+        if constexpr (NT > 64) {
+            // red[] (the residual reduction's, free now) holds the wave sums
+            if (lane == 0) { red[wave] = d2; seg[wave] = n2; }
+            __syncthreads();
+            d2 = 0.0; n2 = 0.0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) { d2 += red[w]; n2 += seg[w]; }
+        }
         const double res = sqrt(d2 / n2);
         bool stop = false;
         int32_t status = kOK;
@@ -225,7 +235,7 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
         else if (st->fixed_iters > 0) { stop = k >= st->fixed_iters; }
         else if (res <= st->tol) { stop = true; }
         else if (k >= st->max_iter) { stop = true; status = kWarnMaxIter; }
-        if (lane == 0) {
+        if (tid == 0) {
             a.res_hist[k - 1] = res;
             st->res = res;
             st->k = k + 1;
@@ -233,7 +243,7 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
         }
         return;
     }
-    if (lane == 0) {
+    if (tid == 0) {
         const double mu = st->mu;
         st->mu_prev = mu;
         const double nm = st->rho * mu;

@@ -1,8 +1,10 @@
-// One-wavefront FP64 dense linear algebra on r x r matrices in LDS (r <= 32):
-// products, symmetrisation and a cyclic Jacobi eigendecomposition
-// (Golub & Van Loan, Matrix Computations, Sec. 8.5) with the parallel
-// round-robin ordering.  Every routine is executed by all 64 lanes of one
-// wavefront and orders its LDS phases with wavefront fences only.
+// FP64 dense linear algebra on r x r matrices in LDS (r <= 32): products,
+// symmetrisation and a cyclic Jacobi eigendecomposition (Golub & Van Loan,
+// Matrix Computations, Sec. 8.5) with the parallel round-robin ordering.
+// Every routine is executed by NT threads: one wavefront (NT = 64, the
+// default; LDS phases ordered with wavefront fences) or a whole workgroup of
+// NT threads (phases ordered with workgroup barriers, which every thread of
+// the workgroup must reach).
 #pragma once
 
 #include "sfr_internal.hpp"
@@ -19,6 +21,25 @@ __device__ __forceinline__ void wsync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Ordering and agreement among the NT threads of the algebra.
+template <int NT>
+__device__ __forceinline__ void lsync()
+{
+    if constexpr (NT == 64) wsync();
+    else __syncthreads();
+}
+template <int NT>
+__device__ __forceinline__ bool l_any(bool p)
+{
+    if constexpr (NT == 64) return __any(p);
+    else return __syncthreads_or(p) != 0;
+}
+template <int NT>
+__device__ __forceinline__ int lid()
+{
+    return NT == 64 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -39,13 +60,13 @@ __device__ __forceinline__ double wave_min(double v)
     return v;
 }
 
-// C = A B (r x r, pitch LDP), one wavefront.  C must not alias A or B.
-template <int N>
+// C = A B (r x r, pitch LDP).  C must not alias A or B.
+template <int N, int NT = 64>
 __device__ inline void wmm(double* C, const double* A, const double* B)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lid<NT>();
 #pragma unroll
-    for (int e0 = 0; e0 < N * N; e0 += 64) {
+    for (int e0 = 0; e0 < N * N; e0 += NT) {
         const int e = e0 + lane;
         if (e >= N * N) break;
         const int i = e / N, j = e % N;
@@ -54,16 +75,16 @@ __device__ inline void wmm(double* C, const double* A, const double* B)
         for (int t = 0; t < N; ++t) s = fma(A[i * LDP + t], B[t * LDP + j], s);
         C[i * LDP + j] = s;
     }
-    wsync();
+    lsync<NT>();
 }
 
 // C = A^T B
-template <int N>
+template <int N, int NT = 64>
 __device__ inline void wmtm(double* C, const double* A, const double* B)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lid<NT>();
 #pragma unroll
-    for (int e0 = 0; e0 < N * N; e0 += 64) {
+    for (int e0 = 0; e0 < N * N; e0 += NT) {
         const int e = e0 + lane;
         if (e >= N * N) break;
         const int i = e / N, j = e % N;
@@ -72,14 +93,14 @@ __device__ inline void wmtm(double* C, const double* A, const double* B)
         for (int t = 0; t < N; ++t) s = fma(A[t * LDP + i], B[t * LDP + j], s);
         C[i * LDP + j] = s;
     }
-    wsync();
+    lsync<NT>();
 }
 
-template <int N>
+template <int N, int NT = 64>
 __device__ inline void wsym(double* A)
 {
-    const int lane = threadIdx.x & 63;
-    for (int e = lane; e < N * N; e += 64) {
+    const int lane = lid<NT>();
+    for (int e = lane; e < N * N; e += NT) {
         const int i = e / N, j = e % N;
         if (i < j) {
             const double s = 0.5 * (A[i * LDP + j] + A[j * LDP + i]);
@@ -87,15 +108,15 @@ __device__ inline void wsym(double* A)
             A[j * LDP + i] = s;
         }
     }
-    wsync();
+    lsync<NT>();
 }
 
-template <int N>
+template <int N, int NT = 64>
 __device__ inline void wcopy(double* D, const double* A)
 {
-    const int lane = threadIdx.x & 63;
-    for (int e = lane; e < N * N; e += 64) D[(e / N) * LDP + e % N] = A[(e / N) * LDP + e % N];
-    wsync();
+    const int lane = lid<NT>();
+    for (int e = lane; e < N * N; e += NT) D[(e / N) * LDP + e % N] = A[(e / N) * LDP + e % N];
+    lsync<NT>();
 }
 
 // Round-robin pairing: position 0 holds player 0, positions 1..N-1 rotate.
@@ -126,10 +147,10 @@ __device__ inline int rr_player(int pos, int round, int N)
 // rows, the columns of one pair) applies . J.  Pair indices are recomputed
 // from the round number, so the only data passed between the phases is
 // (c, s).  Squares of entries above ~1e150 would overflow d^2 + 4 a_pq^2.
-template <int r>
+template <int r, int NT = 64>
 __device__ inline void wjacobi(double* A, double* E, double* cs, double tau = 0.0)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lid<NT>();
     if (r == 1) return;
     constexpr int N = r + (r & 1);
     constexpr int npair = N / 2;
@@ -138,7 +159,7 @@ __device__ inline void wjacobi(double* A, double* E, double* cs, double tau = 0.
     constexpr int nitem = nblk + nrp * npair;     // + 2 x 2 blocks of E
     for (int sweep = 0; sweep < 16; ++sweep) {
         int big = 0, far = 0;
-        for (int e = lane; e < r * r; e += 64) {
+        for (int e = lane; e < r * r; e += NT) {
             const int i = e / r, j = e % r;
             if (i < j) {
                 const double apq = A[i * LDP + j];
@@ -147,7 +168,9 @@ __device__ inline void wjacobi(double* A, double* E, double* cs, double tau = 0.
                 if (!(fabs(apq) <= tau * fmin(fabs(app), fabs(aqq)))) far = 1;
             }
         }
-        if (!__any(big) || !__any(far)) break;
+        const bool any_big = l_any<NT>(big != 0);
+        const bool any_far = l_any<NT>(far != 0);
+        if (!any_big || !any_far) break;
         for (int round = 0; round < N - 1; ++round) {
             if (lane < npair) {
                 int p = rr_player(lane, round, N);
@@ -173,8 +196,8 @@ __device__ inline void wjacobi(double* A, double* E, double* cs, double tau = 0.
                 cs[2 * lane] = c;
                 cs[2 * lane + 1] = s;
             }
-            wsync();
-            for (int it = lane; it < nitem; it += 64) {
+            lsync<NT>();
+            for (int it = lane; it < nitem; it += NT) {
                 if (it < nblk) {
                     const int bi = it / npair, bj = it % npair;
                     if (bi == bj) continue;
@@ -214,7 +237,7 @@ __device__ inline void wjacobi(double* A, double* E, double* cs, double tau = 0.
                     }
                 }
             }
-            wsync();
+            lsync<NT>();
         }
     }
 }
@@ -234,41 +257,41 @@ constexpr double kDkTau = 4e-6;
 // to an identity padding block).  Returns false if A is not positive
 // definite to working precision (the Stiefel projector of eq. (7) needs
 // rank r).
-template <int N>
+template <int N, int NT = 64>
 __device__ inline bool winv_sqrt(double* Out, double* A, double* E, double* T, int nreal, double* cs, double* wbuf)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lid<NT>();
     // A <- E^T A E
-    wmm<N>(T, A, E);
-    wmtm<N>(A, E, T);
-    wsym<N>(A);
-    wjacobi<N>(A, E, cs, kDkTau);
+    wmm<N, NT>(T, A, E);
+    wmtm<N, NT>(A, E, T);
+    wsym<N, NT>(A);
+    wjacobi<N, NT>(A, E, cs, kDkTau);
     // A = D + F, D = diag(d), F off-diagonal with |F_ij| <= kDkTau min(d_i, d_j)
     // (or at the strict Jacobi test).  x = sqrt(d) -> wbuf, y = 1 / x -> cs.
+    // Every thread reads the whole diagonal for the positivity test.
     double wmax = -INFINITY, wmin = INFINITY;
-    for (int i = lane; i < N; i += 64) {
+    for (int i = 0; i < nreal; ++i) {
         const double d = A[i * LDP + i];
-        if (i < nreal) {
-            wmax = fmax(wmax, d);
-            wmin = fmin(wmin, d);
-        }
+        wmax = fmax(wmax, d);
+        wmin = fmin(wmin, d);
+    }
+    for (int i = lane; i < N; i += NT) {
+        const double d = A[i * LDP + i];
         const double x = d > 0.0 ? sqrt(d) : 0.0;
         wbuf[i] = x;
         cs[i] = d > 0.0 ? 1.0 / x : 0.0;
     }
-    wmax = wave_max(wmax);
-    wmin = wave_min(wmin);
-    wsync();
+    lsync<NT>();
     const bool ok = (wmax > 0.0) && (wmin > (double)nreal * DBL_EPSILON * wmax) && isfinite(wmax);
     // W_ij = 1 / (x_i + x_j) -> Out, Phi = F o W -> T
-    for (int e = lane; e < N * N; e += 64) {
+    for (int e = lane; e < N * N; e += NT) {
         const int i = e / N, j = e % N;
         const double den = wbuf[i] + wbuf[j];
         const double w = den > 0.0 ? 1.0 / den : 0.0;
         Out[i * LDP + j] = w;
         T[i * LDP + j] = (i == j) ? 0.0 : A[i * LDP + j] * w;
     }
-    wsync();
+    lsync<NT>();
     // Z = f(D + F) to second order, f(t) = t^{-1/2}:
     //   Z_ij = delta_ij y_i + F_ij f[d_i, d_j] + sum_k F_ik F_kj f[d_i, d_k, d_j],
     //   f[d_i, d_j] = -W_ij y_i y_j,
@@ -276,7 +299,7 @@ __device__ inline bool winv_sqrt(double* Out, double* A, double* E, double* T, i
     // so the sum is W_ij y_i y_j ((x_i + x_j) (Phi Y Phi)_ij + (Phi Phi)_ij).
     // The dropped terms are O(|F|^3) relative.  Z -> A.
 #pragma unroll
-    for (int e0 = 0; e0 < N * N; e0 += 64) {
+    for (int e0 = 0; e0 < N * N; e0 += NT) {
         const int e = e0 + lane;
         if (e >= N * N) break;
         const int i = e / N, j = e % N;
@@ -293,11 +316,11 @@ __device__ inline bool winv_sqrt(double* Out, double* A, double* E, double* T, i
         if (i == j) z += cs[i];
         A[i * LDP + j] = z;
     }
-    wsync();
+    lsync<NT>();
     // Out = E Z E^T
-    wmm<N>(T, E, A);
+    wmm<N, NT>(T, E, A);
 #pragma unroll
-    for (int e0 = 0; e0 < N * N; e0 += 64) {
+    for (int e0 = 0; e0 < N * N; e0 += NT) {
         const int e = e0 + lane;
         if (e >= N * N) break;
         const int i = e / N, j = e % N;
@@ -306,7 +329,7 @@ __device__ inline bool winv_sqrt(double* Out, double* A, double* E, double* T, i
         for (int k = 0; k < N; ++k) s = fma(T[i * LDP + k], E[j * LDP + k], s);
         Out[i * LDP + j] = s;
     }
-    wsync();
+    lsync<NT>();
     return ok;
 }
 
