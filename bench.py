@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 def sweep_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hip", "sfr_internal.hpp"):
+    for f in ("sweep.hip", "sweep_mfma.hip", "exchange.hpp", "sfr_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1503_03004_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
