@@ -116,7 +116,7 @@ sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double l
  *     S_{k+1} = P_ST_{lambda/mu_k}(M - L_{k+1} + Y_k/mu_k) of the last
  *     iteration.
  *   info (host, may be NULL): report.
- * Errors: SFR_ERR_HANDLE (NULL or FR-Nys handle), SFR_ERR_ARG (NULL M/U/B/V,
+ * Errors: SFR_ERR_HANDLE (NULL, FR-Nys or batched handle), SFR_ERR_ARG (NULL M/U/B/V,
  * ldm < n, lds < n), SFR_ERR_NONFINITE, SFR_ERR_RANK, SFR_ERR_DEVICE.
  */
 sfr_status sfr_solve(sfr_handle h, const void* M, int64_t ldm, void* U, double* B, void* V, void* S,
@@ -149,12 +149,67 @@ sfr_status sfr_solve_nys(sfr_handle h, const void* M, int64_t ldm, const int64_t
  *   B (device, r x r, double): the factors of the returned L = U B V^T.
  *   info (host, may be NULL): iters = steps performed, rel_residual = the
  *   last relative change of B, min_eig_B.
- * Errors: SFR_ERR_HANDLE (NULL or FR-Nys handle), SFR_ERR_ARG (NULL M/U/B/V,
+ * Errors: SFR_ERR_HANDLE (NULL, FR-Nys or batched handle), SFR_ERR_ARG (NULL M/U/B/V,
  * ldm < n), SFR_ERR_NONFINITE, SFR_ERR_RANK (rank(M V_i) < r), SFR_ERR_DEVICE.
  * On an error the outputs are left untouched.
  */
 sfr_status sfr_tsvd(sfr_handle h, const void* M, int64_t ldm, void* U, double* B, void* V, sfr_info* info,
                     void* hip_stream);
+
+/*
+ * Batched FR-ADM (Alg. 1 with Alg. 2) for many small independent problems.
+ * One item of a batch: the problem and its outputs.  All pointers are device
+ * pointers, float data (FP32); B is double.
+ *   m, n, r: sizes, 1 <= r <= min(m, n), within the handle's limits.
+ *   lambda > 0, mu > 0 (mu_0), tol >= 0: as in sfr_create.
+ *   M (m x ldm, ldm >= n): read only.
+ *   U (m x r), B (r x r), V (n x r): factors of the returned L = U B V^T.
+ *   S (m x lds, lds >= n) or NULL: the returned sparse part, as in sfr_solve.
+ */
+typedef struct {
+    int64_t m, n;
+    int32_t r;
+    int32_t reserved0;
+    double lambda, mu, tol;
+    const void* M;
+    int64_t ldm;
+    void* U;
+    double* B;
+    void* V;
+    void* S;
+    int64_t lds;
+} sfr_batch_item;
+
+/*
+ * Create a batched handle: `capacity` workspace slots for problems of at
+ * most max_m x max_n and rank max_r (FP32 only).
+ *   1 <= capacity <= 65536; 1 <= max_n <= 512; 1 <= max_m <= 2^22;
+ *   1 <= max_r <= min(16, max_m, max_n).
+ *   opt (required): precision must be SFR_F32, nystrom_l 0; rho, mu_bar,
+ *   max_iter and fixed_iters apply to every item (profile is ignored).
+ * Each slot holds 2 Y buffers (max_m x max_n), 2 P (max_m x 16) and 2 Q
+ * (max_n x 16) buffers in device memory; sfr_workspace_bytes reports the
+ * total.  Returns SFR_ERR_NOMEM if it does not fit.
+ */
+sfr_status sfr_create_batch(sfr_handle* out, int32_t capacity, int64_t max_m, int64_t max_n, int32_t max_r,
+                            const sfr_options* opt);
+
+/*
+ * Solve `count` (0 <= count <= capacity) independent problems with one
+ * kernel launch, one workgroup per problem; each problem runs the same
+ * iteration, stopping rule and outputs as sfr_solve on an FP32 handle.
+ *   items (host, count entries): the problems.  Their output buffers must
+ *     not overlap one another or any input.
+ *   infos (host, count entries, may be NULL): per-item report (sweep_ms 0).
+ *   statuses (host, count entries, may be NULL): per-item status, with the
+ *     meaning of sfr_solve's return value; an item with an error leaves its
+ *     outputs untouched (other items are unaffected).
+ * Returns SFR_ERR_HANDLE (NULL or non-batched handle), SFR_ERR_ARG (an item
+ * out of the handle's limits: nothing is run), SFR_ERR_DEVICE, or else the
+ * first negative per-item status, or SFR_OK (warnings are per item only).
+ */
+sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t count, sfr_info* infos,
+                           int32_t* statuses, void* hip_stream);
 
 /* Release the handle and its workspace.  NULL is accepted. */
 sfr_status sfr_destroy(sfr_handle h);

@@ -57,6 +57,25 @@ class sfr_info(ctypes.Structure):
     ]
 
 
+class sfr_batch_item(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("r", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("lam", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("M", ctypes.c_void_p),
+        ("ldm", ctypes.c_int64),
+        ("U", ctypes.c_void_p),
+        ("B", ctypes.c_void_p),
+        ("V", ctypes.c_void_p),
+        ("S", ctypes.c_void_p),
+        ("lds", ctypes.c_int64),
+    ]
+
+
 class SFRError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
@@ -86,6 +105,11 @@ def lib():
         L.sfr_solve_nys.restype = ctypes.c_int
         L.sfr_tsvd.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.POINTER(sfr_info), vp]
         L.sfr_tsvd.restype = ctypes.c_int
+        L.sfr_create_batch.argtypes = [ctypes.POINTER(vp), i32, i64, i64, i32, ctypes.POINTER(sfr_options)]
+        L.sfr_create_batch.restype = ctypes.c_int
+        L.sfr_solve_batch.argtypes = [vp, ctypes.POINTER(sfr_batch_item), i32, ctypes.POINTER(sfr_info),
+                                      ctypes.POINTER(ctypes.c_int32), vp]
+        L.sfr_solve_batch.restype = ctypes.c_int
         L.sfr_destroy.argtypes = [vp]
         L.sfr_destroy.restype = ctypes.c_int
         L.sfr_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
@@ -230,6 +254,85 @@ class Solver:
         if rc < 0 and raise_on_error:
             raise SFRError(rc, "sfr_tsvd")
         return U, B, V, _info(rc, info)
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().sfr_destroy(self._h)
+        self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class BatchSolver:
+    """A batched handle (sfr_create_batch ... sfr_destroy): many small FP32
+    FR-ADM problems (n <= 512, r <= 16) solved by one kernel launch, one
+    workgroup per problem."""
+
+    def __init__(self, capacity, max_m, max_n, max_r, *, rho=1.5, mu_bar=1e9, max_iter=300, fixed_iters=0):
+        self.capacity, self.max_m, self.max_n, self.max_r = int(capacity), int(max_m), int(max_n), int(max_r)
+        o = sfr_options()
+        o.struct_size = ctypes.sizeof(sfr_options)
+        o.precision = SFR_F32
+        o.rho, o.mu_bar = float(rho), float(mu_bar)
+        o.max_iter, o.fixed_iters = int(max_iter), int(fixed_iters)
+        self._h = ctypes.c_void_p(None)
+        rc = lib().sfr_create_batch(ctypes.byref(self._h), self.capacity, self.max_m, self.max_n, self.max_r,
+                                    ctypes.byref(o))
+        if rc != SFR_OK:
+            self._h = ctypes.c_void_p(None)
+            raise SFRError(rc, "sfr_create_batch")
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_uint64(0)
+        rc = lib().sfr_workspace_bytes(self._h, ctypes.byref(b))
+        if rc != SFR_OK:
+            raise SFRError(rc, "sfr_workspace_bytes")
+        return int(b.value)
+
+    def solve(self, problems, *, want_S=True, outs=None, stream=None, raise_on_error=True):
+        """problems: a list of (M, r, lam, mu, tol) with M a float32 CUDA
+        tensor (row-major).  Returns a list of (U, B, V, S, Info), one per
+        problem (S None if want_S is False)."""
+        import torch
+        count = len(problems)
+        items = (sfr_batch_item * max(count, 1))()
+        keep = []
+        for i, (M, r, lam, mu, tol) in enumerate(problems):
+            if not (isinstance(M, torch.Tensor) and M.is_cuda and M.dtype == torch.float32 and M.dim() == 2):
+                raise TypeError("each M must be a 2-D float32 CUDA (HIP) tensor")
+            if M.stride(1) != 1:
+                raise ValueError("M must be row-major (unit column stride)")
+            m, n = M.shape
+            if outs is None:
+                U = torch.empty((m, r), dtype=torch.float32, device=M.device)
+                B = torch.empty((r, r), dtype=torch.float64, device=M.device)
+                V = torch.empty((n, r), dtype=torch.float32, device=M.device)
+                S = torch.empty((m, n), dtype=torch.float32, device=M.device) if want_S else None
+            else:
+                U, B, V, S = outs[i]
+            keep.append((U, B, V, S))
+            it = items[i]
+            it.m, it.n, it.r = m, n, int(r)
+            it.lam, it.mu, it.tol = float(lam), float(mu), float(tol)
+            it.M, it.ldm = M.data_ptr(), M.stride(0)
+            it.U, it.B, it.V = U.data_ptr(), B.data_ptr(), V.data_ptr()
+            it.S, it.lds = (S.data_ptr(), S.stride(0)) if S is not None else (None, 0)
+        infos = (sfr_info * max(count, 1))()
+        st = (ctypes.c_int32 * max(count, 1))()
+        rc = lib().sfr_solve_batch(self._h, items, count, infos, st, _stream_handle(stream))
+        if rc < 0 and (raise_on_error or rc in (SFR_ERR_ARG, SFR_ERR_HANDLE, SFR_ERR_DEVICE)):
+            raise SFRError(rc, "sfr_solve_batch")
+        return [(*keep[i], _info(int(st[i]), infos[i])) for i in range(count)]
 
     def close(self):
         if self._h and self._h.value:

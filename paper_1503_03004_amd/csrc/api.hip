@@ -534,6 +534,7 @@ sfr_status sfr_destroy(sfr_handle h)
     engine_destroy(h->left);
     engine_destroy(h->top);
     free_all(h->allocs);
+    if (h->items_h) (void)hipHostFree(h->items_h);
     h->magic = 0;
     delete h;
     return SFR_OK;
@@ -543,7 +544,7 @@ sfr_status sfr_workspace_bytes(sfr_handle h, uint64_t* bytes)
 {
     if (!h || h->magic != 0x53465221u) return SFR_ERR_HANDLE;
     if (!bytes) return SFR_ERR_ARG;
-    size_t b = h->main.bytes + h->left.bytes + h->top.bytes;
+    size_t b = h->main.bytes + h->left.bytes + h->top.bytes + h->batch_bytes;
     *bytes = (uint64_t)b;
     return SFR_OK;
 }
@@ -551,7 +552,7 @@ sfr_status sfr_workspace_bytes(sfr_handle h, uint64_t* bytes)
 sfr_status sfr_solve(sfr_handle h, const void* M, int64_t ldm, void* U, double* B, void* V, void* S, int64_t lds,
                      sfr_info* info, void* hip_stream)
 {
-    if (!h || h->magic != 0x53465221u || h->nys) return SFR_ERR_HANDLE;
+    if (!h || h->magic != 0x53465221u || h->nys || h->batch) return SFR_ERR_HANDLE;
     if (!M || !U || !B || !V) return SFR_ERR_ARG;
     if (ldm < h->n || (S && lds < h->n)) return SFR_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -580,7 +581,7 @@ sfr_status sfr_solve(sfr_handle h, const void* M, int64_t ldm, void* U, double* 
 sfr_status sfr_tsvd(sfr_handle h, const void* M, int64_t ldm, void* U, double* B, void* V, sfr_info* info,
                     void* hip_stream)
 {
-    if (!h || h->magic != 0x53465221u || h->nys) return SFR_ERR_HANDLE;
+    if (!h || h->magic != 0x53465221u || h->nys || h->batch) return SFR_ERR_HANDLE;
     if (!M || !U || !B || !V) return SFR_ERR_ARG;
     if (ldm < h->n) return SFR_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);

@@ -1,0 +1,150 @@
+// C ABI of the batched solver (batch.hip): a handle with `capacity` slots of
+// workspace for problems up to max_m x max_n, rank up to max_r; one call
+// solves up to `capacity` independent problems with one kernel launch.
+#include "engine.hpp"
+#include "sfr.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+namespace sfr {
+
+static int batch_bucket(int r)
+{
+    static const int Rs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
+    for (int R : Rs)
+        if (R >= r) return R;
+    return -1;
+}
+
+}  // namespace sfr
+
+using namespace sfr;
+
+extern "C" {
+
+sfr_status sfr_create_batch(sfr_handle* out, int32_t capacity, int64_t max_m, int64_t max_n, int32_t max_r,
+                            const sfr_options* opt)
+{
+    if (!out) return SFR_ERR_ARG;
+    *out = nullptr;
+    if (!opt || opt->struct_size != sizeof(sfr_options)) return SFR_ERR_ARG;
+    sfr_options o = *opt;
+    if (o.precision != SFR_F32 || o.nystrom_l != 0) return SFR_ERR_ARG;
+    if (capacity < 1 || capacity > 65536) return SFR_ERR_ARG;
+    if (max_m < 1 || max_m > (1 << 22) || max_n < 1 || max_n > 512) return SFR_ERR_ARG;
+    if (max_r < 1 || max_r > 16 || max_r > max_m || max_r > max_n) return SFR_ERR_ARG;
+    if (o.rho == 0.0) o.rho = 1.5;
+    if (o.mu_bar == 0.0) o.mu_bar = 1e9;
+    if (o.max_iter == 0) o.max_iter = 300;
+    if (!(o.rho > 1.0) || !(o.mu_bar > 0.0) || o.rho > 1e300 || o.mu_bar > 1e300) return SFR_ERR_ARG;
+    if (o.max_iter < 1 || o.max_iter > 100000 || o.fixed_iters < 0 || o.fixed_iters > 100000) return SFR_ERR_ARG;
+    sfr_ctx* h = new (std::nothrow) sfr_ctx();
+    if (!h) return SFR_ERR_NOMEM;
+    h->batch = true;
+    h->capacity = capacity;
+    h->max_m = max_m;
+    h->max_n = max_n;
+    h->max_r = max_r;
+    h->prm.rho = o.rho;
+    h->prm.mu_bar = o.mu_bar;
+    h->prm.max_iter = o.max_iter;
+    h->prm.fixed_iters = o.fixed_iters;
+    h->ldy = (max_n + 3) / 4 * 4;
+    const size_t ny = (size_t)max_m * h->ldy, np = (size_t)max_m * 16, nq = (size_t)max_n * 16;
+    bool ok = dev_alloc(h->allocs, h->batch_bytes, (void**)&h->items_d, sizeof(BatchItemDev) * (size_t)capacity);
+    h->slot_ws.assign((size_t)capacity * 6, nullptr);
+    for (int s = 0; s < capacity && ok; ++s) {
+        float** w = &h->slot_ws[(size_t)s * 6];
+        ok = ok && dev_alloc(h->allocs, h->batch_bytes, (void**)&w[0], ny * sizeof(float));
+        ok = ok && dev_alloc(h->allocs, h->batch_bytes, (void**)&w[1], ny * sizeof(float));
+        ok = ok && dev_alloc(h->allocs, h->batch_bytes, (void**)&w[2], np * sizeof(float));
+        ok = ok && dev_alloc(h->allocs, h->batch_bytes, (void**)&w[3], np * sizeof(float));
+        ok = ok && dev_alloc(h->allocs, h->batch_bytes, (void**)&w[4], nq * sizeof(float));
+        ok = ok && dev_alloc(h->allocs, h->batch_bytes, (void**)&w[5], nq * sizeof(float));
+    }
+    if (ok && hipHostMalloc((void**)&h->items_h, sizeof(BatchItemDev) * (size_t)capacity, hipHostMallocDefault) !=
+                  hipSuccess) {
+        h->items_h = nullptr;
+        ok = false;
+    }
+    if (!ok) {
+        free_all(h->allocs);
+        (void)hipGetLastError();
+        delete h;
+        return SFR_ERR_NOMEM;
+    }
+    *out = h;
+    return SFR_OK;
+}
+
+sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t count, sfr_info* infos,
+                           int32_t* statuses, void* hip_stream)
+{
+    if (!h || h->magic != 0x53465221u || !h->batch) return SFR_ERR_HANDLE;
+    if (count < 0 || count > h->capacity || (count > 0 && !items)) return SFR_ERR_ARG;
+    if (count == 0) return SFR_OK;
+    // validate every item before any device work
+    int R = 1;
+    for (int32_t i = 0; i < count; ++i) {
+        const sfr_batch_item& it = items[i];
+        if (it.m < 1 || it.m > h->max_m || it.n < 1 || it.n > h->max_n) return SFR_ERR_ARG;
+        if (it.r < 1 || it.r > h->max_r || it.r > it.m || it.r > it.n) return SFR_ERR_ARG;
+        if (!(it.lambda > 0.0) || it.lambda > 1e300 || !(it.mu > 0.0) || it.mu > 1e300) return SFR_ERR_ARG;
+        if (!(it.tol >= 0.0) || it.tol > 1e300) return SFR_ERR_ARG;
+        if (!it.M || !it.U || !it.B || !it.V || it.ldm < it.n || (it.S && it.lds < it.n)) return SFR_ERR_ARG;
+        R = std::max(R, batch_bucket(it.r));
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    for (int32_t i = 0; i < count; ++i) {
+        const sfr_batch_item& it = items[i];
+        BatchItemDev& d = h->items_h[i];
+        memset(&d, 0, sizeof(d));
+        d.m = (int32_t)it.m; d.n = (int32_t)it.n; d.r = it.r; d.ldy = (int32_t)h->ldy;
+        d.lambda = it.lambda; d.mu0 = it.mu; d.tol = it.tol;
+        d.M = static_cast<const float*>(it.M); d.ldm = it.ldm;
+        d.U = static_cast<float*>(it.U); d.B = it.B; d.V = static_cast<float*>(it.V);
+        d.S = static_cast<float*>(it.S); d.lds = it.lds;
+        float* const* w = &h->slot_ws[(size_t)i * 6];
+        d.Y0 = w[0]; d.Y1 = w[1]; d.P0 = w[2]; d.P1 = w[3]; d.Q0 = w[4]; d.Q1 = w[5];
+    }
+    BatchParams bp;
+    bp.rho = h->prm.rho;
+    bp.mu_bar = h->prm.mu_bar;
+    bp.max_iter = h->prm.max_iter;
+    bp.fixed_iters = h->prm.fixed_iters;
+    const size_t bytes = sizeof(BatchItemDev) * (size_t)count;
+    if (hipMemcpyAsync(h->items_d, h->items_h, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_batch(h->items_d, count, R, bp, s) != hipSuccess ||
+        hipMemcpyAsync(h->items_h, h->items_d, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        return SFR_ERR_DEVICE;
+    }
+    sfr_status worst = SFR_OK;
+    for (int32_t i = 0; i < count; ++i) {
+        const BatchItemDev& d = h->items_h[i];
+        sfr_status st = (sfr_status)d.status;
+        if (st == SFR_OK && !(d.min_eig_B > 0.0)) st = SFR_WARN_NOT_SPD;
+        if (d.status == 1) st = SFR_WARN_MAXITER;
+        if (statuses) statuses[i] = st;
+        if (infos) {
+            sfr_info& f = infos[i];
+            memset(&f, 0, sizeof(f));
+            if (st >= 0) {
+                f.iters = d.iters;
+                f.converged = (d.status == SFR_OK) ? 1 : 0;
+                f.rel_residual = d.res;
+                f.min_eig_B = d.min_eig_B;
+                f.mu_final = d.mu_final;
+            }
+        }
+        if (st < 0 && worst >= 0) worst = st;
+    }
+    return worst;
+}
+
+}  // extern "C"

@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
             // wavefront of the first workgroup, before its share of the pass
             __shared__ double Aw[R * LDP], Ew[R * LDP];
             __shared__ __align__(16) double csw[2 * 16];
-            const double w = wmin_eig<R>(st->B, st->r, Aw, Ew, csw);
+            const double w = wmin_eig<R>(st->B, kMaxR, st->r, Aw, Ew, csw);
             if (threadIdx.x == 0) a.st->min_eig_B = w;
         }
     }

@@ -97,6 +97,14 @@ struct sfr_ctx {
     double* core = nullptr;  // r x r workspace of the combine (several blocks)
     void* Ucomb = nullptr;   // m x R combined row factor
     void* Vcomb = nullptr;   // n x R combined column factor
+    // batched handle (sfr_create_batch)
+    bool batch = false;
+    int32_t capacity = 0, max_r = 0;
+    int64_t max_m = 0, max_n = 0, ldy = 0;
+    sfr::BatchItemDev* items_d = nullptr;   // device descriptors (capacity)
+    sfr::BatchItemDev* items_h = nullptr;   // pinned mirror
+    std::vector<float*> slot_ws;            // per slot: Y0, Y1, P0, P1, Q0, Q1
+    size_t batch_bytes = 0;
     std::vector<void*> allocs;
 };
 

@@ -263,7 +263,7 @@ using namespace sfr;
 extern "C" sfr_status sfr_solve_nys(sfr_handle h, const void* M, int64_t ldm, const int64_t* perm, void* U,
                                     double* B, void* V, void* S, int64_t lds, sfr_info* info, void* hip_stream)
 {
-    if (!h || h->magic != 0x53465221u || !h->nys) return SFR_ERR_HANDLE;
+    if (!h || h->magic != 0x53465221u || !h->nys || h->batch) return SFR_ERR_HANDLE;
     if (!M || !perm || !U || !B || !V) return SFR_ERR_ARG;
     if (ldm < h->n || (S && lds < h->n)) return SFR_ERR_ARG;
     // perm must be a permutation of 0..m-1

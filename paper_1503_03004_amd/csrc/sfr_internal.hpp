@@ -169,6 +169,36 @@ struct LowrankArgs {
     double lam, mu;
 };
 
+// One problem of a batched solve (batch.hip): the caller's arguments, the
+// slot's workspace and, on return, its results.  Device memory.
+struct BatchItemDev {
+    int32_t m, n, r, ldy;           // ldy: row pitch of the Y workspace
+    double lambda, mu0, tol;
+    const float* M;
+    int64_t ldm;
+    float* U;
+    double* B;
+    float* V;
+    float* S;                        // may be NULL
+    int64_t lds;
+    float* Y0;
+    float* Y1;
+    float* P0;
+    float* P1;
+    float* Q0;
+    float* Q1;
+    // results
+    int32_t iters, status;
+    double res, min_eig_B, mu_final;
+};
+
+struct BatchParams {
+    double rho, mu_bar;
+    int32_t max_iter, fixed_iters;
+};
+
+hipError_t launch_batch(BatchItemDev* items, int count, int R, const BatchParams& bp, hipStream_t s);
+
 // Host-side launchers (sweep.hip / small.hip / dense.hip).  The sweep takes
 // an optional start/stop event pair bound to its dispatch.
 template <typename T>

@@ -159,31 +159,10 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
     }
     lsync<NT>();
 
-    // ---- U-step: C1 = (B0 G_P B0)^{-1/2}
-    wmm<R, NT>(T1, Bm, Gp);
-    wmm<R, NT>(T2, T1, Bm);
-    wsym<R, NT>(T2);
-    const bool ok1 = winv_sqrt<R, NT>(C1, T2, Ev, T1, r, cs, wbuf);
-    // ---- V-step: K = B0 C1 B0, C2 = (K G_Q K)^{-1/2}
-    wmm<R, NT>(T1, Bm, C1);          // T1 = B0 C1  (the U transform)
-    wmm<R, NT>(Km, T1, Bm);
-    wsym<R, NT>(Km);
-    wmm<R, NT>(T2, Km, Gq);
-    wmm<R, NT>(C2, T2, Km);          // K G_Q K (C2 as scratch)
-    wsym<R, NT>(C2);
-    wcopy<R, NT>(T2, C2);
-    const bool ok2 = winv_sqrt<R, NT>(C2, T2, Ev2, Gp, r, cs, wbuf);   // Gp free now
-    if (!ok1 || !ok2) {
+    if (!lstep_algebra<R, NT>(Gp, Gq, Bm, C1, C2, Km, T1, T2, Ev, Ev2, cs, wbuf, r)) {
         if (tid == 0) { st->status = kErrRank; st->iters = k - 1; st->done = 1; }
         return;
     }
-    // TV = K C2 -> Gp ; B = Sym(C1 B0 G_Q K C2) -> T2 ; TU = B0 C1 B -> Km
-    wmm<R, NT>(Gp, Km, C2);               // TV
-    wmm<R, NT>(T2, C1, Bm);               // C1 B0
-    wmm<R, NT>(C2, T2, Gq);               // C1 B0 G_Q
-    wmm<R, NT>(T2, C2, Gp);               // C1 B0 G_Q K C2
-    wsym<R, NT>(T2);                      // new B
-    wmm<R, NT>(Km, T1, T2);               // TU
     // only the R x R block changes; the rest keeps the values set at the
     // start of the solve (zero, identity on the diagonal of B)
 #pragma unroll
@@ -258,7 +237,7 @@ __global__ void __launch_bounds__(64) final_small_kernel(DevState* st)
 {
     __shared__ double A[R * LDP], Ev[R * LDP];
     __shared__ __align__(16) double cs[2 * 16];
-    const double w = wmin_eig<R>(st->B, st->r, A, Ev, cs);
+    const double w = wmin_eig<R>(st->B, kMaxR, st->r, A, Ev, cs);
     if (threadIdx.x == 0) st->min_eig_B = w;
 }
 

@@ -333,24 +333,65 @@ __device__ inline bool winv_sqrt(double* Out, double* A, double* E, double* T, i
     return ok;
 }
 
-// Smallest eigenvalue of the leading r x r block of B (row pitch kMaxR),
-// one wavefront; A, Ev: LDS scratch R x LDP, cs: 2 * 16.  Full Jacobi
-// convergence from the identity basis.
-template <int R>
-__device__ inline double wmin_eig(const double* B, int r, double* A, double* Ev, double* cs)
+// The r x r algebra of one FixedRankOptStep (Alg. 2) in its one-pass form
+// (Sec. 4.1, eqs. (7), (8)), from the Grams G_P = P^T P, G_Q = Q^T Q of the
+// products P = X V_0, Q = X^T P and the previous SPD factor B_0:
+//   C1 = (B_0 G_P B_0)^{-1/2}            U = P B_0 C1
+//   K  = B_0 C1 B_0, C2 = (K G_Q K)^{-1/2}  V = Q K C2
+//   B  = Sym(C1 B_0 G_Q K C2)             a_i = P_i (B_0 C1 B)
+// Matrices are R x R in LDS with an identity block on the padded indices.
+// On entry Gp, Gq, Bm (= B_0), Ev, Ev2 (warm-start eigenbases); on exit
+// T1 = B_0 C1 (U transform), Km = B_0 C1 B (row factor transform),
+// Gp = K C2 (V transform), T2 = B, and Ev, Ev2 updated.  Returns false if a
+// Gram is not positive definite (rank loss, eq. (7)).
+template <int R, int NT>
+__device__ inline bool lstep_algebra(double* Gp, double* Gq, double* Bm, double* C1, double* C2, double* Km,
+                                     double* T1, double* T2, double* Ev, double* Ev2, double* cs, double* wbuf,
+                                     int r)
 {
-    const int lane = threadIdx.x & 63;
-    for (int e = lane; e < R * R; e += 64) {
+    // U-step: C1 = (B0 G_P B0)^{-1/2}
+    wmm<R, NT>(T1, Bm, Gp);
+    wmm<R, NT>(T2, T1, Bm);
+    wsym<R, NT>(T2);
+    const bool ok1 = winv_sqrt<R, NT>(C1, T2, Ev, T1, r, cs, wbuf);
+    // V-step: K = B0 C1 B0, C2 = (K G_Q K)^{-1/2}
+    wmm<R, NT>(T1, Bm, C1);          // T1 = B0 C1  (the U transform)
+    wmm<R, NT>(Km, T1, Bm);
+    wsym<R, NT>(Km);
+    wmm<R, NT>(T2, Km, Gq);
+    wmm<R, NT>(C2, T2, Km);          // K G_Q K (C2 as scratch)
+    wsym<R, NT>(C2);
+    wcopy<R, NT>(T2, C2);
+    const bool ok2 = winv_sqrt<R, NT>(C2, T2, Ev2, Gp, r, cs, wbuf);   // Gp free now
+    if (!ok1 || !ok2) return false;
+    // TV = K C2 -> Gp ; B = Sym(C1 B0 G_Q K C2) -> T2 ; TU = B0 C1 B -> Km
+    wmm<R, NT>(Gp, Km, C2);               // TV
+    wmm<R, NT>(T2, C1, Bm);               // C1 B0
+    wmm<R, NT>(C2, T2, Gq);               // C1 B0 G_Q
+    wmm<R, NT>(T2, C2, Gp);               // C1 B0 G_Q K C2
+    wsym<R, NT>(T2);                      // new B
+    wmm<R, NT>(Km, T1, T2);               // TU
+    return true;
+}
+
+// Smallest eigenvalue of the leading r x r block of B (row pitch ldb), by NT
+// threads; A, Ev: LDS scratch R x LDP, cs: 2 * 16.  Full Jacobi convergence
+// from the identity basis.
+template <int R, int NT = 64>
+__device__ inline double wmin_eig(const double* B, int ldb, int r, double* A, double* Ev, double* cs)
+{
+    const int lane = lid<NT>();
+    for (int e = lane; e < R * R; e += NT) {
         const int i = e / R, j = e % R;
         const bool pad = (i >= r) || (j >= r);
-        A[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : B[i * kMaxR + j];
+        A[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : B[i * ldb + j];
         Ev[i * LDP + j] = (i == j) ? 1.0 : 0.0;
     }
-    wsync();
-    wjacobi<R>(A, Ev, cs);
+    lsync<NT>();
+    wjacobi<R, NT>(A, Ev, cs);
     double w = INFINITY;
-    for (int i = lane; i < r; i += 64) w = fmin(w, A[i * LDP + i]);
-    return wave_min(w);
+    for (int i = 0; i < r; ++i) w = fmin(w, A[i * LDP + i]);
+    return w;
 }
 
 }  // namespace sfr

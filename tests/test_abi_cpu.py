@@ -21,8 +21,8 @@ def declared():
 
 def test_header_declares_the_entry_points():
     names = declared()
-    for want in ("sfr_create", "sfr_solve", "sfr_solve_nys", "sfr_tsvd", "sfr_destroy", "sfr_status_string",
-                 "sfr_version", "sfr_workspace_bytes"):
+    for want in ("sfr_create", "sfr_solve", "sfr_solve_nys", "sfr_tsvd", "sfr_create_batch", "sfr_solve_batch",
+                 "sfr_destroy", "sfr_status_string", "sfr_version", "sfr_workspace_bytes"):
         assert want in names
 
 
@@ -36,12 +36,14 @@ def test_struct_layouts_match_header(tmp_path):
     """The binding's ctypes structs have the C compiler's size and offsets."""
     import subprocess
     fields = {"sfr_options": [f for f, _ in B.sfr_options._fields_],
-              "sfr_info": [f for f, _ in B.sfr_info._fields_]}
+              "sfr_info": [f for f, _ in B.sfr_info._fields_],
+              "sfr_batch_item": [f for f, _ in B.sfr_batch_item._fields_]}
     lines = ['#include "sfr.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void) {"]
     for st, fs in fields.items():
         lines.append(f'printf("%zu\\n", sizeof({st}));')
         for f in fs:
-            lines.append(f'printf("%zu\\n", offsetof({st}, {f}));')
+            cname = {"lam": "lambda"}.get(f, f)      # a Python keyword in the header
+            lines.append(f'printf("%zu\\n", offsetof({st}, {cname}));')
     lines.append("return 0; }")
     src = tmp_path / "layout.c"
     src.write_text("\n".join(lines))
@@ -49,7 +51,7 @@ def test_struct_layouts_match_header(tmp_path):
     subprocess.check_call(["gcc", "-I", os.path.dirname(HDR), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = []
-    for cls in (B.sfr_options, B.sfr_info):
+    for cls in (B.sfr_options, B.sfr_info, B.sfr_batch_item):
         want.append(ctypes.sizeof(cls))
         want += [getattr(cls, f).offset for f, _ in cls._fields_]
     assert got == want
@@ -107,6 +109,34 @@ def test_create_rejects_wrong_struct_size():
     assert sfr.lib().sfr_create(None, 10, 10, 2, 0.1, 1.0, 1e-7, None) == B.SFR_ERR_ARG
 
 
+@pytest.mark.parametrize("args,kw", [
+    ((0, 100, 64, 4), {}),                # capacity < 1
+    ((70000, 100, 64, 4), {}),            # capacity above 65536
+    ((4, 0, 64, 4), {}),                  # max_m < 1
+    ((4, 100, 0, 4), {}),                 # max_n < 1
+    ((4, 100, 513, 4), {}),               # max_n above 512
+    ((4, 100, 64, 0), {}),                # max_r < 1
+    ((4, 100, 64, 17), {}),               # max_r above 16
+    ((4, 100, 3, 4), {}),                 # max_r > max_n
+    ((4, 100, 64, 4), {"precision": 0}),  # FP32 only
+    ((4, 100, 64, 4), {"nystrom_l": 8}),
+    ((4, 100, 64, 4), {"rho": 1.0}),
+    ((4, 100, 64, 4), {"max_iter": -1}),
+    ((4, 100, 64, 4), {"fixed_iters": -2}),
+    ((4, 100, 64, 4), {"struct_size": 3}),
+])
+def test_create_batch_rejects_invalid_arguments(args, kw):
+    o = B.sfr_options()
+    o.struct_size = ctypes.sizeof(B.sfr_options)
+    o.precision = B.SFR_F32
+    for k, v in kw.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p(None)
+    assert sfr.lib().sfr_create_batch(ctypes.byref(h), *args, ctypes.byref(o)) == B.SFR_ERR_ARG
+    assert not h.value
+    assert sfr.lib().sfr_create_batch(ctypes.byref(h), 4, 100, 64, 4, None) == B.SFR_ERR_ARG
+
+
 def test_null_handle_paths():
     L = sfr.lib()
     info = B.sfr_info()
@@ -114,6 +144,8 @@ def test_null_handle_paths():
     assert L.sfr_solve_nys(None, None, 0, None, None, None, None, None, 0, ctypes.byref(info),
                            None) == B.SFR_ERR_HANDLE
     assert L.sfr_tsvd(None, None, 0, None, None, None, ctypes.byref(info), None) == B.SFR_ERR_HANDLE
+    items = (B.sfr_batch_item * 1)()
+    assert L.sfr_solve_batch(None, items, 1, None, None, None) == B.SFR_ERR_HANDLE
     assert L.sfr_destroy(None) == B.SFR_OK
     b = ctypes.c_uint64(0)
     assert L.sfr_workspace_bytes(None, ctypes.byref(b)) == B.SFR_ERR_HANDLE
