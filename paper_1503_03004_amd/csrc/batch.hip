@@ -26,22 +26,59 @@ constexpr int kBTPB = 64 * kBNW;      // threads per workgroup
 constexpr int kBNMax = 512;           // widest problem (columns)
 constexpr int kBNV = kBNMax / 64;     // columns per lane per row
 
-template <int R>
+// Global-memory views of the descriptor's pointers.  Loaded from memory,
+// the pointers would otherwise be generic (flat) ones: flat accesses also
+// count against the LDS wait counter, so every LDS wait of the band loop
+// would wait for the in-flight HBM loads and stores as well.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) double gdouble;
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T* as_global(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
+__device__ inline float lane_bcast(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// RW rows per wavefront per band (a band is 8 RW rows): two rows share each
+// V column read; one row keeps the larger ranks' band loop within registers.
+template <int R, int RW>
 __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, BatchParams bp)
 {
     static_assert(R <= 16, "batched solver: r <= 16");
+    constexpr int kBRW = RW;
+    constexpr int kBH = kBNW * RW;        // rows per band
     constexpr int E = R * (R + 1) / 2;
     constexpr int NT = kBTPB;
+    constexpr int RP = (R + 3) / 4 * 4;   // rank padded to whole float4 groups
+    constexpr int RC = RP / 4;
+    constexpr int GS = NT / E;            // threads per G_Q entry
     BatchItemDev* it = items + blockIdx.x;
-    const int m = it->m, n = it->n, r = it->r, ldy = it->ldy;
-    const int64_t ldm = it->ldm;
-    const float* __restrict__ M = it->M;
-    const float lam = (float)it->lambda;
+    // the descriptor is read once (uniform: scalar loads) and its pointers
+    // are held in registers for the whole solve
+    const BatchItemDev d = *it;
+    const int m = d.m, n = d.n, r = d.r, ldy = d.ldy;
+    const int64_t ldm = d.ldm;
+    const gfloat* __restrict__ M = as_global(d.M);
+    const float lam = (float)d.lambda;
+    gfloat* const Y0 = as_global(d.Y0);
+    gfloat* const Y1 = as_global(d.Y1);
+    gfloat* const P0 = as_global(d.P0);
+    gfloat* const P1 = as_global(d.P1);
+    gfloat* const Q0 = as_global(d.Q0);
+    gfloat* const Q1 = as_global(d.Q1);
 
-    __shared__ float Vs[R * kBNMax];          // V_k, k-major (Vs[k n + j]); Q staging between iterations
-    __shared__ float Xs[kBNW * kBNMax];       // x of the band
-    __shared__ float Ps[kBNW * 16];           // p of the band's rows
-    __shared__ float TUs[R * R];              // row factor transform (FP32)
+    // V_k in float4 groups of 4 rank entries: (k, j) at ((k/4) kBNMax + j) 4 + k%4,
+    // so a lane reads the R entries of its column with R/4 128-bit reads.
+    // Between the sweep and the step the same space stages Q_k (Vs[j R + k]).
+    __shared__ __align__(16) float Vs[RP * kBNMax];
+    __shared__ __align__(16) float Xs[kBH * kBNMax];   // x of the band; FP64 G_Q partials in the step
+    __shared__ __align__(16) float Ps[kBH * 16];       // p of the band's rows
+    __shared__ __align__(16) float TUt[R * RP];        // T_U transposed: TUt[k RP + t] = T_U[t][k]
+    __shared__ __align__(16) float TVt[R * RP];        // T_V transposed (FP32)
     __shared__ double Gp[R * LDP], Gq[R * LDP], Bm[R * LDP], C1[R * LDP], C2[R * LDP];
     __shared__ double Km[R * LDP], T1[R * LDP], T2[R * LDP], Ev[R * LDP], Ev2[R * LDP];
     __shared__ double TUb[R * LDP], TVd[R * LDP];   // U and V transforms of the last step
@@ -51,11 +88,12 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
     __shared__ double wbuf[kMaxR];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    auto vat = [](int kk, int j) { return ((kk >> 2) * kBNMax + j) * 4 + (kk & 3); };
 
     // ---- initial state of Alg. 1: V_1 = I_{n x r}, B_0 = I, warm bases I
-    for (int e = tid; e < R * n; e += NT) {
-        const int k = e / n, j = e % n;
-        Vs[e] = (j == k && k < r) ? 1.f : 0.f;
+    for (int e = tid; e < RP * n; e += NT) {
+        const int kk = e / n, j = e % n;
+        Vs[vat(kk, j)] = (j == kk && kk < r) ? 1.f : 0.f;
     }
     for (int e = tid; e < R * R; e += NT) {
         const int i = e / R, j = e % R;
@@ -65,20 +103,33 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
         Ev2[i * LDP + j] = id;
         TUb[i * LDP + j] = 0.0;
         TVd[i * LDP + j] = id;
-        TUs[e] = 0.f;
     }
+    for (int e = tid; e < R * RP; e += NT) TUt[e] = 0.f;
     __syncthreads();
 
-    double mu = it->mu0, mu_prev = it->mu0, nrmM = 0.0, res = 0.0;
+    // G_P entry of thread tid (tid < E) and G_Q entry of thread tid (tid < GS E)
+    int gx = 0, gy = 0, qx = 0, qy = 0;
+    if (tid < E) {
+        int rem = tid;
+        while (rem >= R - gx) { rem -= R - gx; ++gx; }
+        gy = gx + rem;
+    }
+    if (tid < GS * E) {
+        int rem = tid % E;
+        while (rem >= R - qx) { rem -= R - qx; ++qx; }
+        qy = qx + rem;
+    }
+
+    double mu = d.mu0, mu_prev = d.mu0, nrmM = 0.0, res = 0.0;
     int32_t status = kOK, iters = 0;
-    const int nbands = (m + kBNW - 1) / kBNW;
+    const int nbands = (m + kBH - 1) / kBH;
     for (int k = 1;; ++k) {
         const int mode = (k == 1) ? 0 : (k == 2 ? 1 : 2);
-        const float* Yp = ((k - 1) & 1) ? it->Y1 : it->Y0;
-        float* Yn = (k & 1) ? it->Y1 : it->Y0;
-        const float* Pp = ((k - 1) & 1) ? it->P1 : it->P0;
-        float* Pn = (k & 1) ? it->P1 : it->P0;
-        float* Qn = (k & 1) ? it->Q1 : it->Q0;
+        const gfloat* Yp = ((k - 1) & 1) ? Y1 : Y0;
+        gfloat* Yn = (k & 1) ? Y1 : Y0;
+        const gfloat* Pp = ((k - 1) & 1) ? P1 : P0;
+        gfloat* Pn = (k & 1) ? P1 : P0;
+        gfloat* Qn = (k & 1) ? Q1 : Q0;
         const float mup = (float)mu_prev;
         const float imup = (mode != 0) ? (float)(1.0 / mu_prev) : 0.f;
         const float imuc = (float)(1.0 / mu);
@@ -88,86 +139,149 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
 #pragma unroll
         for (int kk = 0; kk < R; ++kk) q[kk] = 0.f;
         double gp = 0.0;      // G_P entry `tid` (tid < E)
-        int gx = 0, gy = 0;
-        if (tid < E) {
-            int rem = tid;
-            while (rem >= R - gx) { rem -= R - gx; ++gx; }
-            gy = gx + rem;
-        }
         double acc2 = 0.0;
-        for (int b = 0; b < nbands; ++b) {
-            const int i = b * kBNW + wave;
-            const bool row_ok = i < m;
-            float av[R];
-            if (mode != 0) {
-                float s = 0.f;
-                if (lane < R && row_ok) {
+        // The loads of band b + 1 (M, Y_{k-1} and the P rows) are issued
+        // before band b is computed, so one band's loads are always in
+        // flight behind the arithmetic of the other.
+        auto load_band = [&](int b, float* mv, float* yv, float* pr) {
 #pragma unroll
-                    for (int t = 0; t < R; ++t) s = fmaf(Pp[(int64_t)i * R + t], TUs[t * R + lane], s);
+            for (int h = 0; h < kBRW; ++h) {
+                const int i = b * kBH + h * kBNW + wave;
+                const bool row_ok = i < m;
+#pragma unroll
+                for (int v = 0; v < kBNV; ++v) {
+                    const int j = lane + 64 * v;
+                    const bool ok = row_ok && j < n;
+                    mv[h * kBNV + v] = ok ? M[(int64_t)i * ldm + j] : 0.f;
+                    yv[h * kBNV + v] = (ok && mode == 2) ? Yp[(int64_t)i * ldy + j] : 0.f;
                 }
-#pragma unroll
-                for (int kk = 0; kk < R; ++kk) av[kk] = __shfl(s, kk, 64);
+                // lane t < R holds P_{i,t}
+                pr[h] = (row_ok && mode != 0 && lane < R) ? Pp[(int64_t)i * R + lane] : 0.f;
             }
-            float p[R];
+        };
+        float cm[kBRW * kBNV], cy[kBRW * kBNV], cp[kBRW];
+        load_band(0, cm, cy, cp);
+        for (int b = 0; b < nbands; ++b) {
+            float nm[kBRW * kBNV], ny[kBRW * kBNV], np[kBRW];
 #pragma unroll
-            for (int kk = 0; kk < R; ++kk) p[kk] = 0.f;
+            for (int e = 0; e < kBRW * kBNV; ++e) { nm[e] = 0.f; ny[e] = 0.f; }
+#pragma unroll
+            for (int e = 0; e < kBRW; ++e) np[e] = 0.f;
+            if (b + 1 < nbands) load_band(b + 1, nm, ny, np);
+            // a_i = P_i T_U for the wavefront's rows, uniform (scalar registers)
+            float av[kBRW][R];
+            if (mode != 0) {
+#pragma unroll
+                for (int h = 0; h < kBRW; ++h) {
+                    float pt[R];
+#pragma unroll
+                    for (int t = 0; t < R; ++t) pt[t] = lane_bcast(cp[h], t);
+                    float s = 0.f;
+                    if (lane < R) {
+#pragma unroll
+                        for (int c = 0; c < RC; ++c) {
+                            const float4 tu = *reinterpret_cast<const float4*>(&TUt[lane * RP + 4 * c]);
+                            s = fmaf(pt[4 * c], tu.x, s);
+                            if (4 * c + 1 < R) s = fmaf(pt[4 * c + 1], tu.y, s);
+                            if (4 * c + 2 < R) s = fmaf(pt[4 * c + 2], tu.z, s);
+                            if (4 * c + 3 < R) s = fmaf(pt[4 * c + 3], tu.w, s);
+                        }
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < R; ++kk) av[h][kk] = lane_bcast(s, kk);
+                }
+            }
+            float p[kBRW][R];
+#pragma unroll
+            for (int h = 0; h < kBRW; ++h)
+#pragma unroll
+                for (int kk = 0; kk < R; ++kk) p[h][kk] = 0.f;
             float rowacc = 0.f;
-#pragma unroll 2
+#pragma unroll
             for (int v = 0; v < kBNV; ++v) {
                 const int j = lane + 64 * v;
                 const bool jok = j < n;
-                const bool ok = row_ok && jok;
-                const float mv = ok ? M[(int64_t)i * ldm + j] : 0.f;
-                float x;
-                if (mode == 0) {
-                    x = mv;
-                    rowacc = fmaf(mv, mv, rowacc);
-                } else {
-                    const float yp = (ok && mode == 2) ? Yp[(int64_t)i * ldy + j] : 0.f;
-                    float l = 0.f;
-                    if (jok) {
-#pragma unroll
-                        for (int kk = 0; kk < R; ++kk) l = fmaf(av[kk], Vs[kk * n + j], l);
-                    }
-                    const float Rr = mv - l + yp * imup;
-                    const float y = fminf(fmaxf(mup * Rr, -lam), lam);
-                    const float dy = y - yp;
-                    rowacc = fmaf(dy, dy, rowacc);
-                    x = l + dy * imup + y * imuc;
-                    if (ok) Yn[(int64_t)i * ldy + j] = y;
-                }
-                x = ok ? x : 0.f;
-                Xs[wave * kBNMax + j] = x;
+                // column j of V_k, read once for the wavefront's rows
+                float vv[RP];
                 if (jok) {
 #pragma unroll
-                    for (int kk = 0; kk < R; ++kk) p[kk] = fmaf(x, Vs[kk * n + j], p[kk]);
+                    for (int c = 0; c < RC; ++c) {
+                        const float4 t4 = *reinterpret_cast<const float4*>(&Vs[(c * kBNMax + j) * 4]);
+                        vv[4 * c] = t4.x; vv[4 * c + 1] = t4.y; vv[4 * c + 2] = t4.z; vv[4 * c + 3] = t4.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < RP; ++kk) vv[kk] = 0.f;
+                }
+#pragma unroll
+                for (int h = 0; h < kBRW; ++h) {
+                    const int lr = h * kBNW + wave;
+                    const int i = b * kBH + lr;
+                    const bool ok = (i < m) && jok;
+                    const float mv = cm[h * kBNV + v];
+                    float x;
+                    if (mode == 0) {
+                        x = mv;
+                        rowacc = fmaf(mv, mv, rowacc);
+                    } else {
+                        const float yp = cy[h * kBNV + v];
+                        float l = 0.f;
+#pragma unroll
+                        for (int kk = 0; kk < R; ++kk) l = fmaf(av[h][kk], vv[kk], l);
+                        const float Rr = mv - l + yp * imup;
+                        const float y = fminf(fmaxf(mup * Rr, -lam), lam);
+                        const float dy = y - yp;
+                        rowacc = ok ? fmaf(dy, dy, rowacc) : rowacc;
+                        x = l + dy * imup + y * imuc;
+                        if (ok) Yn[(int64_t)i * ldy + j] = y;
+                    }
+                    x = ok ? x : 0.f;
+                    Xs[lr * kBNMax + j] = x;
+#pragma unroll
+                    for (int kk = 0; kk < R; ++kk) p[h][kk] = fmaf(x, vv[kk], p[h][kk]);
                 }
             }
             acc2 += (double)rowacc;
 #pragma unroll
-            for (int kk = 0; kk < R; ++kk)
-                for (int off = 32; off > 0; off >>= 1) p[kk] += __shfl_xor(p[kk], off, 64);
-            if (lane < 16) {
-                float mine = 0.f;
+            for (int h = 0; h < kBRW; ++h) {
+                const int lr = h * kBNW + wave;
+                const int i = b * kBH + lr;
+                const bool row_ok = i < m;
 #pragma unroll
-                for (int kk = 0; kk < R; ++kk) mine = (kk == lane) ? p[kk] : mine;
-                Ps[wave * 16 + lane] = row_ok ? mine : 0.f;
-                if (row_ok && lane < R) Pn[(int64_t)i * R + lane] = mine;
+                for (int kk = 0; kk < R; ++kk)
+                    for (int off = 32; off > 0; off >>= 1) p[h][kk] += __shfl_xor(p[h][kk], off, 64);
+                if (lane < 16) {
+                    float mine = 0.f;
+#pragma unroll
+                    for (int kk = 0; kk < R; ++kk) mine = (kk == lane) ? p[h][kk] : mine;
+                    Ps[lr * 16 + lane] = row_ok ? mine : 0.f;
+                    if (row_ok && lane < R) Pn[(int64_t)i * R + lane] = mine;
+                }
             }
             __syncthreads();
             // column pass: thread j owns column j; FP64 G_P of the band's rows
             if (tid < n) {
-#pragma unroll 2
-                for (int h = 0; h < kBNW; ++h) {
+#pragma unroll 4
+                for (int h = 0; h < kBH; ++h) {
                     const float xv = Xs[h * kBNMax + tid];
 #pragma unroll
-                    for (int kk = 0; kk < R; ++kk) q[kk] = fmaf(xv, Ps[h * 16 + kk], q[kk]);
+                    for (int c = 0; c < RC; ++c) {
+                        const float4 pp = *reinterpret_cast<const float4*>(&Ps[h * 16 + 4 * c]);
+                        q[4 * c] = fmaf(xv, pp.x, q[4 * c]);
+                        if (4 * c + 1 < R) q[4 * c + 1] = fmaf(xv, pp.y, q[4 * c + 1]);
+                        if (4 * c + 2 < R) q[4 * c + 2] = fmaf(xv, pp.z, q[4 * c + 2]);
+                        if (4 * c + 3 < R) q[4 * c + 3] = fmaf(xv, pp.w, q[4 * c + 3]);
+                    }
                 }
             }
             if (tid < E) {
-                for (int h = 0; h < kBNW; ++h) gp = fma((double)Ps[h * 16 + gx], (double)Ps[h * 16 + gy], gp);
+                for (int h = 0; h < kBH; ++h) gp = fma((double)Ps[h * 16 + gx], (double)Ps[h * 16 + gy], gp);
             }
             __syncthreads();
+#pragma unroll
+            for (int e = 0; e < kBRW * kBNV; ++e) { cm[e] = nm[e]; cy[e] = ny[e]; }
+#pragma unroll
+            for (int e = 0; e < kBRW; ++e) cp[e] = np[e];
         }
         // Q_k: to the workspace (the returned factors read it) and to LDS
         if (tid < n) {
@@ -195,16 +309,32 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
             const int kdone = k - 1;
             if (!isfinite(res)) { stop = true; status = kErrNonFinite; }
             else if (bp.fixed_iters > 0) { stop = kdone >= bp.fixed_iters; }
-            else if (res <= it->tol) { stop = true; }
+            else if (res <= d.tol) { stop = true; }
             else if (kdone >= bp.max_iter) { stop = true; status = kWarnMaxIter; }
             if (stop) iters = kdone;
         }
         if (stop) break;
 
         // ---------------- FP64 step: Grams, Alg. 2 projectors ----------------
+        // G_Q = Q^T Q: GS threads per entry, each over every GS-th column
+        double* gsum = reinterpret_cast<double*>(Xs);
+        if (tid < GS * E) {
+            const int sl = tid / E;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int j = sl;
+            for (; j + 3 * GS < n; j += 4 * GS) {
+                a0 = fma((double)Vs[j * R + qx], (double)Vs[j * R + qy], a0);
+                a1 = fma((double)Vs[(j + GS) * R + qx], (double)Vs[(j + GS) * R + qy], a1);
+                a2 = fma((double)Vs[(j + 2 * GS) * R + qx], (double)Vs[(j + 2 * GS) * R + qy], a2);
+                a3 = fma((double)Vs[(j + 3 * GS) * R + qx], (double)Vs[(j + 3 * GS) * R + qy], a3);
+            }
+            for (; j < n; j += GS) a0 = fma((double)Vs[j * R + qx], (double)Vs[j * R + qy], a0);
+            gsum[tid] = (a0 + a1) + (a2 + a3);
+        }
+        __syncthreads();
         if (tid < E) {
             double gq = 0.0;
-            for (int j = 0; j < n; ++j) gq = fma((double)Vs[j * R + gx], (double)Vs[j * R + gy], gq);
+            for (int sl = 0; sl < GS; ++sl) gq += gsum[sl * E + tid];
             tri[0][tid] = gp;
             tri[1][tid] = gq;
         }
@@ -223,32 +353,46 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
             iters = k - 1;
             break;
         }
-        // the step's transforms (padded block dropped), B_k, and V_{k+1} = Q_k T_V
-        float vn[R];
-        if (tid < n) {
-#pragma unroll
-            for (int kk = 0; kk < R; ++kk) {
-                float s = 0.f;
-                if (kk < r) {
-#pragma unroll
-                    for (int t = 0; t < R; ++t)
-                        if (t < r) s = fmaf(Vs[tid * R + t], (float)Gp[t * LDP + kk], s);
-                }
-                vn[kk] = s;
-            }
-        }
+        // the step's transforms (padded block dropped) and B_k
         for (int e = tid; e < R * R; e += NT) {
             const int i = e / R, j = e % R;
             const bool in = (i < r) && (j < r);
-            TUs[e] = in ? (float)Km[i * LDP + j] : 0.f;
+            TUt[j * RP + i] = in ? (float)Km[i * LDP + j] : 0.f;
+            TVt[j * RP + i] = in ? (float)Gp[i * LDP + j] : 0.f;
             TUb[i * LDP + j] = in ? T1[i * LDP + j] : 0.0;
             TVd[i * LDP + j] = in ? Gp[i * LDP + j] : 0.0;
             Bm[i * LDP + j] = in ? T2[i * LDP + j] : (i == j ? 1.0 : 0.0);
         }
+        if (RP > R) {
+            for (int e = tid; e < R * (RP - R); e += NT) {
+                const int j = e / (RP - R), i = R + e % (RP - R);
+                TUt[j * RP + i] = 0.f;
+                TVt[j * RP + i] = 0.f;
+            }
+        }
         __syncthreads();
+        // V_{k+1} = Q_k T_V from the column's own Q row (registers)
         if (tid < n) {
+            float vn[RP];
 #pragma unroll
-            for (int kk = 0; kk < R; ++kk) Vs[kk * n + tid] = vn[kk];
+            for (int kk = 0; kk < RP; ++kk) vn[kk] = 0.f;
+#pragma unroll
+            for (int kk = 0; kk < R; ++kk) {
+                float s = 0.f;
+#pragma unroll
+                for (int c = 0; c < RC; ++c) {
+                    const float4 tv = *reinterpret_cast<const float4*>(&TVt[kk * RP + 4 * c]);
+                    s = fmaf(q[4 * c], tv.x, s);
+                    if (4 * c + 1 < R) s = fmaf(q[4 * c + 1], tv.y, s);
+                    if (4 * c + 2 < R) s = fmaf(q[4 * c + 2], tv.z, s);
+                    if (4 * c + 3 < R) s = fmaf(q[4 * c + 3], tv.w, s);
+                }
+                vn[kk] = s;
+            }
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                *reinterpret_cast<float4*>(&Vs[(c * kBNMax + tid) * 4]) =
+                    make_float4(vn[4 * c], vn[4 * c + 1], vn[4 * c + 2], vn[4 * c + 3]);
         }
         mu_prev = mu;
         const double nm = bp.rho * mu;
@@ -261,47 +405,105 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
     double min_eig = 0.0;
     if (status >= 0) {
         const int K = iters;
-        const float* PK = (K & 1) ? it->P1 : it->P0;
-        const float* QK = (K & 1) ? it->Q1 : it->Q0;
-        const float* YK = (K >= 2) ? ((K & 1) ? it->Y1 : it->Y0) : nullptr;
-        // U = P TUbar, V = Q TV (FP64 accumulation), B
-        for (int e = tid; e < m * r; e += NT) {
-            const int i = e / r, kk = e % r;
-            double s = 0.0;
-            for (int t = 0; t < r; ++t) s = fma((double)PK[(int64_t)i * R + t], TUb[t * LDP + kk], s);
-            it->U[(int64_t)i * r + kk] = (float)s;
-        }
-        // V_K for the S pass (FP32, k-major in Vs) and the returned V
-        for (int e = tid; e < n * R; e += NT) {
-            const int j = e / R, kk = e % R;
-            double s = 0.0;
-            if (kk < r) {
-                for (int t = 0; t < r; ++t) s = fma((double)QK[(int64_t)j * R + t], TVd[t * LDP + kk], s);
-                it->V[(int64_t)j * r + kk] = (float)s;
+        const gfloat* PK = (K & 1) ? P1 : P0;
+        const gfloat* QK = (K & 1) ? Q1 : Q0;
+        const gfloat* YK = (K & 1) ? Y1 : Y0;     // Y_K (K >= 2); Y_1 = 0
+        const bool haveY = K >= 2;
+        gfloat* const U = as_global(d.U);
+        gfloat* const V = as_global(d.V);
+        gdouble* const Bo = as_global(d.B);
+        gfloat* const S = as_global(d.S);
+        // U = P TUbar, V = Q TV (FP64 accumulation), B; one row per thread
+        for (int i = tid; i < m; i += NT) {
+            float pr[R];
+#pragma unroll
+            for (int t = 0; t < R; ++t) pr[t] = PK[(int64_t)i * R + t];
+#pragma unroll 1
+            for (int kk = 0; kk < r; ++kk) {
+                double s = 0.0;
+#pragma unroll
+                for (int t = 0; t < R; ++t)
+                    if (t < r) s = fma((double)pr[t], TUb[t * LDP + kk], s);
+                U[(int64_t)i * r + kk] = (float)s;
             }
-            Vs[kk * n + j] = (float)s;
         }
-        for (int e = tid; e < r * r; e += NT) it->B[e] = Bm[(e / r) * LDP + e % r];
+        // V_K for the S pass (FP32, grouped layout in Vs) and the returned V
+        for (int j = tid; j < n; j += NT) {
+            float qr[R];
+#pragma unroll
+            for (int t = 0; t < R; ++t) qr[t] = QK[(int64_t)j * R + t];
+#pragma unroll 1
+            for (int kk = 0; kk < RP; ++kk) {
+                double s = 0.0;
+                if (kk < r) {
+#pragma unroll
+                    for (int t = 0; t < R; ++t)
+                        if (t < r) s = fma((double)qr[t], TVd[t * LDP + kk], s);
+                    V[(int64_t)j * r + kk] = (float)s;
+                }
+                Vs[vat(kk, j)] = (float)s;
+            }
+        }
+        for (int e = tid; e < r * r; e += NT) Bo[e] = Bm[(e / r) * LDP + e % r];
         __syncthreads();
-        if (it->S) {
-            const float t = (float)(it->lambda / mu_prev), imu = (float)(1.0 / mu_prev);
+        if (d.S) {
+            const float t = (float)(d.lambda / mu_prev), imu = (float)(1.0 / mu_prev);
+            // one row per wavefront; the next row's loads are issued first
+            auto load_row = [&](int i, float* mv, float* yv, float& pr) {
+#pragma unroll
+                for (int v = 0; v < kBNV; ++v) {
+                    const int j = lane + 64 * v;
+                    const bool ok = j < n;
+                    mv[v] = ok ? M[(int64_t)i * ldm + j] : 0.f;
+                    yv[v] = (ok && haveY) ? YK[(int64_t)i * ldy + j] : 0.f;
+                }
+                pr = (lane < R) ? PK[(int64_t)i * R + lane] : 0.f;
+            };
+            float cm[kBNV], cy[kBNV], cp = 0.f;
+            if (wave < m) load_row(wave, cm, cy, cp);
             for (int i = wave; i < m; i += kBNW) {
+                float nm[kBNV], ny[kBNV], np = 0.f;
+#pragma unroll
+                for (int v = 0; v < kBNV; ++v) { nm[v] = 0.f; ny[v] = 0.f; }
+                if (i + kBNW < m) load_row(i + kBNW, nm, ny, np);
+                float pt[R];
+#pragma unroll
+                for (int tt = 0; tt < R; ++tt) pt[tt] = lane_bcast(cp, tt);
                 float s = 0.f;
                 if (lane < R) {
-                    for (int tt = 0; tt < R; ++tt) s = fmaf(PK[(int64_t)i * R + tt], TUs[tt * R + lane], s);
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) {
+                        const float4 tu = *reinterpret_cast<const float4*>(&TUt[lane * RP + 4 * c]);
+                        s = fmaf(pt[4 * c], tu.x, s);
+                        if (4 * c + 1 < R) s = fmaf(pt[4 * c + 1], tu.y, s);
+                        if (4 * c + 2 < R) s = fmaf(pt[4 * c + 2], tu.z, s);
+                        if (4 * c + 3 < R) s = fmaf(pt[4 * c + 3], tu.w, s);
+                    }
                 }
                 float av[R];
 #pragma unroll
-                for (int kk = 0; kk < R; ++kk) av[kk] = __shfl(s, kk, 64);
-                for (int j = lane; j < n; j += 64) {
-                    float l = 0.f;
+                for (int kk = 0; kk < R; ++kk) av[kk] = lane_bcast(s, kk);
 #pragma unroll
-                    for (int kk = 0; kk < R; ++kk) l = fmaf(av[kk], Vs[kk * n + j], l);
-                    const float yv = YK ? YK[(int64_t)i * ldy + j] : 0.f;
-                    const float Rr = M[(int64_t)i * ldm + j] - l + yv * imu;
-                    const float a1 = Rr - t, b1 = Rr + t;
-                    it->S[(int64_t)i * it->lds + j] = (a1 > 0.f ? a1 : 0.f) + (b1 < 0.f ? b1 : 0.f);
+                for (int v = 0; v < kBNV; ++v) {
+                    const int j = lane + 64 * v;
+                    if (j < n) {
+                        float vv[RP];
+#pragma unroll
+                        for (int c = 0; c < RC; ++c) {
+                            const float4 t4 = *reinterpret_cast<const float4*>(&Vs[(c * kBNMax + j) * 4]);
+                            vv[4 * c] = t4.x; vv[4 * c + 1] = t4.y; vv[4 * c + 2] = t4.z; vv[4 * c + 3] = t4.w;
+                        }
+                        float l = 0.f;
+#pragma unroll
+                        for (int kk = 0; kk < R; ++kk) l = fmaf(av[kk], vv[kk], l);
+                        const float Rr = cm[v] - l + cy[v] * imu;
+                        const float a1 = Rr - t, b1 = Rr + t;
+                        S[(int64_t)i * d.lds + j] = (a1 > 0.f ? a1 : 0.f) + (b1 < 0.f ? b1 : 0.f);
+                    }
                 }
+#pragma unroll
+                for (int v = 0; v < kBNV; ++v) { cm[v] = nm[v]; cy[v] = ny[v]; }
+                cp = np;
             }
         }
         // smallest eigenvalue of the returned B (Appendix, Lemma 2)
@@ -318,11 +520,15 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
 
 #define SFR_BATCH_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16)
 
+#ifndef SFR_BATCH_RW
+#define SFR_BATCH_RW(R) ((R) <= 12 ? 2 : 1)
+#endif
+
 hipError_t launch_batch(BatchItemDev* items, int count, int R, const BatchParams& bp, hipStream_t s)
 {
     switch (R) {
 #define CASE(rr)                                                                                \
-    case rr: hipLaunchKernelGGL(batch_kernel<rr>, dim3(count), dim3(kBTPB), 0, s, items, bp); \
+    case rr: hipLaunchKernelGGL((batch_kernel<rr, SFR_BATCH_RW(rr)>), dim3(count), dim3(kBTPB), 0, s, items, bp); \
         return hipGetLastError();
         SFR_BATCH_R_LIST(CASE)
 #undef CASE
