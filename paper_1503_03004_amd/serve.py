@@ -1,0 +1,173 @@
+"""Continuous-batching front end for many independent decompositions.
+
+Requests (M, r, lambda, mu_0, tol) arrive over time; every problem is solved
+by the batched FR-ADM kernel (one workgroup per problem, the whole iteration
+on one CU; sfr_solve_batch).  The server keeps `workers` batched handles,
+each with its own HIP stream and host thread, so up to `workers` launches
+are on the GPU at once: a worker takes every request that has arrived (up to
+its capacity), launches, and when the launch returns retires the batch and
+takes the next one.  A request's latency is the time from its arrival to the
+return of the launch that solved it.
+
+Admission is by device memory: each handle holds `capacity` workspace slots
+sized for the largest admitted problem, and the capacity is cut so that all
+handles fit in a fraction of the free HBM reported by the runtime.  Requests
+beyond the handles' limits (n > 512, r > 16, m > max_m) are rejected at
+submission.
+
+This module only schedules: all arithmetic runs in the HIP library.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from dataclasses import dataclass, field
+
+from ._binding import BatchSolver, SFRError
+
+# limits of the batched kernel (sfr_create_batch)
+MAX_N = 512
+MAX_R = 16
+
+
+def slot_bytes(max_m: int, max_n: int) -> int:
+    """Device workspace of one batched slot: two Y buffers (max_m x ldy),
+    two P (max_m x 16) and two Q (max_n x 16) buffers, FP32, and its
+    descriptor."""
+    ldy = (max_n + 3) // 4 * 4
+    return 4 * (2 * max_m * ldy + 2 * max_m * 16 + 2 * max_n * 16) + 256
+
+
+@dataclass
+class Request:
+    M: object                 # float32 CUDA tensor, row-major
+    r: int
+    lam: float
+    mu: float
+    tol: float
+    arrival: float = 0.0      # seconds after the start of the run
+    # filled by the server
+    start: float = field(default=float("nan"))
+    done: float = field(default=float("nan"))
+    result: tuple | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class BatchServer:
+    def __init__(self, max_m: int, max_n: int = MAX_N, max_r: int = MAX_R, *, workers: int = 4,
+                 capacity: int = 256, hbm_fraction: float = 0.5, want_S: bool = True, rho: float = 1.5,
+                 mu_bar: float = 1e9, max_iter: int = 300):
+        import torch
+        if not (1 <= max_n <= MAX_N and 1 <= max_r <= MAX_R and max_m >= 1):
+            raise ValueError("batched limits: n <= 512, r <= 16")
+        free, _ = torch.cuda.mem_get_info()
+        per_slot = slot_bytes(max_m, max_n)
+        fit = int(free * hbm_fraction) // (workers * per_slot)
+        if fit < 1:
+            raise MemoryError("not enough free device memory for one batched slot per worker")
+        self.capacity = min(int(capacity), fit)
+        self.max_m, self.max_n, self.max_r = int(max_m), int(max_n), int(max_r)
+        self.want_S = want_S
+        self.workers = int(workers)
+        self.solvers = [BatchSolver(self.capacity, max_m, max_n, max_r, rho=rho, mu_bar=mu_bar, max_iter=max_iter)
+                        for _ in range(self.workers)]
+        self.streams = [torch.cuda.Stream() for _ in range(self.workers)]
+        self.launches = 0
+        self.batch_sizes: list[int] = []
+
+    def admissible(self, req: Request) -> bool:
+        m, n = req.M.shape
+        return m <= self.max_m and n <= self.max_n and 1 <= req.r <= min(self.max_r, m, n)
+
+    def run(self, requests: list[Request]) -> float:
+        """Release the requests at their arrival times (seconds from now),
+        solve them all, and return the wall time of the run.  Each request
+        gets .start, .done (seconds from the start) and .result =
+        (U, B, V, S, Info)."""
+        import torch
+        for q in requests:
+            if not self.admissible(q):
+                raise ValueError("request beyond the server's limits")
+        order = sorted(range(len(requests)), key=lambda i: requests[i].arrival)
+        pending: collections.deque = collections.deque()
+        cv = threading.Condition()
+        state = {"released": 0, "error": None}
+        total = len(requests)
+        t0 = time.perf_counter()
+
+        def worker(w: int):
+            bs, st = self.solvers[w], self.streams[w]
+            if st is not None:
+                torch.cuda.set_stream(st)
+            while True:
+                with cv:
+                    while not pending and state["released"] < total and state["error"] is None:
+                        cv.wait()
+                    if state["error"] is not None or (not pending and state["released"] >= total):
+                        return
+                    batch = [pending.popleft() for _ in range(min(len(pending), self.capacity))]
+                now = time.perf_counter() - t0
+                for q in batch:
+                    q.start = now
+                try:
+                    out = bs.solve([(q.M, q.r, q.lam, q.mu, q.tol) for q in batch], want_S=self.want_S,
+                                   stream=st, raise_on_error=False)
+                except SFRError as e:          # argument or device failure: stop the run
+                    with cv:
+                        state["error"] = e
+                        cv.notify_all()
+                    return
+                done = time.perf_counter() - t0
+                for q, res in zip(batch, out):
+                    q.done = done
+                    q.result = res
+                with cv:
+                    self.launches += 1
+                    self.batch_sizes.append(len(batch))
+
+        threads = [threading.Thread(target=worker, args=(w,), daemon=True) for w in range(self.workers)]
+        for t in threads:
+            t.start()
+        for i in order:
+            q = requests[i]
+            delay = q.arrival - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            with cv:
+                pending.append(q)
+                state["released"] += 1
+                cv.notify()
+        with cv:
+            cv.notify_all()
+        for t in threads:
+            t.join()
+        if state["error"] is not None:
+            raise state["error"]
+        return time.perf_counter() - t0
+
+    def close(self):
+        for s in self.solvers:
+            s.close()
+        self.solvers = []
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def percentile(values, p: float) -> float:
+    """p-th percentile (0..100) by linear interpolation between order
+    statistics."""
+    v = sorted(values)
+    if not v:
+        return float("nan")
+    x = (len(v) - 1) * p / 100.0
+    lo = int(x)
+    hi = min(lo + 1, len(v) - 1)
+    return v[lo] + (v[hi] - v[lo]) * (x - lo)

@@ -1,0 +1,101 @@
+"""Host logic of the continuous-batching server (paper_1503_03004_amd.serve),
+with a stand-in for the batched solver: arrival-ordered release, batches
+within capacity, every request retired exactly once, latency accounting,
+admission limits, percentiles."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_1503_03004_amd import serve
+
+
+class FakeM:
+    def __init__(self, m, n):
+        self.shape = (m, n)
+
+
+class FakeSolver:
+    """Takes `cost` seconds per launch and records what it was given."""
+
+    def __init__(self, capacity, cost=0.004):
+        self.capacity, self.cost = capacity, cost
+        self.calls = []
+        self.lock = threading.Lock()
+
+    def solve(self, items, want_S=True, stream=None, raise_on_error=False):
+        assert 1 <= len(items) <= self.capacity
+        with self.lock:
+            self.calls.append(len(items))
+        time.sleep(self.cost)
+        return [("U", "B", "V", None, ("info", it[1])) for it in items]
+
+    def close(self):
+        pass
+
+
+def make_server(workers=3, capacity=8, cost=0.004):
+    s = serve.BatchServer.__new__(serve.BatchServer)
+    s.capacity, s.workers, s.want_S = capacity, workers, True
+    s.max_m, s.max_n, s.max_r = 2048, 512, 16
+    s.solvers = [FakeSolver(capacity, cost) for _ in range(workers)]
+    s.streams = [None] * workers
+    s.launches, s.batch_sizes = 0, []
+    return s
+
+
+def poisson_requests(count, rate, seed=0):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    return [serve.Request(M=FakeM(100, 50), r=int(rng.integers(2, 17)), lam=0.1, mu=1.0, tol=1e-6,
+                          arrival=float(t[i])) for i in range(count)]
+
+
+def test_every_request_is_retired_once_within_capacity():
+    srv = make_server(workers=3, capacity=8)
+    reqs = poisson_requests(300, rate=3000.0, seed=1)
+    wall = srv.run(reqs)
+    assert all(q.result is not None for q in reqs)
+    assert sum(srv.batch_sizes) == len(reqs) == sum(len(s.calls) and sum(s.calls) for s in srv.solvers)
+    assert max(srv.batch_sizes) <= 8 and srv.launches == len(srv.batch_sizes)
+    for q in reqs:
+        assert q.start >= q.arrival - 1e-9          # never started before it arrived
+        assert q.done >= q.start + 0.004 - 1e-4     # retired after its launch ran
+        assert q.result[4][1] == q.r                # its own result
+    assert wall >= reqs[-1].arrival
+
+
+def test_overload_forms_full_batches():
+    """All requests at t = 0 with slow launches: batches fill to capacity."""
+    srv = make_server(workers=2, capacity=16, cost=0.01)
+    reqs = poisson_requests(160, rate=1e9, seed=2)
+    srv.run(reqs)
+    assert srv.batch_sizes.count(16) >= 8
+
+
+def test_latency_and_percentiles():
+    srv = make_server(workers=4, capacity=4, cost=0.002)
+    reqs = poisson_requests(100, rate=500.0, seed=3)
+    srv.run(reqs)
+    lat = [q.latency for q in reqs]
+    assert min(lat) >= 0.002 - 1e-4
+    assert serve.percentile(lat, 50) <= serve.percentile(lat, 99) <= max(lat)
+    assert serve.percentile([1.0, 2.0, 3.0, 4.0], 50) == 2.5
+    assert serve.percentile([5.0], 99) == 5.0
+
+
+def test_admission_limits():
+    srv = make_server()
+    ok = serve.Request(M=FakeM(2048, 512), r=16, lam=0.1, mu=1.0, tol=1e-6)
+    assert srv.admissible(ok)
+    for m, n, r in ((2049, 100, 4), (100, 513, 4), (100, 100, 17), (10, 100, 11)):
+        assert not srv.admissible(serve.Request(M=FakeM(m, n), r=r, lam=0.1, mu=1.0, tol=1e-6))
+    with pytest.raises(ValueError):
+        srv.run([serve.Request(M=FakeM(100, 600), r=4, lam=0.1, mu=1.0, tol=1e-6)])
+
+
+def test_slot_bytes_matches_the_library_layout():
+    # 2 Y (m x ldy) + 2 P (m x 16) + 2 Q (n x 16) floats, plus the descriptor
+    assert serve.slot_bytes(2048, 512) == 4 * (2 * 2048 * 512 + 2 * 2048 * 16 + 2 * 512 * 16) + 256
+    assert serve.slot_bytes(10, 5) == 4 * (2 * 10 * 8 + 2 * 10 * 16 + 2 * 5 * 16) + 256

@@ -230,3 +230,36 @@ def nystrom_large_device(seed: int = 0, m: int = 40000, n: int = 40000, r: int =
         M[i0:i1] += torch.where(mask, lap, torch.zeros_like(lap))
         del u, mask, v, lap
     return M, A, B, 1.0 / math.sqrt(max(m, n))
+
+
+def stream_device(seed: int = 0, count: int = 4000, rate: float = 2000.0, device="cuda"):
+    """The Poisson request stream (`stream`: arrival times, m U[64, 2048],
+    n U[32, 512], r U{2..16}, outlier fraction U[0.05, 0.15]) with every
+    request's matrix drawn in device memory by torch's seeded generator:
+    L0 = A B^T with N(0,1) factors, Bernoulli(frac) outliers U[-50, 50].
+    mu_0 = 1.25 / ||M||_2 with the norm from a fixed-count power iteration
+    on the device (an input of the solve, shared by every side that solves
+    the request).  Returns a list of dicts (id, t, m, n, r, frac, M, lam, mu).
+    """
+    import torch
+    reqs = stream(seed=seed, count=count, rate=rate)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed + 77)
+    out = []
+    for q in reqs:
+        m, n, r = q["m"], q["n"], q["r"]
+        A = torch.randn(m, r, generator=g, device=device, dtype=torch.float32)
+        B = torch.randn(n, r, generator=g, device=device, dtype=torch.float32)
+        M = A @ B.T
+        mask = torch.rand(m, n, generator=g, device=device) < q["frac"]
+        vals = (torch.rand(m, n, generator=g, device=device) * 2.0 - 1.0) * 50.0
+        M = torch.where(mask, M + vals, M).contiguous()
+        x = torch.ones(n, 1, device=device, dtype=torch.float32) / math.sqrt(n)
+        for _ in range(12):
+            x = M.T @ (M @ x)
+            x = x / torch.linalg.vector_norm(x)
+        s = torch.linalg.vector_norm(M @ x)
+        out.append(dict(q, M=M, lam=1.0 / math.sqrt(max(m, n)), mu_t=s))
+    for d in out:       # one host sync for all the norms
+        d["mu"] = 1.25 / float(d.pop("mu_t"))
+    return out
