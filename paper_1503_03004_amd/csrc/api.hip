@@ -535,6 +535,9 @@ sfr_status sfr_destroy(sfr_handle h)
     engine_destroy(h->top);
     free_all(h->allocs);
     if (h->items_h) (void)hipHostFree(h->items_h);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->side) (void)hipStreamDestroy(h->side);
     h->magic = 0;
     delete h;
     return SFR_OK;

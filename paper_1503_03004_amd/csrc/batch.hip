@@ -38,6 +38,8 @@ __device__ inline __attribute__((address_space(1))) T* as_global(T* p)
     return (__attribute__((address_space(1))) T*)p;
 }
 
+template <bool B> struct BoolTag { static constexpr bool value = B; };
+
 __device__ inline float lane_bcast(float v, int l)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
@@ -45,7 +47,7 @@ __device__ inline float lane_bcast(float v, int l)
 
 // RW rows per wavefront per band (a band is 8 RW rows): two rows share each
 // V column read; one row keeps the larger ranks' band loop within registers.
-template <int R, int RW>
+template <int R, int RW, bool NARROW>
 __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, BatchParams bp)
 {
     static_assert(R <= 16, "batched solver: r <= 16");
@@ -76,7 +78,7 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
     // Between the sweep and the step the same space stages Q_k (Vs[j R + k]).
     __shared__ __align__(16) float Vs[RP * kBNMax];
     __shared__ __align__(16) float Xs[kBH * kBNMax];   // x of the band; FP64 G_Q partials in the step
-    __shared__ __align__(16) float Ps[kBH * 16];       // p of the band's rows
+    __shared__ __align__(16) float Ps[kBH * 8 * 16];   // p of the band's rows (up to 8 rows per wavefront step)
     __shared__ __align__(16) float TUt[R * RP];        // T_U transposed: TUt[k RP + t] = T_U[t][k]
     __shared__ __align__(16) float TVt[R * RP];        // T_V transposed (FP32)
     __shared__ double Gp[R * LDP], Gq[R * LDP], Bm[R * LDP], C1[R * LDP], C2[R * LDP];
@@ -122,7 +124,11 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
 
     double mu = d.mu0, mu_prev = d.mu0, nrmM = 0.0, res = 0.0;
     int32_t status = kOK, iters = 0;
-    const int nbands = (m + kBH - 1) / kBH;
+    // lanes per row: the fewest (8 .. 64) that cover n with 8 columns per
+    // lane, and at least R (a group's lanes form the entries of a_i)
+    int lpr = 8;
+    while (lpr * kBNV < n) lpr <<= 1;
+    if (lpr < (R <= 8 ? 8 : 16)) lpr = (R <= 8 ? 8 : 16);
     for (int k = 1;; ++k) {
         const int mode = (k == 1) ? 0 : (k == 2 ? 1 : 2);
         const gfloat* Yp = ((k - 1) & 1) ? Y1 : Y0;
@@ -140,149 +146,180 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
         for (int kk = 0; kk < R; ++kk) q[kk] = 0.f;
         double gp = 0.0;      // G_P entry `tid` (tid < E)
         double acc2 = 0.0;
-        // The loads of band b + 1 (M, Y_{k-1} and the P rows) are issued
-        // before band b is computed, so one band's loads are always in
-        // flight behind the arithmetic of the other.
-        auto load_band = [&](int b, float* mv, float* yv, float* pr) {
-#pragma unroll
-            for (int h = 0; h < kBRW; ++h) {
-                const int i = b * kBH + h * kBNW + wave;
-                const bool row_ok = i < m;
-#pragma unroll
-                for (int v = 0; v < kBNV; ++v) {
-                    const int j = lane + 64 * v;
-                    const bool ok = row_ok && j < n;
-                    mv[h * kBNV + v] = ok ? M[(int64_t)i * ldm + j] : 0.f;
-                    yv[h * kBNV + v] = (ok && mode == 2) ? Yp[(int64_t)i * ldy + j] : 0.f;
-                }
-                // lane t < R holds P_{i,t}
-                pr[h] = (row_ok && mode != 0 && lane < R) ? Pp[(int64_t)i * R + lane] : 0.f;
-            }
-        };
-        float cm[kBRW * kBNV], cy[kBRW * kBNV], cp[kBRW];
-        load_band(0, cm, cy, cp);
-        for (int b = 0; b < nbands; ++b) {
-            float nm[kBRW * kBNV], ny[kBRW * kBNV], np[kBRW];
-#pragma unroll
-            for (int e = 0; e < kBRW * kBNV; ++e) { nm[e] = 0.f; ny[e] = 0.f; }
-#pragma unroll
-            for (int e = 0; e < kBRW; ++e) np[e] = 0.f;
-            if (b + 1 < nbands) load_band(b + 1, nm, ny, np);
-            // a_i = P_i T_U for the wavefront's rows, uniform (scalar registers)
-            float av[kBRW][R];
-            if (mode != 0) {
+        // NARROW: lpr < 64 lanes per row, 64 / lpr rows per wavefront at once
+        // (broadcasts and reductions within lane groups); otherwise one row
+        // per wavefront, broadcasts through scalar registers.
+        auto sweep_bands = [&](auto tag) __attribute__((always_inline)) {
+            const int L = NARROW ? lpr : 64;          // lanes per row
+            const int RPW = NARROW ? 64 / lpr : 1;    // rows per wavefront and step
+            const int g = NARROW ? lane / lpr : 0;    // row group of this lane
+            const int li = NARROW ? (lane & (lpr - 1)) : lane;
+            const int HB = kBH * RPW;                 // rows per band
+            const int nx = kBNMax / RPW;              // row pitch of Xs
+            const int nb = (m + HB - 1) / HB;
+            auto row_of = [&](int b, int h) { return b * HB + (h * kBNW + wave) * RPW + g; };
+            // The loads of band b + 1 (M, Y_{k-1} and the P rows) are issued
+            // before band b is computed, so one band's loads are always in
+            // flight behind the arithmetic of the other.
+            auto load_band = [&](int b, float* mv, float* yv, float* pr) {
 #pragma unroll
                 for (int h = 0; h < kBRW; ++h) {
-                    float pt[R];
+                    const int i = row_of(b, h);
+                    const bool row_ok = i < m;
 #pragma unroll
-                    for (int t = 0; t < R; ++t) pt[t] = lane_bcast(cp[h], t);
-                    float s = 0.f;
-                    if (lane < R) {
+                    for (int v = 0; v < kBNV; ++v) {
+                        const int j = li + L * v;
+                        const bool ok = row_ok && j < n;
+                        mv[h * kBNV + v] = ok ? M[(int64_t)i * ldm + j] : 0.f;
+                        yv[h * kBNV + v] = (ok && mode == 2) ? Yp[(int64_t)i * ldy + j] : 0.f;
+                    }
+                    // lane t < R of the row's group holds P_{i,t}
+                    pr[h] = (row_ok && mode != 0 && li < R) ? Pp[(int64_t)i * R + li] : 0.f;
+                }
+            };
+            float cm[kBRW * kBNV], cy[kBRW * kBNV], cp[kBRW];
+            load_band(0, cm, cy, cp);
+            for (int b = 0; b < nb; ++b) {
+                float nm[kBRW * kBNV], ny[kBRW * kBNV], np[kBRW];
 #pragma unroll
-                        for (int c = 0; c < RC; ++c) {
-                            const float4 tu = *reinterpret_cast<const float4*>(&TUt[lane * RP + 4 * c]);
-                            s = fmaf(pt[4 * c], tu.x, s);
-                            if (4 * c + 1 < R) s = fmaf(pt[4 * c + 1], tu.y, s);
-                            if (4 * c + 2 < R) s = fmaf(pt[4 * c + 2], tu.z, s);
-                            if (4 * c + 3 < R) s = fmaf(pt[4 * c + 3], tu.w, s);
+                for (int e = 0; e < kBRW * kBNV; ++e) { nm[e] = 0.f; ny[e] = 0.f; }
+#pragma unroll
+                for (int e = 0; e < kBRW; ++e) np[e] = 0.f;
+                if (b + 1 < nb) load_band(b + 1, nm, ny, np);
+                // a_i = P_i T_U for the wavefront's rows
+                float av[kBRW][R];
+                if (mode != 0) {
+#pragma unroll
+                    for (int h = 0; h < kBRW; ++h) {
+                        float s = 0.f;
+                        if constexpr (!NARROW) {
+                            // one row: uniform over the wavefront (scalar registers)
+                            float pt[R];
+#pragma unroll
+                            for (int t = 0; t < R; ++t) pt[t] = lane_bcast(cp[h], t);
+                            if (lane < R) {
+#pragma unroll
+                                for (int c = 0; c < RC; ++c) {
+                                    const float4 tu = *reinterpret_cast<const float4*>(&TUt[lane * RP + 4 * c]);
+                                    s = fmaf(pt[4 * c], tu.x, s);
+                                    if (4 * c + 1 < R) s = fmaf(pt[4 * c + 1], tu.y, s);
+                                    if (4 * c + 2 < R) s = fmaf(pt[4 * c + 2], tu.z, s);
+                                    if (4 * c + 3 < R) s = fmaf(pt[4 * c + 3], tu.w, s);
+                                }
+                            }
+#pragma unroll
+                            for (int kk = 0; kk < R; ++kk) av[h][kk] = lane_bcast(s, kk);
+                        } else {
+                            // one row per lane group: broadcasts within the group
+                            const int base = g * L;
+                            const int kc = li < R ? li : 0;
+#pragma unroll
+                            for (int c = 0; c < RC; ++c) {
+                                const float4 tu = *reinterpret_cast<const float4*>(&TUt[kc * RP + 4 * c]);
+                                s = fmaf(__shfl(cp[h], base + 4 * c, 64), tu.x, s);
+                                if (4 * c + 1 < R) s = fmaf(__shfl(cp[h], base + 4 * c + 1, 64), tu.y, s);
+                                if (4 * c + 2 < R) s = fmaf(__shfl(cp[h], base + 4 * c + 2, 64), tu.z, s);
+                                if (4 * c + 3 < R) s = fmaf(__shfl(cp[h], base + 4 * c + 3, 64), tu.w, s);
+                            }
+#pragma unroll
+                            for (int kk = 0; kk < R; ++kk) av[h][kk] = __shfl(s, base + kk, 64);
                         }
                     }
-#pragma unroll
-                    for (int kk = 0; kk < R; ++kk) av[h][kk] = lane_bcast(s, kk);
                 }
-            }
-            float p[kBRW][R];
+                float p[kBRW][R];
 #pragma unroll
-            for (int h = 0; h < kBRW; ++h)
+                for (int h = 0; h < kBRW; ++h)
 #pragma unroll
-                for (int kk = 0; kk < R; ++kk) p[h][kk] = 0.f;
-            float rowacc = 0.f;
+                    for (int kk = 0; kk < R; ++kk) p[h][kk] = 0.f;
+                float rowacc = 0.f;
 #pragma unroll
-            for (int v = 0; v < kBNV; ++v) {
-                const int j = lane + 64 * v;
-                const bool jok = j < n;
-                // column j of V_k, read once for the wavefront's rows
-                float vv[RP];
-                if (jok) {
+                for (int v = 0; v < kBNV; ++v) {
+                    const int j = li + L * v;
+                    const bool jok = j < n;
+                    // column j of V_k, read once for the wavefront's rows
+                    float vv[RP];
+                    if (jok) {
 #pragma unroll
-                    for (int c = 0; c < RC; ++c) {
-                        const float4 t4 = *reinterpret_cast<const float4*>(&Vs[(c * kBNMax + j) * 4]);
-                        vv[4 * c] = t4.x; vv[4 * c + 1] = t4.y; vv[4 * c + 2] = t4.z; vv[4 * c + 3] = t4.w;
+                        for (int c = 0; c < RC; ++c) {
+                            const float4 t4 = *reinterpret_cast<const float4*>(&Vs[(c * kBNMax + j) * 4]);
+                            vv[4 * c] = t4.x; vv[4 * c + 1] = t4.y; vv[4 * c + 2] = t4.z; vv[4 * c + 3] = t4.w;
+                        }
+                    } else {
+#pragma unroll
+                        for (int kk = 0; kk < RP; ++kk) vv[kk] = 0.f;
                     }
-                } else {
 #pragma unroll
-                    for (int kk = 0; kk < RP; ++kk) vv[kk] = 0.f;
+                    for (int h = 0; h < kBRW; ++h) {
+                        const int lrow = (h * kBNW + wave) * RPW + g;
+                        const int i = b * HB + lrow;
+                        const bool ok = (i < m) && jok;
+                        const float mv = cm[h * kBNV + v];
+                        float x;
+                        if (mode == 0) {
+                            x = mv;
+                            rowacc = fmaf(mv, mv, rowacc);
+                        } else {
+                            const float yp = cy[h * kBNV + v];
+                            float l = 0.f;
+#pragma unroll
+                            for (int kk = 0; kk < R; ++kk) l = fmaf(av[h][kk], vv[kk], l);
+                            const float Rr = mv - l + yp * imup;
+                            const float y = fminf(fmaxf(mup * Rr, -lam), lam);
+                            const float dy = y - yp;
+                            rowacc = ok ? fmaf(dy, dy, rowacc) : rowacc;
+                            x = l + dy * imup + y * imuc;
+                            if (ok) Yn[(int64_t)i * ldy + j] = y;
+                        }
+                        x = ok ? x : 0.f;
+                        Xs[lrow * nx + j] = x;
+#pragma unroll
+                        for (int kk = 0; kk < R; ++kk) p[h][kk] = fmaf(x, vv[kk], p[h][kk]);
+                    }
                 }
+                acc2 += (double)rowacc;
 #pragma unroll
                 for (int h = 0; h < kBRW; ++h) {
-                    const int lr = h * kBNW + wave;
-                    const int i = b * kBH + lr;
-                    const bool ok = (i < m) && jok;
-                    const float mv = cm[h * kBNV + v];
-                    float x;
-                    if (mode == 0) {
-                        x = mv;
-                        rowacc = fmaf(mv, mv, rowacc);
-                    } else {
-                        const float yp = cy[h * kBNV + v];
-                        float l = 0.f;
+                    const int lrow = (h * kBNW + wave) * RPW + g;
+                    const int i = b * HB + lrow;
+                    const bool row_ok = i < m;
 #pragma unroll
-                        for (int kk = 0; kk < R; ++kk) l = fmaf(av[h][kk], vv[kk], l);
-                        const float Rr = mv - l + yp * imup;
-                        const float y = fminf(fmaxf(mup * Rr, -lam), lam);
-                        const float dy = y - yp;
-                        rowacc = ok ? fmaf(dy, dy, rowacc) : rowacc;
-                        x = l + dy * imup + y * imuc;
-                        if (ok) Yn[(int64_t)i * ldy + j] = y;
+                    for (int kk = 0; kk < R; ++kk)
+                        for (int off = L >> 1; off > 0; off >>= 1) p[h][kk] += __shfl_xor(p[h][kk], off, 64);
+                    if (li < 16) {
+                        float mine = 0.f;
+#pragma unroll
+                        for (int kk = 0; kk < R; ++kk) mine = (kk == li) ? p[h][kk] : mine;
+                        Ps[lrow * 16 + li] = row_ok ? mine : 0.f;
+                        if (row_ok && li < R) Pn[(int64_t)i * R + li] = mine;
                     }
-                    x = ok ? x : 0.f;
-                    Xs[lr * kBNMax + j] = x;
-#pragma unroll
-                    for (int kk = 0; kk < R; ++kk) p[h][kk] = fmaf(x, vv[kk], p[h][kk]);
                 }
-            }
-            acc2 += (double)rowacc;
-#pragma unroll
-            for (int h = 0; h < kBRW; ++h) {
-                const int lr = h * kBNW + wave;
-                const int i = b * kBH + lr;
-                const bool row_ok = i < m;
-#pragma unroll
-                for (int kk = 0; kk < R; ++kk)
-                    for (int off = 32; off > 0; off >>= 1) p[h][kk] += __shfl_xor(p[h][kk], off, 64);
-                if (lane < 16) {
-                    float mine = 0.f;
-#pragma unroll
-                    for (int kk = 0; kk < R; ++kk) mine = (kk == lane) ? p[h][kk] : mine;
-                    Ps[lr * 16 + lane] = row_ok ? mine : 0.f;
-                    if (row_ok && lane < R) Pn[(int64_t)i * R + lane] = mine;
-                }
-            }
-            __syncthreads();
-            // column pass: thread j owns column j; FP64 G_P of the band's rows
-            if (tid < n) {
+                __syncthreads();
+                // column pass: thread j owns column j; FP64 G_P of the band's rows
+                if (tid < n) {
 #pragma unroll 4
-                for (int h = 0; h < kBH; ++h) {
-                    const float xv = Xs[h * kBNMax + tid];
+                    for (int h = 0; h < HB; ++h) {
+                        const float xv = Xs[h * nx + tid];
 #pragma unroll
-                    for (int c = 0; c < RC; ++c) {
-                        const float4 pp = *reinterpret_cast<const float4*>(&Ps[h * 16 + 4 * c]);
-                        q[4 * c] = fmaf(xv, pp.x, q[4 * c]);
-                        if (4 * c + 1 < R) q[4 * c + 1] = fmaf(xv, pp.y, q[4 * c + 1]);
-                        if (4 * c + 2 < R) q[4 * c + 2] = fmaf(xv, pp.z, q[4 * c + 2]);
-                        if (4 * c + 3 < R) q[4 * c + 3] = fmaf(xv, pp.w, q[4 * c + 3]);
+                        for (int c = 0; c < RC; ++c) {
+                            const float4 pp = *reinterpret_cast<const float4*>(&Ps[h * 16 + 4 * c]);
+                            q[4 * c] = fmaf(xv, pp.x, q[4 * c]);
+                            if (4 * c + 1 < R) q[4 * c + 1] = fmaf(xv, pp.y, q[4 * c + 1]);
+                            if (4 * c + 2 < R) q[4 * c + 2] = fmaf(xv, pp.z, q[4 * c + 2]);
+                            if (4 * c + 3 < R) q[4 * c + 3] = fmaf(xv, pp.w, q[4 * c + 3]);
+                        }
                     }
                 }
-            }
-            if (tid < E) {
-                for (int h = 0; h < kBH; ++h) gp = fma((double)Ps[h * 16 + gx], (double)Ps[h * 16 + gy], gp);
-            }
-            __syncthreads();
+                if (tid < E) {
+                    for (int h = 0; h < HB; ++h) gp = fma((double)Ps[h * 16 + gx], (double)Ps[h * 16 + gy], gp);
+                }
+                __syncthreads();
 #pragma unroll
-            for (int e = 0; e < kBRW * kBNV; ++e) { cm[e] = nm[e]; cy[e] = ny[e]; }
+                for (int e = 0; e < kBRW * kBNV; ++e) { cm[e] = nm[e]; cy[e] = ny[e]; }
 #pragma unroll
-            for (int e = 0; e < kBRW; ++e) cp[e] = np[e];
-        }
+                for (int e = 0; e < kBRW; ++e) cp[e] = np[e];
+            }
+        };
+        sweep_bands(BoolTag<NARROW>{});
         // Q_k: to the workspace (the returned factors read it) and to LDS
         if (tid < n) {
 #pragma unroll
@@ -364,8 +401,9 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
             Bm[i * LDP + j] = in ? T2[i * LDP + j] : (i == j ? 1.0 : 0.0);
         }
         if (RP > R) {
-            for (int e = tid; e < R * (RP - R); e += NT) {
-                const int j = e / (RP - R), i = R + e % (RP - R);
+            constexpr int PW = RP > R ? RP - R : 1;
+            for (int e = tid; e < R * PW; e += NT) {
+                const int j = e / PW, i = R + e % PW;
                 TUt[j * RP + i] = 0.f;
                 TVt[j * RP + i] = 0.f;
             }
@@ -524,11 +562,17 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
 #define SFR_BATCH_RW(R) ((R) <= 12 ? 2 : 1)
 #endif
 
-hipError_t launch_batch(BatchItemDev* items, int count, int R, const BatchParams& bp, hipStream_t s)
+hipError_t launch_batch(BatchItemDev* items, int count, int R, bool narrow, const BatchParams& bp, hipStream_t s)
 {
     switch (R) {
-#define CASE(rr)                                                                                \
-    case rr: hipLaunchKernelGGL((batch_kernel<rr, SFR_BATCH_RW(rr)>), dim3(count), dim3(kBTPB), 0, s, items, bp); \
+#define CASE(rr)                                                                                          \
+    case rr:                                                                                              \
+        if (narrow)                                                                                       \
+            hipLaunchKernelGGL((batch_kernel<rr, 1, true>), dim3(count), dim3(kBTPB), 0, s, \
+                               items, bp);                                                                \
+        else                                                                                              \
+            hipLaunchKernelGGL((batch_kernel<rr, SFR_BATCH_RW(rr), false>), dim3(count), dim3(kBTPB), 0, s, \
+                               items, bp);                                                                \
         return hipGetLastError();
         SFR_BATCH_R_LIST(CASE)
 #undef CASE

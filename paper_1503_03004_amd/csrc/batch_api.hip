@@ -12,6 +12,9 @@
 
 namespace sfr {
 
+// items with n up to this many columns run in the narrow kernel variant
+constexpr int64_t kBatchNarrowN = 128;
+
 static int batch_bucket(int r)
 {
     static const int Rs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
@@ -71,12 +74,23 @@ sfr_status sfr_create_batch(sfr_handle* out, int32_t capacity, int64_t max_m, in
         h->items_h = nullptr;
         ok = false;
     }
+    // the narrow items' launch runs on a side stream of default priority,
+    // forked from and joined to the caller's stream with events
+    if (ok && (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+               hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+               hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess))
+        ok = false;
     if (!ok) {
         free_all(h->allocs);
+        if (h->items_h) (void)hipHostFree(h->items_h);
+        if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+        if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+        if (h->side) (void)hipStreamDestroy(h->side);
         (void)hipGetLastError();
         delete h;
         return SFR_ERR_NOMEM;
     }
+    h->order.assign((size_t)capacity, 0);
     *out = h;
     return SFR_OK;
 }
@@ -88,7 +102,7 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
     if (count < 0 || count > h->capacity || (count > 0 && !items)) return SFR_ERR_ARG;
     if (count == 0) return SFR_OK;
     // validate every item before any device work
-    int R = 1;
+    int Rw = 1, Rn = 1, nw = 0;
     for (int32_t i = 0; i < count; ++i) {
         const sfr_batch_item& it = items[i];
         if (it.m < 1 || it.m > h->max_m || it.n < 1 || it.n > h->max_n) return SFR_ERR_ARG;
@@ -96,19 +110,29 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
         if (!(it.lambda > 0.0) || it.lambda > 1e300 || !(it.mu > 0.0) || it.mu > 1e300) return SFR_ERR_ARG;
         if (!(it.tol >= 0.0) || it.tol > 1e300) return SFR_ERR_ARG;
         if (!it.M || !it.U || !it.B || !it.V || it.ldm < it.n || (it.S && it.lds < it.n)) return SFR_ERR_ARG;
-        R = std::max(R, batch_bucket(it.r));
+        if (it.n > kBatchNarrowN) {
+            Rw = std::max(Rw, batch_bucket(it.r));
+            ++nw;
+        } else {
+            Rn = std::max(Rn, batch_bucket(it.r));
+        }
+    }
+    // wide items (n > 128) first, then the narrow ones, each in call order
+    {
+        int32_t a = 0, b = nw;
+        for (int32_t i = 0; i < count; ++i) h->order[(items[i].n > kBatchNarrowN) ? a++ : b++] = i;
     }
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    for (int32_t i = 0; i < count; ++i) {
-        const sfr_batch_item& it = items[i];
-        BatchItemDev& d = h->items_h[i];
+    for (int32_t pos = 0; pos < count; ++pos) {
+        const sfr_batch_item& it = items[h->order[pos]];
+        BatchItemDev& d = h->items_h[pos];
         memset(&d, 0, sizeof(d));
         d.m = (int32_t)it.m; d.n = (int32_t)it.n; d.r = it.r; d.ldy = (int32_t)h->ldy;
         d.lambda = it.lambda; d.mu0 = it.mu; d.tol = it.tol;
         d.M = static_cast<const float*>(it.M); d.ldm = it.ldm;
         d.U = static_cast<float*>(it.U); d.B = it.B; d.V = static_cast<float*>(it.V);
         d.S = static_cast<float*>(it.S); d.lds = it.lds;
-        float* const* w = &h->slot_ws[(size_t)i * 6];
+        float* const* w = &h->slot_ws[(size_t)pos * 6];
         d.Y0 = w[0]; d.Y1 = w[1]; d.P0 = w[2]; d.P1 = w[3]; d.Q0 = w[4]; d.Q1 = w[5];
     }
     BatchParams bp;
@@ -117,16 +141,28 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
     bp.max_iter = h->prm.max_iter;
     bp.fixed_iters = h->prm.fixed_iters;
     const size_t bytes = sizeof(BatchItemDev) * (size_t)count;
-    if (hipMemcpyAsync(h->items_d, h->items_h, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
-        launch_batch(h->items_d, count, R, bp, s) != hipSuccess ||
-        hipMemcpyAsync(h->items_h, h->items_d, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+    const int nn = count - nw;
+    bool ok = hipMemcpyAsync(h->items_d, h->items_h, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+    if (ok && nn > 0) {
+        // fork: the side stream waits for the descriptors, runs the narrow
+        // items, and the caller's stream waits for it before the copy back
+        ok = hipEventRecord(h->ev_fork, s) == hipSuccess && hipStreamWaitEvent(h->side, h->ev_fork, 0) == hipSuccess &&
+             launch_batch(h->items_d + nw, nn, Rn, true, bp, h->side) == hipSuccess &&
+             hipEventRecord(h->ev_join, h->side) == hipSuccess;
+    }
+    if (ok && nw > 0) ok = launch_batch(h->items_d, nw, Rw, false, bp, s) == hipSuccess;
+    if (ok && nn > 0) ok = hipStreamWaitEvent(s, h->ev_join, 0) == hipSuccess;
+    if (!ok || hipMemcpyAsync(h->items_h, h->items_d, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
         (void)hipGetLastError();
+        (void)hipStreamSynchronize(h->side);
         return SFR_ERR_DEVICE;
     }
     sfr_status worst = SFR_OK;
-    for (int32_t i = 0; i < count; ++i) {
-        const BatchItemDev& d = h->items_h[i];
+    int32_t worst_i = count;      // the first failing item in call order
+    for (int32_t pos = 0; pos < count; ++pos) {
+        const int32_t i = h->order[pos];
+        const BatchItemDev& d = h->items_h[pos];
         sfr_status st = (sfr_status)d.status;
         if (st == SFR_OK && !(d.min_eig_B > 0.0)) st = SFR_WARN_NOT_SPD;
         if (d.status == 1) st = SFR_WARN_MAXITER;
@@ -142,7 +178,10 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
                 f.mu_final = d.mu_final;
             }
         }
-        if (st < 0 && worst >= 0) worst = st;
+        if (st < 0 && i < worst_i) {
+            worst = st;
+            worst_i = i;
+        }
     }
     return worst;
 }

@@ -104,6 +104,9 @@ struct sfr_ctx {
     sfr::BatchItemDev* items_d = nullptr;   // device descriptors (capacity)
     sfr::BatchItemDev* items_h = nullptr;   // pinned mirror
     std::vector<float*> slot_ws;            // per slot: Y0, Y1, P0, P1, Q0, Q1
+    std::vector<int32_t> order;             // launch position -> caller's item index
+    hipStream_t side = nullptr;             // second launch of a batch (narrow items)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     size_t batch_bytes = 0;
     std::vector<void*> allocs;
 };

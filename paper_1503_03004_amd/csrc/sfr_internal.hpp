@@ -197,7 +197,8 @@ struct BatchParams {
     int32_t max_iter, fixed_iters;
 };
 
-hipError_t launch_batch(BatchItemDev* items, int count, int R, const BatchParams& bp, hipStream_t s);
+// narrow: the kernel variant for n <= 128 (several rows per wavefront)
+hipError_t launch_batch(BatchItemDev* items, int count, int R, bool narrow, const BatchParams& bp, hipStream_t s);
 
 // Host-side launchers (sweep.hip / small.hip / dense.hip).  The sweep takes
 // an optional start/stop event pair bound to its dispatch.

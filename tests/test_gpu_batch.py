@@ -123,15 +123,20 @@ def test_stream_requests_tolerance_driven():
 
 def test_alone_vs_mix_same_bucket_bitwise():
     """An item solved alone and inside a mixed batch of the same rank bucket
-    gives bit-identical outputs and reports."""
+    gives bit-identical outputs and reports; both for a wide item (n > 128)
+    and for a narrow one (n <= 128: the second kernel variant, run beside
+    the first on a forked stream)."""
     A = make(300, 200, 7, seed=1)
-    mix = [make(120, 500, 8, seed=2), A, make(900, 64, 6, seed=3), make(50, 50, 5, seed=4)]
+    C = make(900, 64, 6, seed=3)
+    mix = [make(120, 500, 8, seed=2), A, C, make(50, 50, 5, seed=4)]
     with sfr.BatchSolver(4, 1024, 512, 8, max_iter=200) as bs:
         alone = run_batch(bs, [A], tol=1e-6)[0]
-        inmix = run_batch(bs, mix, tol=1e-6)[1]
-    for k in ("U", "B", "V", "S"):
-        assert np.array_equal(alone[k], inmix[k]), k
-    assert alone["info"] == inmix["info"]
+        alone_c = run_batch(bs, [C], tol=1e-6)[0]
+        out = run_batch(bs, mix, tol=1e-6)
+    for a, b in ((alone, out[1]), (alone_c, out[2])):
+        for k in ("U", "B", "V", "S"):
+            assert np.array_equal(a[k], b[k]), k
+        assert a["info"] == b["info"]
 
 
 def test_alone_vs_mix_across_buckets():
