@@ -72,6 +72,7 @@ def main():
     ap.add_argument("--requests", type=int, default=4000, help="serving: requests in the Poisson stream")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: mean arrival rate (requests/s)")
     ap.add_argument("--workers", type=int, default=4, help="serving: concurrent batched launches")
+    ap.add_argument("--max-batch", type=int, default=0, help="serving: requests per launch (0: capacity)")
     ap.add_argument("--solves", type=int, default=5, help="tolerance-driven solves timed for solves/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-iters", type=int, default=12, help="oracle iterations timed on the host (about 1 s each)")
@@ -288,7 +289,8 @@ def serving(args):
         return [serve.Request(M=q["M"], r=q["r"], lam=q["lam"], mu=q["mu"], tol=tol,
                               arrival=q["t"] if arrivals else 0.0) for q in src]
 
-    server = serve.BatchServer(max_m=2048, max_n=512, max_r=16, workers=args.workers, capacity=256)
+    server = serve.BatchServer(max_m=2048, max_n=512, max_r=16, workers=args.workers, capacity=256,
+                               max_batch=args.max_batch or None)
     server.run(requests(False, range(min(64, len(reqs)))))          # warm-up, untimed
     torch.cuda.synchronize()
 
@@ -382,7 +384,7 @@ def serving(args):
         "config": {"workload": f"serving: Poisson {args.rate:.0f} req/s, m U[64,2048], n U[32,512], r U{{2..16}}, "
                                f"5-15% outliers U[-50,50], FP32, tol {tol}",
                    "requests": len(run_reqs), "rate": args.rate, "workers": args.workers,
-                   "capacity": server.capacity, "seed": args.seed},
+                   "capacity": server.capacity, "max_batch": server.max_batch, "seed": args.seed},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "batch_kernel",
                      "launch_ms": launch_ms, "problems_per_launch": len(one), "hbm_alg_gbs": gbs},

@@ -59,8 +59,8 @@ class Request:
 
 class BatchServer:
     def __init__(self, max_m: int, max_n: int = MAX_N, max_r: int = MAX_R, *, workers: int = 4,
-                 capacity: int = 256, hbm_fraction: float = 0.5, want_S: bool = True, rho: float = 1.5,
-                 mu_bar: float = 1e9, max_iter: int = 300):
+                 capacity: int = 256, max_batch: int | None = None, hbm_fraction: float = 0.5,
+                 want_S: bool = True, rho: float = 1.5, mu_bar: float = 1e9, max_iter: int = 300):
         import torch
         if not (1 <= max_n <= MAX_N and 1 <= max_r <= MAX_R and max_m >= 1):
             raise ValueError("batched limits: n <= 512, r <= 16")
@@ -70,12 +70,16 @@ class BatchServer:
         if fit < 1:
             raise MemoryError("not enough free device memory for one batched slot per worker")
         self.capacity = min(int(capacity), fit)
+        # requests per launch: smaller launches leave room for the next ones
+        # (a launch lasts as long as its slowest problem)
+        self.max_batch = self.capacity if max_batch is None else max(1, min(int(max_batch), self.capacity))
         self.max_m, self.max_n, self.max_r = int(max_m), int(max_n), int(max_r)
         self.want_S = want_S
         self.workers = int(workers)
         self.solvers = [BatchSolver(self.capacity, max_m, max_n, max_r, rho=rho, mu_bar=mu_bar, max_iter=max_iter)
                         for _ in range(self.workers)]
         self.streams = [torch.cuda.Stream() for _ in range(self.workers)]
+        self.classes = worker_classes(self.workers)
         self.launches = 0
         self.batch_sizes: list[int] = []
 
@@ -93,7 +97,12 @@ class BatchServer:
             if not self.admissible(q):
                 raise ValueError("request beyond the server's limits")
         order = sorted(range(len(requests)), key=lambda i: requests[i].arrival)
-        pending: collections.deque = collections.deque()
+        # one queue per class: narrow problems (n <= 128) run in the library's
+        # second kernel variant; keeping the classes apart means a launch
+        # never needs the handle's side stream, so the streams in use stay
+        # at one per worker (HIP maps streams onto a few hardware queues, and
+        # launches that share one run one after the other)
+        queues = {False: collections.deque(), True: collections.deque()}
         cv = threading.Condition()
         state = {"released": 0, "error": None}
         total = len(requests)
@@ -101,6 +110,7 @@ class BatchServer:
 
         def worker(w: int):
             bs, st = self.solvers[w], self.streams[w]
+            pending = queues[self.classes[w]]
             if st is not None:
                 torch.cuda.set_stream(st)
             while True:
@@ -109,7 +119,7 @@ class BatchServer:
                         cv.wait()
                     if state["error"] is not None or (not pending and state["released"] >= total):
                         return
-                    batch = [pending.popleft() for _ in range(min(len(pending), self.capacity))]
+                    batch = [pending.popleft() for _ in range(min(len(pending), self.max_batch))]
                 now = time.perf_counter() - t0
                 for q in batch:
                     q.start = now
@@ -138,9 +148,9 @@ class BatchServer:
             if delay > 0:
                 time.sleep(delay)
             with cv:
-                pending.append(q)
+                queues[is_narrow(q)].append(q)
                 state["released"] += 1
-                cv.notify()
+                cv.notify_all()
         with cv:
             cv.notify_all()
         for t in threads:
@@ -159,6 +169,23 @@ class BatchServer:
 
     def __exit__(self, *exc):
         self.close()
+
+
+NARROW_N = 128   # problems with at most this many columns use the narrow kernel variant
+
+
+def is_narrow(req: Request) -> bool:
+    return req.M.shape[1] <= NARROW_N
+
+
+def worker_classes(workers: int) -> list[bool]:
+    """Class served by each worker (True: narrow).  About a fifth of the
+    stream is narrow (n uniform in [32, 512]), and narrow problems are the
+    cheaper ones, so one worker in four serves them (at least one)."""
+    if workers == 1:
+        raise ValueError("the server needs two workers or more (one per problem class)")
+    nn = max(1, workers // 4)
+    return [False] * (workers - nn) + [True] * nn
 
 
 def percentile(values, p: float) -> float:

@@ -38,6 +38,8 @@ class FakeSolver:
 def make_server(workers=3, capacity=8, cost=0.004):
     s = serve.BatchServer.__new__(serve.BatchServer)
     s.capacity, s.workers, s.want_S = capacity, workers, True
+    s.max_batch = capacity
+    s.classes = serve.worker_classes(workers)
     s.max_m, s.max_n, s.max_r = 2048, 512, 16
     s.solvers = [FakeSolver(capacity, cost) for _ in range(workers)]
     s.streams = [None] * workers
@@ -48,8 +50,8 @@ def make_server(workers=3, capacity=8, cost=0.004):
 def poisson_requests(count, rate, seed=0):
     rng = np.random.default_rng(seed)
     t = np.cumsum(rng.exponential(1.0 / rate, size=count))
-    return [serve.Request(M=FakeM(100, 50), r=int(rng.integers(2, 17)), lam=0.1, mu=1.0, tol=1e-6,
-                          arrival=float(t[i])) for i in range(count)]
+    return [serve.Request(M=FakeM(100, int(rng.integers(32, 513))), r=int(rng.integers(2, 17)), lam=0.1, mu=1.0,
+                          tol=1e-6, arrival=float(t[i])) for i in range(count)]
 
 
 def test_every_request_is_retired_once_within_capacity():
@@ -71,7 +73,38 @@ def test_overload_forms_full_batches():
     srv = make_server(workers=2, capacity=16, cost=0.01)
     reqs = poisson_requests(160, rate=1e9, seed=2)
     srv.run(reqs)
-    assert srv.batch_sizes.count(16) >= 8
+    assert srv.batch_sizes.count(16) >= 6
+
+
+def test_classes_are_served_by_their_own_workers():
+    srv = make_server(workers=4, capacity=8)
+    assert srv.classes == [False, False, False, True]
+    seen = {w: set() for w in range(4)}
+    for w, bs in enumerate(srv.solvers):
+        orig = bs.solve
+
+        def solve(items, _w=w, _orig=orig, **kw):
+            seen[_w].update(serve.is_narrow(serve.Request(M=it[0], r=1, lam=1, mu=1, tol=0)) for it in items)
+            return _orig(items, **kw)
+        bs.solve = solve
+    reqs = poisson_requests(200, rate=5000.0, seed=5)
+    for q in reqs:
+        q.M = FakeM(100, q.M.shape[1])
+    # pass the matrix through the fake solver's items
+    srv.run(reqs)
+    assert all(q.result is not None for q in reqs)
+    for w in range(4):
+        assert seen[w] <= {srv.classes[w]}
+    with pytest.raises(ValueError):
+        serve.worker_classes(1)
+
+
+def test_max_batch_caps_each_launch():
+    srv = make_server(workers=2, capacity=16, cost=0.01)
+    srv.max_batch = 5
+    reqs = poisson_requests(60, rate=1e9, seed=4)
+    srv.run(reqs)
+    assert max(srv.batch_sizes) == 5 and sum(srv.batch_sizes) == 60
 
 
 def test_latency_and_percentiles():
