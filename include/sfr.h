@@ -71,6 +71,20 @@ typedef struct {
                                 sfr_info.sweep_ms (the events add a few us per launch) */
     double mu_left;          /* FR-Nys: initial penalty of the m x l sub-solve (> 0) */
     double mu_top;           /* FR-Nys: initial penalty of the l x n sub-solve (> 0) */
+    int32_t bf16;            /* nonzero (SFR_F32 FR-ADM handles only): BF16-operand contractions
+                                for the leading iterations.  Such a sweep runs on the matrix cores
+                                with its three contractions (l = a_i V^T, p = X V, Q = X^T P)
+                                taking BF16 operands with FP32 accumulation; M, Y and all stored
+                                values stay FP32, and the r x r algebra and the reductions stay
+                                FP64.  The BF16 phase ends after bf16_iters iterations or at a
+                                relative residual <= bf16_tol, whichever comes first; FP32
+                                iterations then continue from its returned iterate (same buffers,
+                                transforms and mu) under the handle's rule, within the same
+                                iteration budget.  Both 0: every iteration in BF16.  Needs n >= the
+                                matrix-core slice width (1024 columns for r <= 12, 512 above):
+                                sfr_create returns SFR_ERR_ARG otherwise; sfr_tsvd ignores it. */
+    int32_t bf16_iters;      /* >= 0, only with bf16 */
+    double bf16_tol;         /* >= 0, only with bf16 */
 } sfr_options;
 
 /* Per-solve report. */

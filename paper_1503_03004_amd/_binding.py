@@ -39,6 +39,9 @@ class sfr_options(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("mu_left", ctypes.c_double),
         ("mu_top", ctypes.c_double),
+        ("bf16", ctypes.c_int32),
+        ("bf16_iters", ctypes.c_int32),
+        ("bf16_tol", ctypes.c_double),
     ]
 
 
@@ -154,10 +157,14 @@ class Solver:
 
     precision: "f64" (SFR_F64) or "f32" (SFR_F32).  mu is mu_0 of Alg. 1.
     nystrom_l > 0 makes an FR-Nys handle (Alg. 3) that needs mu_left/mu_top.
+    bf16 (FP32 FR-ADM handles): BF16-operand contractions on the matrix cores
+    for the leading iterations (until bf16_iters iterations or a residual <=
+    bf16_tol), then FP32 iterations from that iterate.
     """
 
     def __init__(self, m, n, r, lam, mu, tol=1e-7, *, precision="f64", rho=1.5, mu_bar=1e9,
-                 max_iter=300, fixed_iters=0, nystrom_l=0, mu_left=0.0, mu_top=0.0, profile=False):
+                 max_iter=300, fixed_iters=0, nystrom_l=0, mu_left=0.0, mu_top=0.0, profile=False,
+                 bf16=False, bf16_iters=0, bf16_tol=0.0):
         self.m, self.n, self.r = int(m), int(n), int(r)
         self.precision = precision
         o = sfr_options()
@@ -170,6 +177,7 @@ class Solver:
         o.nystrom_l = int(nystrom_l)
         o.profile = 1 if profile else 0
         o.mu_left, o.mu_top = float(mu_left), float(mu_top)
+        o.bf16, o.bf16_iters, o.bf16_tol = (1 if bf16 else 0), int(bf16_iters), float(bf16_tol)
         self.nystrom_l = int(nystrom_l)
         self._h = ctypes.c_void_p(None)
         rc = lib().sfr_create(ctypes.byref(self._h), self.m, self.n, self.r, float(lam), float(mu), float(tol),

@@ -259,11 +259,27 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         Mk = static_cast<const T*>(e.Mpad);
         ldk = e.ldmpad;
     }
+    // the first phase's stopping rule: the handle's, or for a two-phase BF16
+    // solve its bulk phase's (see below)
+    const bool two_phase = p.bf16 && !tsvd && (p.bf16_iters > 0 || p.bf16_tol > 0.0);
+    const int budget = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
+    int fixed1 = p.fixed_iters, max1 = p.max_iter;
+    double tol1 = p.tol;
+    if (two_phase) {
+        const int cap = p.bf16_iters > 0 ? std::min(p.bf16_iters, budget) : budget;
+        if (p.bf16_tol > 0.0) {
+            fixed1 = 0;
+            tol1 = p.bf16_tol;
+            max1 = cap;
+        } else {
+            fixed1 = cap;
+        }
+    }
     DevState& h = *e.host_state;
     memset(&h, 0, sizeof(DevState));
     h.m = e.m; h.n = e.ne; h.r = e.r; h.R = e.R;
-    h.max_iter = p.max_iter; h.fixed_iters = p.fixed_iters;
-    h.lambda = p.lambda; h.rho = p.rho; h.mu_bar = p.mu_bar; h.tol = p.tol;
+    h.max_iter = max1; h.fixed_iters = fixed1;
+    h.lambda = p.lambda; h.rho = p.rho; h.mu_bar = p.mu_bar; h.tol = tol1;
     h.M = Mk; h.ldm = ldk;
     h.k = 1; h.done = 0; h.status = 0;
     h.mu = mu0; h.mu_prev = mu0;
@@ -283,8 +299,16 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
 
     // FR-ADM stops at the start of a step (iteration k - 1 converged), Alg. 4
     // at the end of one, so FR-ADM launches one more sweep/step pair.
-    const int limit = (p.fixed_iters > 0 ? p.fixed_iters : p.max_iter) + (tsvd ? 0 : 1);
-    const bool fixed = p.fixed_iters > 0;
+    //
+    // A BF16 solve runs in two phases.  The bulk phase takes the leading
+    // iterations with BF16-operand contractions, until bf16_iters iterations
+    // or a residual <= bf16_tol, whichever comes first, within the handle's
+    // own budget.  FP32 iterations then continue from its returned iterate
+    // under the handle's rule.  The switch has to come while the iteration
+    // still contracts: late in a solve (large mu) L hardly moves and S
+    // absorbs the residual, so FP32 iterations there do not remove an error
+    // in L.
+    const int limit = (fixed1 > 0 ? fixed1 : max1) + (tsvd ? 0 : 1);
     const int batch = 8;
     // Profiling: start/stop events bound to every general sweep (k >= 3).
     if (p.profile) {
@@ -295,72 +319,87 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
             e.prof_ev.push_back(ev);
         }
     }
-    int k = 1;
-    int launched_batches = 0, checked_batches = 0;
-    auto enqueue_batch = [&](void) -> sfr_status {
-        for (int b = 0; b < batch && k <= limit; ++b, ++k) {
-            SweepArgs<T> a;
-            a.st = e.st;
-            a.Yprev = static_cast<const T*>(e.Y[(k - 1) & 1]);
-            a.Ynext = static_cast<T*>(e.Y[k & 1]);
-            a.ldy = e.ldy;
-            a.Pprev = static_cast<const T*>(e.P[(k - 1) & 1]);
-            a.Pnext = static_cast<T*>(e.P[k & 1]);
-            a.Qprev = static_cast<const T*>(e.Q[(k - 1) & 1]);
-            a.Qpart = static_cast<T*>(e.Qpart);
-            a.dy2part = e.dy2part;
-            a.exch = e.exch;
-            a.m = e.m; a.n = e.ne;
-            a.mode = (k == 1 || tsvd) ? 0 : (k == 2 ? 1 : 2);
-            const SweepCfg& sc = e.cfg[a.mode == 0 ? 1 : 0];
-            a.lpr = sc.lpr; a.nv = sc.nv; a.W = sc.W; a.c = sc.c; a.cpx = sc.cpx; a.xcd_local = sc.xcd_local;
-            a.ncl = sc.ncl; a.nbands = sc.nbands; a.nbl_max = e.tag_stride;
-            const bool timed = p.profile && k >= 3;
-            hipEvent_t ev0 = timed ? e.prof_ev[2 * (k - 3)] : nullptr;
-            hipEvent_t ev1 = timed ? e.prof_ev[2 * (k - 3) + 1] : nullptr;
-            if constexpr (sizeof(T) == 4) {
-                if (sc.mfma) HIPCHK(launch_sweep_mfma(a, e.R, sc.grid, sc.lds, s, ev0, ev1));
-                else HIPCHK(launch_sweep<T>(a, e.R, sc.grid, sc.lds, s, ev0, ev1));
-            } else {
-                HIPCHK(launch_sweep<T>(a, e.R, sc.grid, sc.lds, s, ev0, ev1));
-            }
-            GramArgs<T> g;
-            g.st = e.st;
-            g.Qpart = static_cast<const T*>(e.Qpart);
-            g.Qnext = static_cast<T*>(e.Q[k & 1]);
-            g.Pnext = static_cast<const T*>(e.P[k & 1]);
-            g.GQpart = e.GQpart; g.GPpart = e.GPpart;
-            g.m = e.m; g.n = e.ne; g.ncl = sc.ncl;
-            g.rows_q = e.rows_q; g.nqb = e.nqb; g.rows_p = e.rows_p; g.npb = e.npb;
-            HIPCHK(launch_gram<T>(g, e.R, s));
-            StepArgs sa;
-            sa.st = e.st;
-            sa.GPpart = e.GPpart; sa.npb = e.npb;
-            sa.GQpart = e.GQpart; sa.nqb = e.nqb;
-            sa.dy2part = e.dy2part; sa.ndy = sc.grid;
-            sa.res_hist = e.res_hist;
-            HIPCHK(launch_step(sa, e.R, s));
+    // one iteration: sweep k, Gram reduction, FP64 step.  bf: BF16-operand
+    // contractions (matrix-core sweep); timed_ok: HIP events bound to the
+    // sweep's dispatch when profiling.
+    auto enqueue_iter = [&](int k, bool bf, bool timed_ok) -> sfr_status {
+        SweepArgs<T> a;
+        a.st = e.st;
+        a.Yprev = static_cast<const T*>(e.Y[(k - 1) & 1]);
+        a.Ynext = static_cast<T*>(e.Y[k & 1]);
+        a.ldy = e.ldy;
+        a.Pprev = static_cast<const T*>(e.P[(k - 1) & 1]);
+        a.Pnext = static_cast<T*>(e.P[k & 1]);
+        a.Qprev = static_cast<const T*>(e.Q[(k - 1) & 1]);
+        a.Qpart = static_cast<T*>(e.Qpart);
+        a.dy2part = e.dy2part;
+        a.exch = e.exch;
+        a.m = e.m; a.n = e.ne;
+        a.mode = (k == 1 || tsvd) ? 0 : (k == 2 ? 1 : 2);
+        const SweepCfg& sc = e.cfg[(a.mode == 0 || bf) ? 1 : 0];
+        a.lpr = sc.lpr; a.nv = sc.nv; a.W = sc.W; a.c = sc.c; a.cpx = sc.cpx; a.xcd_local = sc.xcd_local;
+        a.ncl = sc.ncl; a.nbands = sc.nbands; a.nbl_max = e.tag_stride;
+        const bool timed = timed_ok && p.profile && k >= 3 && k <= limit;
+        hipEvent_t ev0 = timed ? e.prof_ev[2 * (k - 3)] : nullptr;
+        hipEvent_t ev1 = timed ? e.prof_ev[2 * (k - 3) + 1] : nullptr;
+        if constexpr (sizeof(T) == 4) {
+            if (sc.mfma) HIPCHK(launch_sweep_mfma(a, e.R, sc.grid, sc.lds, s, ev0, ev1, bf));
+            else HIPCHK(launch_sweep<T>(a, e.R, sc.grid, sc.lds, s, ev0, ev1));
+        } else {
+            HIPCHK(launch_sweep<T>(a, e.R, sc.grid, sc.lds, s, ev0, ev1));
         }
-        if (!fixed) {
-            const int slot = launched_batches & 1;
-            HIPCHK(hipMemcpyAsync(&e.host_poll[slot], e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipEventRecord(e.poll_ev[slot], s));
-        }
-        ++launched_batches;
+        GramArgs<T> g;
+        g.st = e.st;
+        g.Qpart = static_cast<const T*>(e.Qpart);
+        g.Qnext = static_cast<T*>(e.Q[k & 1]);
+        g.Pnext = static_cast<const T*>(e.P[k & 1]);
+        g.GQpart = e.GQpart; g.GPpart = e.GPpart;
+        g.m = e.m; g.n = e.ne; g.ncl = sc.ncl;
+        g.rows_q = e.rows_q; g.nqb = e.nqb; g.rows_p = e.rows_p; g.npb = e.npb;
+        HIPCHK(launch_gram<T>(g, e.R, s));
+        StepArgs sa;
+        sa.st = e.st;
+        sa.GPpart = e.GPpart; sa.npb = e.npb;
+        sa.GQpart = e.GQpart; sa.nqb = e.nqb;
+        sa.dy2part = e.dy2part; sa.ndy = sc.grid;
+        sa.res_hist = e.res_hist;
+        HIPCHK(launch_step(sa, e.R, s));
         return SFR_OK;
     };
-    sfr_status es;
-    if (fixed) {
-        while (k <= limit) {
-            es = enqueue_batch();
-            if (es != SFR_OK) return es;
+    // One phase: iterations k0 .. lim, queued in one go (fixed rule) or in
+    // batches of 8 with one batch running ahead of the host's check of the
+    // previous one.  *K receives the returned iterate when the host knows
+    // it (fixed rule: lim - 1; polled: from the state), else -1.
+    auto run_phase = [&](int k0, int lim, bool bf, bool fixed_rule, bool timed_ok, int* K) -> sfr_status {
+        *K = -1;
+        int k = k0;
+        int launched_batches = 0, checked_batches = 0;   // this phase's poll slots
+        auto enqueue_batch = [&](void) -> sfr_status {
+            for (int b = 0; b < batch && k <= lim; ++b, ++k) {
+                const sfr_status es = enqueue_iter(k, bf, timed_ok);
+                if (es != SFR_OK) return es;
+            }
+            if (!fixed_rule) {
+                const int slot = launched_batches & 1;
+                HIPCHK(hipMemcpyAsync(&e.host_poll[slot], e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipEventRecord(e.poll_ev[slot], s));
+            }
+            ++launched_batches;
+            return SFR_OK;
+        };
+        sfr_status es;
+        if (fixed_rule) {
+            while (k <= lim) {
+                es = enqueue_batch();
+                if (es != SFR_OK) return es;
+            }
+            *K = lim - 1;   // if the phase failed instead, what follows returns at once
+            return SFR_OK;
         }
-    } else {
         es = enqueue_batch();
         if (es != SFR_OK) return es;
-        bool done = false;
-        while (!done) {
-            if (k <= limit) {
+        for (;;) {
+            if (k <= lim) {
                 es = enqueue_batch();
                 if (es != SFR_OK) return es;
             }
@@ -368,9 +407,25 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
             HIPCHK(hipEventSynchronize(e.poll_ev[slot]));
             const DevState& ph = e.host_poll[slot];
             ++checked_batches;
-            if (ph.done || ph.exch_timeout) done = true;
-            else if (checked_batches == launched_batches && k > limit) break;  // reported below
+            if (ph.done || ph.exch_timeout) {
+                if (ph.done && ph.status >= 0 && !ph.exch_timeout) *K = ph.iters;
+                return SFR_OK;
+            }
+            if (checked_batches == launched_batches && k > lim) return SFR_OK;   // reported below
         }
+    };
+    int bulk_iters = -1;
+    sfr_status es = run_phase(1, limit, p.bf16, fixed1 > 0, true, &bulk_iters);
+    if (es != SFR_OK) return es;
+    if (two_phase && bulk_iters >= 1 && bulk_iters < budget) {
+        // ---- FP32 iterations from the bulk phase's returned iterate K: the
+        // state goes back to the handle's rule; sweep K + 1 is run again, so
+        // the exchange words of its first run are cleared
+        HIPCHK(launch_refine_start(e.st, p.fixed_iters, p.tol, p.max_iter, s));
+        if (e.exch_words) HIPCHK(launch_fill_u64(e.exch, e.exch_words, s));
+        int K2 = -1;
+        es = run_phase(bulk_iters + 1, budget + 1, false, p.fixed_iters > 0, false, &K2);
+        if (es != SFR_OK) return es;
     }
     // ---- outputs of the returned iterate, then one wait
     PingPong<T> pp;
@@ -405,7 +460,9 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
     e.sweep_ms = 0.0;
     e.sweeps_timed = 0;
     if (p.profile && h.done) {
-        const int last = std::min(h.iters + (tsvd ? 0 : 1), limit);  // sweeps that did work
+        // sweeps that did work (of a two-phase BF16 solve: its bulk phase)
+        const int kstop = (two_phase && bulk_iters >= 1) ? bulk_iters : h.iters;
+        const int last = std::min(kstop + (tsvd ? 0 : 1), limit);
         for (int kk = 3; kk <= last; ++kk) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, e.prof_ev[2 * (kk - 3)], e.prof_ev[2 * (kk - 3) + 1]));
@@ -483,6 +540,9 @@ sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double l
     if (m > (int64_t)1 << 30 || n > (int64_t)1 << 30) return SFR_ERR_ARG;
     if (!(lambda > 0.0) || !(tol >= 0.0) || lambda > 1e300 || tol > 1e300) return SFR_ERR_ARG;
     if (o.precision != SFR_F64 && o.precision != SFR_F32) return SFR_ERR_ARG;
+    if (o.bf16 != 0 && (o.precision != SFR_F32 || o.nystrom_l != 0)) return SFR_ERR_ARG;
+    if (o.bf16_iters < 0 || o.bf16_iters > 100000 || !(o.bf16_tol >= 0.0) || o.bf16_tol > 1e300) return SFR_ERR_ARG;
+    if (o.bf16 == 0 && (o.bf16_iters != 0 || o.bf16_tol != 0.0)) return SFR_ERR_ARG;
     if (o.rho == 0.0) o.rho = 1.5;
     if (o.mu_bar == 0.0) o.mu_bar = 1e9;
     if (o.max_iter == 0) o.max_iter = 300;
@@ -506,11 +566,16 @@ sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double l
     h->prm.rho = o.rho; h->prm.mu_bar = o.mu_bar;
     h->prm.max_iter = o.max_iter; h->prm.fixed_iters = o.fixed_iters;
     h->prm.profile = o.profile != 0;
+    h->prm.bf16 = o.bf16 != 0;
+    h->prm.bf16_iters = o.bf16_iters;
+    h->prm.bf16_tol = o.bf16_tol;
     h->mu_left = o.mu_left; h->mu_top = o.mu_top;
     const int hist = std::max(o.max_iter, o.fixed_iters);
     sfr_status st;
     if (!nys) {
         st = engine_create(h->main, (int)m, (int)n, r, h->f64, hist);
+        // the BF16 bulk phase runs on the matrix-core sweep
+        if (st == SFR_OK && h->prm.bf16 && !h->main.cfg[1].mfma) st = SFR_ERR_ARG;
     } else {
         st = nys_setup(h);
     }

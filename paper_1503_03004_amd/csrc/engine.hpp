@@ -57,6 +57,13 @@ struct Params {
     double lambda = 0, mu0 = 0, tol = 0, rho = 1.5, mu_bar = 1e9;
     int max_iter = 300, fixed_iters = 0;
     bool profile = false;
+    // BF16-operand contractions (FP32 storage; matrix-core sweep) for the
+    // leading iterations: until bf16_iters iterations or a residual <=
+    // bf16_tol (either 0: not used); FP32 iterations then continue from that
+    // iterate under the rule above.  Both 0: every iteration in BF16.
+    bool bf16 = false;
+    int bf16_iters = 0;
+    double bf16_tol = 0.0;
 };
 
 // What a solve writes once the iteration has stopped: the factors U, B, V

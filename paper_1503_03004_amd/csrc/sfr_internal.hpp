@@ -224,11 +224,15 @@ bool sweep_mfma_supported(int R);
 size_t sweep_mfma_lds_bytes(int R);
 int sweep_mfma_width(int R);
 hipError_t sweep_mfma_prepare(int R, size_t lds, int* blocks_per_cu);
+// bf16: the contractions take BF16 operands (FP32 accumulation)
 hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int grid, size_t lds, hipStream_t s,
-                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool bf16 = false);
 
 hipError_t launch_step(const StepArgs& a, int R, hipStream_t s);
 hipError_t launch_final_small(DevState* st, int R, hipStream_t s);
+// Continue a stopped iteration from its returned iterate K under a new
+// stopping rule (no-op if it stopped with an error, or with no budget left).
+hipError_t launch_refine_start(DevState* st, int fixed_iters, double tol, int max_iter, hipStream_t s);
 
 template <typename T>
 hipError_t launch_init_q(T* Q, int n, int r, int R, hipStream_t s);

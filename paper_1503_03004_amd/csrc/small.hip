@@ -254,6 +254,32 @@ hipError_t launch_step(const StepArgs& a, int R, hipStream_t s)
     return hipGetLastError();
 }
 
+// Continue a stopped solve from its returned iterate K (the second phase of
+// a BF16 solve): every buffer of iterate K (Y_K, P_K, Q_K) and the state of
+// its step (transforms, B, mu, the warm-start bases) are intact, so this only
+// installs the new stopping rule, clears the stop and sets the next sweep to
+// K + 1.  A solve that stopped with an error, or with no iterations left in
+// the new rule, stays stopped.
+__global__ void refine_start_kernel(DevState* st, int fixed_iters, double tol, int max_iter)
+{
+    if (threadIdx.x != 0) return;
+    if (!st->done || st->status < 0 || st->exch_timeout) return;
+    const int K = st->iters;
+    if (K >= (fixed_iters > 0 ? fixed_iters : max_iter)) return;
+    st->status = kOK;
+    st->fixed_iters = fixed_iters;
+    st->tol = tol;
+    st->max_iter = max_iter;
+    st->k = K + 1;
+    st->done = 0;
+}
+
+hipError_t launch_refine_start(DevState* st, int fixed_iters, double tol, int max_iter, hipStream_t s)
+{
+    hipLaunchKernelGGL(refine_start_kernel, dim3(1), dim3(64), 0, s, st, fixed_iters, tol, max_iter);
+    return hipGetLastError();
+}
+
 hipError_t launch_final_small(DevState* st, int R, hipStream_t s)
 {
     switch (R) {

@@ -81,7 +81,31 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int R>
+// BF16-operand form (FP32 accumulation): v_mfma_f32_16x16x16_bf16 takes four
+// consecutive K entries per lane where the FP32 instruction takes one, so the
+// four operands a lane feeds to four FP32 steps go to one BF16 instruction.
+// The K index is then visited in another order, the same for A and B, which
+// leaves the contraction unchanged.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float x)
+{
+    // round to nearest, ties to even (finite inputs)
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+__device__ __forceinline__ f32x4 mfma_bf16(const float (&a)[4], const float (&b)[4], f32x4 c)
+{
+    const bf16x4 av = {to_bf16(a[0]), to_bf16(a[1]), to_bf16(a[2]), to_bf16(a[3])};
+    const bf16x4 bv = {to_bf16(b[0]), to_bf16(b[1]), to_bf16(b[2]), to_bf16(b[3])};
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+}
+
+// BF: the three contractions take BF16 operands (FP32 accumulation); M, Y
+// and every stored value stay FP32.
+template <int R, bool BF>
 __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a)
 {
     using SH = MShape<R>;
@@ -232,8 +256,21 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
                     }
                 } else {
                     f32x4 lv = {0.f, 0.f, 0.f, 0.f};
+                    if constexpr (BF) {
 #pragma unroll
-                    for (int s = 0; s < S1; ++s) lv = mfma4(va1[t][s], aop[s], lv);
+                        for (int s0 = 0; s0 < S1; s0 += 4) {
+                            float av4[4], bv4[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                av4[u] = (s0 + u < S1) ? va1[t][s0 + u] : 0.f;
+                                bv4[u] = (s0 + u < S1) ? aop[s0 + u] : 0.f;
+                            }
+                            lv = mfma_bf16(av4, bv4, lv);
+                        }
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < S1; ++s) lv = mfma4(va1[t][s], aop[s], lv);
+                    }
                     float ypv[4] = {0.f, 0.f, 0.f, 0.f};
                     if (mode == 2) {
                         ypv[0] = yv[t].x; ypv[1] = yv[t].y; ypv[2] = yv[t].z; ypv[3] = yv[t].w;
@@ -255,10 +292,15 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
                 }
                 *reinterpret_cast<float4*>(Xw + ((size_t)buf * kMH + lr) * kMXP + 16 * t + 4 * lq) =
                     make_float4(x[0], x[1], x[2], x[3]);
+                if constexpr (BF) {
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
+                    for (int rt = 0; rt < RT; ++rt) pacc[rt] = mfma_bf16(va2[t][rt], x, pacc[rt]);
+                } else {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) pacc[rt] = mfma4(va2[t][rt][u], x[u], pacc[rt]);
+                    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) pacc[rt] = mfma4(va2[t][rt][u], x[u], pacc[rt]);
+                }
                 if (j + 1 < nbl) issue_load(j + 1, t);
             }
             acc2 += (double)rowacc;
@@ -321,11 +363,19 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
                 for (int s = 0; s < 4; ++s) b3[rt][s] = PS[bb * PT + rt * 256 + (4 * s + lq) * 16 + lr];
 #pragma unroll
             for (int t = 0; t < kMTiles; ++t) {
+                if constexpr (BF) {
+                    float a3[4];
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const float a3 = Xw[((size_t)bb * kMH + 4 * s + lq) * kMXP + 16 * t + lr];
+                    for (int s = 0; s < 4; ++s) a3[s] = Xw[((size_t)bb * kMH + 4 * s + lq) * kMXP + 16 * t + lr];
 #pragma unroll
-                    for (int rt = 0; rt < RT; ++rt) qacc[t][rt] = mfma4(a3, b3[rt][s], qacc[t][rt]);
+                    for (int rt = 0; rt < RT; ++rt) qacc[t][rt] = mfma_bf16(a3, b3[rt], qacc[t][rt]);
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float a3 = Xw[((size_t)bb * kMH + 4 * s + lq) * kMXP + 16 * t + lr];
+#pragma unroll
+                        for (int rt = 0; rt < RT; ++rt) qacc[t][rt] = mfma4(a3, b3[rt][s], qacc[t][rt]);
+                    }
                 }
             }
         }
@@ -391,10 +441,13 @@ int sweep_mfma_width(int R)
     }
 }
 
-static void* sweep_mfma_fn(int R)
+static void* sweep_mfma_fn(int R, bool bf16)
 {
     switch (R) {
-#define CASE(r) case r: return reinterpret_cast<void*>(&sweep_mfma_kernel<r>);
+#define CASE(r)                                                                             \
+    case r:                                                                                 \
+        return bf16 ? reinterpret_cast<void*>(&sweep_mfma_kernel<r, true>)                  \
+                    : reinterpret_cast<void*>(&sweep_mfma_kernel<r, false>);
         SFR_MFMA_R_LIST(CASE)
 #undef CASE
     default: return nullptr;
@@ -403,27 +456,37 @@ static void* sweep_mfma_fn(int R)
 
 hipError_t sweep_mfma_prepare(int R, size_t lds, int* blocks_per_cu)
 {
-    void* fn = sweep_mfma_fn(R);
-    if (!fn) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kMTPB, lds);
+    // both operand forms share the launch shape and LDS size
+    for (int bf = 1; bf >= 0; --bf) {
+        void* fn = sweep_mfma_fn(R, bf != 0);
+        if (!fn) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, sweep_mfma_fn(R, false), kMTPB, lds);
 }
 
 hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int grid, size_t lds, hipStream_t s,
-                             hipEvent_t ev0, hipEvent_t ev1)
+                             hipEvent_t ev0, hipEvent_t ev1, bool bf16)
 {
     switch (R) {
-#define CASE(r)                                                                                         \
-    case r:                                                                                             \
-        if (ev0)                                                                                        \
-            hipExtLaunchKernelGGL((sweep_mfma_kernel<r>), dim3(grid), dim3(kMTPB), (uint32_t)lds, s, ev0, \
-                                  ev1, 0u, a);                                                          \
-        else                                                                                            \
-            hipLaunchKernelGGL((sweep_mfma_kernel<r>), dim3(grid), dim3(kMTPB), lds, s, a);            \
+#define LAUNCH(r, BF)                                                                                       \
+    if (ev0)                                                                                                \
+        hipExtLaunchKernelGGL((sweep_mfma_kernel<r, BF>), dim3(grid), dim3(kMTPB), (uint32_t)lds, s, ev0, ev1, \
+                              0u, a);                                                                       \
+    else                                                                                                    \
+        hipLaunchKernelGGL((sweep_mfma_kernel<r, BF>), dim3(grid), dim3(kMTPB), lds, s, a);
+#define CASE(r)                 \
+    case r:                     \
+        if (bf16) {             \
+            LAUNCH(r, true)     \
+        } else {                \
+            LAUNCH(r, false)    \
+        }                       \
         return hipGetLastError();
         SFR_MFMA_R_LIST(CASE)
 #undef CASE
+#undef LAUNCH
     default: return hipErrorInvalidValue;
     }
 }

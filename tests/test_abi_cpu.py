@@ -94,6 +94,12 @@ def _create(m, n, r, lam, mu, tol, **kw):
     ((10, 10, 2, 0.1, 1.0, 1e-7), {"nystrom_l": 1}),   # l < r
     ((10, 10, 2, 0.1, 1.0, 1e-7), {"nystrom_l": 11}),  # l > min(m, n)
     ((10, 10, 2, 0.1, 1.0, 1e-7), {"nystrom_l": 4}),   # missing mu_left / mu_top
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"bf16": 1}),                          # BF16 needs FP32 storage
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"bf16": 1, "precision": 1, "nystrom_l": 4, "mu_left": 1.0, "mu_top": 1.0}),
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"bf16_iters": 3, "precision": 1}),   # BF16 fields without bf16
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"bf16_tol": 1e-3, "precision": 1}),
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"bf16": 1, "precision": 1, "bf16_iters": -1}),
+    ((10, 10, 2, 0.1, 1.0, 1e-7), {"bf16": 1, "precision": 1, "bf16_tol": -1.0}),
 ])
 def test_create_rejects_invalid_arguments(args, kw):
     rc, h = _create(*args, **kw)

@@ -1,0 +1,120 @@
+"""GPU parity of BF16-operand solves (sfr_options.bf16): the matrix-core sweep
+with its three contractions on BF16 operands (FP32 accumulation, FP32 M and
+Y, FP64 r x r algebra) for the leading iterations, FP32 iterations after.
+
+Bars, relative Frobenius error of L and S against the FP64 oracle at the
+same iteration count:
+  * every iteration in BF16: 3e-3.  BF16 keeps 8 significant bits (unit
+    roundoff 2^-9 ~ 2e-3); a product of two rounded operands carries about
+    twice that, and the solve's L inherits it (measured 1.1e-3 to 1.8e-3);
+  * a BF16 head then FP32 iterations: 1e-5, the FP32 bar.  The switch has to
+    come while the iteration still contracts (before mu grows large): FP32
+    iterations then remove the BF16 error (measured 2e-7, as pure FP32).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_1503_03004_amd as sfr
+
+pytestmark = pytest.mark.gpu
+
+BF16_BAR = 3e-3
+FP32_BAR = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    sfr.lib()
+    yield
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def problem(m, n, r, seed=1):
+    inst = workloads.large_fp32(seed=seed, m=m, n=n, r=r)
+    Md = inst.M.astype(np.float32).astype(np.float64)
+    return Md, inst.lam, workloads.default_mu0(Md)
+
+
+def gpu_solve(Md, r, lam, mu0, **kw):
+    Mt = torch.from_numpy(Md.astype(np.float32)).cuda()
+    with sfr.Solver(Md.shape[0], Md.shape[1], r, lam, mu0, kw.pop("tol", 1e-6), precision="f32", **kw) as s:
+        U, B, V, S, info = s.solve(Mt)
+        torch.cuda.synchronize()
+    return (U.double() @ B @ V.double().T).cpu().numpy(), S.double().cpu().numpy(), info
+
+
+def errors(Md, r, lam, mu0, L, S, iters):
+    o = oracle.fradm(Md, r, lam, mu0, fixed_iters=iters)
+    return rel(L, o["U"] @ o["B"] @ o["V"].T), rel(S, o["S"])
+
+
+SHAPES = [(2000, 1100, 10), (1200, 1000, 16), (900, 1100, 32)]
+
+
+@pytest.mark.parametrize("m,n,r", SHAPES)
+def test_every_iteration_bf16(m, n, r):
+    Md, lam, mu0 = problem(m, n, r)
+    L, S, info = gpu_solve(Md, r, lam, mu0, fixed_iters=12, bf16=True)
+    assert info.iters == 12 and info.status in (sfr.SFR_OK, sfr.SFR_WARN_NOT_SPD)
+    eL, eS = errors(Md, r, lam, mu0, L, S, 12)
+    print(f"{m}x{n} r={r} all BF16: errL {eL:.2e} errS {eS:.2e}")
+    assert eL <= BF16_BAR and eS <= BF16_BAR
+    assert eL > 1e-5       # the BF16 operands are really in use
+
+
+@pytest.mark.parametrize("m,n,r", SHAPES)
+@pytest.mark.parametrize("head", [1, 2, 4, 10])
+def test_bf16_head_then_fp32(m, n, r, head):
+    """BF16 for the first `head` iterations (1: X = M; 2: Y_1 = 0; then the
+    general sweep) of 20, FP32 after: the FP32 bar at the same count."""
+    Md, lam, mu0 = problem(m, n, r)
+    L, S, info = gpu_solve(Md, r, lam, mu0, fixed_iters=20, bf16=True, bf16_iters=head)
+    assert info.iters == 20
+    eL, eS = errors(Md, r, lam, mu0, L, S, 20)
+    print(f"{m}x{n} r={r} BF16 head {head}: errL {eL:.2e} errS {eS:.2e}")
+    assert eL <= FP32_BAR and eS <= FP32_BAR
+
+
+@pytest.mark.parametrize("m,n,r", SHAPES[:2])
+def test_tolerance_solve_with_bf16_until_residual(m, n, r):
+    """tol 1e-6 with BF16 until the residual reaches 1e-3: the stop comes
+    within one iteration of the FP64 oracle's and matches it there."""
+    Md, lam, mu0 = problem(m, n, r)
+    ot = oracle.fradm(Md, r, lam, mu0, tol=1e-6, max_iter=300)
+    L, S, info = gpu_solve(Md, r, lam, mu0, tol=1e-6, max_iter=300, bf16=True, bf16_tol=1e-3)
+    assert info.status in (sfr.SFR_OK, sfr.SFR_WARN_NOT_SPD) and info.converged
+    assert abs(info.iters - ot["iters"]) <= 1
+    eL, eS = errors(Md, r, lam, mu0, L, S, info.iters)
+    print(f"{m}x{n} r={r}: {info.iters} iterations (oracle {ot['iters']}), errL {eL:.2e} errS {eS:.2e}")
+    assert eL <= FP32_BAR and eS <= FP32_BAR
+
+
+def test_bf16_head_longer_than_the_budget():
+    """bf16_iters beyond fixed_iters: every iteration is BF16 (no FP32 tail)."""
+    Md, lam, mu0 = problem(1500, 1100, 6)
+    La, Sa, ia = gpu_solve(Md, 6, lam, mu0, fixed_iters=8, bf16=True)
+    Lb, Sb, ib = gpu_solve(Md, 6, lam, mu0, fixed_iters=8, bf16=True, bf16_iters=50)
+    assert ia.iters == ib.iters == 8
+    assert np.array_equal(La, Lb) and np.array_equal(Sa, Sb)
+
+
+def test_fp32_solves_unchanged_by_the_option():
+    """bf16 off: bit-identical to a handle created without the new fields set."""
+    Md, lam, mu0 = problem(1200, 1100, 8)
+    La, Sa, _ = gpu_solve(Md, 8, lam, mu0, fixed_iters=6)
+    Lb, Sb, _ = gpu_solve(Md, 8, lam, mu0, fixed_iters=6, bf16=False, bf16_iters=0, bf16_tol=0.0)
+    assert np.array_equal(La, Lb) and np.array_equal(Sa, Sb)
+
+
+def test_bf16_needs_a_matrix_core_slice():
+    """n below the matrix-core slice width (1024 columns for r <= 12)."""
+    with pytest.raises(sfr.SFRError) as e:
+        sfr.Solver(300, 500, 4, 0.1, 1.0, 1e-6, precision="f32", bf16=True)
+    assert e.value.code == sfr.SFR_ERR_ARG
