@@ -76,6 +76,11 @@ def main():
     ap.add_argument("--solves", type=int, default=5, help="tolerance-driven solves timed for solves/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-iters", type=int, default=12, help="oracle iterations timed on the host (about 1 s each)")
+    ap.add_argument("--rank", type=int, default=0, help="large_fp32 / tsvd_fp32: rank r (default 10)")
+    ap.add_argument("--bf16-iters", type=int, default=0,
+                    help="BF16-operand contractions for the first K iterations of every solve, FP32 after")
+    ap.add_argument("--bf16-tol", type=float, default=1e-3,
+                    help="with --bf16-iters: tolerance-driven solves leave BF16 at this residual")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -98,12 +103,13 @@ def main():
     t0 = time.time()
     tsvd = args.workload == "tsvd_fp32"
     if args.workload in ("large_fp32", "tsvd_fp32"):
-        inst = workloads.large_fp32(seed=args.seed)
+        rk = args.rank or 10
+        inst = workloads.large_fp32(seed=args.seed, r=rk)
         precision, esz, tol = "f32", 4, 1e-6
-        desc = "FR-ADM, m=n=8000, r=10, FP32, 10% outliers U[-100,100]"
+        desc = f"FR-ADM, m=n=8000, r={rk}, FP32, 10% outliers U[-100,100]"
         if tsvd:
             tol = 1e-6
-            desc = "FixedRankOptFull (Alg. 4) rank-10 TSVD of the same 8000x8000 FP32 matrix"
+            desc = f"FixedRankOptFull (Alg. 4) rank-{rk} TSVD of the same 8000x8000 FP32 matrix"
     elif args.workload == "plain_fp64":
         inst = workloads.plain_fp64(seed=args.seed)
         precision, esz, tol = "f64", 8, 1e-7
@@ -115,6 +121,15 @@ def main():
     m, n = inst.M.shape
     r = inst.r
     mu0 = workloads.default_mu0(inst.M)
+    # BF16 head (FP32 FR-ADM only): fixed-count solves take BF16 for their
+    # first --bf16-iters iterations, tolerance-driven ones until --bf16-tol
+    bf_fixed, bf_tol = {}, {}
+    if args.bf16_iters > 0:
+        if precision != "f32" or tsvd:
+            print("bench.py: --bf16-iters applies to FP32 FR-ADM workloads", file=sys.stderr)
+            sys.exit(2)
+        bf_fixed = dict(bf16=True, bf16_iters=args.bf16_iters)
+        bf_tol = dict(bf16=True, bf16_tol=args.bf16_tol)
     tdt = torch.float64 if precision == "f64" else torch.float32
     M = torch.from_numpy(np.ascontiguousarray(inst.M)).to(device=dev, dtype=tdt)
     torch.cuda.synchronize()
@@ -139,13 +154,13 @@ def main():
 
     # ---- warmup: W untimed iterations
     if args.warmup > 0:
-        with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=args.warmup) as w:
+        with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=args.warmup, **bf_fixed) as w:
             run(w)
     torch.cuda.synchronize()
 
     # ---- timed: exactly K iterations (plus the output pass writing U, B, V, S)
     K = args.steps
-    solver = sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K)
+    solver = sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K, **bf_fixed)
     U = torch.empty((m, r), dtype=tdt, device=dev)
     Bm = torch.empty((r, r), dtype=torch.float64, device=dev)
     V = torch.empty((n, r), dtype=tdt, device=dev)
@@ -163,7 +178,8 @@ def main():
     solver.close()
     # ---- the same K iterations again with HIP events bound to every sweep
     # dispatch (kept out of the run above: the events cost a few us a launch)
-    with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K, profile=True) as sp:
+    with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K, profile=True,
+                    **bf_fixed) as sp:
         _, _, _, _, pinfo = run(sp, out=(U, Bm, V, S), stream=stream)
     torch.cuda.synchronize()
     sweep_ms = pinfo.sweep_ms
@@ -173,13 +189,16 @@ def main():
     bytes_per_el = (1 if tsvd else 3) * esz  # read M (, read Y_{k-1}, write Y_k)
     alg_bytes = bytes_per_el * m * n
     achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
-    traffic = measured_traffic(args.workload)
+    # the committed counters were taken on the default configuration only
+    default_cfg = (not args.rank or args.rank == 10) and not bf_fixed
+    traffic = measured_traffic(args.workload) if default_cfg else None
+    sweep_name = "sweep_mfma_kernel" if (bf_fixed or r > 12 or tsvd) else "sweep_kernel"
 
     # ---- full tolerance-driven solves: solves/s and latency percentiles
     lat = []
     solve_iters = None
     Ls = None
-    with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, max_iter=300) as s2:
+    with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, max_iter=300, **bf_tol) as s2:
         for i in range(max(1, args.solves)):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -215,13 +234,16 @@ def main():
         cpu = {"value": oi / tc, "unit": "iters/s", "cores": 1, "kind": "oracle",
                "sample": f"{oi} {'Alg. 4 steps' if tsvd else 'FR-ADM iterations'} of the same {m}x{n} r={r} "
                          f"input, FP64, one thread ({tc:.1f} s)"}
-        with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=oi) as s3:
+        # a BF16 head of the same share of the iterations as in the timed run
+        bf_par = dict(bf_fixed, bf16_iters=max(1, (args.bf16_iters * oi) // K)) if bf_fixed else {}
+        with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=oi, **bf_par) as s3:
             U3, B3, V3, S3, _ = run(s3)
         torch.cuda.synchronize()
         rows = np.random.default_rng(2).choice(m, min(m, 128), replace=False)
         Lg = (U3.double()[rows] @ B3 @ V3.double().T).cpu().numpy()
         Lo = o["U"][rows] @ o["B"] @ o["V"].T
-        parity = {"iterations": oi, "rel_err_L": rel(Lg, Lo),
+        parity = {"iterations": oi, **({"bf16_iters": bf_par["bf16_iters"]} if bf_par else {}),
+                  "rel_err_L": rel(Lg, Lo),
                   "rel_err_S": None if tsvd else rel(S3.double()[rows].cpu().numpy(), o["S"][rows]),
                   "rows_sampled": int(rows.size)}
         print(f"[bench] oracle {oi} iterations in {tc:.1f} s; parity {parity}", file=sys.stderr, flush=True)
@@ -237,13 +259,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": precision,
+        "dtype": "bf16-operands+f32" if bf_fixed else precision,
         "data": "synthetic",
         "config": {"workload": desc, "m": m, "n": n, "r": r, "lambda": inst.lam, "mu0": mu0,
-                   "rho": 1.5, "mu_bar": 1e9, "seed": args.seed},
+                   "rho": 1.5, "mu_bar": 1e9, "seed": args.seed,
+                   **({"bf16_iters": args.bf16_iters, "bf16_tol": args.bf16_tol} if bf_fixed else {})},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "sweep_kernel", "sweep_us": sweep_ms * 1e3,
+                     "kernel": sweep_name, "sweep_us": sweep_ms * 1e3,
                      "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "solves_per_s": 1e3 / float(np.mean(lat)),
