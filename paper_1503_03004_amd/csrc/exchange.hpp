@@ -11,6 +11,12 @@
 
 #include "sfr_internal.hpp"
 
+// 1: non-temporal hints on the sweeps' streams (measured +2-4 % iterations/s
+// at 8000^2, r = 10, alternating with 0 on one device)
+#ifndef SFR_NT_STREAMS
+#define SFR_NT_STREAMS 1
+#endif
+
 namespace sfr {
 
 template <typename T> struct Vec;
@@ -30,6 +36,38 @@ __device__ __forceinline__ void store_vec(T* p, const T (&v)[Vec<T>::N])
     typename Vec<T>::t x;
     __builtin_memcpy(&x, v, sizeof(x));
     *reinterpret_cast<typename Vec<T>::t*>(p) = x;
+}
+
+// Streaming forms for data touched once per sweep (M, Y_{k-1} read, Y_k
+// written): non-temporal hints, so the streams do not displace the cached
+// exchange words and factor slices.
+template <typename T> struct NtVec;
+template <> struct NtVec<float> { typedef float t __attribute__((ext_vector_type(4))); };
+template <> struct NtVec<double> { typedef double t __attribute__((ext_vector_type(2))); };
+
+template <typename T>
+__device__ __forceinline__ void load_vec_stream(const T* p, T (&v)[Vec<T>::N])
+{
+#if SFR_NT_STREAMS
+    const typename NtVec<T>::t x = __builtin_nontemporal_load(reinterpret_cast<const typename NtVec<T>::t*>(p));
+#pragma unroll
+    for (int i = 0; i < Vec<T>::N; ++i) v[i] = x[i];
+#else
+    load_vec<T>(p, v);
+#endif
+}
+
+template <typename T>
+__device__ __forceinline__ void store_vec_stream(T* p, const T (&v)[Vec<T>::N])
+{
+#if SFR_NT_STREAMS
+    typename NtVec<T>::t x;
+#pragma unroll
+    for (int i = 0; i < Vec<T>::N; ++i) x[i] = v[i];
+    __builtin_nontemporal_store(x, reinterpret_cast<typename NtVec<T>::t*>(p));
+#else
+    store_vec<T>(p, v);
+#endif
 }
 
 // Number of 32-bit halves per exchanged value.

@@ -253,8 +253,8 @@ __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs
         const int ii = bb * H + wave * rpw + rg;
         const int col = c0 + (li + lpr * v) * VEC;
         const bool ok = (v < nv) && (ii < m) && (col < n);
-        load_vec<T>(M + (ok ? (int64_t)ii * ldm + col : 0), mvv[v]);
-        if (mode == 2) load_vec<T>(a.Yprev + (ok ? (int64_t)ii * ldy + col : 0), ypv[v]);
+        load_vec_stream<T>(M + (ok ? (int64_t)ii * ldm + col : 0), mvv[v]);
+        if (mode == 2) load_vec_stream<T>(a.Yprev + (ok ? (int64_t)ii * ldy + col : 0), ypv[v]);
     };
     if (nbl > 0) {
 #pragma unroll
@@ -355,7 +355,7 @@ __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs
                         x[e] = l + dy * imu_prev + y * imu_cur;
                         yn[e] = y;
                     }
-                    if (ok) store_vec<T>(a.Ynext + (int64_t)i * ldy + col, yn);
+                    if (ok) store_vec_stream<T>(a.Ynext + (int64_t)i * ldy + col, yn);
                 }
                 if (!ok) {
 #pragma unroll

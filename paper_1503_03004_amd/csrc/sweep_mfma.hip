@@ -33,6 +33,13 @@
 
 #include <hip/hip_ext.h>
 
+// Non-temporal hints on this sweep's streams measured slower (8000^2: r = 20
+// 382 against 378 us, X = M sweeps 113 against 107 us, alternating on one
+// device), unlike the vector sweep's: off by default.
+#ifndef SFR_NT_MFMA
+#define SFR_NT_MFMA 0
+#endif
+
 namespace sfr {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -208,8 +215,18 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
         const int i = (cl + jb * ncl) * kMH + lr;
         const int col = cw + 16 * t + 4 * lq;
         const bool ok = (i < m) && (col < n);
+#if SFR_NT_MFMA
+        float v4[4];
+        load_vec_stream<float>(M + (ok ? (int64_t)i * ldm + col : 0), v4);
+        mv[t] = make_float4(v4[0], v4[1], v4[2], v4[3]);
+        if (mode == 2) {
+            load_vec_stream<float>(a.Yprev + (ok ? (int64_t)i * ldy + col : 0), v4);
+            yv[t] = make_float4(v4[0], v4[1], v4[2], v4[3]);
+        }
+#else
         mv[t] = *reinterpret_cast<const float4*>(M + (ok ? (int64_t)i * ldm + col : 0));
         if (mode == 2) yv[t] = *reinterpret_cast<const float4*>(a.Yprev + (ok ? (int64_t)i * ldy + col : 0));
+#endif
     };
     if (nbl > 0) {
 #pragma unroll
@@ -288,7 +305,11 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
                         x[e] = ok ? (l + dy * imu_prev + y * imu_cur) : 0.f;
                         yn[e] = y;
                     }
+#if SFR_NT_MFMA
+                    if (ok) store_vec_stream<float>(a.Ynext + (int64_t)i * ldy + col, yn);
+#else
                     if (ok) *reinterpret_cast<float4*>(a.Ynext + (int64_t)i * ldy + col) = make_float4(yn[0], yn[1], yn[2], yn[3]);
+#endif
                 }
                 *reinterpret_cast<float4*>(Xw + ((size_t)buf * kMH + lr) * kMXP + 16 * t + 4 * lq) =
                     make_float4(x[0], x[1], x[2], x[3]);
