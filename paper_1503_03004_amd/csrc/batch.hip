@@ -19,6 +19,8 @@
 #include "sfr_internal.hpp"
 #include "small_la.hpp"
 
+#include <stdlib.h>
+
 namespace sfr {
 
 constexpr int kBNW = 8;               // wavefronts per workgroup
@@ -40,6 +42,25 @@ __device__ inline __attribute__((address_space(1))) T* as_global(T* p)
 
 template <bool B> struct BoolTag { static constexpr bool value = B; };
 
+typedef float bf32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf32x4 bmfma4(float a, float b, bf32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Matrix-core form of the band loop (wide problems, R = 8..16): bands of 16
+// rows; wavefront w owns the 16-column tiles w, w + 8, w + 16, w + 24.  The
+// contractions run on v_mfma_f32_16x16x4_f32 with the single-problem
+// matrix-core sweep's lane layout (lane l: lr = l % 16, lq = l / 16 supplies
+// A[lr][lq], B[lq][lr] and receives D[4 lq + e][lr]):
+//   l   (16 columns x 16 rows of a tile) = V_tile . a_band^T      K = R
+//   p   (R x 16 rows)                   += V_tile^T-slices . x    K = 16 columns
+//   Q   (16 columns x R)                += x_tile^T . P_band      K = 16 rows
+// so lane (lr, lq) holds row lr, columns 4 lq .. 4 lq + 3 of each tile.
+constexpr int kMB = 16;                 // rows per band
+constexpr int kMXP = 4 * 16 + 16;       // LDS pitch of a wavefront's x rows (4 tiles + pad)
+
 __device__ inline float lane_bcast(float v, int l)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
@@ -47,10 +68,11 @@ __device__ inline float lane_bcast(float v, int l)
 
 // RW rows per wavefront per band (a band is 8 RW rows): two rows share each
 // V column read; one row keeps the larger ranks' band loop within registers.
-template <int R, int RW, bool NARROW>
+template <int R, int RW, bool NARROW, bool MF>
 __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, BatchParams bp)
 {
     static_assert(R <= 16, "batched solver: r <= 16");
+    static_assert(!MF || (!NARROW && R >= 8), "matrix-core form: wide problems, R >= 8");
     constexpr int kBRW = RW;
     constexpr int kBH = kBNW * RW;        // rows per band
     constexpr int E = R * (R + 1) / 2;
@@ -77,8 +99,12 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
     // so a lane reads the R entries of its column with R/4 128-bit reads.
     // Between the sweep and the step the same space stages Q_k (Vs[j R + k]).
     __shared__ __align__(16) float Vs[RP * kBNMax];
-    __shared__ __align__(16) float Xs[kBH * kBNMax];   // x of the band; FP64 G_Q partials in the step
-    __shared__ __align__(16) float Ps[kBH * 8 * 16];   // p of the band's rows (up to 8 rows per wavefront step)
+    __shared__ __align__(16) float Xs[MF ? 1024 : kBH * kBNMax];   // x of the band; FP64 G_Q partials in the step
+    __shared__ __align__(16) float Ps[MF ? 16 : kBH * 8 * 16];     // p of the band's rows (up to 8 rows per wavefront step)
+    // matrix-core form: per-wavefront x tiles, per-wavefront p partials, the band's p
+    __shared__ __align__(16) float XwA[MF ? kBNW * kMB * kMXP : 1];
+    __shared__ __align__(16) float PWA[MF ? kBNW * 256 : 1];
+    __shared__ __align__(16) float PSA[MF ? 256 : 1];
     __shared__ __align__(16) float TUt[R * RP];        // T_U transposed: TUt[k RP + t] = T_U[t][k]
     __shared__ __align__(16) float TVt[R * RP];        // T_V transposed (FP32)
     __shared__ double Gp[R * LDP], Gq[R * LDP], Bm[R * LDP], C1[R * LDP], C2[R * LDP];
@@ -319,7 +345,152 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
                 for (int e = 0; e < kBRW; ++e) cp[e] = np[e];
             }
         };
-        sweep_bands(BoolTag<NARROW>{});
+        if constexpr (MF) {
+            constexpr int S1 = (R + 3) / 4;
+            const int lr = lane & 15, lq = lane >> 4;
+            const int ntile = (n + 15) / 16;
+            // this lane's V operands for its tiles: l product A[lr][lq] = V[col 16 tg + lr][rank 4 s + lq],
+            // p product A[lr][lq] = V[col 16 tg + 4 lq + e][rank lr]
+            float va1[4][S1], va2[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c0 = 16 * (wave + 8 * u);
+#pragma unroll
+                for (int s2 = 0; s2 < S1; ++s2) {
+                    const int kk = 4 * s2 + lq, j = c0 + lr;
+                    va1[u][s2] = (kk < R && j < n) ? Vs[vat(kk, j)] : 0.f;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int j = c0 + 4 * lq + e;
+                    va2[u][e] = (lr < R && j < n) ? Vs[vat(lr, j)] : 0.f;
+                }
+            }
+            bf32x4 qacc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) qacc[u] = bf32x4{0.f, 0.f, 0.f, 0.f};
+            float* Xw = XwA + wave * kMB * kMXP;
+            const int nb = (m + kMB - 1) / kMB;
+            for (int b = 0; b < nb; ++b) {
+                const int i = b * kMB + lr;
+                const bool row_ok = i < m;
+                // a_i = P_i T_U for entries 4 s + lq
+                float aop[S1];
+                if (mode != 0) {
+                    float prow[R];
+#pragma unroll
+                    for (int t = 0; t < R; ++t) prow[t] = row_ok ? Pp[(int64_t)i * R + t] : 0.f;
+#pragma unroll
+                    for (int s2 = 0; s2 < S1; ++s2) {
+                        const int kk = 4 * s2 + lq;
+                        float v = 0.f;
+                        if (kk < R) {
+#pragma unroll
+                            for (int t = 0; t < R; ++t) v = fmaf(prow[t], TUt[kk * RP + t], v);
+                        }
+                        aop[s2] = v;
+                    }
+                }
+                bf32x4 pacc = {0.f, 0.f, 0.f, 0.f};
+                float rowacc = 0.f;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int tg = wave + 8 * u;
+                    if (tg < ntile) {     // uniform over the wavefront
+                        const int col = 16 * tg + 4 * lq;
+                        float mv[4], yp[4] = {0.f, 0.f, 0.f, 0.f}, x[4];
+                        bool okv[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            okv[e] = row_ok && (col + e < n);
+                            mv[e] = okv[e] ? M[(int64_t)i * ldm + col + e] : 0.f;
+                        }
+                        if (mode == 0) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                x[e] = mv[e];
+                                rowacc = fmaf(mv[e], mv[e], rowacc);
+                            }
+                        } else {
+                            bf32x4 lv = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                            for (int s2 = 0; s2 < S1; ++s2) lv = bmfma4(va1[u][s2], aop[s2], lv);
+                            if (mode == 2 && row_ok && col < n) {
+                                const bf32x4 y4 = *reinterpret_cast<const __attribute__((address_space(1))) bf32x4*>(
+                                    Yp + (int64_t)i * ldy + col);
+                                yp[0] = y4[0]; yp[1] = y4[1]; yp[2] = y4[2]; yp[3] = y4[3];
+                            }
+                            float yn[4];
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const float ype = okv[e] ? yp[e] : 0.f;
+                                const float Rr = mv[e] - lv[e] + ype * imup;
+                                const float y = fminf(fmaxf(mup * Rr, -lam), lam);
+                                const float dy = y - ype;
+                                rowacc = okv[e] ? fmaf(dy, dy, rowacc) : rowacc;
+                                x[e] = okv[e] ? (lv[e] + dy * imup + y * imuc) : 0.f;
+                                yn[e] = y;
+                            }
+                            // col < n and col % 4 == 0: the vector stays inside the row's ldy >= n (rounded up to 4)
+                            if (row_ok && col < n)
+                                *reinterpret_cast<__attribute__((address_space(1))) bf32x4*>(Yn + (int64_t)i * ldy + col) =
+                                    bf32x4{yn[0], yn[1], yn[2], yn[3]};
+                        }
+                        *reinterpret_cast<float4*>(Xw + lr * kMXP + 16 * u + 4 * lq) = make_float4(x[0], x[1], x[2], x[3]);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) pacc = bmfma4(va2[u][e], x[e], pacc);
+                    }
+                }
+                acc2 += (double)rowacc;
+                // lane (lr, lq) holds p[row lr][rank 4 lq + e] of this wavefront's columns
+#pragma unroll
+                for (int e = 0; e < 4; ++e) PWA[wave * 256 + lr * 16 + 4 * lq + e] = pacc[e];
+                __syncthreads();
+                if (tid < 256) {
+                    float sum = 0.f;
+#pragma unroll
+                    for (int w = 0; w < kBNW; ++w) sum += PWA[w * 256 + tid];
+                    PSA[tid] = sum;
+                    const int hh = tid >> 4, kk = tid & 15;
+                    if (kk < R && b * kMB + hh < m) Pn[(int64_t)(b * kMB + hh) * R + kk] = sum;
+                }
+                __syncthreads();
+                // column pass: Q[col 16 tg + 4 lq + e][rank lr] += x^T p over the band's rows
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (wave + 8 * u < ntile) {
+#pragma unroll
+                        for (int s2 = 0; s2 < 4; ++s2) {
+                            const float a3 = Xw[(4 * s2 + lq) * kMXP + 16 * u + lr];
+                            const float b3 = PSA[(4 * s2 + lq) * 16 + lr];
+                            qacc[u] = bmfma4(a3, b3, qacc[u]);
+                        }
+                    }
+                }
+                if (tid < E) {
+#pragma unroll 4
+                    for (int h = 0; h < kMB; ++h) gp = fma((double)PSA[h * 16 + gx], (double)PSA[h * 16 + gy], gp);
+                }
+                __syncthreads();
+            }
+            // Q_k from the MFMA layout to the staging rows (Vs[j R + k]), then
+            // into each column thread's registers
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c0 = 16 * (wave + 8 * u) + 4 * lq;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (lr < R && c0 + e < n) Vs[(c0 + e) * R + lr] = qacc[u][e];
+            }
+            __syncthreads();
+            if (tid < n) {
+#pragma unroll
+                for (int kk = 0; kk < R; ++kk) q[kk] = Vs[tid * R + kk];
+            }
+            __syncthreads();
+        } else {
+            sweep_bands(BoolTag<NARROW>{});
+        }
         // Q_k: to the workspace (the returned factors read it) and to LDS
         if (tid < n) {
 #pragma unroll
@@ -562,17 +733,26 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
 #define SFR_BATCH_RW(R) ((R) <= 12 ? 2 : 1)
 #endif
 
+static bool batch_mfma_enabled()
+{
+    const char* v = getenv("SFR_BATCH_MFMA");
+    return !(v && v[0] == '0');
+}
+
 hipError_t launch_batch(BatchItemDev* items, int count, int R, bool narrow, const BatchParams& bp, hipStream_t s)
 {
+    const bool mf = !narrow && R >= 8 && batch_mfma_enabled();
     switch (R) {
-#define CASE(rr)                                                                                          \
-    case rr:                                                                                              \
-        if (narrow)                                                                                       \
-            hipLaunchKernelGGL((batch_kernel<rr, 1, true>), dim3(count), dim3(kBTPB), 0, s, \
-                               items, bp);                                                                \
-        else                                                                                              \
-            hipLaunchKernelGGL((batch_kernel<rr, SFR_BATCH_RW(rr), false>), dim3(count), dim3(kBTPB), 0, s, \
-                               items, bp);                                                                \
+#define CASE(rr)                                                                                             \
+    case rr:                                                                                                 \
+        if (narrow)                                                                                          \
+            hipLaunchKernelGGL((batch_kernel<rr, 1, true, false>), dim3(count), dim3(kBTPB), 0, s, items, bp);  \
+        else if (mf)                                                                                         \
+            hipLaunchKernelGGL((batch_kernel<rr, 1, false, (rr >= 8)>), dim3(count), dim3(kBTPB), 0, s, items, \
+                               bp);                                                                          \
+        else                                                                                                 \
+            hipLaunchKernelGGL((batch_kernel<rr, SFR_BATCH_RW(rr), false, false>), dim3(count), dim3(kBTPB), 0, \
+                               s, items, bp);                                                                \
         return hipGetLastError();
         SFR_BATCH_R_LIST(CASE)
 #undef CASE

@@ -269,3 +269,18 @@ def test_full_capacity_stream_batch():
     assert all(g["info"].iters == 15 for g in out)
     for k in (0, 31, 64, 127):
         check_vs_oracle(probs[k], out[k], 15, f"stream[{k}]")
+
+
+@pytest.mark.parametrize("form", ["mfma", "vector"])
+@pytest.mark.parametrize("fixed", [2, 3, 7])
+def test_wide_rank_buckets_in_both_forms(form, fixed, monkeypatch):
+    """Wide problems of ranks 8..16 run the matrix-core band loop (16-row
+    bands, v_mfma_f32_16x16x4_f32) unless SFR_BATCH_MFMA=0 selects the vector
+    one; both against the oracle, every rank bucket from 8 on (r = 9 and 10
+    pad to 12 entries in the grouped V layout)."""
+    monkeypatch.setenv("SFR_BATCH_MFMA", "1" if form == "mfma" else "0")
+    probs = [make(300, 300, r, seed=40 + r) for r in (8, 9, 10, 12, 16)] + [make(1500, 480, 10, seed=9)]
+    for p in probs:
+        with sfr.BatchSolver(1, p["M"].shape[0], p["M"].shape[1], p["r"], fixed_iters=fixed) as bs:
+            g = run_batch(bs, [p])[0]
+        check_vs_oracle(p, g, fixed, f"{form} r={p['r']}")
