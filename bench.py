@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: mean arrival rate (requests/s)")
     ap.add_argument("--workers", type=int, default=4, help="serving: concurrent batched launches")
     ap.add_argument("--max-batch", type=int, default=0, help="serving: requests per launch (0: capacity)")
+    ap.add_argument("--no-autotune", action="store_true", help="serving: keep the built-in band-loop forms")
     ap.add_argument("--solves", type=int, default=5, help="tolerance-driven solves timed for solves/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-iters", type=int, default=12, help="oracle iterations timed on the host (about 1 s each)")
@@ -315,7 +316,10 @@ def serving(args):
     server = serve.BatchServer(max_m=2048, max_n=512, max_r=16, workers=args.workers, capacity=256,
                                max_batch=args.max_batch or None)
     server.run(requests(False, range(min(64, len(reqs)))))          # warm-up, untimed
+    # autotune the band-loop form per problem class and rank bucket on a sample of the stream
+    tuned = server.tune(requests(False, range(min(256, len(reqs))))) if not args.no_autotune else {}
     torch.cuda.synchronize()
+    print(f"[serving] autotuned forms: {tuned}", file=sys.stderr, flush=True)
 
     # ---- the stream at its offered rate
     server.launches, server.batch_sizes = 0, []
@@ -417,6 +421,7 @@ def serving(args):
         "saturated_solves_per_s": capacity,
         "launches": stream_launches,
         "mean_batch": mean_batch,
+        "autotuned": {f"{'narrow' if k[0] else 'wide'} r<={k[1]}": v for k, v in tuned.items()},
         "median_iters": float(np.median(iters)),
         "failed": len(bad),
         "parity_vs_oracle": parity,

@@ -225,6 +225,27 @@ sfr_status sfr_create_batch(sfr_handle* out, int32_t capacity, int64_t max_m, in
 sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t count, sfr_info* infos,
                            int32_t* statuses, void* hip_stream);
 
+/*
+ * Autotuner of a batched handle: for every (class, rank bucket) present
+ * among `items` -- class 0: n > 128, class 1: n <= 128; buckets r = 1, 2, 3,
+ * 4, 5, 6, 8, 10, 12, 16 -- times each form of the batched kernel's band
+ * loop on those items (4 iterations, after one warm-up run) and records the
+ * fastest in the handle; later sfr_solve_batch calls on the handle use it.
+ * The forms are exact and give the same iteration within rounding: lane
+ * groups of 8 or 16 lanes per row (class 1 only), one or two rows per
+ * wavefront over 64 lanes, and the matrix-core band loop (r buckets >= 8).
+ * Untuned (class, bucket) pairs keep the built-in choice.
+ *   items (host, count entries): as for sfr_solve_batch; their output
+ *     buffers are overwritten with 4-iteration results.
+ *   table (host, 20 entries, may be NULL): receives the choice per
+ *     [class * 10 + bucket index]: 0 not tuned, 1 lane groups, 2 one row per
+ *     wavefront, 3 two rows, 4 matrix cores.
+ * Errors: SFR_ERR_HANDLE (NULL or non-batched handle), SFR_ERR_ARG (an item
+ * out of the handle's limits), SFR_ERR_DEVICE.
+ */
+sfr_status sfr_tune_batch(sfr_handle h, const sfr_batch_item* items, int32_t count, int32_t* table,
+                          void* hip_stream);
+
 /* Release the handle and its workspace.  NULL is accepted. */
 sfr_status sfr_destroy(sfr_handle h);
 

@@ -113,6 +113,8 @@ def lib():
         L.sfr_solve_batch.argtypes = [vp, ctypes.POINTER(sfr_batch_item), i32, ctypes.POINTER(sfr_info),
                                       ctypes.POINTER(ctypes.c_int32), vp]
         L.sfr_solve_batch.restype = ctypes.c_int
+        L.sfr_tune_batch.argtypes = [vp, ctypes.POINTER(sfr_batch_item), i32, ctypes.POINTER(ctypes.c_int32), vp]
+        L.sfr_tune_batch.restype = ctypes.c_int
         L.sfr_destroy.argtypes = [vp]
         L.sfr_destroy.restype = ctypes.c_int
         L.sfr_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
@@ -341,6 +343,37 @@ class BatchSolver:
         if rc < 0 and (raise_on_error or rc in (SFR_ERR_ARG, SFR_ERR_HANDLE, SFR_ERR_DEVICE)):
             raise SFRError(rc, "sfr_solve_batch")
         return [(*keep[i], _info(int(st[i]), infos[i])) for i in range(count)]
+
+    VARIANTS = {0: "default", 1: "lane groups", 2: "one row per wavefront", 3: "two rows per wavefront",
+                4: "matrix cores"}
+    BUCKETS = (1, 2, 3, 4, 5, 6, 8, 10, 12, 16)
+
+    def autotune(self, problems, *, stream=None):
+        """Time the batched kernel's band-loop forms on `problems` (a list of
+        (M, r, lam, mu, tol), as for solve) and keep the fastest per problem
+        class and rank bucket.  Returns {(narrow, bucket): form name} for the
+        tuned pairs."""
+        import torch
+        items = (sfr_batch_item * max(len(problems), 1))()
+        keep = []
+        for i, (M, r, lam, mu, tol) in enumerate(problems):
+            m, n = M.shape
+            U = torch.empty((m, r), dtype=torch.float32, device=M.device)
+            B = torch.empty((r, r), dtype=torch.float64, device=M.device)
+            V = torch.empty((n, r), dtype=torch.float32, device=M.device)
+            keep.append((U, B, V))
+            it = items[i]
+            it.m, it.n, it.r = m, n, int(r)
+            it.lam, it.mu, it.tol = float(lam), float(mu), float(tol)
+            it.M, it.ldm = M.data_ptr(), M.stride(0)
+            it.U, it.B, it.V = U.data_ptr(), B.data_ptr(), V.data_ptr()
+            it.S, it.lds = None, 0
+        table = (ctypes.c_int32 * 20)()
+        rc = lib().sfr_tune_batch(self._h, items, len(problems), table, _stream_handle(stream))
+        if rc != SFR_OK:
+            raise SFRError(rc, "sfr_tune_batch")
+        return {(bool(c), self.BUCKETS[b]): self.VARIANTS[table[c * 10 + b]]
+                for c in range(2) for b in range(10) if table[c * 10 + b]}
 
     def close(self):
         if self._h and self._h.value:

@@ -739,20 +739,41 @@ static bool batch_mfma_enabled()
     return !(v && v[0] == '0');
 }
 
-hipError_t launch_batch(BatchItemDev* items, int count, int R, bool narrow, const BatchParams& bp, hipStream_t s)
+int batch_default_variant(int R, bool narrow)
 {
-    const bool mf = !narrow && R >= 8 && batch_mfma_enabled();
+    if (narrow) return kBVNarrow;
+    if (R >= 8 && batch_mfma_enabled()) return kBVMfma;
+    return SFR_BATCH_RW(R) == 2 ? kBVRow2 : kBVRow1;
+}
+
+bool batch_variant_valid(int R, int variant)
+{
+    return variant == kBVNarrow || variant == kBVRow1 || variant == kBVRow2 || (variant == kBVMfma && R >= 8);
+}
+
+hipError_t launch_batch(BatchItemDev* items, int count, int R, bool narrow, int variant, const BatchParams& bp,
+                        hipStream_t s)
+{
+    if (variant == kBVAuto) variant = batch_default_variant(R, narrow);
+    if (!batch_variant_valid(R, variant)) return hipErrorInvalidValue;
     switch (R) {
-#define CASE(rr)                                                                                             \
-    case rr:                                                                                                 \
-        if (narrow)                                                                                          \
-            hipLaunchKernelGGL((batch_kernel<rr, 1, true, false>), dim3(count), dim3(kBTPB), 0, s, items, bp);  \
-        else if (mf)                                                                                         \
-            hipLaunchKernelGGL((batch_kernel<rr, 1, false, (rr >= 8)>), dim3(count), dim3(kBTPB), 0, s, items, \
-                               bp);                                                                          \
-        else                                                                                                 \
-            hipLaunchKernelGGL((batch_kernel<rr, SFR_BATCH_RW(rr), false, false>), dim3(count), dim3(kBTPB), 0, \
-                               s, items, bp);                                                                \
+#define CASE(rr)                                                                                               \
+    case rr:                                                                                                   \
+        switch (variant) {                                                                                     \
+        case kBVNarrow:                                                                                        \
+            hipLaunchKernelGGL((batch_kernel<rr, 1, true, false>), dim3(count), dim3(kBTPB), 0, s, items, bp); \
+            break;                                                                                             \
+        case kBVMfma:                                                                                          \
+            hipLaunchKernelGGL((batch_kernel<rr, 1, false, (rr >= 8)>), dim3(count), dim3(kBTPB), 0, s, items,   \
+                               bp);                                                                            \
+            break;                                                                                             \
+        case kBVRow2:                                                                                          \
+            hipLaunchKernelGGL((batch_kernel<rr, 2, false, false>), dim3(count), dim3(kBTPB), 0, s, items, bp); \
+            break;                                                                                             \
+        default:                                                                                               \
+            hipLaunchKernelGGL((batch_kernel<rr, 1, false, false>), dim3(count), dim3(kBTPB), 0, s, items, bp); \
+            break;                                                                                             \
+        }                                                                                                      \
         return hipGetLastError();
         SFR_BATCH_R_LIST(CASE)
 #undef CASE

@@ -15,12 +15,45 @@ namespace sfr {
 // items with n up to this many columns run in the narrow kernel variant
 constexpr int64_t kBatchNarrowN = 128;
 
+static const int kBatchBuckets[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
+constexpr int kNumBatchBuckets = 10;
+
 static int batch_bucket(int r)
 {
-    static const int Rs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
-    for (int R : Rs)
+    for (int R : kBatchBuckets)
         if (R >= r) return R;
     return -1;
+}
+
+static int bucket_index(int R)
+{
+    for (int i = 0; i < kNumBatchBuckets; ++i)
+        if (kBatchBuckets[i] == R) return i;
+    return -1;
+}
+
+static bool item_valid(const sfr_ctx* h, const sfr_batch_item& it)
+{
+    if (it.m < 1 || it.m > h->max_m || it.n < 1 || it.n > h->max_n) return false;
+    if (it.r < 1 || it.r > h->max_r || it.r > it.m || it.r > it.n) return false;
+    if (!(it.lambda > 0.0) || it.lambda > 1e300 || !(it.mu > 0.0) || it.mu > 1e300) return false;
+    if (!(it.tol >= 0.0) || it.tol > 1e300) return false;
+    if (!it.M || !it.U || !it.B || !it.V || it.ldm < it.n || (it.S && it.lds < it.n)) return false;
+    return true;
+}
+
+// descriptor of the caller's item `it` in launch position `pos` (workspace slot pos)
+static void fill_desc(sfr_ctx* h, const sfr_batch_item& it, int32_t pos)
+{
+    BatchItemDev& d = h->items_h[pos];
+    memset(&d, 0, sizeof(d));
+    d.m = (int32_t)it.m; d.n = (int32_t)it.n; d.r = it.r; d.ldy = (int32_t)h->ldy;
+    d.lambda = it.lambda; d.mu0 = it.mu; d.tol = it.tol;
+    d.M = static_cast<const float*>(it.M); d.ldm = it.ldm;
+    d.U = static_cast<float*>(it.U); d.B = it.B; d.V = static_cast<float*>(it.V);
+    d.S = static_cast<float*>(it.S); d.lds = it.lds;
+    float* const* w = &h->slot_ws[(size_t)pos * 6];
+    d.Y0 = w[0]; d.Y1 = w[1]; d.P0 = w[2]; d.P1 = w[3]; d.Q0 = w[4]; d.Q1 = w[5];
 }
 
 }  // namespace sfr
@@ -105,11 +138,7 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
     int Rw = 1, Rn = 1, nw = 0;
     for (int32_t i = 0; i < count; ++i) {
         const sfr_batch_item& it = items[i];
-        if (it.m < 1 || it.m > h->max_m || it.n < 1 || it.n > h->max_n) return SFR_ERR_ARG;
-        if (it.r < 1 || it.r > h->max_r || it.r > it.m || it.r > it.n) return SFR_ERR_ARG;
-        if (!(it.lambda > 0.0) || it.lambda > 1e300 || !(it.mu > 0.0) || it.mu > 1e300) return SFR_ERR_ARG;
-        if (!(it.tol >= 0.0) || it.tol > 1e300) return SFR_ERR_ARG;
-        if (!it.M || !it.U || !it.B || !it.V || it.ldm < it.n || (it.S && it.lds < it.n)) return SFR_ERR_ARG;
+        if (!item_valid(h, it)) return SFR_ERR_ARG;
         if (it.n > kBatchNarrowN) {
             Rw = std::max(Rw, batch_bucket(it.r));
             ++nw;
@@ -123,18 +152,7 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
         for (int32_t i = 0; i < count; ++i) h->order[(items[i].n > kBatchNarrowN) ? a++ : b++] = i;
     }
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    for (int32_t pos = 0; pos < count; ++pos) {
-        const sfr_batch_item& it = items[h->order[pos]];
-        BatchItemDev& d = h->items_h[pos];
-        memset(&d, 0, sizeof(d));
-        d.m = (int32_t)it.m; d.n = (int32_t)it.n; d.r = it.r; d.ldy = (int32_t)h->ldy;
-        d.lambda = it.lambda; d.mu0 = it.mu; d.tol = it.tol;
-        d.M = static_cast<const float*>(it.M); d.ldm = it.ldm;
-        d.U = static_cast<float*>(it.U); d.B = it.B; d.V = static_cast<float*>(it.V);
-        d.S = static_cast<float*>(it.S); d.lds = it.lds;
-        float* const* w = &h->slot_ws[(size_t)pos * 6];
-        d.Y0 = w[0]; d.Y1 = w[1]; d.P0 = w[2]; d.P1 = w[3]; d.Q0 = w[4]; d.Q1 = w[5];
-    }
+    for (int32_t pos = 0; pos < count; ++pos) fill_desc(h, items[h->order[pos]], pos);
     BatchParams bp;
     bp.rho = h->prm.rho;
     bp.mu_bar = h->prm.mu_bar;
@@ -147,10 +165,10 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
         // fork: the side stream waits for the descriptors, runs the narrow
         // items, and the caller's stream waits for it before the copy back
         ok = hipEventRecord(h->ev_fork, s) == hipSuccess && hipStreamWaitEvent(h->side, h->ev_fork, 0) == hipSuccess &&
-             launch_batch(h->items_d + nw, nn, Rn, true, bp, h->side) == hipSuccess &&
+             launch_batch(h->items_d + nw, nn, Rn, true, h->variant[1][bucket_index(Rn)], bp, h->side) == hipSuccess &&
              hipEventRecord(h->ev_join, h->side) == hipSuccess;
     }
-    if (ok && nw > 0) ok = launch_batch(h->items_d, nw, Rw, false, bp, s) == hipSuccess;
+    if (ok && nw > 0) ok = launch_batch(h->items_d, nw, Rw, false, h->variant[0][bucket_index(Rw)], bp, s) == hipSuccess;
     if (ok && nn > 0) ok = hipStreamWaitEvent(s, h->ev_join, 0) == hipSuccess;
     if (!ok || hipMemcpyAsync(h->items_h, h->items_d, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
@@ -184,6 +202,74 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
         }
     }
     return worst;
+}
+
+sfr_status sfr_tune_batch(sfr_handle h, const sfr_batch_item* items, int32_t count, int32_t* table,
+                          void* hip_stream)
+{
+    if (!h || h->magic != 0x53465221u || !h->batch) return SFR_ERR_HANDLE;
+    if (count < 0 || count > h->capacity || (count > 0 && !items)) return SFR_ERR_ARG;
+    for (int32_t i = 0; i < count; ++i)
+        if (!item_valid(h, items[i])) return SFR_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    constexpr int kTuneIters = 4;
+    BatchParams bp;
+    bp.rho = h->prm.rho;
+    bp.mu_bar = h->prm.mu_bar;
+    bp.max_iter = h->prm.max_iter;
+    bp.fixed_iters = kTuneIters;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipGetLastError();
+        return SFR_ERR_DEVICE;
+    }
+    sfr_status st = SFR_OK;
+    // one group per (class, rank bucket) present among the items
+    for (int cls = 0; cls < 2 && st == SFR_OK; ++cls) {
+        for (int bi = 0; bi < kNumBatchBuckets && st == SFR_OK; ++bi) {
+            const int R = kBatchBuckets[bi];
+            int32_t g = 0;
+            for (int32_t i = 0; i < count; ++i) {
+                const bool narrow = items[i].n <= kBatchNarrowN;
+                if ((narrow ? 1 : 0) == cls && batch_bucket(items[i].r) == R) fill_desc(h, items[i], g++);
+            }
+            if (g == 0) continue;
+            const size_t bytes = sizeof(BatchItemDev) * (size_t)g;
+            int best = kBVAuto;
+            float best_ms = 0.f;
+            const int cands[] = {kBVNarrow, kBVRow1, kBVRow2, kBVMfma};
+            for (int v : cands) {
+                if (!batch_variant_valid(R, v) || (v == kBVNarrow && cls == 0)) continue;
+                float ms = 0.f;
+                for (int rep = 0; rep < 2 && st == SFR_OK; ++rep) {   // the first run warms up
+                    if (hipMemcpyAsync(h->items_d, h->items_h, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+                        hipEventRecord(e0, s) != hipSuccess ||
+                        launch_batch(h->items_d, g, R, cls == 1, v, bp, s) != hipSuccess ||
+                        hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                        st = SFR_ERR_DEVICE;
+                }
+                if (st != SFR_OK) break;
+                if (best == kBVAuto || ms < best_ms) {
+                    best = v;
+                    best_ms = ms;
+                }
+            }
+            if (st == SFR_OK) h->variant[cls][bi] = (int8_t)best;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SFR_OK) {
+        (void)hipGetLastError();
+        return st;
+    }
+    if (table) {
+        for (int cls = 0; cls < 2; ++cls)
+            for (int bi = 0; bi < kNumBatchBuckets; ++bi) table[cls * kNumBatchBuckets + bi] = h->variant[cls][bi];
+    }
+    return SFR_OK;
 }
 
 }  // extern "C"

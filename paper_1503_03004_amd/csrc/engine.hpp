@@ -112,6 +112,7 @@ struct sfr_ctx {
     sfr::BatchItemDev* items_h = nullptr;   // pinned mirror
     std::vector<float*> slot_ws;            // per slot: Y0, Y1, P0, P1, Q0, Q1
     std::vector<int32_t> order;             // launch position -> caller's item index
+    int8_t variant[2][16] = {};             // [narrow][bucket index]: tuned band-loop form (0: default)
     hipStream_t side = nullptr;             // second launch of a batch (narrow items)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     size_t batch_bytes = 0;

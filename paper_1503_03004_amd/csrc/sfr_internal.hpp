@@ -197,8 +197,15 @@ struct BatchParams {
     int32_t max_iter, fixed_iters;
 };
 
-// narrow: the kernel variant for n <= 128 (several rows per wavefront)
-hipError_t launch_batch(BatchItemDev* items, int count, int R, bool narrow, const BatchParams& bp, hipStream_t s);
+// Forms of the batched kernel's band loop (all exact; they differ in speed):
+// lane groups of 8/16 lanes per row (narrow problems), one or two rows per
+// wavefront over 64 lanes, or the matrix-core loop (R >= 8).
+enum : int { kBVAuto = 0, kBVNarrow = 1, kBVRow1 = 2, kBVRow2 = 3, kBVMfma = 4 };
+int batch_default_variant(int R, bool narrow);
+bool batch_variant_valid(int R, int variant);
+// narrow: the items have n <= 128; variant kBVAuto picks the default form
+hipError_t launch_batch(BatchItemDev* items, int count, int R, bool narrow, int variant, const BatchParams& bp,
+                        hipStream_t s);
 
 // Host-side launchers (sweep.hip / small.hip / dense.hip).  The sweep takes
 // an optional start/stop event pair bound to its dispatch.

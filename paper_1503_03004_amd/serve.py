@@ -83,6 +83,18 @@ class BatchServer:
         self.launches = 0
         self.batch_sizes: list[int] = []
 
+    def tune(self, sample: list[Request]) -> dict:
+        """Autotune every worker's handle on a sample of requests (the
+        band-loop form per problem class and rank bucket, sfr_tune_batch).
+        Returns the table chosen by the first handle."""
+        items = [(q.M, q.r, q.lam, q.mu, q.tol) for q in sample[: self.capacity] if self.admissible(q)]
+        table = {}
+        for w, bs in enumerate(self.solvers):
+            t = bs.autotune(items, stream=self.streams[w])
+            if w == 0:
+                table = t
+        return table
+
     def admissible(self, req: Request) -> bool:
         m, n = req.M.shape
         return m <= self.max_m and n <= self.max_n and 1 <= req.r <= min(self.max_r, m, n)

@@ -22,7 +22,7 @@ def declared():
 def test_header_declares_the_entry_points():
     names = declared()
     for want in ("sfr_create", "sfr_solve", "sfr_solve_nys", "sfr_tsvd", "sfr_create_batch", "sfr_solve_batch",
-                 "sfr_destroy", "sfr_status_string", "sfr_version", "sfr_workspace_bytes"):
+                 "sfr_tune_batch", "sfr_destroy", "sfr_status_string", "sfr_version", "sfr_workspace_bytes"):
         assert want in names
 
 
@@ -152,6 +152,7 @@ def test_null_handle_paths():
     assert L.sfr_tsvd(None, None, 0, None, None, None, ctypes.byref(info), None) == B.SFR_ERR_HANDLE
     items = (B.sfr_batch_item * 1)()
     assert L.sfr_solve_batch(None, items, 1, None, None, None) == B.SFR_ERR_HANDLE
+    assert L.sfr_tune_batch(None, items, 1, None, None) == B.SFR_ERR_HANDLE
     assert L.sfr_destroy(None) == B.SFR_OK
     b = ctypes.c_uint64(0)
     assert L.sfr_workspace_bytes(None, ctypes.byref(b)) == B.SFR_ERR_HANDLE

@@ -284,3 +284,32 @@ def test_wide_rank_buckets_in_both_forms(form, fixed, monkeypatch):
         with sfr.BatchSolver(1, p["M"].shape[0], p["M"].shape[1], p["r"], fixed_iters=fixed) as bs:
             g = run_batch(bs, [p])[0]
         check_vs_oracle(p, g, fixed, f"{form} r={p['r']}")
+
+
+def test_autotune_records_a_form_per_class_and_bucket():
+    """sfr_tune_batch times the band-loop forms on the given problems and
+    records one per (class, rank bucket) present; solves on the tuned handle
+    still match the oracle (every form is exact)."""
+    probs = [make(600, 400, 10, seed=50), make(900, 300, 16, seed=51), make(500, 100, 4, seed=52),
+             make(700, 64, 12, seed=53), make(300, 200, 3, seed=54)]
+    items = [(torch.from_numpy(p["M"]).cuda(), p["r"], p["lam"], p["mu"], 1e-6) for p in probs]
+    with sfr.BatchSolver(len(probs), 900, 400, 16, fixed_iters=5) as bs:
+        table = bs.autotune(items)
+        torch.cuda.synchronize()
+        print("tuned:", table)
+        assert set(table) == {(False, 10), (False, 16), (True, 4), (True, 12), (False, 3)}
+        assert all(v in ("lane groups", "one row per wavefront", "two rows per wavefront", "matrix cores")
+                   for v in table.values())
+        assert table[(False, 3)] != "matrix cores"        # rank bucket below the matrix-core forms
+        assert table[(False, 10)] != "lane groups"        # lane groups only for narrow problems
+        out = run_batch(bs, probs)
+    for p, g in zip(probs, out):
+        check_vs_oracle(p, g, 5, "tuned")
+
+
+def test_autotune_rejects_items_beyond_the_limits():
+    p = make(100, 80, 4, seed=55)
+    with sfr.BatchSolver(1, 100, 80, 4) as bs:
+        with pytest.raises(sfr.SFRError) as e:
+            bs.autotune([(torch.from_numpy(p["M"]).cuda(), 5, p["lam"], p["mu"], 1e-6)])
+        assert e.value.code == sfr.SFR_ERR_ARG
