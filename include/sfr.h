@@ -199,8 +199,9 @@ typedef struct {
  * most max_m x max_n and rank max_r (FP32 only).
  *   1 <= capacity <= 65536; 1 <= max_n <= 512; 1 <= max_m <= 2^22;
  *   1 <= max_r <= min(16, max_m, max_n).
- *   opt (required): precision must be SFR_F32, nystrom_l 0; rho, mu_bar,
- *   max_iter and fixed_iters apply to every item (profile is ignored).
+ *   opt (required): precision must be SFR_F32, nystrom_l 0 and the BF16
+ *   fields 0; rho, mu_bar, max_iter and fixed_iters apply to every item
+ *   (profile is ignored).
  * Each slot holds 2 Y buffers (max_m x max_n), 2 P (max_m x 16) and 2 Q
  * (max_n x 16) buffers in device memory; sfr_workspace_bytes reports the
  * total.  Returns SFR_ERR_NOMEM if it does not fit.

@@ -70,6 +70,7 @@ sfr_status sfr_create_batch(sfr_handle* out, int32_t capacity, int64_t max_m, in
     if (!opt || opt->struct_size != sizeof(sfr_options)) return SFR_ERR_ARG;
     sfr_options o = *opt;
     if (o.precision != SFR_F32 || o.nystrom_l != 0) return SFR_ERR_ARG;
+    if (o.bf16 != 0 || o.bf16_iters != 0 || o.bf16_tol != 0.0) return SFR_ERR_ARG;   // FP32 operands only
     if (capacity < 1 || capacity > 65536) return SFR_ERR_ARG;
     if (max_m < 1 || max_m > (1 << 22) || max_n < 1 || max_n > 512) return SFR_ERR_ARG;
     if (max_r < 1 || max_r > 16 || max_r > max_m || max_r > max_n) return SFR_ERR_ARG;
