@@ -113,8 +113,10 @@ def test_fp32_solves_unchanged_by_the_option():
     assert np.array_equal(La, Lb) and np.array_equal(Sa, Sb)
 
 
-def test_bf16_needs_a_matrix_core_slice():
-    """n below the matrix-core slice width (1024 columns for r <= 12)."""
+@pytest.mark.parametrize("m,n,r", [(300, 500, 4), (262144, 48, 3)])
+def test_bf16_needs_a_matrix_core_slice(m, n, r):
+    """n below the matrix-core slice width (1024 columns for r <= 12),
+    including the photometric-stereo shape (48 images)."""
     with pytest.raises(sfr.SFRError) as e:
-        sfr.Solver(300, 500, 4, 0.1, 1.0, 1e-6, precision="f32", bf16=True)
+        sfr.Solver(m, n, r, 0.1, 1.0, 1e-6, precision="f32", bf16=True)
     assert e.value.code == sfr.SFR_ERR_ARG

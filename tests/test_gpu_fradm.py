@@ -230,6 +230,34 @@ def test_full_size_8000_fp32_first_iterations():
     assert rel(g["S"], o["S"]) <= 1e-5
 
 
+def test_photometric_full_size_fp32():
+    """The photometric-stereo shape of Sec. 5.2 at full size (262144 pixels x
+    48 images, r = 3, FP32, Lambertian L0 with specular outliers and
+    shadows): the GPU run to the oracle's own stopping iteration (tol 1e-7),
+    L and S compared on every entry."""
+    inst = workloads.photometric(seed=0)
+    Md = inst.M.astype(np.float64)
+    mu0 = workloads.default_mu0(Md)
+    o = oracle.fradm(Md, 3, inst.lam, mu0, tol=1e-7)
+    g = gpu_solve(inst.M, 3, inst.lam, mu0, "f32", fixed_iters=o["iters"])
+    assert g["info"].iters == o["iters"]
+    compare(g, o, "f32", f"photometric 262144x48 r3, {o['iters']} iterations")
+
+
+def test_photometric_tolerance_driven_fp32():
+    """Same shape at a quarter of the pixels, tolerance-driven on both sides:
+    the GPU stops within one iteration of the oracle (the FP32 residual
+    decides the stop) and matches the oracle run to the same count."""
+    inst = workloads.photometric(seed=3, m=65536)
+    Md = inst.M.astype(np.float64)
+    mu0 = workloads.default_mu0(Md)
+    g = gpu_solve(inst.M, 3, inst.lam, mu0, "f32", tol=1e-6)
+    o_ref = oracle.fradm(Md, 3, inst.lam, mu0, tol=1e-6)
+    assert abs(g["info"].iters - o_ref["iters"]) <= 1, (g["info"].iters, o_ref["iters"])
+    o = oracle.fradm(Md, 3, inst.lam, mu0, fixed_iters=g["info"].iters)
+    compare(g, o, "f32", f"photometric 65536x48 r3 tol 1e-6, {g['info'].iters} iterations")
+
+
 @pytest.mark.parametrize("sweep", ["mfma", "vector"])
 @pytest.mark.parametrize("m,n,r", [(300, 1100, 10), (1037, 2048, 4), (64, 5000, 12), (2100, 1024, 1),
                                    (300, 1100, 16), (200, 2000, 20), (1037, 700, 24), (150, 1500, 32)])
