@@ -369,6 +369,36 @@ def serving(args):
     tflops = flops / (launch_ms * 1e-3) / 1e12
     gbs = hbm / (launch_ms * 1e-3) / 1e9
 
+    # ---- the same requests through the single-problem engine (sfr_solve),
+    # one solve after another on the same stream, handles created beforehand;
+    # results compared with the batched ones at the same tolerance
+    handles = [sfr.Solver(q.M.shape[0], q.M.shape[1], q.r, q.lam, q.mu, tol, precision="f32") for q in one]
+    for h, q in zip(handles, one):
+        h.solve(q.M, stream=stream)                                     # warm
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    singles = [h.solve(q.M, stream=stream) for h, q in zip(handles, one)]
+    torch.cuda.synchronize()
+    single_rate = len(one) / (time.perf_counter() - t1)
+    for h in handles:
+        h.close()
+    same, dL, dS = 0, [], []
+    for rb, ro in zip(res, singles):
+        if rb[4].iters != ro[4].iters:
+            continue
+        same += 1
+        Lb = (rb[0].double() @ rb[1] @ rb[2].double().T).cpu().numpy()
+        Lo = (ro[0].double() @ ro[1] @ ro[2].double().T).cpu().numpy()
+        dL.append(rel(Lb, Lo))
+        dS.append(rel(rb[3].double().cpu().numpy(), ro[3].double().cpu().numpy()))
+    per_instance = {"solves_per_s": single_rate, "requests": len(one), "same_iters": same,
+                    "max_rel_diff_L": max(dL) if dL else None, "max_rel_diff_S": max(dS) if dS else None,
+                    "batched_one_launch_solves_per_s": len(one) / (launch_ms * 1e-3),
+                    "note": "sfr_solve per request, sequential on one stream, FP32, same tol; diffs against "
+                            "the batched results of the same requests"}
+    print(f"[serving] per-problem engine: {single_rate:.0f} solves/s on the same {len(one)} requests "
+          f"(batched, one launch: {len(one) / (launch_ms * 1e-3):.0f}/s); {per_instance}", file=sys.stderr, flush=True)
+
     # ---- FP64 oracle on a bounded sample of the stream: host rate and parity
     cpu = None
     parity = None
@@ -419,6 +449,7 @@ def serving(args):
         "p50_ms": serve.percentile(lat_ms, 50),
         "p99_ms": serve.percentile(lat_ms, 99),
         "saturated_solves_per_s": capacity,
+        "per_instance_fp32": per_instance,
         "launches": stream_launches,
         "mean_batch": mean_batch,
         "autotuned": {f"{'narrow' if k[0] else 'wide'} r<={k[1]}": v for k, v in tuned.items()},

@@ -155,9 +155,12 @@ static sfr_status configure(Engine& e)
     e.max_grid = std::max(e.cfg[0].grid, e.cfg[1].grid);
     e.max_ncl = std::max(e.cfg[0].ncl, e.cfg[1].ncl);
     e.exch_words = std::max(exch_words_of(e, e.cfg[0]), exch_words_of(e, e.cfg[1]));
-    // Gram launch shape
+    // Gram launch shape.  Q: rows per workgroup such that each thread sums
+    // about 32 cluster partials, with as many workgroups as that takes.
+    // P: at least kTPB / R rows per workgroup.
     const int rows = kTPB / e.R;
-    e.nqb = std::max(1, std::min((e.ne + rows - 1) / rows, kMaxGramPartials));
+    const int qrows = std::max(1, std::min(rows, (kTPB * 32) / (e.R * std::max(1, e.max_ncl))));
+    e.nqb = std::max(1, std::min((e.ne + qrows - 1) / qrows, kMaxGramPartials));
     e.rows_q = (e.ne + e.nqb - 1) / e.nqb;
     e.npb = std::max(1, std::min((e.m + rows - 1) / rows, kMaxGramPartials));
     e.rows_p = (e.m + e.npb - 1) / e.npb;

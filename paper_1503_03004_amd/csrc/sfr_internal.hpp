@@ -32,6 +32,7 @@ namespace sfr {
 
 constexpr int kMaxR = 32;
 constexpr int kTPB = 256;            // threads per workgroup of the streaming kernels
+constexpr int kGramU = 8;            // P loads in flight per thread of the Gram kernel
 constexpr int kXCD = 8;              // accelerator complex dies on MI355X
 constexpr uint32_t kSpinLimit = 1u << 24;
 // Residual partials the step kernel loads in its first round (one per

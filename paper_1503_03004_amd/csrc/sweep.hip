@@ -514,71 +514,125 @@ __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs
 
 // Sum the cluster partials of Q (fixed order), write Q, and form the
 // upper triangles of G_Q = Q^T Q and G_P = P^T P in FP64 per workgroup.
+//
+// A workgroup takes its rows in segments held in LDS as FP64.  P is m x R
+// row-major, so a P segment is one contiguous run that each thread reads
+// with kGramU coalesced loads, all in flight together.  A Q entry is the
+// sum of its ncl cluster partials: the clusters of an entry are cut into NS
+// contiguous slots, one thread per (entry, slot) with the loads of a slot
+// in flight together, and the slot sums are added in slot order.  The Gram
+// entries are then split over G row classes (rows jl = g mod G, G threads
+// per entry) whose sums are added in class order.  Every sum has a fixed
+// order, so results are bitwise repeatable.
 template <typename T, int R>
 __global__ void __launch_bounds__(kTPB) gram_kernel(GramArgs<T> a)
 {
     if (a.st->done) return;
     constexpr int E = R * (R + 1) / 2;
-    constexpr int ROWS = kTPB / R;
-    __shared__ double tile[ROWS * R];
+    constexpr int SEGP = (kGramU * kTPB) / R;       // P rows per segment
+    constexpr int SEGQ = kTPB / R;                  // Q rows per segment
+    constexpr int G = (E >= kTPB) ? 1 : kTPB / E;   // threads per Gram entry
+    constexpr int EU = (E + kTPB - 1) / kTPB;       // Gram entries per thread (G == 1)
+    constexpr int CH = 32;                          // cluster partials in flight per thread
+    __shared__ double tile[SEGP * R];
+    __shared__ T qslot[kTPB];
+    __shared__ double gred[kTPB];
     const int tid = threadIdx.x;
     const int blk = blockIdx.x;
-    double acc[(E + kTPB - 1) / kTPB];
-#pragma unroll
-    for (int u = 0; u < (E + kTPB - 1) / kTPB; ++u) acc[u] = 0.0;
     const bool isq = blk < a.nqb;
     const int nrows = isq ? a.n : a.m;
     const int per = isq ? a.rows_q : a.rows_p;
     const int r0 = (isq ? blk : blk - a.nqb) * per;
     const int r1 = min(nrows, r0 + per);
-    for (int base = r0; base < r1; base += ROWS) {
-        if (tid < ROWS * R) {
-            const int jl = tid / R, k = tid % R;
-            const int j = base + jl;
-            double v = 0.0;
-            if (j < r1) {
-                if (isq) {
-                    // all cluster partials of (j, k) in flight at once, in
-                    // batches of 32 unconditional (clamped) loads; summed in
-                    // cluster order
-                    constexpr int CH = 32;
-                    T s = 0;
-                    for (int c0 = 0; c0 < a.ncl; c0 += CH) {
-                        T w[CH];
+    const int seg = isq ? SEGQ : SEGP;
+
+    // Gram entries of this thread: (x, y), x <= y, of entry e
+    const int g = (G > 1) ? tid / E : 0;
+    const bool gact = (G > 1) ? (tid < E * G) : true;
+    int ex[EU], ey[EU];
+    double acc[EU];
 #pragma unroll
-                        for (int u = 0; u < CH; ++u)
-                            w[u] = a.Qpart[((size_t)min(c0 + u, a.ncl - 1) * a.n + j) * R + k];
+    for (int u = 0; u < EU; ++u) {
+        int e = (G > 1) ? tid % E : tid + u * kTPB;
+        if (e >= E) e = E - 1;
+        int x = 0, rem = e;
+        while (rem >= R - x) { rem -= R - x; ++x; }
+        ex[u] = x;
+        ey[u] = x + rem;
+        acc[u] = 0.0;
+    }
+
+    for (int base = r0; base < r1; base += seg) {
+        const int nr = min(seg, r1 - base);
+        const int ne = nr * R;
+        if (isq) {
+            const int ns = kTPB / ne;                   // slots per entry (ne <= kTPB)
+            const int cps = (a.ncl + ns - 1) / ns;      // clusters per slot
+            if (tid < ne * ns) {
+                const int e = tid % ne, sl = tid / ne;
+                const int j = base + e / R, k = e % R;
+                const int c0 = sl * cps, c1 = min(a.ncl, c0 + cps);
+                T sum = 0;
+                for (int cb = c0; cb < c1; cb += CH) {
+                    T w[CH];
 #pragma unroll
-                        for (int u = 0; u < CH; ++u) s += (c0 + u < a.ncl) ? w[u] : T(0);
-                    }
-                    a.Qnext[(int64_t)j * R + k] = s;
-                    v = (double)s;
-                } else {
-                    v = (double)a.Pnext[(int64_t)j * R + k];
+                    for (int u = 0; u < CH; ++u)
+                        w[u] = a.Qpart[((size_t)min(cb + u, a.ncl - 1) * a.n + j) * R + k];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) sum += (cb + u < c1) ? w[u] : T(0);
                 }
+                qslot[tid] = sum;
             }
-            tile[tid] = v;
+            __syncthreads();
+            if (tid < ne) {
+                T sum = 0;
+                for (int sl = 0; sl < ns; ++sl) sum += qslot[sl * ne + tid];
+                a.Qnext[(int64_t)base * R + tid] = sum;
+                tile[tid] = (double)sum;
+            }
+        } else {
+            const T* src = a.Pnext + (int64_t)base * R;
+            T v[kGramU];
+#pragma unroll
+            for (int u = 0; u < kGramU; ++u) v[u] = src[min(tid + u * kTPB, ne - 1)];
+#pragma unroll
+            for (int u = 0; u < kGramU; ++u)
+                if (tid + u * kTPB < ne) tile[tid + u * kTPB] = (double)v[u];
         }
         __syncthreads();
+        if (G > 1) {
+            if (gact) {
+                const int x = ex[0], y = ey[0];
+                double sum = 0.0;
+                for (int jl = g; jl < nr; jl += G) sum = fma(tile[jl * R + x], tile[jl * R + y], sum);
+                acc[0] += sum;
+            }
+        } else {
 #pragma unroll
-        for (int u = 0; u < (E + kTPB - 1) / kTPB; ++u) {
-            int e = tid + u * kTPB;
-            if (e < E) {
-                int x = 0, rem = e;
-                while (rem >= R - x) { rem -= R - x; ++x; }
-                const int y = x + rem;
-                double s = 0.0;
-                for (int jl = 0; jl < ROWS; ++jl) s = fma(tile[jl * R + x], tile[jl * R + y], s);
-                acc[u] += s;
+            for (int u = 0; u < EU; ++u) {
+                if (tid + u * kTPB < E) {
+                    const int x = ex[u], y = ey[u];
+                    double sum = 0.0;
+                    for (int jl = 0; jl < nr; ++jl) sum = fma(tile[jl * R + x], tile[jl * R + y], sum);
+                    acc[u] += sum;
+                }
             }
         }
         __syncthreads();
     }
     double* out = isq ? (a.GQpart + (size_t)blk * E) : (a.GPpart + (size_t)(blk - a.nqb) * E);
+    if (G > 1) {
+        if (gact) gred[tid] = acc[0];                   // tid = g * E + e
+        __syncthreads();
+        if (tid < E) {
+            double sum = 0.0;
+            for (int gg = 0; gg < G; ++gg) sum += gred[gg * E + tid];
+            out[tid] = sum;
+        }
+    } else {
 #pragma unroll
-    for (int u = 0; u < (E + kTPB - 1) / kTPB; ++u) {
-        int e = tid + u * kTPB;
-        if (e < E) out[e] = acc[u];
+        for (int u = 0; u < EU; ++u)
+            if (tid + u * kTPB < E) out[tid + u * kTPB] = acc[u];
     }
 }
 
