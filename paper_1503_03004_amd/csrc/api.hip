@@ -70,7 +70,10 @@ static sfr_status configure_sweep(const Engine& e, SweepCfg& sc, bool mfma)
         }
     }
     if (sc.mfma) {
-        const int mw = sweep_mfma_width(e.R);
+        // the R = 16 bucket takes its wide form (8 tiles per wavefront,
+        // 1024-column slices) where n holds one such slice
+        sc.tiles = (e.R == 16 && e.ne >= sweep_mfma_width(16, 8)) ? 8 : 0;
+        const int mw = sweep_mfma_width(e.R, sc.tiles);
         sc.lpr = 64; sc.nv = 4; sc.c = (e.ne + mw - 1) / mw;
     } else if (best_lpr > 0) {
         sc.lpr = best_lpr; sc.nv = best_nv; sc.c = 1;
@@ -87,15 +90,15 @@ static sfr_status configure_sweep(const Engine& e, SweepCfg& sc, bool mfma)
         }
         sc.c = (e.ne + 64 * vec * sc.nv - 1) / (64 * vec * sc.nv);
     }
-    sc.W = sc.mfma ? sweep_mfma_width(e.R) : sc.lpr * vec * sc.nv;
+    sc.W = sc.mfma ? sweep_mfma_width(e.R, sc.tiles) : sc.lpr * vec * sc.nv;
     const int tpb = e.f64 ? sweep_threads<double>(e.R) : sweep_threads<float>(e.R);
     sc.H = sc.mfma ? 16 : (tpb / 64) * (64 / sc.lpr);
     sc.nbands = (e.m + sc.H - 1) / sc.H;
-    if (sc.mfma) sc.lds = sweep_mfma_lds_bytes(e.R);
+    if (sc.mfma) sc.lds = sweep_mfma_lds_bytes(e.R, sc.tiles);
     else sc.lds = e.f64 ? lds_of<double>(e.R, sc.lpr, sc.W, sc.c) : lds_of<float>(e.R, sc.lpr, sc.W, sc.c);
 
     int bpc = 0;
-    hipError_t herr = sc.mfma ? sweep_mfma_prepare(e.R, sc.lds, &bpc)
+    hipError_t herr = sc.mfma ? sweep_mfma_prepare(e.R, sc.tiles, sc.lds, &bpc)
                               : (e.f64 ? sweep_prepare<double>(e.R, sc.lds, &bpc) : sweep_prepare<float>(e.R, sc.lds, &bpc));
     if (herr != hipSuccess || bpc < 1) return SFR_ERR_DEVICE;
     int dev = 0, cus = 0;
@@ -135,9 +138,11 @@ static size_t exch_words_of(const Engine& e, const SweepCfg& sc)
 
 // The matrix-core sweep takes FP32 problems with at least one full member
 // slice (1024 columns for R <= 12, 512 above).  It runs the sweeps of mode 0
-// (X = M: the first FR-ADM sweep and every Alg. 4 step) and, for R >= 16,
-// every sweep: there it is the faster kernel.  For R <= 12 the FR-ADM general
-// sweeps stay on the vector kernel, whose row-contiguous loads stream better.
+// (X = M: the first FR-ADM sweep and every Alg. 4 step) and, for R >= 12,
+// every sweep: there it is the faster kernel (at R = 12 the vector kernel's
+// per-lane state takes the whole register file, one wave per SIMD).  For
+// R <= 10 the FR-ADM general sweeps stay on the vector kernel, whose
+// row-contiguous loads stream better.
 // SFR_SWEEP=vector or =mfma in the environment forces one kernel for every
 // sweep (both are exact; used to test both).
 static sfr_status configure(Engine& e)
@@ -145,8 +150,8 @@ static sfr_status configure(Engine& e)
     const char* pick = getenv("SFR_SWEEP");
     const bool want_vector = pick && strcmp(pick, "vector") == 0;
     const bool want_mfma = pick && strcmp(pick, "mfma") == 0;
-    const bool mfma_ok = !e.f64 && sweep_mfma_supported(e.R) && e.ne >= sweep_mfma_width(e.R);
-    const bool general_mfma = mfma_ok && !want_vector && (want_mfma || e.R >= 16);
+    const bool mfma_ok = !e.f64 && sweep_mfma_supported(e.R) && e.ne >= sweep_mfma_width(e.R, 0);
+    const bool general_mfma = mfma_ok && !want_vector && (want_mfma || e.R >= 12);
     sfr_status st = configure_sweep(e, e.cfg[0], general_mfma);
     if (st != SFR_OK) return st;
     st = configure_sweep(e, e.cfg[1], mfma_ok && !want_vector);
@@ -346,7 +351,7 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         hipEvent_t ev0 = timed ? e.prof_ev[2 * (k - 3)] : nullptr;
         hipEvent_t ev1 = timed ? e.prof_ev[2 * (k - 3) + 1] : nullptr;
         if constexpr (sizeof(T) == 4) {
-            if (sc.mfma) HIPCHK(launch_sweep_mfma(a, e.R, sc.grid, sc.lds, s, ev0, ev1, bf));
+            if (sc.mfma) HIPCHK(launch_sweep_mfma(a, e.R, sc.tiles, sc.grid, sc.lds, s, ev0, ev1, bf));
             else HIPCHK(launch_sweep<T>(a, e.R, sc.grid, sc.lds, s, ev0, ev1));
         } else {
             HIPCHK(launch_sweep<T>(a, e.R, sc.grid, sc.lds, s, ev0, ev1));

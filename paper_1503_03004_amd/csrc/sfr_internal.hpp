@@ -227,13 +227,15 @@ template <typename T>
 hipError_t sweep_prepare(int R, size_t lds, int* blocks_per_cu);
 
 // Matrix-core sweep (sweep_mfma.hip): FP32, R <= 32, member slices of
-// sweep_mfma_width(R) columns, 16-row bands, 512-thread workgroups.
+// sweep_mfma_width(R, tiles) columns, 16-row bands, 512-thread workgroups.
+// tiles: 16-column tiles per wavefront, 0 for the bucket's default form; 8
+// selects the wide form of the R = 16 bucket (1024-column slices).
 bool sweep_mfma_supported(int R);
-size_t sweep_mfma_lds_bytes(int R);
-int sweep_mfma_width(int R);
-hipError_t sweep_mfma_prepare(int R, size_t lds, int* blocks_per_cu);
+size_t sweep_mfma_lds_bytes(int R, int tiles);
+int sweep_mfma_width(int R, int tiles);
+hipError_t sweep_mfma_prepare(int R, int tiles, size_t lds, int* blocks_per_cu);
 // bf16: the contractions take BF16 operands (FP32 accumulation)
-hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int grid, size_t lds, hipStream_t s,
+hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int tiles, int grid, size_t lds, hipStream_t s,
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool bf16 = false);
 
 hipError_t launch_step(const StepArgs& a, int R, hipStream_t s);

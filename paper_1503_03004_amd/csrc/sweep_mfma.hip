@@ -16,7 +16,8 @@
 // Work decomposition
 //   * A band is 16 rows.  A workgroup is 8 wavefronts; wave w owns 16 TPW
 //     consecutive columns of its member's slice (TPW = 8 tiles of 16 columns
-//     for R <= 12, 4 above), for every band.  Ranks are padded to 16-wide
+//     for R <= 12, 4 above; the R = 16 bucket also has a wide form with 8,
+//     taken where n holds its 1024-column slices), for every band.  Ranks are padded to 16-wide
 //     tiles (one, or two for R > 16).  The V values a lane needs for its
 //     tiles are loaded into registers once.
 //   * Row pass: per tile, l (ceil(R/4) MFMA), the S/dual step, Y_k, x, the
@@ -49,11 +50,11 @@ constexpr int kMTPB = 64 * kMW8;         // threads per workgroup
 constexpr int kMH = 16;                  // rows per band
 
 // Compile-time shape for rank bucket R.
-template <int R>
+template <int R, int TW = 0>
 struct MShape {
     static constexpr int RT = (R + 15) / 16;          // 16-wide rank tiles (p, Q)
     static constexpr int S1 = (R + 3) / 4;            // K steps of the l product
-    static constexpr int TPW = (R <= 12) ? 8 : 4;     // 16-column tiles per wavefront
+    static constexpr int TPW = TW ? TW : ((R <= 12) ? 8 : 4);   // 16-column tiles per wavefront
     static constexpr int COLS = 16 * TPW;             // columns per wavefront
     static constexpr int WIDTH = kMW8 * COLS;         // columns per member slice
     static constexpr int XP = COLS + 16;              // LDS pitch of a row of a wave's x tile (floats)
@@ -63,10 +64,10 @@ struct MfmaLds {
     size_t tu, xw, pw, ps, red, total;
 };
 
-template <int R>
+template <int R, int TW = 0>
 __host__ __device__ inline MfmaLds mfma_lds()
 {
-    using S = MShape<R>;
+    using S = MShape<R, TW>;
     auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
     MfmaLds L;
     size_t o = 0;
@@ -112,10 +113,10 @@ __device__ __forceinline__ f32x4 mfma_bf16(const float (&a)[4], const float (&b)
 
 // BF: the three contractions take BF16 operands (FP32 accumulation); M, Y
 // and every stored value stay FP32.
-template <int R, bool BF>
+template <int R, bool BF, int TW = 0>
 __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a)
 {
-    using SH = MShape<R>;
+    using SH = MShape<R, TW>;
     constexpr int RT = SH::RT, S1 = SH::S1, kMTiles = SH::TPW, kMCols = SH::COLS;
     constexpr int kMWidth = SH::WIDTH, kMXP = SH::XP;
     constexpr int PT = 256 * RT;      // (row, padded rank) entries of one band
@@ -149,7 +150,7 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
     int32_t* tflag = &st->exch_timeout;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    const MfmaLds L = mfma_lds<R>();
+    const MfmaLds L = mfma_lds<R, TW>();
     float* TUs = reinterpret_cast<float*>(smem + L.tu);
     float* Xall = reinterpret_cast<float*>(smem + L.xw);
     float* Xw = Xall + (size_t)wave * 2 * kMH * kMXP;
@@ -442,8 +443,12 @@ bool sweep_mfma_supported(int R)
     }
 }
 
-size_t sweep_mfma_lds_bytes(int R)
+// tiles = 8 selects the wide form of the R = 16 bucket; 0 the default form.
+static bool wide16(int R, int tiles) { return R == 16 && tiles == 8; }
+
+size_t sweep_mfma_lds_bytes(int R, int tiles)
 {
+    if (wide16(R, tiles)) return mfma_lds<16, 8>().total;
     switch (R) {
 #define CASE(r) case r: return mfma_lds<r>().total;
         SFR_MFMA_R_LIST(CASE)
@@ -452,8 +457,9 @@ size_t sweep_mfma_lds_bytes(int R)
     }
 }
 
-int sweep_mfma_width(int R)
+int sweep_mfma_width(int R, int tiles)
 {
+    if (wide16(R, tiles)) return MShape<16, 8>::WIDTH;
     switch (R) {
 #define CASE(r) case r: return MShape<r>::WIDTH;
         SFR_MFMA_R_LIST(CASE)
@@ -462,8 +468,11 @@ int sweep_mfma_width(int R)
     }
 }
 
-static void* sweep_mfma_fn(int R, bool bf16)
+static void* sweep_mfma_fn(int R, int tiles, bool bf16)
 {
+    if (wide16(R, tiles))
+        return bf16 ? reinterpret_cast<void*>(&sweep_mfma_kernel<16, true, 8>)
+                    : reinterpret_cast<void*>(&sweep_mfma_kernel<16, false, 8>);
     switch (R) {
 #define CASE(r)                                                                             \
     case r:                                                                                 \
@@ -475,28 +484,37 @@ static void* sweep_mfma_fn(int R, bool bf16)
     }
 }
 
-hipError_t sweep_mfma_prepare(int R, size_t lds, int* blocks_per_cu)
+hipError_t sweep_mfma_prepare(int R, int tiles, size_t lds, int* blocks_per_cu)
 {
     // both operand forms share the launch shape and LDS size
     for (int bf = 1; bf >= 0; --bf) {
-        void* fn = sweep_mfma_fn(R, bf != 0);
+        void* fn = sweep_mfma_fn(R, tiles, bf != 0);
         if (!fn) return hipErrorInvalidValue;
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, sweep_mfma_fn(R, false), kMTPB, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, sweep_mfma_fn(R, tiles, false), kMTPB, lds);
 }
 
-hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int grid, size_t lds, hipStream_t s,
+hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int tiles, int grid, size_t lds, hipStream_t s,
                              hipEvent_t ev0, hipEvent_t ev1, bool bf16)
 {
-    switch (R) {
-#define LAUNCH(r, BF)                                                                                       \
+#define LAUNCH_TW(r, BF, TW)                                                                                \
     if (ev0)                                                                                                \
-        hipExtLaunchKernelGGL((sweep_mfma_kernel<r, BF>), dim3(grid), dim3(kMTPB), (uint32_t)lds, s, ev0, ev1, \
-                              0u, a);                                                                       \
+        hipExtLaunchKernelGGL((sweep_mfma_kernel<r, BF, TW>), dim3(grid), dim3(kMTPB), (uint32_t)lds, s, ev0,  \
+                              ev1, 0u, a);                                                                  \
     else                                                                                                    \
-        hipLaunchKernelGGL((sweep_mfma_kernel<r, BF>), dim3(grid), dim3(kMTPB), lds, s, a);
+        hipLaunchKernelGGL((sweep_mfma_kernel<r, BF, TW>), dim3(grid), dim3(kMTPB), lds, s, a);
+#define LAUNCH(r, BF) LAUNCH_TW(r, BF, 0)
+    if (wide16(R, tiles)) {
+        if (bf16) {
+            LAUNCH_TW(16, true, 8)
+        } else {
+            LAUNCH_TW(16, false, 8)
+        }
+        return hipGetLastError();
+    }
+    switch (R) {
 #define CASE(r)                 \
     case r:                     \
         if (bf16) {             \
@@ -508,6 +526,7 @@ hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int grid, size_t 
         SFR_MFMA_R_LIST(CASE)
 #undef CASE
 #undef LAUNCH
+#undef LAUNCH_TW
     default: return hipErrorInvalidValue;
     }
 }

@@ -55,7 +55,7 @@ def errors(Md, r, lam, mu0, L, S, iters):
     return rel(L, o["U"] @ o["B"] @ o["V"].T), rel(S, o["S"])
 
 
-SHAPES = [(2000, 1100, 10), (1200, 1000, 16), (900, 1100, 32)]
+SHAPES = [(2000, 1100, 10), (1200, 1000, 16), (900, 1100, 32), (1000, 1100, 16)]
 
 
 @pytest.mark.parametrize("m,n,r", SHAPES)

@@ -260,7 +260,8 @@ def test_photometric_tolerance_driven_fp32():
 
 @pytest.mark.parametrize("sweep", ["mfma", "vector"])
 @pytest.mark.parametrize("m,n,r", [(300, 1100, 10), (1037, 2048, 4), (64, 5000, 12), (2100, 1024, 1),
-                                   (300, 1100, 16), (200, 2000, 20), (1037, 700, 24), (150, 1500, 32)])
+                                   (300, 1100, 16), (700, 800, 16), (400, 2100, 13), (200, 2000, 20),
+                                   (1037, 700, 24), (150, 1500, 32)])
 def test_both_fp32_sweeps(monkeypatch, sweep, m, n, r):
     """FP32 shapes that both sweeps take: the matrix-core sweep and the vector
     sweep (SFR_SWEEP selects) each against the oracle."""
