@@ -371,6 +371,7 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         sa.GQpart = e.GQpart; sa.nqb = e.nqb;
         sa.dy2part = e.dy2part; sa.ndy = sc.grid;
         sa.res_hist = e.res_hist;
+        sa.dk_tau = e.f64 ? kDkTauF64 : kDkTauF32;
         HIPCHK(launch_step(sa, e.R, s));
         return SFR_OK;
     };

@@ -556,7 +556,7 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
             Gq[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : tri[1][t];
         }
         __syncthreads();
-        if (!lstep_algebra<R, NT>(Gp, Gq, Bm, C1, C2, Km, T1, T2, Ev, Ev2, cs, wbuf, r)) {
+        if (!lstep_algebra<R, NT>(Gp, Gq, Bm, C1, C2, Km, T1, T2, Ev, Ev2, cs, wbuf, r, kDkTauF32)) {
             status = kErrRank;
             iters = k - 1;
             break;

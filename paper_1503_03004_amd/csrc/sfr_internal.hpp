@@ -132,12 +132,21 @@ struct GramArgs {
 };
 
 // FP64 r x r step (one workgroup).
+// Relative off-diagonal size at which the Jacobi sweeps of the step's
+// inverse square roots stop, the rest being a second-order expansion with
+// relative error O(tau^3 r^2): about 1e-16 for FP64 solves; for FP32 solves
+// about 1e-11 r^2, far below the FP32 rounding of the m x n work (~1e-7),
+// and it saves about one sweep per decomposition.
+constexpr double kDkTauF64 = 4e-6;
+constexpr double kDkTauF32 = 2e-4;
+
 struct StepArgs {
     DevState* st;
     const double* GPpart; int32_t npb;
     const double* GQpart; int32_t nqb;
     const double* dy2part; int32_t ndy;
     double* res_hist;     // res_hist[k-1] = residual of iteration k
+    double dk_tau;        // kDkTauF64 or kDkTauF32
 };
 
 // The ping-pong buffers of one solve (P, Q: m x R, n x R; Y: m x n with

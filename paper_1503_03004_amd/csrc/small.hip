@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
     }
     lsync<NT>();
 
-    if (!lstep_algebra<R, NT>(Gp, Gq, Bm, C1, C2, Km, T1, T2, Ev, Ev2, cs, wbuf, r)) {
+    if (!lstep_algebra<R, NT>(Gp, Gq, Bm, C1, C2, Km, T1, T2, Ev, Ev2, cs, wbuf, r, a.dk_tau)) {
         if (tid == 0) { st->status = kErrRank; st->iters = k - 1; st->done = 1; }
         return;
     }

@@ -242,31 +242,29 @@ __device__ inline void wjacobi(double* A, double* E, double* cs, double tau = 0.
     }
 }
 
-// Relative off-diagonal size at which the Jacobi sweeps of winv_sqrt stop:
-// |a_ij| <= kDkTau min(a_ii, a_jj) in the current basis.  The rest of the
-// way is the second-order expansion of t^{-1/2} about the diagonal, whose
-// error is O(kDkTau^3) relative (about 1e-16 here).  Across FR-ADM
-// iterations the Grams move less and less, so the previous iteration's
-// basis soon meets this bound with no sweep at all.
-constexpr double kDkTau = 4e-6;
-
-// Out = A^{-1/2} for symmetric A (destroyed), one wavefront.  E: on entry
-// the warm-start basis, on exit a basis in which A is diagonal to within
-// kDkTau (updated only by the sweeps that were needed).  T, cs, wbuf:
+// Out = A^{-1/2} for symmetric A (destroyed), one wavefront.  The Jacobi
+// sweeps stop once |a_ij| <= tau min(a_ii, a_jj) in the current basis; the
+// rest of the way is the second-order expansion of t^{-1/2} about the
+// diagonal, whose error is O(tau^3 r^2) relative (tau: kDkTauF64 or
+// kDkTauF32).  Across FR-ADM iterations the Grams move less and less, so the
+// previous iteration's basis soon meets this bound with no sweep at all.
+// E: on entry the warm-start basis, on exit a basis in which A is diagonal
+// to within tau (updated only by the sweeps that were needed).  T, cs, wbuf:
 // scratch.  Only the leading `nreal` eigenvalues are tested (the rest belong
 // to an identity padding block).  Returns false if A is not positive
 // definite to working precision (the Stiefel projector of eq. (7) needs
 // rank r).
 template <int N, int NT = 64>
-__device__ inline bool winv_sqrt(double* Out, double* A, double* E, double* T, int nreal, double* cs, double* wbuf)
+__device__ inline bool winv_sqrt(double* Out, double* A, double* E, double* T, int nreal, double* cs, double* wbuf,
+                                 double tau)
 {
     const int lane = lid<NT>();
     // A <- E^T A E
     wmm<N, NT>(T, A, E);
     wmtm<N, NT>(A, E, T);
     wsym<N, NT>(A);
-    wjacobi<N, NT>(A, E, cs, kDkTau);
-    // A = D + F, D = diag(d), F off-diagonal with |F_ij| <= kDkTau min(d_i, d_j)
+    wjacobi<N, NT>(A, E, cs, tau);
+    // A = D + F, D = diag(d), F off-diagonal with |F_ij| <= tau min(d_i, d_j)
     // (or at the strict Jacobi test).  x = sqrt(d) -> wbuf, y = 1 / x -> cs.
     // Every thread reads the whole diagonal for the positivity test.
     double wmax = -INFINITY, wmin = INFINITY;
@@ -343,17 +341,18 @@ __device__ inline bool winv_sqrt(double* Out, double* A, double* E, double* T, i
 // On entry Gp, Gq, Bm (= B_0), Ev, Ev2 (warm-start eigenbases); on exit
 // T1 = B_0 C1 (U transform), Km = B_0 C1 B (row factor transform),
 // Gp = K C2 (V transform), T2 = B, and Ev, Ev2 updated.  Returns false if a
-// Gram is not positive definite (rank loss, eq. (7)).
+// Gram is not positive definite (rank loss, eq. (7)).  tau: the Jacobi stop
+// of the two inverse square roots (winv_sqrt).
 template <int R, int NT>
 __device__ inline bool lstep_algebra(double* Gp, double* Gq, double* Bm, double* C1, double* C2, double* Km,
                                      double* T1, double* T2, double* Ev, double* Ev2, double* cs, double* wbuf,
-                                     int r)
+                                     int r, double tau)
 {
     // U-step: C1 = (B0 G_P B0)^{-1/2}
     wmm<R, NT>(T1, Bm, Gp);
     wmm<R, NT>(T2, T1, Bm);
     wsym<R, NT>(T2);
-    const bool ok1 = winv_sqrt<R, NT>(C1, T2, Ev, T1, r, cs, wbuf);
+    const bool ok1 = winv_sqrt<R, NT>(C1, T2, Ev, T1, r, cs, wbuf, tau);
     // V-step: K = B0 C1 B0, C2 = (K G_Q K)^{-1/2}
     wmm<R, NT>(T1, Bm, C1);          // T1 = B0 C1  (the U transform)
     wmm<R, NT>(Km, T1, Bm);
@@ -362,7 +361,7 @@ __device__ inline bool lstep_algebra(double* Gp, double* Gq, double* Bm, double*
     wmm<R, NT>(C2, T2, Km);          // K G_Q K (C2 as scratch)
     wsym<R, NT>(C2);
     wcopy<R, NT>(T2, C2);
-    const bool ok2 = winv_sqrt<R, NT>(C2, T2, Ev2, Gp, r, cs, wbuf);   // Gp free now
+    const bool ok2 = winv_sqrt<R, NT>(C2, T2, Ev2, Gp, r, cs, wbuf, tau);   // Gp free now
     if (!ok1 || !ok2) return false;
     // TV = K C2 -> Gp ; B = Sym(C1 B0 G_Q K C2) -> T2 ; TU = B0 C1 B -> Km
     wmm<R, NT>(Gp, Km, C2);               // TV
