@@ -18,8 +18,10 @@ namespace sfr {
 // Workgroup size of the step kernel: the partial sums are latency bound,
 // so as many threads as the r x r algebra's register use allows (1024
 // threads leave 128 registers a lane, which buckets 5 and 12 and up exceed).
+// Up to R = 4 (2E <= 20 Gram entries) 256 threads already take every
+// partial in one round of loads, and the workgroup barriers cost less.
 template <int R>
-constexpr int step_tpb() { return (R <= 10 && R != 5) ? 1024 : 512; }
+constexpr int step_tpb() { return R <= 4 ? 256 : ((R <= 10 && R != 5) ? 1024 : 512); }
 
 // The r x r matrices are held R x R (R the rank bucket, a compile-time
 // size) with an identity block on the padded indices: every product and
