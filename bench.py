@@ -43,6 +43,26 @@ def sweep_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def host_info() -> dict:
+    """CPU model, logical CPUs and memory of the host that times the oracle."""
+    model, mem_kib = None, None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    mem_kib = int(line.split()[1])
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(),
+            "mem_gib": round(mem_kib / 2 ** 20, 1) if mem_kib else None}
+
+
 def copy_bandwidth_gbs(dev) -> float:
     """Read + write bandwidth of a plain device copy (torch copy_ of 512 MiB),
     mean of 10 copies timed with HIP events: the achievable streaming rate
@@ -256,7 +276,7 @@ def main():
         else:
             o = oracle.fradm(Md, r, inst.lam, mu0, fixed_iters=oi)
         tc = time.perf_counter() - t1
-        cpu = {"value": oi / tc, "unit": "iters/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": oi / tc, "unit": "iters/s", "cores": 1, "kind": "oracle", "host": host_info(),
                "sample": f"{oi} {'Alg. 4 steps' if tsvd else 'FR-ADM iterations'} of the same {m}x{n} r={r} "
                          f"input, FP64, one thread ({tc:.1f} s)"}
         # a BF16 head of the same share of the iterations as in the timed run
@@ -443,7 +463,7 @@ def serving(args):
             if time.perf_counter() - t1 > 12.0:
                 break
         tc = time.perf_counter() - t1
-        cpu = {"value": done / tc, "unit": "solves/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": done / tc, "unit": "solves/s", "cores": 1, "kind": "oracle", "host": host_info(),
                "sample": f"the first {done} requests of the stream solved to tol {tol} in FP64 on one thread "
                          f"({tc:.1f} s)"}
         parity = {"requests_compared": len(errs), "max_rel_err": max(errs) if errs else None,

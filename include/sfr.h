@@ -101,13 +101,22 @@ typedef struct {
                                 iterations 2..K (ms); else 0 */
     int32_t sweeps_timed;    /* number of launches averaged in sweep_ms */
     int32_t reserved1;
+    double mu0;              /* the initial penalty mu_0 used: sfr_solve, the handle's mu or
+                                1.25 / ||M||_2 for a handle created with mu <= 0;
+                                sfr_solve_batch, the item's mu; else 0 */
 } sfr_info;
 
 /*
  * Create a solver for m x n inputs and rank r.
  *   m, n >= 1, 1 <= r <= min(m, n, 32).
  *   lambda > 0: weight of ||S||_1; the S-step threshold is lambda/mu_k.
- *   mu > 0: initial penalty mu_0 of Alg. 1 (finite).
+ *   mu > 0: initial penalty mu_0 of Alg. 1 (finite).  mu <= 0 (finite,
+ *     FR-ADM handles): each sfr_solve takes mu_0 = 1.25 / ||M||_2, with
+ *     ||M||_2 the largest eigenvalue of B after Alg. 4 on M (run to a relative
+ *     change of B of 1e-6, at most 60 steps, in the caller's U, B, V before the
+ *     solve overwrites them); sfr_info.mu0 reports it.  Alg. 1's literal
+ *     mu_0 = 1 does not recover the planted L on the synthetic workloads;
+ *     this scale of the initial threshold does.
  *   tol >= 0: stop at the first iteration k with
  *       ||M - L_{k+1} - S_{k+1}||_F / ||M||_F <= tol
  *     (Alg. 1 leaves "converged" unspecified; this is the reading taken).

@@ -57,6 +57,7 @@ class sfr_info(ctypes.Structure):
         ("sweep_ms", ctypes.c_double),
         ("sweeps_timed", ctypes.c_int32),
         ("reserved1", ctypes.c_int32),
+        ("mu0", ctypes.c_double),
     ]
 
 
@@ -145,6 +146,7 @@ class Info:
     mu_final: float
     sweep_ms: float
     sweeps_timed: int
+    mu0: float = 0.0
 
 
 def _stream_handle(stream):
@@ -396,7 +398,7 @@ class BatchSolver:
 def _info(rc, info):
     return Info(status=int(rc), iters=info.iters, iters_top=info.iters_top, converged=bool(info.converged),
                 rel_residual=info.rel_residual, min_eig_B=info.min_eig_B, mu_final=info.mu_final,
-                sweep_ms=info.sweep_ms, sweeps_timed=info.sweeps_timed)
+                sweep_ms=info.sweep_ms, sweeps_timed=info.sweeps_timed, mu0=info.mu0)
 
 
 def solve(M, r, lam, mu, tol=1e-7, **opts):

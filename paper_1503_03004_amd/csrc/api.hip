@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 namespace sfr {
@@ -507,10 +508,42 @@ static sfr_status fill_info(const Engine& e, sfr_info* info, sfr_status st)
         info->mu_final = h.mu_prev;
         info->sweep_ms = e.sweep_ms;
         info->sweeps_timed = e.sweeps_timed;
+        info->mu0 = 0.0;
     }
     if (st != SFR_OK) return st;
     if (h.status == kWarnMaxIter) return SFR_WARN_MAXITER;
     if (!(h.min_eig_B > 0.0)) return SFR_WARN_NOT_SPD;
+    return SFR_OK;
+}
+
+// mu_0 = 1.25 / ||M||_2, the initial penalty taken for handles created with
+// mu <= 0.  ||M||_2 is the largest eigenvalue of B after Alg. 4 on M (run to
+// a change of B of 1e-6 relative, at most 60 steps, into the caller's U, B,
+// V, which the solve then overwrites).
+template <typename T>
+static sfr_status estimate_mu0(sfr_ctx* h, const T* M, int64_t ldm, T* U, double* B, T* V, hipStream_t s,
+                               double* mu0)
+{
+    Engine& e = h->main;
+    Params p = h->prm;
+    p.tol = 1e-6;
+    p.fixed_iters = 0;
+    p.max_iter = 60;
+    p.bf16 = false;
+    p.bf16_iters = 0;
+    p.bf16_tol = 0.0;
+    p.profile = false;
+    OutputSpec<T> o;
+    o.U = U; o.B = B; o.V = V;
+    o.min_eig = false;
+    const sfr_status st = engine_iterate<T>(e, p, 1.0, M, ldm, o, s, true);
+    if (st < 0) return st;
+    HIPCHK(launch_max_eig(e.st, e.R, s));
+    double smax = 0.0;
+    HIPCHK(hipMemcpyAsync(&smax, &e.st->max_eig_B, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!(smax > 0.0) || !std::isfinite(smax)) return SFR_ERR_NONFINITE;
+    *mu0 = 1.25 / smax;
     return SFR_OK;
 }
 
@@ -563,7 +596,7 @@ sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double l
         if (o.nystrom_l < r || o.nystrom_l > m || o.nystrom_l > n) return SFR_ERR_ARG;
         if (!(o.mu_left > 0.0) || !(o.mu_top > 0.0) || o.mu_left > 1e300 || o.mu_top > 1e300) return SFR_ERR_ARG;
     } else {
-        if (!(mu > 0.0) || mu > 1e300) return SFR_ERR_ARG;
+        if (!std::isfinite(mu) || mu > 1e300) return SFR_ERR_ARG;
     }
     sfr_ctx* h = new (std::nothrow) sfr_ctx();
     if (!h) return SFR_ERR_NOMEM;
@@ -572,6 +605,7 @@ sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double l
     h->nys = nys;
     h->l = o.nystrom_l;
     h->prm.lambda = lambda; h->prm.mu0 = mu; h->prm.tol = tol;
+    h->mu_auto = !nys && !(mu > 0.0);
     h->prm.rho = o.rho; h->prm.mu_bar = o.mu_bar;
     h->prm.max_iter = o.max_iter; h->prm.fixed_iters = o.fixed_iters;
     h->prm.profile = o.profile != 0;
@@ -634,25 +668,30 @@ sfr_status sfr_solve(sfr_handle h, const void* M, int64_t ldm, void* U, double* 
     if (ldm < h->n || (S && lds < h->n)) return SFR_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     Engine& e = h->main;
-    sfr_status st;
+    sfr_status st = SFR_OK;
+    double mu0 = h->prm.mu0;
     if (h->f64) {
         OutputSpec<double> o;
         o.U = static_cast<double*>(U); o.B = B; o.V = static_cast<double*>(V);
         o.M = static_cast<const double*>(M); o.ldm = ldm; o.S = static_cast<double*>(S); o.lds = lds;
         o.min_eig = true;
-        st = engine_iterate<double>(e, h->prm, h->prm.mu0, static_cast<const double*>(M), ldm, o, s);
+        if (h->mu_auto) st = estimate_mu0<double>(h, o.M, ldm, o.U, B, o.V, s, &mu0);
+        if (st == SFR_OK) st = engine_iterate<double>(e, h->prm, mu0, static_cast<const double*>(M), ldm, o, s);
     } else {
         OutputSpec<float> o;
         o.U = static_cast<float*>(U); o.B = B; o.V = static_cast<float*>(V);
         o.M = static_cast<const float*>(M); o.ldm = ldm; o.S = static_cast<float*>(S); o.lds = lds;
         o.min_eig = true;
-        st = engine_iterate<float>(e, h->prm, h->prm.mu0, static_cast<const float*>(M), ldm, o, s);
+        if (h->mu_auto) st = estimate_mu0<float>(h, o.M, ldm, o.U, B, o.V, s, &mu0);
+        if (st == SFR_OK) st = engine_iterate<float>(e, h->prm, mu0, static_cast<const float*>(M), ldm, o, s);
     }
     if (st < 0) {
         if (info) memset(info, 0, sizeof(*info));
         return st;
     }
-    return fill_info(e, info, st);
+    st = fill_info(e, info, st);
+    if (info) info->mu0 = mu0;
+    return st;
 }
 
 sfr_status sfr_tsvd(sfr_handle h, const void* M, int64_t ldm, void* U, double* B, void* V, sfr_info* info,

@@ -195,6 +195,7 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
                 f.rel_residual = d.res;
                 f.min_eig_B = d.min_eig_B;
                 f.mu_final = d.mu_final;
+                f.mu0 = items[i].mu;
             }
         }
         if (st < 0 && i < worst_i) {

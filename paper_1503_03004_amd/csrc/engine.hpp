@@ -93,6 +93,7 @@ struct sfr_ctx {
     bool nys = false;
     int32_t l = 0;
     sfr::Params prm;
+    bool mu_auto = false;   // mu <= 0 at creation: mu_0 = 1.25 / ||M||_2 per solve
     double mu_left = 0, mu_top = 0;
     sfr::Engine main;       // FR-ADM engine (m x n)
     sfr::Engine left, top;  // FR-Nys sub-engines (m x l, l x n)

@@ -69,6 +69,7 @@ struct DevState {
     double mu_prev;     // mu_{k-1} used by the next sweep's S/Y step
     double res;         // last residual ||M - L - S||_F / ||M||_F
     double min_eig_B;   // filled by the finalize step
+    double max_eig_B;   // largest eigenvalue of B (launch_max_eig)
     double B[kMaxR * kMaxR];
     double TU[kMaxR * kMaxR];     // a_i = P_i TU gives L rows (L = A V^T)
     double TUbar[kMaxR * kMaxR];  // U = P TUbar
@@ -249,6 +250,8 @@ hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int tiles, int gr
 
 hipError_t launch_step(const StepArgs& a, int R, hipStream_t s);
 hipError_t launch_final_small(DevState* st, int R, hipStream_t s);
+// Largest eigenvalue of the returned B into st->max_eig_B.
+hipError_t launch_max_eig(DevState* st, int R, hipStream_t s);
 // Continue a stopped iteration from its returned iterate K under a new
 // stopping rule (no-op if it stopped with an error, or with no budget left).
 hipError_t launch_refine_start(DevState* st, int fixed_iters, double tol, int max_iter, hipStream_t s);

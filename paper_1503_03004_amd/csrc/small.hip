@@ -243,6 +243,31 @@ __global__ void __launch_bounds__(64) final_small_kernel(DevState* st)
     if (threadIdx.x == 0) st->min_eig_B = w;
 }
 
+// Largest eigenvalue of the returned B.  After Alg. 4 on M, B has the r
+// leading singular values of M as its eigenvalues (Theorem 2), so this is
+// ||M||_2 (full Jacobi convergence from the identity basis).
+template <int R>
+__global__ void __launch_bounds__(64) max_eig_kernel(DevState* st)
+{
+    __shared__ double A[R * LDP], Ev[R * LDP];
+    __shared__ __align__(16) double cs[2 * 16];
+    const int lane = threadIdx.x;
+    const int r = st->r;
+    for (int e = lane; e < R * R; e += 64) {
+        const int i = e / R, j = e % R;
+        const bool pad = (i >= r) || (j >= r);
+        A[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : st->B[i * kMaxR + j];
+        Ev[i * LDP + j] = (i == j) ? 1.0 : 0.0;
+    }
+    lsync<64>();
+    wjacobi<R, 64>(A, Ev, cs);
+    if (lane == 0) {
+        double w = -INFINITY;
+        for (int i = 0; i < r; ++i) w = fmax(w, A[i * LDP + i]);
+        st->max_eig_B = w;
+    }
+}
+
 #define SFR_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
 
 hipError_t launch_step(const StepArgs& a, int R, hipStream_t s)
@@ -279,6 +304,17 @@ __global__ void refine_start_kernel(DevState* st, int fixed_iters, double tol, i
 hipError_t launch_refine_start(DevState* st, int fixed_iters, double tol, int max_iter, hipStream_t s)
 {
     hipLaunchKernelGGL(refine_start_kernel, dim3(1), dim3(64), 0, s, st, fixed_iters, tol, max_iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_eig(DevState* st, int R, hipStream_t s)
+{
+    switch (R) {
+#define CASE(rr) case rr: hipLaunchKernelGGL(max_eig_kernel<rr>, dim3(1), dim3(64), 0, s, st); break;
+        SFR_R_LIST(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -84,7 +84,8 @@ def _create(m, n, r, lam, mu, tol, **kw):
     ((100, 100, 33, 0.1, 1.0, 1e-7), {}),        # r above the supported 32
     ((10, 10, 2, 0.0, 1.0, 1e-7), {}),           # lambda <= 0
     ((10, 10, 2, float("nan"), 1.0, 1e-7), {}),  # lambda NaN
-    ((10, 10, 2, 0.1, 0.0, 1e-7), {}),           # mu <= 0
+    ((10, 10, 2, 0.1, float("nan"), 1e-7), {}),  # mu NaN (mu <= 0 selects the default)
+    ((10, 10, 2, 0.1, float("inf"), 1e-7), {}),  # mu infinite
     ((10, 10, 2, 0.1, float("inf"), 1e-7), {}),  # mu infinite
     ((10, 10, 2, 0.1, 1.0, -1.0), {}),           # tol < 0
     ((10, 10, 2, 0.1, 1.0, 1e-7), {"precision": 7}),

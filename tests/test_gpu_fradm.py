@@ -94,6 +94,26 @@ def test_plain_fp64_tolerance_driven_same_stop():
     assert rel(g["U"] @ g["B"] @ g["V"].T, inst.L0) <= 1e-5
 
 
+@pytest.mark.parametrize("precision,shape", [("f64", (400, 400, 5)), ("f32", (1500, 1200, 8))])
+def test_default_mu0_from_spectral_norm(precision, shape):
+    """A handle created with mu <= 0 takes mu_0 = 1.25 / ||M||_2, with ||M||_2
+    from Alg. 4 on M: the reported mu_0 matches the exact spectral norm
+    (numpy SVD), and the solve matches the oracle run with that mu_0."""
+    m, n, r = shape
+    if precision == "f64":
+        inst = workloads.plain_fp64(seed=4)
+    else:
+        inst = workloads.planted(m, n, r, seed=11, frac=0.08, kind="uniform", scale=50.0, dtype=np.float32)
+    Md = inst.M.astype(np.float64)
+    exact = 1.25 / np.linalg.norm(Md, 2)
+    g = gpu_solve(inst.M, r, inst.lam, 0.0, precision, tol=1e-6 if precision == "f32" else 1e-7)
+    mu0 = g["info"].mu0
+    print(f"{precision}: mu0 gpu {mu0:.12e} exact {exact:.12e} rel {abs(mu0 / exact - 1):.1e}")
+    assert abs(mu0 / exact - 1.0) <= 1e-6
+    o = oracle.fradm(Md, r, inst.lam, mu0, fixed_iters=g["info"].iters)
+    compare(g, o, precision, f"default mu0 {precision}")
+
+
 @pytest.mark.parametrize("fixed", [1, 2, 3, 8])
 def test_fp64_each_sweep_mode(fixed):
     """Iteration 1 (X = M), 2 (Y_1 = 0) and the general sweep."""
