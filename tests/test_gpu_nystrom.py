@@ -117,6 +117,7 @@ def test_nystrom_full_size_40000():
     m = n = 40000
     r, l, iters = 20, 80, 25
     M, A, B, lam = workloads.nystrom_large_device(seed=0)
+    assert bool(torch.isfinite(M).all())
     perm = workloads.row_permutation(m, seed=11)
     pt = torch.from_numpy(perm).cuda()
     C = M[pt, :l].double().cpu().numpy()

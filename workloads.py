@@ -212,7 +212,8 @@ def nystrom_large_device(seed: int = 0, m: int = 40000, n: int = 40000, r: int =
     """The 40000 x 40000, r = 20 workload drawn directly in device memory
     with torch's seeded generator (the host copy would be 6.4 GB): L0 =
     A B^T with N(0,1) factors, a Bernoulli(frac) outlier mask and
-    Laplace(0, scale) outlier values (inverse-CDF draw).  Returns
+    Laplace(0, scale) outlier values (inverse-CDF draw, finite: the uniform
+    draw is kept away from 0).  Returns
     (M, A, B, lam) with M float32 on `device`."""
     import torch
     g = torch.Generator(device=device)
@@ -225,7 +226,10 @@ def nystrom_large_device(seed: int = 0, m: int = 40000, n: int = 40000, r: int =
         i1 = min(m, i0 + rows_per)
         u = torch.rand(i1 - i0, n, generator=g, device=device)
         mask = u < frac
-        v = torch.rand(i1 - i0, n, generator=g, device=device) - 0.5
+        # FP32 uniforms are multiples of 2^-24 and include 0, where the
+        # inverse CDF is infinite: the draw is clamped to the smallest
+        # representable quantile (|Laplace| <= 24 ln 2 * scale, about 333)
+        v = torch.rand(i1 - i0, n, generator=g, device=device).clamp_(min=2.0 ** -25) - 0.5
         lap = -scale * torch.sign(v) * torch.log1p(-2.0 * v.abs())
         M[i0:i1] += torch.where(mask, lap, torch.zeros_like(lap))
         del u, mask, v, lap
