@@ -110,6 +110,9 @@ __device__ __forceinline__ T readlane(T v, int lane)
 // Exchange words of one band are read ahead of use: a lane holds up to
 // kGatherAhead words, loaded before its row pass and checked after it.
 constexpr int kGatherAhead = 2;
+// Exchange words a lane reads together when it gathers a band's words after
+// its row pass (clusters too wide for the words read ahead).
+constexpr int kGatherBatchV = 4;
 
 // Byte offsets of the dynamic LDS regions of one sweep workgroup.
 struct SweepLds {
@@ -418,11 +421,38 @@ __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs
                         }
                     }
                 } else {
-                    for (int e = lane; e < c * R; e += 64) {
-                        const int qq = e / R, k = e % R;
-                        const unsigned long long* src =
-                            a.exch + (((((size_t)cl * kExchSlots + slot) * c + qq) * H + h) * R + k) * WD;
-                        gx[e] = fetch<T>(src, tag, tflag);
+                    // a lane reads kGatherBatchV of its words together (word
+                    // indices clamped into range), then polls those whose tag
+                    // has not arrived: one round trip per batch
+                    const int nw = c * R;
+                    const unsigned long long* base = a.exch + (((size_t)cl * kExchSlots + slot) * c) * H * R * WD;
+                    for (int e0 = lane; e0 < nw; e0 += 64 * kGatherBatchV) {
+                        unsigned long long w[kGatherBatchV][WD];
+#pragma unroll
+                        for (int u = 0; u < kGatherBatchV; ++u) {
+                            const int e = min(e0 + 64 * u, nw - 1);
+                            const int qq = e / R, k = e % R;
+                            const unsigned long long* src = base + (((size_t)qq * H + h) * R + k) * WD;
+#pragma unroll
+                            for (int hw = 0; hw < WD; ++hw) w[u][hw] = peek_word(src + hw);
+                        }
+#pragma unroll
+                        for (int u = 0; u < kGatherBatchV; ++u) {
+                            const int e = e0 + 64 * u;
+                            if (e < nw) {
+                                const int qq = e / R, k = e % R;
+                                const unsigned long long* src = base + (((size_t)qq * H + h) * R + k) * WD;
+#pragma unroll
+                                for (int hw = 0; hw < WD; ++hw)
+                                    if ((uint32_t)(w[u][hw] >> 32) != tag) w[u][hw] = spin_word(src + hw, tag, tflag);
+                                if constexpr (WD == 1) {
+                                    gx[e] = __uint_as_float((uint32_t)(w[u][0] & 0xffffffffull));
+                                } else {
+                                    gx[e] = __longlong_as_double(
+                                        (long long)((w[u][WD - 1] << 32) | (w[u][0] & 0xffffffffull)));
+                                }
+                            }
+                        }
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

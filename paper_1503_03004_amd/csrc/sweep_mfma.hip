@@ -48,6 +48,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMW8 = 8;                  // wavefronts per workgroup
 constexpr int kMTPB = 64 * kMW8;         // threads per workgroup
 constexpr int kMH = 16;                  // rows per band
+constexpr int kGatherBatch = 8;          // exchange words read together per thread
 
 // Compile-time shape for rank bucket R.
 template <int R, int TW = 0>
@@ -354,12 +355,24 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
             const int slot = jb & (kExchSlots - 1);
             float s = 0.f;
             if (prk < R) {
-                const unsigned long long* base = a.exch + (((size_t)cl * kExchSlots + slot) * c) * kMH * R;
-                for (int qq = 0; qq < c; ++qq) {
-                    const unsigned long long* src = base + ((size_t)qq * kMH + prow_) * R + prk;
-                    unsigned long long w = peek_word(src);
-                    if ((uint32_t)(w >> 32) != tag) w = spin_word(src, tag, tflag);
-                    s += __uint_as_float((uint32_t)(w & 0xffffffffull));
+                // the words of kGatherBatch members are read together (member
+                // indices clamped into range), then those whose tag has not
+                // arrived yet are polled: one round trip per batch instead of
+                // one per member
+                const unsigned long long* base =
+                    a.exch + (((size_t)cl * kExchSlots + slot) * c) * kMH * R + (size_t)prow_ * R + prk;
+                const size_t qstride = (size_t)kMH * R;
+                for (int q0 = 0; q0 < c; q0 += kGatherBatch) {
+                    unsigned long long w[kGatherBatch];
+#pragma unroll
+                    for (int u = 0; u < kGatherBatch; ++u) w[u] = peek_word(base + (size_t)min(q0 + u, c - 1) * qstride);
+#pragma unroll
+                    for (int u = 0; u < kGatherBatch; ++u) {
+                        if (q0 + u < c) {
+                            if ((uint32_t)(w[u] >> 32) != tag) w[u] = spin_word(base + (size_t)(q0 + u) * qstride, tag, tflag);
+                            s += __uint_as_float((uint32_t)(w[u] & 0xffffffffull));
+                        }
+                    }
                 }
             }
             PS[(jb & 1) * PT + tid] = s;
