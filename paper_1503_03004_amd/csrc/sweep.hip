@@ -111,8 +111,10 @@ __device__ __forceinline__ T readlane(T v, int lane)
 // kGatherAhead words, loaded before its row pass and checked after it.
 constexpr int kGatherAhead = 2;
 // Exchange words a lane reads together when it gathers a band's words after
-// its row pass (clusters too wide for the words read ahead).
-constexpr int kGatherBatchV = 4;
+// its row pass (clusters too wide for the words read ahead): 8 for FP32
+// values, 4 for FP64 (two words each).
+template <typename T>
+constexpr int gather_batch() { return sizeof(T) == 4 ? 8 : 4; }
 
 // Byte offsets of the dynamic LDS regions of one sweep workgroup.
 struct SweepLds {
@@ -421,15 +423,16 @@ __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs
                         }
                     }
                 } else {
-                    // a lane reads kGatherBatchV of its words together (word
+                    // a lane reads gather_batch<T>() of its words together (word
                     // indices clamped into range), then polls those whose tag
                     // has not arrived: one round trip per batch
                     const int nw = c * R;
                     const unsigned long long* base = a.exch + (((size_t)cl * kExchSlots + slot) * c) * H * R * WD;
-                    for (int e0 = lane; e0 < nw; e0 += 64 * kGatherBatchV) {
-                        unsigned long long w[kGatherBatchV][WD];
+                    constexpr int GB = gather_batch<T>();
+                    for (int e0 = lane; e0 < nw; e0 += 64 * GB) {
+                        unsigned long long w[GB][WD];
 #pragma unroll
-                        for (int u = 0; u < kGatherBatchV; ++u) {
+                        for (int u = 0; u < GB; ++u) {
                             const int e = min(e0 + 64 * u, nw - 1);
                             const int qq = e / R, k = e % R;
                             const unsigned long long* src = base + (((size_t)qq * H + h) * R + k) * WD;
@@ -437,7 +440,7 @@ __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs
                             for (int hw = 0; hw < WD; ++hw) w[u][hw] = peek_word(src + hw);
                         }
 #pragma unroll
-                        for (int u = 0; u < kGatherBatchV; ++u) {
+                        for (int u = 0; u < GB; ++u) {
                             const int e = e0 + 64 * u;
                             if (e < nw) {
                                 const int qq = e / R, k = e % R;
