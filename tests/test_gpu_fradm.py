@@ -139,6 +139,8 @@ def test_fp64_each_sweep_mode(fixed):
     (500, 64, 20, "f32"),     # r = 20 bucket
     (400, 300, 32, "f64"),    # largest supported rank
     (48, 36000, 20, "f32"),   # clusters wider than one XCD's share of the grid
+    (64, 20000, 10, "f32"),   # vector sweep, 20-member clusters: exchange words gathered in batches
+    (40, 8000, 10, "f64"),    # the same in FP64 (two words per value)
 ])
 def test_shapes(m, n, r, precision):
     inst = workloads.planted(m, n, r, seed=m + n + r, frac=0.05, kind="uniform", scale=20.0,
@@ -281,7 +283,7 @@ def test_photometric_tolerance_driven_fp32():
 @pytest.mark.parametrize("sweep", ["mfma", "vector"])
 @pytest.mark.parametrize("m,n,r", [(300, 1100, 10), (1037, 2048, 4), (64, 5000, 12), (2100, 1024, 1),
                                    (300, 1100, 16), (700, 800, 16), (400, 2100, 13), (200, 2000, 20),
-                                   (1037, 700, 24), (150, 1500, 32)])
+                                   (1037, 700, 24), (150, 1500, 32), (40, 30000, 20)])
 def test_both_fp32_sweeps(monkeypatch, sweep, m, n, r):
     """FP32 shapes that both sweeps take: the matrix-core sweep and the vector
     sweep (SFR_SWEEP selects) each against the oracle."""
