@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <thread>
 
 namespace sfr {
 
@@ -198,6 +199,13 @@ sfr_status nys_setup(sfr_ctx* h)
     ok = ok && dev_alloc(h->allocs, bytes, &h->Vcomb, (size_t)n * R * esz);
     if (!ok) return SFR_ERR_NOMEM;
     h->left.bytes += bytes;
+    // the l x n sub-solve runs on a second stream beside the m x l one
+    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return SFR_ERR_DEVICE;
+    }
     return SFR_OK;
 }
 
@@ -208,14 +216,40 @@ static sfr_status nys_run(sfr_ctx* h, const T* M, int64_t ldm, T* U, double* B, 
     const int m = (int)h->m, n = (int)h->n, r = h->r, l = h->l;
     const int R = h->left.R;
     HIPCHK(launch_nys_gather<T>(M, ldm, h->perm_d, m, n, l, static_cast<T*>(h->C), static_cast<T*>(h->Rb), s));
+    // The two sub-solves are independent: the l x n one runs on the side
+    // stream, driven from a host thread, while this thread drives the m x l
+    // one on the caller's stream; each engine_iterate waits for its own
+    // stream, and the join orders the combine after both.
+    HIPCHK(hipEventRecord(h->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
     OutputSpec<T> ol;
     ol.U = static_cast<T*>(h->UL); ol.B = h->BL; ol.V = static_cast<T*>(h->VL);
-    sfr_status st = engine_iterate<T>(h->left, h->prm, h->mu_left, static_cast<const T*>(h->C), l, ol, s);
-    if (st != SFR_OK) return st;
     OutputSpec<T> ot;
     ot.U = static_cast<T*>(h->UT); ot.B = h->BT; ot.V = static_cast<T*>(h->VT);
-    st = engine_iterate<T>(h->top, h->prm, h->mu_top, static_cast<const T*>(h->Rb), n, ot, s);
-    if (st != SFR_OK) return st;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    sfr_status st_top = SFR_ERR_DEVICE;
+    auto run_top = [&]() {
+        if (hipSetDevice(dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+        st_top = engine_iterate<T>(h->top, h->prm, h->mu_top, static_cast<const T*>(h->Rb), n, ot, h->side);
+    };
+    std::thread top;
+    bool threaded = true;
+    try {
+        top = std::thread(run_top);
+    } catch (...) {   // no thread available: the two sub-solves run one after the other
+        threaded = false;
+    }
+    const sfr_status st_left = engine_iterate<T>(h->left, h->prm, h->mu_left, static_cast<const T*>(h->C), l, ol, s);
+    if (threaded) top.join();
+    else run_top();
+    HIPCHK(hipEventRecord(h->ev_join, h->side));
+    HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
+    if (st_left != SFR_OK) return st_left;
+    if (st_top != SFR_OK) return st_top;
     double* Wl = h->core;
     double* Zr = Wl + r * r;
     double* sig = Zr + r * r;
