@@ -627,6 +627,9 @@ sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double l
         engine_destroy(h->left);
         engine_destroy(h->top);
         free_all(h->allocs);
+        if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+        if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+        if (h->side) (void)hipStreamDestroy(h->side);
         delete h;
         return st;
     }
