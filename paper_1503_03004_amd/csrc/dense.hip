@@ -176,31 +176,42 @@ __global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
 #pragma unroll
         for (int k = 0; k < R; ++k) vk[k][e] = (j + e < n) ? Vt[(int64_t)(j + e) * R + k] : T(0);
     const bool full = (VEC == 1) || (j + VEC <= n);
-    for (int i = i0; i < i1; ++i) {
-        T av[R];
+    // RU rows per step: the M (and Y) loads of all of them are in flight
+    // together before any is used
+    constexpr int RU = (R * sizeof(T) <= 64) ? 4 : 2;
+    for (int i = i0; i < i1; i += RU) {
+        T mv[RU][VEC], yv[RU][VEC];
 #pragma unroll
-        for (int k = 0; k < R; ++k) av[k] = A[(int64_t)i * R + k];
-        T mv[VEC], yv[VEC], out[VEC];
+        for (int u = 0; u < RU; ++u) {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) { mv[e] = T(0); yv[e] = T(0); }
-        if (full) {
-            vload<T, VEC>(M + (int64_t)i * ldm + j, mv);
-            if (mode == 0 && Y) vload<T, VEC>(Y + (int64_t)i * ldy + j, yv);
-        }
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            T l = 0;
-#pragma unroll
-            for (int k = 0; k < R; ++k) l = fma(av[k], vk[k][e], l);
-            if (mode == 0) {
-                const T Rr = mv[e] - l + yv[e] * imu;
-                const T a = Rr - t, b = Rr + t;
-                out[e] = (a > T(0) ? a : T(0)) + (b < T(0) ? b : T(0));
-            } else {
-                out[e] = mv[e] - l;
+            for (int e = 0; e < VEC; ++e) { mv[u][e] = T(0); yv[u][e] = T(0); }
+            if (full && i + u < i1) {
+                vload<T, VEC>(M + (int64_t)(i + u) * ldm + j, mv[u]);
+                if (mode == 0 && Y) vload<T, VEC>(Y + (int64_t)(i + u) * ldy + j, yv[u]);
             }
         }
-        if (full) vstore<T, VEC>(S + (int64_t)i * lds + j, out);
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            if (i + u >= i1) break;
+            T av[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) av[k] = A[(int64_t)(i + u) * R + k];
+            T out[VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                T l = 0;
+#pragma unroll
+                for (int k = 0; k < R; ++k) l = fma(av[k], vk[k][e], l);
+                if (mode == 0) {
+                    const T Rr = mv[u][e] - l + yv[u][e] * imu;
+                    const T a = Rr - t, b = Rr + t;
+                    out[e] = (a > T(0) ? a : T(0)) + (b < T(0) ? b : T(0));
+                } else {
+                    out[e] = mv[u][e] - l;
+                }
+            }
+            if (full) vstore<T, VEC>(S + (int64_t)(i + u) * lds + j, out);
+        }
     }
 }
 
