@@ -110,6 +110,34 @@ def test_nystrom_argument_errors():
         assert e.value.code == sfr.SFR_ERR_HANDLE
 
 
+@pytest.mark.parametrize("block", ["top", "left"])
+def test_nystrom_sub_solve_error_reported(block):
+    """An error in either sub-solve (they run concurrently, the l x n one on
+    a second stream) is returned, and the outputs are left untouched.  With
+    V_0 = I_{n x r}, zero columns 0..r-1 in a block make X V_0 rank-deficient
+    (SFR_ERR_RANK): rows perm[:l] of M for the l x n block; every row of M
+    for the m x l block, whose columns 0..l-1 are M's."""
+    rng = np.random.default_rng(12)
+    m, n, r, l = 300, 200, 3, 12
+    M = rng.standard_normal((m, n))
+    perm = workloads.row_permutation(m, seed=2)
+    if block == "top":
+        M[perm[:l], :r] = 0.0
+    else:
+        M[:, :r] = 0.0
+    Mt = torch.from_numpy(M).cuda()
+    U = torch.full((m, r), 7.0, dtype=torch.float64, device="cuda")
+    V = torch.full((n, r), 7.0, dtype=torch.float64, device="cuda")
+    B = torch.full((r, r), 7.0, dtype=torch.float64, device="cuda")
+    S = torch.full((m, n), 7.0, dtype=torch.float64, device="cuda")
+    with sfr.Solver(m, n, r, 0.1, 1.0, 1e-7, precision="f64", nystrom_l=l, mu_left=0.1, mu_top=0.1) as s:
+        out = s.solve_nys(Mt, perm, out=(U, B, V, S), raise_on_error=False)
+        torch.cuda.synchronize()
+    assert out[4].status == sfr.SFR_ERR_RANK, out[4].status
+    for t in (U, V, B, S):
+        assert bool((t == 7.0).all())
+
+
 def test_nystrom_full_size_40000():
     """The 40000 x 40000, r = 20, l = 80 FP32 workload, drawn on the device:
     the oracle solves the two gathered blocks in FP64 and evaluates 20000
