@@ -131,6 +131,8 @@ __device__ __forceinline__ void vstore(T* p, const T (&v)[VEC])
 // vectors down the band.  The row factor A_i is uniform over the
 // workgroup.  Vector paths need n, ldm, ldy, lds multiples of VEC and
 // 16-byte aligned bases; otherwise VEC = 1.
+constexpr int kLowrankRows = 64;   // rows of a lowrank_pass workgroup's band
+
 template <typename T, int VEC, int R>
 __global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
 {
@@ -168,6 +170,10 @@ __global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
     const int i1 = min(m, i0 + rows_per_blk);
     const int jj = tid * VEC;
     const int j = j0 + jj;
+    // the band's row factors (one coalesced load, then broadcast reads)
+    __shared__ T Ab[kLowrankRows * R];
+    for (int e = tid; e < (i1 - i0) * R; e += 256) Ab[e] = A[(int64_t)i0 * R + e];
+    __syncthreads();
     if (j >= n) return;
     // this thread's VEC columns of Vt stay in registers for the whole band
     T vk[R][VEC];
@@ -195,7 +201,7 @@ __global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
             if (i + u >= i1) break;
             T av[R];
 #pragma unroll
-            for (int k = 0; k < R; ++k) av[k] = A[(int64_t)(i + u) * R + k];
+            for (int k = 0; k < R; ++k) av[k] = Ab[(i + u - i0) * R + k];
             T out[VEC];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
@@ -247,7 +253,7 @@ template <typename T>
 hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s)
 {
     constexpr int V = 16 / sizeof(T);
-    a.rows_per_blk = 64;
+    a.rows_per_blk = kLowrankRows;
     auto al = [](const void* p) { return ((uintptr_t)p % 16) == 0; };
     bool ys = a.st ? (al(a.pp.Y[0]) && al(a.pp.Y[1])) : (!a.Y || al(a.Y));
     const bool vec = (a.n % V == 0) && (a.ldm % V == 0) && (a.lds % V == 0) && al(a.M) && al(a.S) &&
