@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
     const bool full = (VEC == 1) || (j + VEC <= n);
     // RU rows per step: the M (and Y) loads of all of them are in flight
     // together before any is used
-    constexpr int RU = (R * sizeof(T) <= 64) ? 4 : 2;
+    constexpr int RU = (sizeof(T) == 4) ? 8 : 4;
     for (int i = i0; i < i1; i += RU) {
         T mv[RU][VEC], yv[RU][VEC];
 #pragma unroll
