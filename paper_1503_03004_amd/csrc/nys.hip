@@ -20,21 +20,30 @@
 
 namespace sfr {
 
-// One wavefront: from U_L (rows 0..l-1 used), B_L, U_T, B_T build G and its
-// SVD.  status: 0, or kErrRank if A^T A or G is singular.  The r x r
+// Threads of the combine's r x r algebra: one wavefront up to R = 12, a
+// workgroup of 512 from R = 16 (as the step kernel: each Jacobi round then
+// has >= 128 2 x 2 blocks).
+template <int R>
+constexpr int nys_combine_threads() { return R >= 16 ? 512 : 64; }
+
+// From U_L (rows 0..l-1 used), B_L, U_T, B_T build G and its SVD, by NT
+// threads.  status: 0, or kErrRank if A^T A or G is singular.  The r x r
 // matrices are held R x R with an identity block on the padded indices.
 template <typename T, int R>
-__global__ void __launch_bounds__(64) nys_combine_kernel(const T* UL, const double* BL, const T* UT,
-                                                         const double* BT, int l, int r, double* Wl,
-                                                         double* Zr, double* sig, int32_t* status)
+__global__ void __launch_bounds__(nys_combine_threads<R>()) nys_combine_kernel(const T* UL, const double* BL,
+                                                                               const T* UT, const double* BT,
+                                                                               int l, int r, double* Wl,
+                                                                               double* Zr, double* sig,
+                                                                               int32_t* status)
 {
+    constexpr int NT = nys_combine_threads<R>();
     __shared__ double H1[R * LDP], H2[R * LDP], Bl[R * LDP], Bt[R * LDP];
     __shared__ double T1[R * LDP], T2[R * LDP], Ev[R * LDP], G[R * LDP];
     __shared__ __align__(16) double cs[2 * 16];
     __shared__ double wbuf[kMaxR];
-    const int lane = threadIdx.x & 63;
+    const int lane = lid<NT>();
     // H1 = U_L[0:l]^T U_L[0:l], H2 = U_L[0:l]^T U_T
-    for (int e = lane; e < R * R; e += 64) {
+    for (int e = lane; e < R * R; e += NT) {
         const int a = e / R, b = e % R;
         const bool pad = (a >= r) || (b >= r);
         double s1 = 0.0, s2 = 0.0;
@@ -52,64 +61,59 @@ __global__ void __launch_bounds__(64) nys_combine_kernel(const T* UL, const doub
         Bt[a * LDP + b] = pad ? id : BT[a * r + b];
         Ev[a * LDP + b] = id;
     }
-    wsync();
+    lsync<NT>();
     // A^T A = B_L H1 B_L
-    wmm<R>(T1, Bl, H1);
-    wmm<R>(T2, T1, Bl);
-    wsym<R>(T2);
-    wjacobi<R>(T2, Ev, cs);
+    wmm<R, NT>(T1, Bl, H1);
+    wmm<R, NT>(T2, T1, Bl);
+    wsym<R, NT>(T2);
+    wjacobi<R, NT>(T2, Ev, cs);
+    for (int i = lane; i < R; i += NT) wbuf[i] = T2[i * LDP + i];
+    lsync<NT>();
+    // every thread reads the whole diagonal for the rank test
     double wmax = -INFINITY, wmin = INFINITY;
-    for (int i = lane; i < R; i += 64) {
-        wbuf[i] = T2[i * LDP + i];
-        if (i < r) {
-            wmax = fmax(wmax, wbuf[i]);
-            wmin = fmin(wmin, wbuf[i]);
-        }
+    for (int i = 0; i < r; ++i) {
+        wmax = fmax(wmax, wbuf[i]);
+        wmin = fmin(wmin, wbuf[i]);
     }
-    wmax = wave_max(wmax);
-    wmin = wave_min(wmin);
-    wsync();
     bool ok = (wmax > 0.0) && (wmin > (double)r * DBL_EPSILON * wmax) && isfinite(wmax);
     // T1 = (A^T A)^{-1}
-    for (int e = lane; e < R * R; e += 64) {
+    for (int e = lane; e < R * R; e += NT) {
         const int i = e / R, j = e % R;
         double s = 0.0;
         for (int t = 0; t < R; ++t) s = fma(Ev[i * LDP + t] / wbuf[t], Ev[j * LDP + t], s);
         T1[i * LDP + j] = s;
     }
-    wsync();
+    lsync<NT>();
     // G = B_L (A^T A)^{-1} (B_L H2) B_T
-    wmm<R>(T2, Bl, T1);      // B_L (A^T A)^{-1}
-    wmm<R>(H1, Bl, H2);      // A^T U_T = B_L H2
-    wmm<R>(T1, T2, H1);
-    wmm<R>(G, T1, Bt);
+    wmm<R, NT>(T2, Bl, T1);      // B_L (A^T A)^{-1}
+    wmm<R, NT>(H1, Bl, H2);      // A^T U_T = B_L H2
+    wmm<R, NT>(T1, T2, H1);
+    wmm<R, NT>(G, T1, Bt);
     // SVD of G from the eigendecomposition of G^T G = Zr diag(sig^2) Zr^T
-    wmtm<R>(T2, G, G);
-    wsym<R>(T2);
-    for (int e = lane; e < R * R; e += 64) Ev[(e / R) * LDP + e % R] = ((e / R) == (e % R)) ? 1.0 : 0.0;
-    wsync();
-    wjacobi<R>(T2, Ev, cs);
-    double smax = -INFINITY, smin = INFINITY;
-    for (int i = lane; i < R; i += 64) {
+    wmtm<R, NT>(T2, G, G);
+    wsym<R, NT>(T2);
+    for (int e = lane; e < R * R; e += NT) Ev[(e / R) * LDP + e % R] = ((e / R) == (e % R)) ? 1.0 : 0.0;
+    lsync<NT>();
+    wjacobi<R, NT>(T2, Ev, cs);
+    for (int i = lane; i < R; i += NT) {
         const double w = T2[i * LDP + i];
         wbuf[i] = w > 0.0 ? sqrt(w) : 0.0;
-        if (i < r) {
-            smax = fmax(smax, wbuf[i]);
-            smin = fmin(smin, wbuf[i]);
-        }
     }
-    smax = wave_max(smax);
-    smin = wave_min(smin);
-    wsync();
+    lsync<NT>();
+    double smax = -INFINITY, smin = INFINITY;
+    for (int i = 0; i < r; ++i) {
+        smax = fmax(smax, wbuf[i]);
+        smin = fmin(smin, wbuf[i]);
+    }
     ok = ok && (smax > 0.0) && (smin > (double)r * DBL_EPSILON * smax) && isfinite(smax);
     // Wl = G Zr diag(1/sig)
-    wmm<R>(T1, G, Ev);
-    for (int e = lane; e < r * r; e += 64) {
+    wmm<R, NT>(T1, G, Ev);
+    for (int e = lane; e < r * r; e += NT) {
         const int i = e / r, j = e % r;
         Wl[i * r + j] = wbuf[j] > 0.0 ? T1[i * LDP + j] / wbuf[j] : 0.0;
         Zr[i * r + j] = Ev[i * LDP + j];
     }
-    for (int i = lane; i < r; i += 64) sig[i] = wbuf[i];
+    for (int i = lane; i < r; i += NT) sig[i] = wbuf[i];
     if (lane == 0) *status = ok ? kOK : kErrRank;
 }
 
@@ -120,8 +124,8 @@ static hipError_t launch_nys_combine(int R, const T* UL, const double* BL, const
     switch (R) {
 #define CASE(rr)                                                                                          \
     case rr:                                                                                              \
-        hipLaunchKernelGGL((nys_combine_kernel<T, rr>), dim3(1), dim3(64), 0, s, UL, BL, UT, BT, l, r, Wl, \
-                           Zr, sig, status);                                                              \
+        hipLaunchKernelGGL((nys_combine_kernel<T, rr>), dim3(1), dim3(nys_combine_threads<rr>()), 0, s, UL, BL, \
+                           UT, BT, l, r, Wl, Zr, sig, status);                                            \
         break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(8) CASE(10) CASE(12) CASE(16) CASE(20) CASE(24)
         CASE(32)
