@@ -31,6 +31,10 @@ MUTANTS = [
     ("pinv_keeps_smallest", "while (j > 0 && sig[idx[j - 1]] < sig[v])", "while (j > 0 && sig[idx[j - 1]] > sig[v])"),
     ("nystrom_unshuffle_dropped", "int64_t dst = perm[i];", "int64_t dst = i;"),
     ("residual_uses_old_Y", "double E = M[i] - L[i] - S[i];", "double E = M[i] - L[i] - S[i] + 1e-3 * Y[i];"),
+    ("Lstep_input_uses_next_mu", "X[i] = M[i] - S[i] + Y[i] / mk;", "X[i] = M[i] - S[i] + Y[i] / (rho * mk);"),
+    ("V0_shifted", "V[i * r + j] = (i == j) ? 1.0 : 0.0;", "V[i * r + j] = (i == j + 1) ? 1.0 : 0.0;"),
+    ("B0_not_identity", "B[i * r + j] = (i == j) ? 1.0 : 0.0;", "B[i * r + j] = (i == j) ? 1.0 + (double)i : 0.0;"),
+    ("Sstep_uses_next_mu", "const double t = lambda / mk;", "const double t = lambda / (rho * mk);"),
 ]
 
 PIN_TESTS = [
@@ -41,6 +45,7 @@ PIN_TESTS = [
     pins.test_fr_step_invariants_and_lemma1,
     pins.test_fr_step_identity_B0_gives_symmetric_product,
     pins.test_fradm_iteration_identities,
+    pins.test_fradm_starts_from_identity_factors,
     pins.test_lambda_mu_equivalence,
     pins.test_nystrom_exact_on_rank_r_and_reading,
     pins.test_nystrom_blocks_matches_full,

@@ -244,6 +244,21 @@ def test_fr_full_converges_to_tsvd_at_theorem2_rate():
 # Alg. 1 per-iteration identities and invariants (P4, P7)
 # --------------------------------------------------------------------------
 
+def _np_polar(A):
+    """P_O[A] of eq. (7) from LAPACK's thin SVD A = Q diag(s) Z^T: Q Z^T."""
+    Q, _, Zt = np.linalg.svd(A, full_matrices=False)
+    return Q @ Zt
+
+
+def _np_fixed_rank_step(X, B0, V0):
+    """Alg. 2 on X written with numpy: U = P_O[X V0 B0], V = P_O[X^T U B0]
+    (eq. (7)), B = Sym(U^T X V) (eq. (8))."""
+    U = _np_polar(X @ V0 @ B0)
+    V = _np_polar(X.T @ U @ B0)
+    C = U.T @ X @ V
+    return U, 0.5 * (C + C.T), V
+
+
 def test_fradm_iteration_identities():
     inst = workloads.plain_fp64(seed=1, m=60, n=50, r=3)
     mu0 = workloads.default_mu0(inst.M)
@@ -252,10 +267,21 @@ def test_fradm_iteration_identities():
     for k in range(12):
         Y_old = st.Y.copy()
         S_old = st.S.copy()
-        X = M - S_old + Y_old / st.mu.value
+        B_old = st.B.copy()
+        V_old = st.V.copy()
+        mu_k = st.mu.value
         res, rc = st.step()
         mk = st.mu_used
         assert rc == oracle.ORC_OK
+        assert mk == mu_k
+        # The L-step (Alg. 1) is FixedRankOptStep (Alg. 2) on
+        # X = M - S_k + Y_k / mu_k with the previous (B_k, V_k): compare the
+        # returned factors with the SVD closed forms of eqs. (7), (8).
+        X = M - S_old + Y_old / mu_k
+        Ue, Be, Ve = _np_fixed_rank_step(X, B_old, V_old)
+        np.testing.assert_allclose(st.U, Ue, atol=1e-10)
+        np.testing.assert_allclose(st.V, Ve, atol=1e-10)
+        np.testing.assert_allclose(st.B, Be, atol=1e-10 * np.abs(Be).max())
         L = st.U @ st.B @ st.V.T
         np.testing.assert_allclose(L, st.L, atol=1e-12 * np.abs(L).max())
         # Stiefel factors, symmetric B, rank r
@@ -276,8 +302,38 @@ def test_fradm_iteration_identities():
         np.testing.assert_allclose(st.S, np.sign(R) * np.maximum(np.abs(R) - inst.lam / mk, 0), atol=1e-12)
         # continuation
         assert st.mu.value == min(1e9, 1.5 * mk)
-        # the L-step is FixedRankOptStep on X
-        assert np.isfinite(X).all()
+
+
+def test_fradm_starts_from_identity_factors():
+    """Alg. 1 starts from S = Y = 0, B_0 = I_r and V_0 = I_{n x r} (the
+    first r columns of I_n, reading of the transposed initialisation), so
+    the first L-step input is M itself and iteration 1 returns
+    U = P_O[M I_{n x r}], V = P_O[M^T U], B = Sym(U^T M V) (eqs. (7), (8)).
+    The identity factors are built here, independently of the oracle's own
+    initialisation."""
+    inst = workloads.plain_fp64(seed=4, m=40, n=30, r=4)
+    mu0 = workloads.default_mu0(inst.M)
+    M, r = inst.M, inst.r
+    I_nr = np.eye(M.shape[1], r)
+    U1 = _np_polar(M @ I_nr)
+    V1 = _np_polar(M.T @ U1)
+    C = U1.T @ M @ V1
+    B1 = 0.5 * (C + C.T)
+    one = oracle.fradm(M, r, inst.lam, mu0, fixed_iters=1)
+    np.testing.assert_allclose(one["U"], U1, atol=1e-11)
+    np.testing.assert_allclose(one["V"], V1, atol=1e-11)
+    np.testing.assert_allclose(one["B"], B1, atol=1e-11 * np.abs(B1).max())
+    # the S- and dual steps of iteration 1 with S_1 = Y_1 = 0 and mu_0
+    L1 = U1 @ B1 @ V1.T
+    R = M - L1
+    t = inst.lam / mu0
+    S1 = np.sign(R) * np.maximum(np.abs(R) - t, 0.0)
+    np.testing.assert_allclose(one["S"], S1, atol=1e-11 * np.abs(M).max())
+    # the stepping interface starts from the same state
+    st = oracle.FradmState(M, r, inst.lam, mu0)
+    np.testing.assert_array_equal(st.V, I_nr)
+    np.testing.assert_array_equal(st.B, np.eye(r))
+    assert not st.S.any() and not st.Y.any()
 
 
 def test_fradm_kkt_at_convergence():
