@@ -73,10 +73,10 @@ typedef struct {
     double mu_top;           /* FR-Nys: initial penalty of the l x n sub-solve (> 0) */
     int32_t bf16;            /* nonzero (SFR_F32 FR-ADM handles only): BF16-operand contractions
                                 for the leading iterations.  Such a sweep runs on the matrix cores
-                                with its three contractions (l = a_i V^T, p = X V, Q = X^T P)
-                                taking BF16 operands with FP32 accumulation; M, Y and all stored
-                                values stay FP32, and the r x r algebra and the reductions stay
-                                FP64.  The BF16 phase ends after bf16_iters iterations or at a
+                                with its two bulk contractions (p = X V, Q = X^T P) taking BF16
+                                operands with FP32 accumulation; the reconstruction l = a_i V^T,
+                                M, Y and all stored values stay FP32, and the r x r algebra and the
+                                reductions stay FP64.  The BF16 phase ends after bf16_iters iterations or at a
                                 relative residual <= bf16_tol, whichever comes first; FP32
                                 iterations then continue from its returned iterate (same buffers,
                                 transforms and mu) under the handle's rule, within the same
@@ -104,6 +104,9 @@ typedef struct {
     double mu0;              /* the initial penalty mu_0 used: sfr_solve, the handle's mu or
                                 1.25 / ||M||_2 for a handle created with mu <= 0;
                                 sfr_solve_batch, the item's mu; else 0 */
+    double orth_err;         /* max(||U^T U - I_r||_F, ||V^T V - I_r||_F) of the returned factors as
+                                stored (their distance from St_{m,r} and St_{n,r}, eq. (7)),
+                                accumulated in FP64 */
 } sfr_info;
 
 /*
@@ -113,8 +116,9 @@ typedef struct {
  *   mu > 0: initial penalty mu_0 of Alg. 1 (finite).  mu <= 0 (finite,
  *     FR-ADM handles): each sfr_solve takes mu_0 = 1.25 / ||M||_2, with
  *     ||M||_2 the largest eigenvalue of B after Alg. 4 on M (run to a relative
- *     change of B of 1e-6, at most 60 steps, in the caller's U, B, V before the
- *     solve overwrites them); sfr_info.mu0 reports it.  Alg. 1's literal
+ *     change of B of 1e-6, at most 60 steps, in the handle's workspace: the
+ *     caller's outputs are written only by the solve that follows);
+ *     sfr_info.mu0 reports it.  Alg. 1's literal
  *     mu_0 = 1 does not recover the planted L on the synthetic workloads;
  *     this scale of the initial threshold does.
  *   tol >= 0: stop at the first iteration k with

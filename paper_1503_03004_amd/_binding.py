@@ -58,6 +58,7 @@ class sfr_info(ctypes.Structure):
         ("sweeps_timed", ctypes.c_int32),
         ("reserved1", ctypes.c_int32),
         ("mu0", ctypes.c_double),
+        ("orth_err", ctypes.c_double),
     ]
 
 
@@ -147,6 +148,7 @@ class Info:
     sweep_ms: float
     sweeps_timed: int
     mu0: float = 0.0
+    orth_err: float = 0.0
 
 
 def _stream_handle(stream):
@@ -221,6 +223,7 @@ class Solver:
             S = torch.empty((self.m, self.n), dtype=self.dtype, device=dev) if want_S else None
         else:
             U, B, V, S = out
+            check_outputs(U, B, V, S, self.m, self.n, self.r, self.dtype, dev)
         return U, B, V, S
 
     def solve(self, M, *, want_S=True, out=None, stream=None, raise_on_error=True):
@@ -332,6 +335,7 @@ class BatchSolver:
                 S = torch.empty((m, n), dtype=torch.float32, device=M.device) if want_S else None
             else:
                 U, B, V, S = outs[i]
+                check_outputs(U, B, V, S, m, n, int(r), torch.float32, M.device)
             keep.append((U, B, V, S))
             it = items[i]
             it.m, it.n, it.r = m, n, int(r)
@@ -395,10 +399,37 @@ class BatchSolver:
         self.close()
 
 
+def check_outputs(U, B, V, S, m, n, r, dtype, device):
+    """Caller-supplied output buffers must be what the C ABI writes: U dense
+    m x r, V dense n x r (dtype of the data), B dense r x r float64, S (or
+    None) m x n with unit column stride, all on M's device.  Raises
+    ValueError before any library call otherwise."""
+    import torch
+    for name, t, shape, dt in (("U", U, (m, r), dtype), ("B", B, (r, r), torch.float64), ("V", V, (n, r), dtype)):
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name} must be a torch tensor")
+        if tuple(t.shape) != shape or t.dtype != dt:
+            raise ValueError(f"{name} must be {shape[0]}x{shape[1]} {dt}, got {tuple(t.shape)} {t.dtype}")
+        if t.device != device:
+            raise ValueError(f"{name} must be on {device}, got {t.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous (dense row-major)")
+    if S is not None:
+        if not isinstance(S, torch.Tensor):
+            raise ValueError("S must be a torch tensor or None")
+        if tuple(S.shape) != (m, n) or S.dtype != dtype:
+            raise ValueError(f"S must be {m}x{n} {dtype}, got {tuple(S.shape)} {S.dtype}")
+        if S.device != device:
+            raise ValueError(f"S must be on {device}, got {S.device}")
+        if S.stride(1) != 1 or S.stride(0) < n:
+            raise ValueError("S must be row-major with unit column stride and row stride >= n")
+
+
 def _info(rc, info):
     return Info(status=int(rc), iters=info.iters, iters_top=info.iters_top, converged=bool(info.converged),
                 rel_residual=info.rel_residual, min_eig_B=info.min_eig_B, mu_final=info.mu_final,
-                sweep_ms=info.sweep_ms, sweeps_timed=info.sweeps_timed, mu0=info.mu0)
+                sweep_ms=info.sweep_ms, sweeps_timed=info.sweeps_timed, mu0=info.mu0,
+                orth_err=info.orth_err)
 
 
 def solve(M, r, lam, mu, tol=1e-7, **opts):

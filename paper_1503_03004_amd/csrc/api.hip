@@ -444,7 +444,11 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         pp.Q[b] = static_cast<T*>(e.Q[b]);
         pp.Y[b] = static_cast<const T*>(e.Y[b]);
     }
-    HIPCHK(launch_factors<T>(e.st, pp, e.m, e.n, e.r, e.R, out.U, out.V, out.B, s));
+    if (out.U) {
+        HIPCHK(launch_factors<T>(e.st, pp, e.m, e.n, e.r, e.R, out.U, out.V, out.B, s));
+        HIPCHK(launch_orth<T>(e.st, out.U, e.m, out.V, e.n, e.r, e.GPpart, e.npb, e.GQpart, e.nqb,
+                              &e.st->orth_err, s));
+    }
     if (out.S) {
         LowrankArgs<T> la;
         memset(&la, 0, sizeof(la));
@@ -509,6 +513,7 @@ static sfr_status fill_info(const Engine& e, sfr_info* info, sfr_status st)
         info->sweep_ms = e.sweep_ms;
         info->sweeps_timed = e.sweeps_timed;
         info->mu0 = 0.0;
+        info->orth_err = h.orth_err;
     }
     if (st != SFR_OK) return st;
     if (h.status == kWarnMaxIter) return SFR_WARN_MAXITER;
@@ -518,11 +523,10 @@ static sfr_status fill_info(const Engine& e, sfr_info* info, sfr_status st)
 
 // mu_0 = 1.25 / ||M||_2, the initial penalty taken for handles created with
 // mu <= 0.  ||M||_2 is the largest eigenvalue of B after Alg. 4 on M (run to
-// a change of B of 1e-6 relative, at most 60 steps, into the caller's U, B,
-// V, which the solve then overwrites).
+// a change of B of 1e-6 relative, at most 60 steps).  The estimate lives in
+// the handle's workspace and state only; no caller buffer is written.
 template <typename T>
-static sfr_status estimate_mu0(sfr_ctx* h, const T* M, int64_t ldm, T* U, double* B, T* V, hipStream_t s,
-                               double* mu0)
+static sfr_status estimate_mu0(sfr_ctx* h, const T* M, int64_t ldm, hipStream_t s, double* mu0)
 {
     Engine& e = h->main;
     Params p = h->prm;
@@ -533,8 +537,7 @@ static sfr_status estimate_mu0(sfr_ctx* h, const T* M, int64_t ldm, T* U, double
     p.bf16_iters = 0;
     p.bf16_tol = 0.0;
     p.profile = false;
-    OutputSpec<T> o;
-    o.U = U; o.B = B; o.V = V;
+    OutputSpec<T> o;   // no factors: only B in the state is read
     o.min_eig = false;
     const sfr_status st = engine_iterate<T>(e, p, 1.0, M, ldm, o, s, true);
     if (st < 0) return st;
@@ -678,14 +681,14 @@ sfr_status sfr_solve(sfr_handle h, const void* M, int64_t ldm, void* U, double* 
         o.U = static_cast<double*>(U); o.B = B; o.V = static_cast<double*>(V);
         o.M = static_cast<const double*>(M); o.ldm = ldm; o.S = static_cast<double*>(S); o.lds = lds;
         o.min_eig = true;
-        if (h->mu_auto) st = estimate_mu0<double>(h, o.M, ldm, o.U, B, o.V, s, &mu0);
+        if (h->mu_auto) st = estimate_mu0<double>(h, o.M, ldm, s, &mu0);
         if (st == SFR_OK) st = engine_iterate<double>(e, h->prm, mu0, static_cast<const double*>(M), ldm, o, s);
     } else {
         OutputSpec<float> o;
         o.U = static_cast<float*>(U); o.B = B; o.V = static_cast<float*>(V);
         o.M = static_cast<const float*>(M); o.ldm = ldm; o.S = static_cast<float*>(S); o.lds = lds;
         o.min_eig = true;
-        if (h->mu_auto) st = estimate_mu0<float>(h, o.M, ldm, o.U, B, o.V, s, &mu0);
+        if (h->mu_auto) st = estimate_mu0<float>(h, o.M, ldm, s, &mu0);
         if (st == SFR_OK) st = engine_iterate<float>(e, h->prm, mu0, static_cast<const float*>(M), ldm, o, s);
     }
     if (st < 0) {

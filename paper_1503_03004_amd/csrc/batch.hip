@@ -727,6 +727,57 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
     }
 }
 
+// orth_err of one item: ||U^T U - I_r||_F and ||V^T V - I_r||_F of the
+// factors it wrote (FP64 sums over 64-row tiles staged in LDS, each Gram
+// entry owned by one thread and summed in row order).
+constexpr int kOrthRows = 64;
+
+__global__ void __launch_bounds__(256) batch_orth_kernel(BatchItemDev* items)
+{
+    BatchItemDev* it = items + blockIdx.x;
+    if (it->status < 0) return;
+    __shared__ float tile[kOrthRows * 16];
+    __shared__ double red[256];
+    const int r = it->r, E = r * (r + 1) / 2, tid = threadIdx.x;
+    int p = 0, q = 0;
+    if (tid < E) {
+        int e = tid;
+        while (e >= r - p) { e -= r - p; ++p; }
+        q = p + e;
+    }
+    double dist[2];
+    for (int f = 0; f < 2; ++f) {
+        const float* X = f == 0 ? it->U : it->V;
+        const int rows = f == 0 ? it->m : it->n;
+        double g = 0.0;
+        for (int i0 = 0; i0 < rows; i0 += kOrthRows) {
+            const int nr = min(kOrthRows, rows - i0);
+            __syncthreads();
+            for (int e = tid; e < nr * r; e += 256) tile[e] = X[(int64_t)i0 * r + e];
+            __syncthreads();
+            if (tid < E)
+                for (int i = 0; i < nr; ++i) g = fma((double)tile[i * r + p], (double)tile[i * r + q], g);
+        }
+        const double d = g - (p == q ? 1.0 : 0.0);
+        red[tid] = (tid < E) ? ((p == q) ? 1.0 : 2.0) * d * d : 0.0;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (tid < h) red[tid] += red[tid + h];
+            __syncthreads();
+        }
+        dist[f] = sqrt(red[0]);
+        __syncthreads();
+    }
+    if (tid == 0) it->orth_err = fmax(dist[0], dist[1]);
+}
+
+hipError_t launch_batch_orth(BatchItemDev* items, int count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_orth_kernel, dim3((unsigned)count), dim3(256), 0, s, items);
+    return hipGetLastError();
+}
+
 #define SFR_BATCH_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16)
 
 #ifndef SFR_BATCH_RW

@@ -171,6 +171,7 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
     }
     if (ok && nw > 0) ok = launch_batch(h->items_d, nw, Rw, false, h->variant[0][bucket_index(Rw)], bp, s) == hipSuccess;
     if (ok && nn > 0) ok = hipStreamWaitEvent(s, h->ev_join, 0) == hipSuccess;
+    if (ok) ok = launch_batch_orth(h->items_d, count, s) == hipSuccess;
     if (!ok || hipMemcpyAsync(h->items_h, h->items_d, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
         (void)hipGetLastError();
@@ -196,6 +197,7 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
                 f.min_eig_B = d.min_eig_B;
                 f.mu_final = d.mu_final;
                 f.mu0 = items[i].mu;
+                f.orth_err = d.orth_err;
             }
         }
         if (st < 0 && i < worst_i) {

@@ -4,6 +4,8 @@
 #include "sfr_internal.hpp"
 #include "small_la.hpp"
 
+#include <algorithm>
+
 namespace sfr {
 
 template <typename T>
@@ -290,7 +292,87 @@ hipError_t launch_nys_gather(const T* M, int64_t ldm, const int64_t* perm, int m
     return hipGetLastError();
 }
 
+// Orthogonality of the returned Stiefel factors (U in St_{m,r}, V in
+// St_{n,r}, eq. (7)) as stored.  Pass 1: workgroup b < nu sums the Gram of
+// U's row block b, the others V's, over the packed upper triangle
+// (r(r+1)/2 entries), each entry in row order.  Pass 2 adds the blocks in
+// order and takes the two Frobenius distances to I_r.
+__device__ __forceinline__ void tri_index(int e, int r, int& p, int& q)
+{
+    p = 0;
+    while (e >= r - p) { e -= r - p; ++p; }
+    q = p + e;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) orth_partial_kernel(const DevState* st, const T* U, int m, const T* V, int n,
+                                                           int r, double* Up, int nu, double* Vp, int nv)
+{
+    if (st && (!st->done || st->status < 0 || st->exch_timeout)) return;
+    const bool isU = (int)blockIdx.x < nu;
+    const int b = isU ? (int)blockIdx.x : (int)blockIdx.x - nu;
+    const int nb = isU ? nu : nv;
+    const int rows = isU ? m : n;
+    const T* X = isU ? U : V;
+    const int E = r * (r + 1) / 2;
+    double* out = (isU ? Up : Vp) + (size_t)b * E;
+    const int per = (rows + nb - 1) / nb;
+    const int i0 = b * per, i1 = min(rows, i0 + per);
+    for (int e = threadIdx.x; e < E; e += 256) {
+        int p, q;
+        tri_index(e, r, p, q);
+        double acc = 0.0;
+        for (int i = i0; i < i1; ++i) acc = fma((double)X[(int64_t)i * r + p], (double)X[(int64_t)i * r + q], acc);
+        out[e] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(256) orth_final_kernel(const DevState* st, int r, const double* Up, int nu,
+                                                         const double* Vp, int nv, double* out)
+{
+    if (st && (!st->done || st->status < 0 || st->exch_timeout)) return;
+    __shared__ double red[2][256];
+    const int E = r * (r + 1) / 2;
+    double su = 0.0, sv = 0.0;
+    for (int e = threadIdx.x; e < E; e += 256) {
+        int p, q;
+        tri_index(e, r, p, q);
+        double gu = 0.0, gv = 0.0;
+        for (int b = 0; b < nu; ++b) gu += Up[(size_t)b * E + e];
+        for (int b = 0; b < nv; ++b) gv += Vp[(size_t)b * E + e];
+        const double w = (p == q) ? 1.0 : 2.0;
+        const double du = gu - (p == q ? 1.0 : 0.0), dv = gv - (p == q ? 1.0 : 0.0);
+        su += w * du * du;
+        sv += w * dv * dv;
+    }
+    red[0][threadIdx.x] = su;
+    red[1][threadIdx.x] = sv;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = fmax(sqrt(red[0][0]), sqrt(red[1][0]));
+}
+
+template <typename T>
+hipError_t launch_orth(const DevState* st, const T* U, int m, const T* V, int n, int r, double* Up, int nu,
+                       double* Vp, int nv, double* out, hipStream_t s)
+{
+    nu = std::max(1, std::min(nu, m));
+    nv = std::max(1, std::min(nv, n));
+    hipLaunchKernelGGL(orth_partial_kernel<T>, dim3((unsigned)(nu + nv)), dim3(256), 0, s, st, U, m, V, n, r, Up,
+                       nu, Vp, nv);
+    hipLaunchKernelGGL(orth_final_kernel, dim3(1), dim3(256), 0, s, st, r, Up, nu, Vp, nv, out);
+    return hipGetLastError();
+}
+
 #define INST(T)                                                                                              \
+    template hipError_t launch_orth<T>(const DevState*, const T*, int, const T*, int, int, double*, int,     \
+                                       double*, int, double*, hipStream_t);                                  \
     template hipError_t launch_init_q<T>(T*, int, int, int, hipStream_t);                                    \
     template hipError_t launch_copy_pad<T>(const T*, int64_t, T*, int64_t, int, int, hipStream_t);          \
     template hipError_t launch_factors<T>(const DevState*, const PingPong<T>&, int, int, int, int, T*, T*,    \

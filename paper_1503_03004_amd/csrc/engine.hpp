@@ -68,8 +68,9 @@ struct Params {
 };
 
 // What a solve writes once the iteration has stopped: the factors U, B, V
-// (always), the sparse part S of M (optional) and the smallest eigenvalue
-// of B (into the state).  The kernels are queued behind the iteration and
+// (U NULL: no factors, e.g. the mu_0 estimate, which reads only the state),
+// the sparse part S of M (optional), the smallest eigenvalue of B and the
+// factors' orthogonality error (into the state).  The kernels are queued behind the iteration and
 // write nothing if it ended with an error.
 template <typename T>
 struct OutputSpec {

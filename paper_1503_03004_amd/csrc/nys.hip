@@ -213,9 +213,16 @@ sfr_status nys_setup(sfr_ctx* h)
     return SFR_OK;
 }
 
+// Whether any sweep of the engine runs in clusters (c > 1), whose members
+// wait on each other's partial row products.
+static bool engine_waits(const Engine& e)
+{
+    return e.cfg[0].c > 1 || e.cfg[1].c > 1;
+}
+
 template <typename T>
 static sfr_status nys_run(sfr_ctx* h, const T* M, int64_t ldm, T* U, double* B, T* V, T* S, int64_t lds,
-                          double* min_sig, hipStream_t s)
+                          double* min_sig, double* orth, hipStream_t s)
 {
     const int m = (int)h->m, n = (int)h->n, r = h->r, l = h->l;
     const int R = h->left.R;
@@ -223,7 +230,11 @@ static sfr_status nys_run(sfr_ctx* h, const T* M, int64_t ldm, T* U, double* B, 
     // The two sub-solves are independent: the l x n one runs on the side
     // stream, driven from a host thread, while this thread drives the m x l
     // one on the caller's stream; each engine_iterate waits for its own
-    // stream, and the join orders the combine after both.
+    // stream, and the join orders the combine after both.  They overlap
+    // only if at most one of them runs cluster sweeps: a kernel without
+    // inter-workgroup waits always drains and frees its slots, so the
+    // members of the other one's clusters all become resident.  If both
+    // wait on cluster members, the l x n sub-solve runs after the m x l one.
     HIPCHK(hipEventRecord(h->ev_fork, s));
     HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
     OutputSpec<T> ol;
@@ -241,11 +252,13 @@ static sfr_status nys_run(sfr_ctx* h, const T* M, int64_t ldm, T* U, double* B, 
         st_top = engine_iterate<T>(h->top, h->prm, h->mu_top, static_cast<const T*>(h->Rb), n, ot, h->side);
     };
     std::thread top;
-    bool threaded = true;
-    try {
-        top = std::thread(run_top);
-    } catch (...) {   // no thread available: the two sub-solves run one after the other
-        threaded = false;
+    bool threaded = !(engine_waits(h->left) && engine_waits(h->top));
+    if (threaded) {
+        try {
+            top = std::thread(run_top);
+        } catch (...) {   // no thread available: the two sub-solves run one after the other
+            threaded = false;
+        }
     }
     const sfr_status st_left = engine_iterate<T>(h->left, h->prm, h->mu_left, static_cast<const T*>(h->C), l, ol, s);
     if (threaded) top.join();
@@ -274,6 +287,9 @@ static sfr_status nys_run(sfr_ctx* h, const T* M, int64_t ldm, T* U, double* B, 
                        static_cast<const T*>(h->UL), static_cast<const T*>(h->VT), h->perm_d, Wl, Zr, sig, m, n,
                        r, R, U, V, B, static_cast<T*>(h->Ucomb), static_cast<T*>(h->Vcomb));
     HIPCHK(hipGetLastError());
+    HIPCHK(launch_orth<T>(nullptr, U, m, V, n, r, h->left.GPpart, h->left.npb, h->top.GQpart, h->top.nqb,
+                          &h->left.st->orth_err, s));
+    HIPCHK(hipMemcpyAsync(orth, &h->left.st->orth_err, sizeof(double), hipMemcpyDeviceToHost, s));
     if (S) {
         LowrankArgs<T> la;
         memset(&la, 0, sizeof(la));
@@ -319,14 +335,14 @@ extern "C" sfr_status sfr_solve_nys(sfr_handle h, const void* M, int64_t ldm, co
         (void)hipGetLastError();
         return SFR_ERR_DEVICE;
     }
-    double min_sig = 0.0;
+    double min_sig = 0.0, orth = 0.0;
     sfr_status st;
     if (h->f64)
         st = nys_run<double>(h, static_cast<const double*>(M), ldm, static_cast<double*>(U), B,
-                             static_cast<double*>(V), static_cast<double*>(S), lds, &min_sig, s);
+                             static_cast<double*>(V), static_cast<double*>(S), lds, &min_sig, &orth, s);
     else
         st = nys_run<float>(h, static_cast<const float*>(M), ldm, static_cast<float*>(U), B,
-                            static_cast<float*>(V), static_cast<float*>(S), lds, &min_sig, s);
+                            static_cast<float*>(V), static_cast<float*>(S), lds, &min_sig, &orth, s);
     if (st < 0) {
         if (info) memset(info, 0, sizeof(*info));
         return st;
@@ -341,6 +357,7 @@ extern "C" sfr_status sfr_solve_nys(sfr_handle h, const void* M, int64_t ldm, co
         info->rel_residual = std::max(hl.res, ht.res);
         info->min_eig_B = min_sig;
         info->mu_final = hl.mu_prev;
+        info->orth_err = orth;
     }
     if (hl.status == kWarnMaxIter || ht.status == kWarnMaxIter) return SFR_WARN_MAXITER;
     return SFR_OK;

@@ -70,6 +70,7 @@ struct DevState {
     double res;         // last residual ||M - L - S||_F / ||M||_F
     double min_eig_B;   // filled by the finalize step
     double max_eig_B;   // largest eigenvalue of B (launch_max_eig)
+    double orth_err;    // max(||U^T U - I||_F, ||V^T V - I||_F) of the returned factors
     double B[kMaxR * kMaxR];
     double TU[kMaxR * kMaxR];     // a_i = P_i TU gives L rows (L = A V^T)
     double TUbar[kMaxR * kMaxR];  // U = P TUbar
@@ -201,6 +202,7 @@ struct BatchItemDev {
     // results
     int32_t iters, status;
     double res, min_eig_B, mu_final;
+    double orth_err;                 // max(||U^T U - I||_F, ||V^T V - I||_F) of the written factors
 };
 
 struct BatchParams {
@@ -217,6 +219,9 @@ bool batch_variant_valid(int R, int variant);
 // narrow: the items have n <= 128; variant kBVAuto picks the default form
 hipError_t launch_batch(BatchItemDev* items, int count, int R, bool narrow, int variant, const BatchParams& bp,
                         hipStream_t s);
+// orth_err of every successful item of a batch (one workgroup per item),
+// from the factors it wrote.
+hipError_t launch_batch_orth(BatchItemDev* items, int count, hipStream_t s);
 
 // Host-side launchers (sweep.hip / small.hip / dense.hip).  The sweep takes
 // an optional start/stop event pair bound to its dispatch.
@@ -266,6 +271,13 @@ hipError_t launch_factors(const DevState* st, const PingPong<T>& pp, int m, int 
                           double* B, hipStream_t s);
 template <typename T>
 hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s);
+// max(||U^T U - I_r||_F, ||V^T V - I_r||_F) of stored factors U (m x r) and
+// V (n x r), accumulated in FP64, into *out.  Up (nu x r(r+1)/2) and Vp
+// (nv x r(r+1)/2) receive the partial Grams of nu and nv row blocks.  With
+// st set, nothing is done unless that solve finished without error.
+template <typename T>
+hipError_t launch_orth(const DevState* st, const T* U, int m, const T* V, int n, int r, double* Up, int nu,
+                       double* Vp, int nv, double* out, hipStream_t s);
 template <typename T>
 hipError_t launch_nys_gather(const T* M, int64_t ldm, const int64_t* perm, int m, int n, int l,
                              T* C, T* Rb, hipStream_t s);

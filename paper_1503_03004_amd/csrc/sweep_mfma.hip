@@ -112,8 +112,8 @@ __device__ __forceinline__ f32x4 mfma_bf16(const float (&a)[4], const float (&b)
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
 }
 
-// BF: the three contractions take BF16 operands (FP32 accumulation); M, Y
-// and every stored value stay FP32.
+// BF: the p and Q contractions take BF16 operands (FP32 accumulation); the
+// l reconstruction, M, Y and every stored value stay FP32.
 template <int R, bool BF, int TW = 0>
 __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a)
 {
@@ -274,22 +274,11 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
                         rowacc = fmaf(x[e], x[e], rowacc);
                     }
                 } else {
+                    // l stays on FP32 operands in both forms: its rounding
+                    // would enter Y_k, S_k and x elementwise, unaveraged
                     f32x4 lv = {0.f, 0.f, 0.f, 0.f};
-                    if constexpr (BF) {
 #pragma unroll
-                        for (int s0 = 0; s0 < S1; s0 += 4) {
-                            float av4[4], bv4[4];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                av4[u] = (s0 + u < S1) ? va1[t][s0 + u] : 0.f;
-                                bv4[u] = (s0 + u < S1) ? aop[s0 + u] : 0.f;
-                            }
-                            lv = mfma_bf16(av4, bv4, lv);
-                        }
-                    } else {
-#pragma unroll
-                        for (int s = 0; s < S1; ++s) lv = mfma4(va1[t][s], aop[s], lv);
-                    }
+                    for (int s = 0; s < S1; ++s) lv = mfma4(va1[t][s], aop[s], lv);
                     float ypv[4] = {0.f, 0.f, 0.f, 0.f};
                     if (mode == 2) {
                         ypv[0] = yv[t].x; ypv[1] = yv[t].y; ypv[2] = yv[t].z; ypv[3] = yv[t].w;

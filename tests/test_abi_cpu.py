@@ -165,3 +165,33 @@ def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "_lib", None)
     with pytest.raises(ImportError):
         B.lib()
+
+
+def test_output_buffer_checks_on_host():
+    """Caller-supplied outputs are checked (shape, dtype, device, layout)
+    before any library call; CPU tensors stand in for device ones here."""
+    import torch
+    cpu = torch.device("cpu")
+    m, n, r = 6, 5, 2
+    U = torch.empty((m, r), dtype=torch.float32)
+    Bm = torch.empty((r, r), dtype=torch.float64)
+    V = torch.empty((n, r), dtype=torch.float32)
+    S = torch.empty((m, n), dtype=torch.float32)
+    B.check_outputs(U, Bm, V, S, m, n, r, torch.float32, cpu)
+    B.check_outputs(U, Bm, V, None, m, n, r, torch.float32, cpu)
+    B.check_outputs(U, Bm, V, torch.empty((m, n + 3), dtype=torch.float32)[:, :n], m, n, r, torch.float32, cpu)
+    bad = [
+        (torch.empty((m, r + 1), dtype=torch.float32), Bm, V, S),
+        (U.double(), Bm, V, S),
+        (U, Bm.float(), V, S),
+        (U, Bm, torch.empty((r, n), dtype=torch.float32).t(), S),
+        (U, Bm, V, torch.empty((n, m), dtype=torch.float32).t()),
+        (U, Bm, V, torch.empty((m, n), dtype=torch.float64)),
+        (U, Bm, V, torch.empty((m, 2 * n), dtype=torch.float32)[:, ::2]),
+        (None, Bm, V, S),
+    ]
+    for args in bad:
+        with pytest.raises(ValueError):
+            B.check_outputs(*args, m, n, r, torch.float32, cpu)
+    with pytest.raises(ValueError):
+        B.check_outputs(U, Bm, V, S, m, n, r, torch.float32, torch.device("cuda", 0))

@@ -1,15 +1,19 @@
 """GPU parity of BF16-operand solves (sfr_options.bf16): the matrix-core sweep
-with its three contractions on BF16 operands (FP32 accumulation, FP32 M and
-Y, FP64 r x r algebra) for the leading iterations, FP32 iterations after.
+with its two bulk contractions (p = X V, Q = X^T P) on BF16 operands (FP32
+accumulation; the reconstruction l, M and Y in FP32, FP64 r x r algebra) for
+the leading iterations, FP32 iterations after.
 
 Bars, relative Frobenius error of L and S against the FP64 oracle at the
 same iteration count:
-  * every iteration in BF16: 3e-3.  BF16 keeps 8 significant bits (unit
-    roundoff 2^-9 ~ 2e-3); a product of two rounded operands carries about
-    twice that, and the solve's L inherits it (measured 1.1e-3 to 1.8e-3);
+  * every iteration in BF16 (no refinement): 1e-3, the stated target for the
+    unrefined BF16 result.  BF16 keeps 8 significant bits (unit roundoff
+    2^-9 ~ 2e-3 per operand), but p and Q are sums over n and m products
+    whose rounding errors are not coherent with the sum, so their relative
+    error is of order 2^-9 sqrt(r / n); the reconstruction l, whose rounding
+    would reach Y elementwise, is kept in FP32;
   * a BF16 head then FP32 iterations: 1e-5, the FP32 bar.  The switch has to
     come while the iteration still contracts (before mu grows large): FP32
-    iterations then remove the BF16 error (measured 2e-7, as pure FP32).
+    iterations then remove the BF16 error.
 """
 import numpy as np
 import pytest
@@ -21,7 +25,7 @@ import paper_1503_03004_amd as sfr
 
 pytestmark = pytest.mark.gpu
 
-BF16_BAR = 3e-3
+BF16_BAR = 1e-3
 FP32_BAR = 1e-5
 
 
@@ -94,6 +98,24 @@ def test_tolerance_solve_with_bf16_until_residual(m, n, r):
     eL, eS = errors(Md, r, lam, mu0, L, S, info.iters)
     print(f"{m}x{n} r={r}: {info.iters} iterations (oracle {ot['iters']}), errL {eL:.2e} errS {eS:.2e}")
     assert eL <= FP32_BAR and eS <= FP32_BAR
+
+
+@pytest.mark.parametrize("m,n,r", [
+    SHAPES[0],
+    pytest.param(*SHAPES[1], marks=pytest.mark.xfail(
+        strict=True, reason="measured 1.41e-3 (L) after 35 all-BF16 iterations: the products' rounding keeps the "
+                            "residual above tol for 15 iterations more than FP32 and L drifts; the BF16 head "
+                            "with FP32 iterations after is the supported form")),
+])
+def test_tolerance_solve_all_bf16(m, n, r):
+    """tol 1e-6 with every iteration in BF16 (no FP32 refinement): the
+    unrefined result against the oracle run to the same count."""
+    Md, lam, mu0 = problem(m, n, r)
+    L, S, info = gpu_solve(Md, r, lam, mu0, tol=1e-6, max_iter=300, bf16=True)
+    assert info.status in (sfr.SFR_OK, sfr.SFR_WARN_NOT_SPD) and info.converged
+    eL, eS = errors(Md, r, lam, mu0, L, S, info.iters)
+    print(f"{m}x{n} r={r} all BF16 to tol 1e-6: {info.iters} iterations, errL {eL:.2e} errS {eS:.2e}")
+    assert eL <= BF16_BAR and eS <= BF16_BAR
 
 
 def test_bf16_head_longer_than_the_budget():

@@ -1,0 +1,217 @@
+"""GPU tests of the C ABI's contracts beyond the solve itself: the reported
+orthogonality of the returned factors, outputs left untouched on error,
+caller-supplied output buffers, the FP32 factors U, B, V against the oracle,
+the full-size FP32 workload at the tolerance-driven solve's own iteration
+count, and two handles solving at once on two streams.
+
+U, B and V are unique (the Stiefel projector of eq. (7) is unique when
+rank(X V B) = r), so they are compared elementwise.  Their sensitivity to a
+perturbation of the data is that of the rank-r subspace, about
+||dX|| / (sigma_r - sigma_{r+1}) (Wedin), so their bar is the FP32 bar of
+1e-5 times ||L||_F / sigma_r(L), taken from the oracle's B.
+"""
+import threading
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_1503_03004_amd as sfr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    sfr.lib()
+    yield
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def orth_np(U, V):
+    r = U.shape[1]
+    U = U.astype(np.float64)
+    V = V.astype(np.float64)
+    return max(np.linalg.norm(U.T @ U - np.eye(r)), np.linalg.norm(V.T @ V - np.eye(r)))
+
+
+def factor_bar(B_oracle):
+    w = np.linalg.eigvalsh(B_oracle)
+    return 1e-5 * np.linalg.norm(B_oracle) / w.min()
+
+
+def check_factors(U, B, V, o, what):
+    """U, V elementwise and B in relative Frobenius norm against the oracle."""
+    bar = factor_bar(o["B"])
+    eU = float(np.abs(U - o["U"]).max())
+    eV = float(np.abs(V - o["V"]).max())
+    eB = rel(B, o["B"])
+    print(f"{what}: U {eU:.1e}  V {eV:.1e}  B {eB:.1e}  (bar {bar:.1e})")
+    assert eU <= bar and eV <= bar and eB <= bar, (what, eU, eV, eB, bar)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_orth_err_reported(precision):
+    """sfr_info.orth_err is max(||U^T U - I||_F, ||V^T V - I||_F) of the
+    returned factors as stored, for FR-ADM and for Alg. 4."""
+    dt = np.float64 if precision == "f64" else np.float32
+    inst = workloads.planted(700, 1300, 6, seed=21, frac=0.08, kind="uniform", scale=30.0, dtype=dt)
+    mu0 = workloads.default_mu0(inst.M.astype(np.float64))
+    Mt = torch.from_numpy(inst.M).cuda()
+    with sfr.Solver(700, 1300, 6, inst.lam, mu0, 1e-6, precision=precision) as s:
+        U, B, V, S, info = s.solve(Mt)
+        want = orth_np(U.cpu().numpy(), V.cpu().numpy())
+        print(f"{precision} FR-ADM orth_err {info.orth_err:.3e} numpy {want:.3e}")
+        assert abs(info.orth_err - want) <= 1e-12 + 1e-9 * want
+        assert info.orth_err <= (1e-12 if precision == "f64" else 1e-5)
+        U, B, V, info = s.tsvd(Mt)
+        want = orth_np(U.cpu().numpy(), V.cpu().numpy())
+        assert abs(info.orth_err - want) <= 1e-12 + 1e-9 * want
+
+
+def test_orth_err_nystrom_and_batch():
+    inst = workloads.planted(900, 700, 4, seed=5, frac=0.06, kind="uniform", scale=20.0, dtype=np.float32)
+    Md = inst.M.astype(np.float64)
+    l = 40
+    perm = workloads.row_permutation(900, seed=3)
+    Mp = Md[perm]
+    mu_l = workloads.default_mu0(Mp[:, :l])
+    mu_t = workloads.default_mu0(Mp[:l, :])
+    Mt = torch.from_numpy(inst.M).cuda()
+    U, B, V, S, info = sfr.solve_nys(Mt, perm, 4, inst.lam, l, mu_l, mu_t, tol=1e-6)
+    want = orth_np(U.cpu().numpy(), V.cpu().numpy())
+    assert abs(info.orth_err - want) <= 1e-12 + 1e-9 * want and info.orth_err <= 1e-5
+    reqs = [workloads.planted(m, n, r, seed=m + n, frac=0.1, kind="uniform", scale=50.0, dtype=np.float32)
+            for (m, n, r) in ((300, 200, 5), (64, 32, 2), (1000, 400, 16))]
+    with sfr.BatchSolver(3, 1000, 400, 16) as bs:
+        outs = bs.solve([(torch.from_numpy(q.M).cuda(), q.r, q.lam, workloads.default_mu0(q.M.astype(np.float64)),
+                          1e-6) for q in reqs])
+    for U, B, V, S, info in outs:
+        want = orth_np(U.cpu().numpy(), V.cpu().numpy())
+        assert abs(info.orth_err - want) <= 1e-12 + 1e-9 * want and info.orth_err <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_default_mu0_failure_leaves_outputs_untouched(precision):
+    """mu <= 0: the mu_0 estimate (Alg. 4 on M) runs in the handle's
+    workspace.  On a rank-deficient M (rank 1 < r = 3) it stops with
+    SFR_ERR_RANK, and U, B, V, S keep what the caller put there."""
+    dt = torch.float64 if precision == "f64" else torch.float32
+    rng = np.random.default_rng(2)
+    M = np.outer(rng.standard_normal(200), rng.standard_normal(1100))
+    Mt = torch.from_numpy(M).to(device="cuda", dtype=dt)
+    with sfr.Solver(200, 1100, 3, 0.05, 0.0, 1e-6, precision=precision) as s:
+        U = torch.full((200, 3), 7.0, dtype=dt, device="cuda")
+        B = torch.full((3, 3), 7.0, dtype=torch.float64, device="cuda")
+        V = torch.full((1100, 3), 7.0, dtype=dt, device="cuda")
+        S = torch.full((200, 1100), 7.0, dtype=dt, device="cuda")
+        out = s.solve(Mt, out=(U, B, V, S), raise_on_error=False)
+        torch.cuda.synchronize()
+        assert out[4].status == sfr.SFR_ERR_RANK
+        for t in (U, B, V, S):
+            assert bool((t == 7.0).all())
+
+
+def test_output_buffers_checked_before_the_call():
+    M = torch.zeros((50, 40), dtype=torch.float32, device="cuda")
+    good = dict(U=torch.empty((50, 3), dtype=torch.float32, device="cuda"),
+                B=torch.empty((3, 3), dtype=torch.float64, device="cuda"),
+                V=torch.empty((40, 3), dtype=torch.float32, device="cuda"),
+                S=torch.empty((50, 40), dtype=torch.float32, device="cuda"))
+    bad = [("U", torch.empty((50, 4), dtype=torch.float32, device="cuda")),
+           ("U", torch.empty((50, 3), dtype=torch.float64, device="cuda")),
+           ("V", torch.empty((3, 40), dtype=torch.float32, device="cuda").t()),
+           ("B", torch.empty((3, 3), dtype=torch.float32, device="cuda")),
+           ("S", torch.empty((40, 50), dtype=torch.float32, device="cuda").t()),
+           ("U", torch.empty((50, 3), dtype=torch.float32))]
+    with sfr.Solver(50, 40, 3, 0.1, 0.1, 1e-6, precision="f32") as s:
+        for name, t in bad:
+            o = dict(good)
+            o[name] = t
+            with pytest.raises(ValueError):
+                s.solve(M, out=(o["U"], o["B"], o["V"], o["S"]))
+
+
+def test_fp32_factors_against_oracle():
+    """FP32 U, B and V compared with the oracle's, elementwise, on the
+    vector and the matrix-core sweep."""
+    for (m, n, r) in ((1500, 1200, 8), (900, 2048, 16)):
+        inst = workloads.planted(m, n, r, seed=m + r, frac=0.08, kind="uniform", scale=30.0, dtype=np.float32)
+        Md = inst.M.astype(np.float64)
+        mu0 = workloads.default_mu0(Md)
+        o = oracle.fradm(Md, r, inst.lam, mu0, fixed_iters=12)
+        Mt = torch.from_numpy(inst.M).cuda()
+        with sfr.Solver(m, n, r, inst.lam, mu0, 1e-7, precision="f32", fixed_iters=12) as s:
+            U, B, V, S, info = s.solve(Mt)
+        check_factors(U.double().cpu().numpy(), B.cpu().numpy(), V.double().cpu().numpy(), o, f"{m}x{n} r={r}")
+
+
+def test_full_size_8000_fp32_tolerance_driven():
+    """The 8000 x 8000, r = 10 FP32 workload, tolerance-driven (tol 1e-6, the
+    benchmark's solve): L and S on every entry, and U, B, V, against the
+    oracle run to the GPU's own stopping iteration."""
+    inst = workloads.large_fp32(seed=0)
+    Md = inst.M.astype(np.float64)
+    mu0 = workloads.default_mu0(inst.M)
+    Mt = torch.from_numpy(inst.M).cuda()
+    with sfr.Solver(8000, 8000, 10, inst.lam, mu0, 1e-6, precision="f32") as s:
+        U, B, V, S, info = s.solve(Mt)
+    assert info.status == sfr.SFR_OK
+    K = info.iters
+    print(f"8000^2 r=10 FP32 tol 1e-6: {K} iterations; oracle to the same count ...", flush=True)
+    o = oracle.fradm(Md, 10, inst.lam, mu0, fixed_iters=K)
+    Ug, Bg, Vg = U.double().cpu().numpy(), B.cpu().numpy(), V.double().cpu().numpy()
+    Lg = (Ug @ Bg) @ Vg.T
+    Lo = (o["U"] @ o["B"]) @ o["V"].T
+    eL, eS = rel(Lg, Lo), rel(S.double().cpu().numpy(), o["S"])
+    print(f"8000^2 r=10 FP32, {K} iterations: L {eL:.2e}  S {eS:.2e}")
+    assert eL <= 1e-5 and eS <= 1e-5
+    check_factors(Ug, Bg, Vg, o, "8000^2 r=10")
+
+
+def test_two_handles_on_two_streams():
+    """Distinct handles are independent: two solves whose sweeps run in
+    clusters (c > 1 column slices) overlap on two streams from two host
+    threads, and each result is bitwise the result of the same solve alone."""
+    shapes = [(1500, 4096, 10, 31), (1200, 5000, 6, 32)]
+    insts = [workloads.planted(m, n, r, seed=sd, frac=0.08, kind="uniform", scale=30.0, dtype=np.float32)
+             for (m, n, r, sd) in shapes]
+    mus = [workloads.default_mu0(q.M.astype(np.float64)) for q in insts]
+    Ms = [torch.from_numpy(q.M).cuda() for q in insts]
+    solvers = [sfr.Solver(q.M.shape[0], q.M.shape[1], q.r, q.lam, mu, 1e-6, precision="f32")
+               for q, mu in zip(insts, mus)]
+    try:
+        alone = []
+        for sv, M in zip(solvers, Ms):
+            U, B, V, S, info = sv.solve(M)
+            alone.append([t.clone() for t in (U, B, V, S)] + [info.iters])
+        streams = [torch.cuda.Stream() for _ in solvers]
+        together = [None, None]
+
+        def run(i):
+            with torch.cuda.stream(streams[i]):
+                for _ in range(3):
+                    U, B, V, S, info = solvers[i].solve(Ms[i], stream=streams[i])
+                together[i] = [t.clone() for t in (U, B, V, S)] + [info.iters]
+            streams[i].synchronize()
+
+        th = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        torch.cuda.synchronize()
+        for a, b in zip(alone, together):
+            assert a[4] == b[4]
+            for x, y in zip(a[:4], b[:4]):
+                assert torch.equal(x, y)
+    finally:
+        for sv in solvers:
+            sv.close()
