@@ -44,6 +44,8 @@ typedef enum {
     SFR_ERR_RANK = -4,       /* rank(X V B) < r: P_O of eq. (7) is not unique */
     SFR_ERR_NONFINITE = -5,  /* NaN/Inf in M or in the iteration */
     SFR_ERR_HANDLE = -6,     /* NULL or wrong-kind handle */
+    SFR_ERR_SCRATCH = -7,    /* sfr_solve_noalloc: the problem needs more device workspace than
+                                its static scratch holds */
     SFR_WARN_MAXITER = 1,    /* max_iter reached before the tolerance */
     SFR_WARN_NOT_SPD = 2     /* returned B has a non-positive eigenvalue (eq. (8) is
                                 not guaranteed SPD away from the optimum, Appendix) */
@@ -259,6 +261,35 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
  */
 sfr_status sfr_tune_batch(sfr_handle h, const sfr_batch_item* items, int32_t count, int32_t* table,
                           void* hip_stream);
+
+/*
+ * FR-ADM without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, hosts that forbid
+ * hipMalloc.  The same solve as sfr_create(m, n, r, lambda, mu, tol, opt)
+ * followed by sfr_solve(h, M, ldm, U, B, V, S, lds, info, hip_stream) and
+ * sfr_destroy(h), with the same arguments, results and statuses, and the same
+ * kernels.
+ *   Workspace: a static device array of 128 MiB per device (held by each
+ *     device the library runs on until the process ends) instead of a
+ *     handle's allocations.  It holds the two m x n dual buffers Y and the
+ *     factor, partial-sum and exchange buffers (and a padded copy of M when
+ *     M is not 16-byte aligned with ldm a multiple of 4 (FP32) or 2 (FP64),
+ *     or n is not): FP32 problems up to about 3000 x 3000 fit (less at
+ *     larger r).  A problem that needs more returns SFR_ERR_SCRATCH before
+ *     any device work.  No hipMalloc, hipFree, pinned host memory or HIP
+ *     event is used; progress is read by synchronising hip_stream.
+ *   Options: as for sfr_create, except that nystrom_l and profile must be 0
+ *     (SFR_ERR_ARG otherwise).
+ *   Concurrency: every call on one device uses that device's one scratch
+ *     array and host-side state, which keep the last call's contents (the
+ *     call initialises everything it reads); calls that overlap on one
+ *     device race and must not be made.
+ * Errors: those of sfr_create and sfr_solve (outputs left untouched), and
+ * SFR_ERR_SCRATCH.
+ */
+sfr_status sfr_solve_noalloc(int64_t m, int64_t n, int32_t r, double lambda, double mu, double tol,
+                             const sfr_options* opt, const void* M, int64_t ldm, void* U, double* B, void* V,
+                             void* S, int64_t lds, sfr_info* info, void* hip_stream);
 
 /* Release the handle and its workspace.  NULL is accepted. */
 sfr_status sfr_destroy(sfr_handle h);

@@ -20,6 +20,7 @@ SFR_ERR_DEVICE = -3
 SFR_ERR_RANK = -4
 SFR_ERR_NONFINITE = -5
 SFR_ERR_HANDLE = -6
+SFR_ERR_SCRATCH = -7
 SFR_WARN_MAXITER = 1
 SFR_WARN_NOT_SPD = 2
 
@@ -117,6 +118,9 @@ def lib():
         L.sfr_solve_batch.restype = ctypes.c_int
         L.sfr_tune_batch.argtypes = [vp, ctypes.POINTER(sfr_batch_item), i32, ctypes.POINTER(ctypes.c_int32), vp]
         L.sfr_tune_batch.restype = ctypes.c_int
+        L.sfr_solve_noalloc.argtypes = [i64, i64, i32, d, d, d, ctypes.POINTER(sfr_options), vp, i64, vp, vp,
+                                         vp, vp, i64, ctypes.POINTER(sfr_info), vp]
+        L.sfr_solve_noalloc.restype = ctypes.c_int
         L.sfr_destroy.argtypes = [vp]
         L.sfr_destroy.restype = ctypes.c_int
         L.sfr_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
@@ -430,6 +434,45 @@ def _info(rc, info):
                 rel_residual=info.rel_residual, min_eig_B=info.min_eig_B, mu_final=info.mu_final,
                 sweep_ms=info.sweep_ms, sweeps_timed=info.sweeps_timed, mu0=info.mu0,
                 orth_err=info.orth_err)
+
+
+def _options(precision, rho=1.5, mu_bar=1e9, max_iter=300, fixed_iters=0, nystrom_l=0, mu_left=0.0, mu_top=0.0,
+             profile=False, bf16=False, bf16_iters=0, bf16_tol=0.0):
+    o = sfr_options()
+    o.struct_size = ctypes.sizeof(sfr_options)
+    o.precision = SFR_F64 if precision == "f64" else SFR_F32
+    o.rho, o.mu_bar = float(rho), float(mu_bar)
+    o.max_iter, o.fixed_iters = int(max_iter), int(fixed_iters)
+    o.nystrom_l = int(nystrom_l)
+    o.profile = 1 if profile else 0
+    o.mu_left, o.mu_top = float(mu_left), float(mu_top)
+    o.bf16, o.bf16_iters, o.bf16_tol = (1 if bf16 else 0), int(bf16_iters), float(bf16_tol)
+    return o
+
+
+def solve_noalloc(M, r, lam, mu, tol, out, *, stream=None, raise_on_error=True, **opts):
+    """sfr_solve_noalloc: FR-ADM with the library's static device scratch
+    (no device allocation by the library).  out = (U, B, V, S or None): the
+    caller's output tensors, checked as for Solver.solve.  Returns Info."""
+    import torch
+    if not (isinstance(M, torch.Tensor) and M.is_cuda and M.dim() == 2 and M.stride(1) == 1):
+        raise TypeError("M must be a row-major 2-D CUDA (HIP) tensor")
+    precision = "f64" if M.dtype == torch.float64 else "f32"
+    if M.dtype not in (torch.float64, torch.float32):
+        raise ValueError("M must be float64 or float32")
+    m, n = M.shape
+    U, B, V, S = out
+    check_outputs(U, B, V, S, m, n, int(r), M.dtype, M.device)
+    o = _options(precision, **opts)
+    info = sfr_info()
+    rc = lib().sfr_solve_noalloc(m, n, int(r), float(lam), float(mu), float(tol), ctypes.byref(o),
+                                 ctypes.c_void_p(M.data_ptr()), M.stride(0), ctypes.c_void_p(U.data_ptr()),
+                                 ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(V.data_ptr()),
+                                 ctypes.c_void_p(S.data_ptr()) if S is not None else None,
+                                 S.stride(0) if S is not None else 0, ctypes.byref(info), _stream_handle(stream))
+    if rc < 0 and raise_on_error:
+        raise SFRError(rc, "sfr_solve_noalloc")
+    return _info(rc, info)
 
 
 def solve(M, r, lam, mu, tol=1e-7, **opts):

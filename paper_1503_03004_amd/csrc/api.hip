@@ -174,7 +174,7 @@ static sfr_status configure(Engine& e)
     return SFR_OK;
 }
 
-sfr_status engine_create(Engine& e, int m, int n, int r, bool f64, int hist_len)
+sfr_status engine_plan(Engine& e, int m, int n, int r, bool f64, int hist_len)
 {
     e.m = m; e.n = n; e.r = r; e.f64 = f64;
     e.esz = f64 ? 8 : 4;
@@ -186,22 +186,17 @@ sfr_status engine_create(Engine& e, int m, int n, int r, bool f64, int hist_len)
     sfr_status cs = configure(e);
     if (cs != SFR_OK) return cs;
     e.ldy = e.ne;
-    const size_t mn = (size_t)e.m * (size_t)e.ldy;
-    bool ok = true;
-    for (int b = 0; b < 2 && ok; ++b) ok = dev_alloc(e.allocs, e.bytes, &e.Y[b], mn * e.esz);
-    for (int b = 0; b < 2 && ok; ++b) ok = dev_alloc(e.allocs, e.bytes, &e.P[b], (size_t)e.m * e.R * e.esz);
-    for (int b = 0; b < 2 && ok; ++b) ok = dev_alloc(e.allocs, e.bytes, &e.Q[b], (size_t)e.ne * e.R * e.esz);
-    if (ok) ok = dev_alloc(e.allocs, e.bytes, &e.Qpart, (size_t)e.max_ncl * e.ne * e.R * e.esz);
-    if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.dy2part, sizeof(double) * (size_t)e.max_grid);
-    if (ok && e.exch_words) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.exch, 8 * e.exch_words);
-    if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.GQpart, sizeof(double) * (size_t)e.nqb * e.E);
-    if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.GPpart, sizeof(double) * (size_t)e.npb * e.E);
-    if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.st, sizeof(DevState));
-    if (ok) ok = dev_alloc(e.allocs, e.bytes, (void**)&e.res_hist, sizeof(double) * (size_t)(hist_len + 2));
-    if (ok && e.ne != e.n) {
-        e.ldmpad = e.ne;
-        ok = dev_alloc(e.allocs, e.bytes, &e.Mpad, (size_t)e.m * e.ldmpad * e.esz);
-    }
+    return SFR_OK;
+}
+
+sfr_status engine_create(Engine& e, int m, int n, int r, bool f64, int hist_len)
+{
+    sfr_status ps = engine_plan(e, m, n, r, f64, hist_len);
+    if (ps != SFR_OK) return ps;
+    bool ok = engine_buffers(e, e.ne != e.n, [&](size_t sz) -> void* {
+        void* p = nullptr;
+        return dev_alloc(e.allocs, e.bytes, &p, sz) ? p : nullptr;
+    });
     if (ok && hipHostMalloc((void**)&e.host_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
         e.host_state = nullptr;
         ok = false;
@@ -392,7 +387,7 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
             if (!fixed_rule) {
                 const int slot = launched_batches & 1;
                 HIPCHK(hipMemcpyAsync(&e.host_poll[slot], e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipEventRecord(e.poll_ev[slot], s));
+                if (e.poll_ev[slot]) HIPCHK(hipEventRecord(e.poll_ev[slot], s));
             }
             ++launched_batches;
             return SFR_OK;
@@ -414,7 +409,10 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
                 if (es != SFR_OK) return es;
             }
             const int slot = checked_batches & 1;
-            HIPCHK(hipEventSynchronize(e.poll_ev[slot]));
+            // without poll events (an engine that owns no host objects) the
+            // whole stream is waited for, which covers this batch's snapshot
+            if (e.poll_ev[slot]) HIPCHK(hipEventSynchronize(e.poll_ev[slot]));
+            else HIPCHK(hipStreamSynchronize(s));
             const DevState& ph = e.host_poll[slot];
             ++checked_batches;
             if (ph.done || ph.exch_timeout) {
@@ -526,10 +524,9 @@ static sfr_status fill_info(const Engine& e, sfr_info* info, sfr_status st)
 // a change of B of 1e-6 relative, at most 60 steps).  The estimate lives in
 // the handle's workspace and state only; no caller buffer is written.
 template <typename T>
-static sfr_status estimate_mu0(sfr_ctx* h, const T* M, int64_t ldm, hipStream_t s, double* mu0)
+static sfr_status estimate_mu0(Engine& e, const Params& prm, const T* M, int64_t ldm, hipStream_t s, double* mu0)
 {
-    Engine& e = h->main;
-    Params p = h->prm;
+    Params p = prm;
     p.tol = 1e-6;
     p.fixed_iters = 0;
     p.max_iter = 60;
@@ -550,32 +547,42 @@ static sfr_status estimate_mu0(sfr_ctx* h, const T* M, int64_t ldm, hipStream_t 
     return SFR_OK;
 }
 
-extern "C" {
+namespace sfr {
 
-const char* sfr_version(void) { return "0.1.0"; }
-
-const char* sfr_status_string(sfr_status s)
+sfr_status engine_solve(Engine& e, const Params& prm, bool mu_auto, const void* M, int64_t ldm, void* U, double* B,
+                        void* V, void* S, int64_t lds, sfr_info* info, hipStream_t s)
 {
-    switch (s) {
-    case SFR_OK: return "ok";
-    case SFR_ERR_ARG: return "invalid argument";
-    case SFR_ERR_NOMEM: return "device workspace allocation failed";
-    case SFR_ERR_DEVICE: return "HIP runtime error or device wait bound reached";
-    case SFR_ERR_RANK: return "rank(X V B) < r: Stiefel projector not unique";
-    case SFR_ERR_NONFINITE: return "non-finite value in M or in the iteration";
-    case SFR_ERR_HANDLE: return "invalid handle for this call";
-    case SFR_WARN_MAXITER: return "max_iter reached before the tolerance";
-    case SFR_WARN_NOT_SPD: return "returned B is not positive definite";
+    sfr_status st = SFR_OK;
+    double mu0 = prm.mu0;
+    if (e.f64) {
+        OutputSpec<double> o;
+        o.U = static_cast<double*>(U); o.B = B; o.V = static_cast<double*>(V);
+        o.M = static_cast<const double*>(M); o.ldm = ldm; o.S = static_cast<double*>(S); o.lds = lds;
+        o.min_eig = true;
+        if (mu_auto) st = estimate_mu0<double>(e, prm, o.M, ldm, s, &mu0);
+        if (st == SFR_OK) st = engine_iterate<double>(e, prm, mu0, static_cast<const double*>(M), ldm, o, s);
+    } else {
+        OutputSpec<float> o;
+        o.U = static_cast<float*>(U); o.B = B; o.V = static_cast<float*>(V);
+        o.M = static_cast<const float*>(M); o.ldm = ldm; o.S = static_cast<float*>(S); o.lds = lds;
+        o.min_eig = true;
+        if (mu_auto) st = estimate_mu0<float>(e, prm, o.M, ldm, s, &mu0);
+        if (st == SFR_OK) st = engine_iterate<float>(e, prm, mu0, static_cast<const float*>(M), ldm, o, s);
     }
-    return "unknown status";
+    if (st < 0) {
+        if (info) memset(info, 0, sizeof(*info));
+        return st;
+    }
+    st = fill_info(e, info, st);
+    if (info) info->mu0 = mu0;
+    return st;
 }
 
-sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double lambda, double mu, double tol,
-                      const sfr_options* opt)
+// Host-side validation of sfr_create's arguments; `o` receives the options
+// with their defaults filled in.
+sfr_status validate_create(int64_t m, int64_t n, int32_t r, double lambda, double mu, double tol,
+                           const sfr_options* opt, sfr_options& o)
 {
-    if (!out) return SFR_ERR_ARG;
-    *out = nullptr;
-    sfr_options o;
     memset(&o, 0, sizeof(o));
     if (opt) {
         if (opt->struct_size != sizeof(sfr_options)) return SFR_ERR_ARG;
@@ -593,28 +600,67 @@ sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double l
     if (o.max_iter == 0) o.max_iter = 300;
     if (!(o.rho > 1.0) || !(o.mu_bar > 0.0) || o.rho > 1e300 || o.mu_bar > 1e300) return SFR_ERR_ARG;
     if (o.max_iter < 1 || o.max_iter > 100000 || o.fixed_iters < 0 || o.fixed_iters > 100000) return SFR_ERR_ARG;
-    const bool nys = o.nystrom_l > 0;
     if (o.nystrom_l < 0) return SFR_ERR_ARG;
-    if (nys) {
+    if (o.nystrom_l > 0) {
         if (o.nystrom_l < r || o.nystrom_l > m || o.nystrom_l > n) return SFR_ERR_ARG;
         if (!(o.mu_left > 0.0) || !(o.mu_top > 0.0) || o.mu_left > 1e300 || o.mu_top > 1e300) return SFR_ERR_ARG;
     } else {
         if (!std::isfinite(mu) || mu > 1e300) return SFR_ERR_ARG;
     }
+    return SFR_OK;
+}
+
+void params_from(const sfr_options& o, double lambda, double mu, double tol, Params& p)
+{
+    p.lambda = lambda; p.mu0 = mu; p.tol = tol;
+    p.rho = o.rho; p.mu_bar = o.mu_bar;
+    p.max_iter = o.max_iter; p.fixed_iters = o.fixed_iters;
+    p.profile = o.profile != 0;
+    p.bf16 = o.bf16 != 0;
+    p.bf16_iters = o.bf16_iters;
+    p.bf16_tol = o.bf16_tol;
+}
+
+}  // namespace sfr
+
+extern "C" {
+
+const char* sfr_version(void) { return "0.1.0"; }
+
+const char* sfr_status_string(sfr_status s)
+{
+    switch (s) {
+    case SFR_OK: return "ok";
+    case SFR_ERR_ARG: return "invalid argument";
+    case SFR_ERR_NOMEM: return "device workspace allocation failed";
+    case SFR_ERR_DEVICE: return "HIP runtime error or device wait bound reached";
+    case SFR_ERR_RANK: return "rank(X V B) < r: Stiefel projector not unique";
+    case SFR_ERR_NONFINITE: return "non-finite value in M or in the iteration";
+    case SFR_ERR_HANDLE: return "invalid handle for this call";
+    case SFR_ERR_SCRATCH: return "problem needs more device workspace than the static scratch holds";
+    case SFR_WARN_MAXITER: return "max_iter reached before the tolerance";
+    case SFR_WARN_NOT_SPD: return "returned B is not positive definite";
+    }
+    return "unknown status";
+}
+
+sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double lambda, double mu, double tol,
+                      const sfr_options* opt)
+{
+    if (!out) return SFR_ERR_ARG;
+    *out = nullptr;
+    sfr_options o;
+    const sfr_status vs = validate_create(m, n, r, lambda, mu, tol, opt, o);
+    if (vs != SFR_OK) return vs;
+    const bool nys = o.nystrom_l > 0;
     sfr_ctx* h = new (std::nothrow) sfr_ctx();
     if (!h) return SFR_ERR_NOMEM;
     h->m = m; h->n = n; h->r = r;
     h->f64 = (o.precision == SFR_F64);
     h->nys = nys;
     h->l = o.nystrom_l;
-    h->prm.lambda = lambda; h->prm.mu0 = mu; h->prm.tol = tol;
+    params_from(o, lambda, mu, tol, h->prm);
     h->mu_auto = !nys && !(mu > 0.0);
-    h->prm.rho = o.rho; h->prm.mu_bar = o.mu_bar;
-    h->prm.max_iter = o.max_iter; h->prm.fixed_iters = o.fixed_iters;
-    h->prm.profile = o.profile != 0;
-    h->prm.bf16 = o.bf16 != 0;
-    h->prm.bf16_iters = o.bf16_iters;
-    h->prm.bf16_tol = o.bf16_tol;
     h->mu_left = o.mu_left; h->mu_top = o.mu_top;
     const int hist = std::max(o.max_iter, o.fixed_iters);
     sfr_status st;
@@ -672,32 +718,8 @@ sfr_status sfr_solve(sfr_handle h, const void* M, int64_t ldm, void* U, double* 
     if (!h || h->magic != 0x53465221u || h->nys || h->batch) return SFR_ERR_HANDLE;
     if (!M || !U || !B || !V) return SFR_ERR_ARG;
     if (ldm < h->n || (S && lds < h->n)) return SFR_ERR_ARG;
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    Engine& e = h->main;
-    sfr_status st = SFR_OK;
-    double mu0 = h->prm.mu0;
-    if (h->f64) {
-        OutputSpec<double> o;
-        o.U = static_cast<double*>(U); o.B = B; o.V = static_cast<double*>(V);
-        o.M = static_cast<const double*>(M); o.ldm = ldm; o.S = static_cast<double*>(S); o.lds = lds;
-        o.min_eig = true;
-        if (h->mu_auto) st = estimate_mu0<double>(h, o.M, ldm, s, &mu0);
-        if (st == SFR_OK) st = engine_iterate<double>(e, h->prm, mu0, static_cast<const double*>(M), ldm, o, s);
-    } else {
-        OutputSpec<float> o;
-        o.U = static_cast<float*>(U); o.B = B; o.V = static_cast<float*>(V);
-        o.M = static_cast<const float*>(M); o.ldm = ldm; o.S = static_cast<float*>(S); o.lds = lds;
-        o.min_eig = true;
-        if (h->mu_auto) st = estimate_mu0<float>(h, o.M, ldm, s, &mu0);
-        if (st == SFR_OK) st = engine_iterate<float>(e, h->prm, mu0, static_cast<const float*>(M), ldm, o, s);
-    }
-    if (st < 0) {
-        if (info) memset(info, 0, sizeof(*info));
-        return st;
-    }
-    st = fill_info(e, info, st);
-    if (info) info->mu0 = mu0;
-    return st;
+    return engine_solve(h->main, h->prm, h->mu_auto, M, ldm, U, B, V, S, lds, info,
+                        static_cast<hipStream_t>(hip_stream));
 }
 
 sfr_status sfr_tsvd(sfr_handle h, const void* M, int64_t ldm, void* U, double* B, void* V, sfr_info* info,

@@ -4,6 +4,7 @@
 #include "sfr_internal.hpp"
 #include "sfr.h"
 
+#include <algorithm>
 #include <vector>
 
 namespace sfr {
@@ -124,7 +125,48 @@ struct sfr_ctx {
 
 
 namespace sfr {
+// Shape of an engine (sizes, rank bucket, launch configurations); no
+// device memory is touched.
+sfr_status engine_plan(Engine& e, int m, int n, int r, bool f64, int hist_len);
+// engine_plan, then the device workspace (hipMalloc) and the pinned host
+// mirrors and poll events.
 sfr_status engine_create(Engine& e, int m, int n, int r, bool f64, int hist_len);
+
+// Assign the planned engine's device buffers in a fixed order, each from
+// get(bytes) (nullptr: failure).  pad: also a padded copy of M (m x ne).
+template <typename Get>
+bool engine_buffers(Engine& e, bool pad, Get&& get)
+{
+    const size_t mn = (size_t)e.m * (size_t)e.ldy;
+    for (int b = 0; b < 2; ++b)
+        if (!(e.Y[b] = get(mn * e.esz))) return false;
+    for (int b = 0; b < 2; ++b)
+        if (!(e.P[b] = get((size_t)e.m * e.R * e.esz))) return false;
+    for (int b = 0; b < 2; ++b)
+        if (!(e.Q[b] = get((size_t)e.ne * e.R * e.esz))) return false;
+    if (!(e.Qpart = get((size_t)e.max_ncl * e.ne * e.R * e.esz))) return false;
+    if (!(e.dy2part = static_cast<double*>(get(sizeof(double) * (size_t)e.max_grid)))) return false;
+    if (e.exch_words && !(e.exch = static_cast<unsigned long long*>(get(8 * e.exch_words)))) return false;
+    if (!(e.GQpart = static_cast<double*>(get(sizeof(double) * (size_t)e.nqb * e.E)))) return false;
+    if (!(e.GPpart = static_cast<double*>(get(sizeof(double) * (size_t)e.npb * e.E)))) return false;
+    if (!(e.st = static_cast<DevState*>(get(sizeof(DevState))))) return false;
+    if (!(e.res_hist = static_cast<double*>(get(sizeof(double) * (size_t)(e.hist_len + 2))))) return false;
+    if (pad) {
+        e.ldmpad = e.ne;
+        if (!(e.Mpad = get((size_t)e.m * e.ldmpad * e.esz))) return false;
+    }
+    return true;
+}
+
+// sfr_create's host-side argument checks; o receives the options with the
+// defaults filled in.
+sfr_status validate_create(int64_t m, int64_t n, int32_t r, double lambda, double mu, double tol,
+                           const sfr_options* opt, sfr_options& o);
+void params_from(const sfr_options& o, double lambda, double mu, double tol, Params& p);
+// FR-ADM on an engine (sfr_solve): the mu_0 estimate if mu_auto, the
+// iteration, the outputs and the report.
+sfr_status engine_solve(Engine& e, const Params& prm, bool mu_auto, const void* M, int64_t ldm, void* U, double* B,
+                        void* V, void* S, int64_t lds, sfr_info* info, hipStream_t s);
 void engine_destroy(Engine& e);
 bool dev_alloc(std::vector<void*>& list, size_t& bytes, void** p, size_t sz);
 void free_all(std::vector<void*>& list);

@@ -44,7 +44,7 @@ constexpr int kMaxGramPartials = 256;
 // Status codes mirrored from the public header (kept numerically equal).
 enum : int32_t {
     kOK = 0, kErrArg = -1, kErrNoMem = -2, kErrDevice = -3, kErrRank = -4,
-    kErrNonFinite = -5, kErrHandle = -6,
+    kErrNonFinite = -5, kErrHandle = -6, kErrScratch = -7,
     kWarnMaxIter = 1, kWarnNotSPD = 2
 };
 

@@ -22,7 +22,8 @@ def declared():
 def test_header_declares_the_entry_points():
     names = declared()
     for want in ("sfr_create", "sfr_solve", "sfr_solve_nys", "sfr_tsvd", "sfr_create_batch", "sfr_solve_batch",
-                 "sfr_tune_batch", "sfr_destroy", "sfr_status_string", "sfr_version", "sfr_workspace_bytes"):
+                 "sfr_tune_batch", "sfr_destroy", "sfr_status_string", "sfr_version", "sfr_workspace_bytes",
+                 "sfr_solve_noalloc"):
         assert want in names
 
 
@@ -60,7 +61,7 @@ def test_struct_layouts_match_header(tmp_path):
 def test_status_strings_and_version():
     L = sfr.lib()
     assert L.sfr_version().decode().count(".") == 2
-    for code in (0, -1, -2, -3, -4, -5, -6, 1, 2):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, 1, 2):
         s = L.sfr_status_string(code).decode()
         assert s and s != "unknown status"
     assert L.sfr_status_string(99).decode() == "unknown status"
@@ -195,3 +196,33 @@ def test_output_buffer_checks_on_host():
             B.check_outputs(*args, m, n, r, torch.float32, cpu)
     with pytest.raises(ValueError):
         B.check_outputs(U, Bm, V, S, m, n, r, torch.float32, torch.device("cuda", 0))
+
+
+def test_noalloc_rejects_invalid_arguments_on_host():
+    """sfr_solve_noalloc validates on the host before any device call: the
+    checks of sfr_create, NULL buffers, ld < n, and the options it does not
+    take (FR-Nys, profiling)."""
+    L = sfr.lib()
+    info = B.sfr_info()
+    dummy = ctypes.c_void_p(16)
+
+    def call(m=100, n=80, r=3, lam=0.1, mu=0.5, tol=1e-7, opt=None, M=dummy, ldm=80, U=dummy, Bp=dummy, V=dummy,
+             S=None, lds=0):
+        o = ctypes.byref(opt) if opt is not None else None
+        return L.sfr_solve_noalloc(m, n, r, lam, mu, tol, o, M, ldm, U, Bp, V, S, lds, ctypes.byref(info), None)
+
+    assert call(m=0) == B.SFR_ERR_ARG
+    assert call(r=81) == B.SFR_ERR_ARG
+    assert call(lam=0.0) == B.SFR_ERR_ARG
+    assert call(mu=float("nan")) == B.SFR_ERR_ARG
+    assert call(M=None) == B.SFR_ERR_ARG
+    assert call(V=None) == B.SFR_ERR_ARG
+    assert call(ldm=79) == B.SFR_ERR_ARG
+    assert call(S=dummy, lds=10) == B.SFR_ERR_ARG
+    o = B._options("f32", nystrom_l=10, mu_left=1.0, mu_top=1.0)
+    assert call(opt=o) == B.SFR_ERR_ARG
+    o = B._options("f32", profile=True)
+    assert call(opt=o) == B.SFR_ERR_ARG
+    o = B._options("f32")
+    o.struct_size = 3
+    assert call(opt=o) == B.SFR_ERR_ARG
