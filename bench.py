@@ -98,6 +98,60 @@ def measured_traffic(workload: str):
     return d.get("bytes_per_launch")
 
 
+def _oracle_worker(seed, iters, barrier, queue):
+    """One oracle process of the all-cores leg: draws the 8000^2 input itself,
+    waits for the others, then times `iters` FR-ADM iterations (one thread)."""
+    import oracle
+    import workloads
+    inst = workloads.large_fp32(seed=seed)
+    Md = inst.M.astype(np.float64)
+    mu0 = workloads.default_mu0(inst.M)
+    barrier.wait()
+    t = time.perf_counter()
+    oracle.fradm(Md, inst.r, inst.lam, mu0, fixed_iters=iters)
+    queue.put(time.perf_counter() - t)
+
+
+def oracle_all_cores(seed: int, iters: int, procs: int) -> dict:
+    """The oracle as it stands, on every core of the host share at once: one
+    single-threaded process per core, each running `iters` iterations of the
+    same 8000^2 r = 10 workload, started together.  Aggregate throughput =
+    procs * iters / (slowest process's time)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        barrier = ctx.Barrier(procs)
+        queue = ctx.Queue()
+        ps = [ctx.Process(target=_oracle_worker, args=(seed, iters, barrier, queue)) for _ in range(procs)]
+        for p in ps:
+            p.start()
+        import queue as queue_mod
+        times = []
+        while len(times) < procs:
+            try:
+                times.append(queue.get(timeout=2))
+            except queue_mod.Empty:
+                if any(p.exitcode not in (None, 0) for p in ps):
+                    for p in ps:
+                        p.kill()
+                    raise RuntimeError("an oracle process of the all-cores leg failed")
+        for p in ps:
+            p.join()
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    slowest = max(times)
+    return {"value": procs * iters / slowest, "unit": "iters/s", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} concurrent single-threaded oracle processes, {iters} FR-ADM iterations each of the "
+                      f"same 8000x8000 r=10 input, FP64; aggregate over the slowest ({slowest:.1f} s)"}
+
+
 def rel(a, b):
     nb = float(np.linalg.norm(b))
     return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
@@ -119,6 +173,10 @@ def main():
     ap.add_argument("--nys-l", type=int, default=80, help="nystrom: sampled rows and columns l (default 4r = 80)")
     ap.add_argument("--solves", type=int, default=5, help="tolerance-driven solves timed for solves/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-config4", action="store_true",
+                    help="large_fp32: skip the 40000^2 FR-Nys / full FR-ADM figures in the default line")
+    ap.add_argument("--all-cores-iters", type=int, default=2,
+                    help="large_fp32: oracle iterations per process in the all-cores CPU leg (0: skip)")
     ap.add_argument("--oracle-iters", type=int, default=12, help="oracle iterations timed on the host (about 1 s each)")
     ap.add_argument("--rank", type=int, default=0, help="large_fp32 / tsvd_fp32: rank r (default 10)")
     ap.add_argument("--bf16-iters", type=int, default=0,
@@ -330,6 +388,18 @@ def main():
                          ("Table 1, FR-ADM 8000^2 r=10 (outliers in [-1,1]): 28 iterations in 27.42 s "
                           "(~1.0 it/s) on a 3.2 GHz desktop CPU; not the same workload"),
     }
+    default_line = args.workload == "large_fp32" and default_cfg
+    if default_line and not args.no_cpu_baseline and args.all_cores_iters > 0:
+        procs = max(1, min(16, os.cpu_count() or 1))
+        out["cpu_baseline_all_cores"] = oracle_all_cores(args.seed, args.all_cores_iters, procs)
+        print(f"[bench] oracle on {procs} cores: {out['cpu_baseline_all_cores']['value']:.2f} iters/s",
+              file=sys.stderr, flush=True)
+    if default_line and not args.no_config4:
+        torch.cuda.empty_cache()
+        c4 = nystrom_measure(args, l=80)
+        out["config4_nystrom"] = {k: c4[k] for k in ("config", "value", "unit", "ms_per_step", "nys_iters",
+                                                     "nys_rel_err_vs_L0", "full_fradm", "parity_vs_oracle",
+                                                     "cpu_baseline", "roofline")}
     print(json.dumps(out), flush=True)
 
 
@@ -337,6 +407,10 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X, published (packed FP32)
 
 
 def nystrom(args):
+    print(json.dumps(nystrom_measure(args, l=args.nys_l)), flush=True)
+
+
+def nystrom_measure(args, l):
     """FR-Nys workload (Alg. 3): m = n = 40000, r = 20, l = 4r = 80 sampled
     rows and columns, FP32, L0 = A B^T with N(0,1) factors and 7 % Laplace(0,
     20) outliers, drawn on the device.  value = FR-Nys solves/s (tol 1e-6 on
@@ -351,7 +425,7 @@ def nystrom(args):
     import paper_1503_03004_amd as sfr
 
     m = n = 40000
-    r, l, tol, fixed = 20, args.nys_l, 1e-6, 25
+    r, tol, fixed = 20, 1e-6, 25
     t0 = time.time()
     M, A, B, lam = workloads.nystrom_large_device(seed=args.seed)
     assert bool(torch.isfinite(M).all()), "non-finite input"
@@ -469,7 +543,7 @@ def nystrom(args):
         "parity_vs_oracle": parity,
         "paper_context": "Sec. 5.1: FR-Nys is faster than FR-ADM at low rank on large matrices",
     }
-    print(json.dumps(out_line), flush=True)
+    return out_line
 
 
 def serving(args):

@@ -113,7 +113,14 @@ typedef struct {
 
 /*
  * Create a solver for m x n inputs and rank r.
- *   m, n >= 1, 1 <= r <= min(m, n, 32).
+ *   m, n >= 1, 1 <= r <= min(m, n, 1024).  Ranks up to 32 run the fused
+ *   one-pass sweeps (FP64 or FP32).  Ranks 33 to 1024 (Table 2's r = 0.1 m,
+ *   the clustering shapes of Sec. 5.3) run the large-rank engine: FP32
+ *   FR-ADM and Alg. 4 only (precision SFR_F32, nystrom_l 0, bf16 0, else
+ *   SFR_ERR_ARG), with the m x n contractions as matrix-core GEMM tiles and
+ *   the r x r algebra in FP64 through Newton-Schulz inverse square roots; an
+ *   r x r Gram that iteration cannot invert (condition number beyond about
+ *   1e7) gives SFR_ERR_RANK.
  *   lambda > 0: weight of ||S||_1; the S-step threshold is lambda/mu_k.
  *   mu > 0: initial penalty mu_0 of Alg. 1 (finite).  mu <= 0 (finite,
  *     FR-ADM handles): each sfr_solve takes mu_0 = 1.25 / ||M||_2, with
@@ -279,7 +286,7 @@ sfr_status sfr_tune_batch(sfr_handle h, const sfr_batch_item* items, int32_t cou
  *     any device work.  No hipMalloc, hipFree, pinned host memory or HIP
  *     event is used; progress is read by synchronising hip_stream.
  *   Options: as for sfr_create, except that nystrom_l and profile must be 0
- *     (SFR_ERR_ARG otherwise).
+ *     and r <= 32 (SFR_ERR_ARG otherwise).
  *   Concurrency: every call on one device uses that device's one scratch
  *     array and host-side state, which keep the last call's contents (the
  *     call initialises everything it reads); calls that overlap on one

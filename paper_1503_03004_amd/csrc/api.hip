@@ -588,7 +588,7 @@ sfr_status validate_create(int64_t m, int64_t n, int32_t r, double lambda, doubl
         if (opt->struct_size != sizeof(sfr_options)) return SFR_ERR_ARG;
         o = *opt;
     }
-    if (m < 1 || n < 1 || r < 1 || r > kMaxR || r > m || r > n) return SFR_ERR_ARG;
+    if (m < 1 || n < 1 || r < 1 || r > kMaxRLarge || r > m || r > n) return SFR_ERR_ARG;
     if (m > (int64_t)1 << 30 || n > (int64_t)1 << 30) return SFR_ERR_ARG;
     if (!(lambda > 0.0) || !(tol >= 0.0) || lambda > 1e300 || tol > 1e300) return SFR_ERR_ARG;
     if (o.precision != SFR_F64 && o.precision != SFR_F32) return SFR_ERR_ARG;
@@ -601,6 +601,9 @@ sfr_status validate_create(int64_t m, int64_t n, int32_t r, double lambda, doubl
     if (!(o.rho > 1.0) || !(o.mu_bar > 0.0) || o.rho > 1e300 || o.mu_bar > 1e300) return SFR_ERR_ARG;
     if (o.max_iter < 1 || o.max_iter > 100000 || o.fixed_iters < 0 || o.fixed_iters > 100000) return SFR_ERR_ARG;
     if (o.nystrom_l < 0) return SFR_ERR_ARG;
+    // ranks above the fused sweeps' bucket run on the large-rank engine:
+    // FP32 FR-ADM (and Alg. 4) only
+    if (r > kMaxR && (o.precision != SFR_F32 || o.nystrom_l != 0 || o.bf16 != 0)) return SFR_ERR_ARG;
     if (o.nystrom_l > 0) {
         if (o.nystrom_l < r || o.nystrom_l > m || o.nystrom_l > n) return SFR_ERR_ARG;
         if (!(o.mu_left > 0.0) || !(o.mu_top > 0.0) || o.mu_left > 1e300 || o.mu_top > 1e300) return SFR_ERR_ARG;
@@ -664,7 +667,9 @@ sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double l
     h->mu_left = o.mu_left; h->mu_top = o.mu_top;
     const int hist = std::max(o.max_iter, o.fixed_iters);
     sfr_status st;
-    if (!nys) {
+    if (r > kMaxR) {
+        st = lr_create(&h->lr, (int)m, (int)n, r, hist);
+    } else if (!nys) {
         st = engine_create(h->main, (int)m, (int)n, r, h->f64, hist);
         // the BF16 bulk phase runs on the matrix-core sweep
         if (st == SFR_OK && h->prm.bf16 && !h->main.cfg[1].mfma) st = SFR_ERR_ARG;
@@ -672,6 +677,7 @@ sfr_status sfr_create(sfr_handle* out, int64_t m, int64_t n, int32_t r, double l
         st = nys_setup(h);
     }
     if (st != SFR_OK) {
+        lr_destroy(h->lr);
         engine_destroy(h->main);
         engine_destroy(h->left);
         engine_destroy(h->top);
@@ -690,6 +696,7 @@ sfr_status sfr_destroy(sfr_handle h)
 {
     if (!h) return SFR_OK;
     if (h->magic != 0x53465221u) return SFR_ERR_HANDLE;
+    lr_destroy(h->lr);
     engine_destroy(h->main);
     engine_destroy(h->left);
     engine_destroy(h->top);
@@ -707,7 +714,7 @@ sfr_status sfr_workspace_bytes(sfr_handle h, uint64_t* bytes)
 {
     if (!h || h->magic != 0x53465221u) return SFR_ERR_HANDLE;
     if (!bytes) return SFR_ERR_ARG;
-    size_t b = h->main.bytes + h->left.bytes + h->top.bytes + h->batch_bytes;
+    size_t b = h->main.bytes + h->left.bytes + h->top.bytes + h->batch_bytes + lr_bytes(h->lr);
     *bytes = (uint64_t)b;
     return SFR_OK;
 }
@@ -718,6 +725,9 @@ sfr_status sfr_solve(sfr_handle h, const void* M, int64_t ldm, void* U, double* 
     if (!h || h->magic != 0x53465221u || h->nys || h->batch) return SFR_ERR_HANDLE;
     if (!M || !U || !B || !V) return SFR_ERR_ARG;
     if (ldm < h->n || (S && lds < h->n)) return SFR_ERR_ARG;
+    if (h->lr)
+        return lr_solve(h->lr, h->prm, h->mu_auto, static_cast<const float*>(M), ldm, static_cast<float*>(U), B,
+                        static_cast<float*>(V), static_cast<float*>(S), lds, info, static_cast<hipStream_t>(hip_stream));
     return engine_solve(h->main, h->prm, h->mu_auto, M, ldm, U, B, V, S, lds, info,
                         static_cast<hipStream_t>(hip_stream));
 }
@@ -729,6 +739,9 @@ sfr_status sfr_tsvd(sfr_handle h, const void* M, int64_t ldm, void* U, double* B
     if (!M || !U || !B || !V) return SFR_ERR_ARG;
     if (ldm < h->n) return SFR_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (h->lr)
+        return lr_tsvd(h->lr, h->prm, static_cast<const float*>(M), ldm, static_cast<float*>(U), B,
+                       static_cast<float*>(V), info, s);
     Engine& e = h->main;
     sfr_status st;
     if (h->f64) {

@@ -17,6 +17,12 @@ struct SweepCfg {
     size_t lds = 0;
 };
 
+struct LrEngine;   // large-rank FR-ADM engine (lr.hip)
+
+// Residual history entries every engine holds at least: the mu_0 estimate
+// (Alg. 4 on M) runs up to 60 steps whatever the handle's max_iter.
+constexpr int kResHistMin = 64;
+
 struct Engine {
     int m = 0, n = 0, ne = 0, r = 0, R = 0;   // ne: column count the kernels see (padded)
     bool f64 = false;
@@ -99,6 +105,7 @@ struct sfr_ctx {
     double mu_left = 0, mu_top = 0;
     sfr::Engine main;       // FR-ADM engine (m x n)
     sfr::Engine left, top;  // FR-Nys sub-engines (m x l, l x n)
+    sfr::LrEngine* lr = nullptr;  // large-rank engine (r > 32)
     // FR-Nys workspace
     void* C = nullptr;
     void* Rb = nullptr;
@@ -125,6 +132,16 @@ struct sfr_ctx {
 
 
 namespace sfr {
+// Large-rank FR-ADM engine (kMaxR < r <= kMaxRLarge, FP32; lr.hip).
+struct LrEngine;
+sfr_status lr_create(LrEngine** out, int m, int n, int r, int hist_len);
+void lr_destroy(LrEngine* e);
+size_t lr_bytes(const LrEngine* e);
+sfr_status lr_solve(LrEngine* e, const Params& prm, bool mu_auto, const float* M, int64_t ldm, float* U, double* B,
+                    float* V, float* S, int64_t lds, sfr_info* info, hipStream_t s);
+sfr_status lr_tsvd(LrEngine* e, const Params& prm, const float* M, int64_t ldm, float* U, double* B, float* V,
+                   sfr_info* info, hipStream_t s);
+
 // Shape of an engine (sizes, rank bucket, launch configurations); no
 // device memory is touched.
 sfr_status engine_plan(Engine& e, int m, int n, int r, bool f64, int hist_len);
@@ -150,7 +167,8 @@ bool engine_buffers(Engine& e, bool pad, Get&& get)
     if (!(e.GQpart = static_cast<double*>(get(sizeof(double) * (size_t)e.nqb * e.E)))) return false;
     if (!(e.GPpart = static_cast<double*>(get(sizeof(double) * (size_t)e.npb * e.E)))) return false;
     if (!(e.st = static_cast<DevState*>(get(sizeof(DevState))))) return false;
-    if (!(e.res_hist = static_cast<double*>(get(sizeof(double) * (size_t)(e.hist_len + 2))))) return false;
+    if (!(e.res_hist = static_cast<double*>(get(sizeof(double) * (size_t)(std::max(e.hist_len, kResHistMin) + 2)))))
+        return false;
     if (pad) {
         e.ldmpad = e.ne;
         if (!(e.Mpad = get((size_t)e.m * e.ldmpad * e.esz))) return false;

@@ -69,8 +69,9 @@ extern "C" sfr_status sfr_solve_noalloc(int64_t m, int64_t n, int32_t r, double 
     sfr_options o;
     const sfr_status vs = validate_create(m, n, r, lambda, mu, tol, opt, o);
     if (vs != SFR_OK) return vs;
-    // FR-Nys keeps a second stream and host thread; profiling creates events
-    if (o.nystrom_l != 0 || o.profile != 0) return SFR_ERR_ARG;
+    // FR-Nys keeps a second stream and host thread; profiling creates events;
+    // the large-rank engine (r > 32) owns its own workspace
+    if (o.nystrom_l != 0 || o.profile != 0 || r > kMaxR) return SFR_ERR_ARG;
     if (!M || !U || !B || !V) return SFR_ERR_ARG;
     if (ldm < n || (S && lds < n)) return SFR_ERR_ARG;
     Params prm;

@@ -30,7 +30,8 @@
 
 namespace sfr {
 
-constexpr int kMaxR = 32;
+constexpr int kMaxR = 32;           // ranks of the fused sweeps
+constexpr int kMaxRLarge = 1024;     // ranks of the large-rank engine (lr.hip)
 constexpr int kTPB = 256;            // threads per workgroup of the streaming kernels
 constexpr int kGramU = 8;            // P loads in flight per thread of the Gram kernel
 constexpr int kXCD = 8;              // accelerator complex dies on MI355X
