@@ -376,64 +376,85 @@ __device__ __forceinline__ bool gate_closed(const Gate64& g)
     return false;
 }
 
+typedef double lr_f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kT64K = 64;   // K depth of one LDS stage of the FP64 products
+
+// One 32 x 32 tile of op(A) op(B) (R x R, FP64) on v_mfma_f64_16x16x4_f64:
+// wavefront w of the workgroup owns the 16 x 16 quadrant (w / 2, w % 2).
+// The instruction takes A[l % 16][l / 16] and B[l / 16][l % 16] from lane l
+// (as the FP32 one does) but returns D[l / 16 + 4 e][l % 16] in its e-th
+// register (checked on the device: the FP32 16x16x4 form returns
+// D[4 (l / 16) + e][l % 16] instead).  K is staged through LDS
+// in chunks of 64, all of a chunk's loads in flight at once.
+__device__ __forceinline__ void tile64(const double* __restrict__ A, int ta, const double* __restrict__ B, int tb,
+                                       int N, int i0, int j0, double (*As)[kT64K + 1], double (*Bs)[kT64 + 1],
+                                       lr_f64x4& acc)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int qi = 16 * (wave >> 1), qj = 16 * (wave & 1);
+    acc = lr_f64x4{0.0, 0.0, 0.0, 0.0};
+    constexpr int NL = kT64 * kT64K / 256;   // loads per thread per operand and chunk
+    for (int k0 = 0; k0 < N; k0 += kT64K) {
+        double va[NL], vb[NL];
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int e = tid + 256 * u;
+            // A: row i (of 32), column k (of 64); consecutive threads take the
+            // contiguous index of the stored layout
+            int i, k;
+            if (ta) { k = e / kT64; i = e % kT64; } else { i = e / kT64K; k = e % kT64K; }
+            const int gi = i0 + i, gk = k0 + k;
+            va[u] = (gi < N && gk < N) ? (ta ? A[(size_t)gk * N + gi] : A[(size_t)gi * N + gk]) : 0.0;
+            int kb, j;
+            if (tb) { j = e / kT64K; kb = e % kT64K; } else { kb = e / kT64; j = e % kT64; }
+            const int gj = j0 + j, gkb = k0 + kb;
+            vb[u] = (gj < N && gkb < N) ? (tb ? B[(size_t)gj * N + gkb] : B[(size_t)gkb * N + gj]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int e = tid + 256 * u;
+            int i, k;
+            if (ta) { k = e / kT64; i = e % kT64; } else { i = e / kT64K; k = e % kT64K; }
+            As[i][k] = va[u];
+            int kb, j;
+            if (tb) { j = e / kT64K; kb = e % kT64K; } else { kb = e / kT64; j = e % kT64; }
+            Bs[kb][j] = vb[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kT64K; kk += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[qi + (lane & 15)][kk + (lane >> 4)],
+                                                      Bs[kk + (lane >> 4)][qj + (lane & 15)], acc, 0, 0, 0);
+    }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(256) lr_gemm64_kernel(Prod64 p0, Prod64 p1, int N, Gate64 gate, double* part)
 {
     if (gate_closed(gate)) return;
     const Prod64& p = blockIdx.z == 0 ? p0 : p1;
-    __shared__ double As[kT64][kT64 + 1], Bs[kT64][kT64 + 1];
+    __shared__ double As[kT64][kT64K + 1], Bs[kT64K][kT64 + 1];
     __shared__ double red[4];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int i0 = blockIdx.y * kT64, j0 = blockIdx.x * kT64;
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (int k0 = 0; k0 < N; k0 += kT64) {
-        for (int e = threadIdx.x; e < kT64 * kT64; e += 256) {
-            const int a = e / kT64, b = e % kT64;
-            // As[i][k] = op(A)[i0 + i][k0 + k];  Bs[k][j] = op(B)[k0 + k][j0 + j]
-            {
-                int i, k;
-                if (p.ta) { k = a; i = b; } else { i = a; k = b; }
-                const int gi = i0 + i, gk = k0 + k;
-                double v = 0.0;
-                if (gi < N && gk < N) v = p.ta ? p.A[(size_t)gk * N + gi] : p.A[(size_t)gi * N + gk];
-                As[i][k] = v;
-            }
-            {
-                int k, j;
-                if (p.tb) { j = a; k = b; } else { k = a; j = b; }
-                const int gj = j0 + j, gk = k0 + k;
-                double v = 0.0;
-                if (gj < N && gk < N) v = p.tb ? p.B[(size_t)gj * N + gk] : p.B[(size_t)gk * N + gj];
-                Bs[k][j] = v;
-            }
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < kT64; ++kk) {
-            const double a0 = As[2 * ty][kk], a1 = As[2 * ty + 1][kk];
-            const double b0 = Bs[kk][2 * tx], b1 = Bs[kk][2 * tx + 1];
-            acc[0][0] = fma(a0, b0, acc[0][0]);
-            acc[0][1] = fma(a0, b1, acc[0][1]);
-            acc[1][0] = fma(a1, b0, acc[1][0]);
-            acc[1][1] = fma(a1, b1, acc[1][1]);
-        }
-        __syncthreads();
-    }
+    lr_f64x4 acc;
+    tile64(p.A, p.ta, p.B, p.tb, N, i0, j0, As, Bs, acc);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double r2 = 0.0;
-    for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 2; ++v) {
-            const int i = i0 + 2 * ty + u, j = j0 + 2 * tx + v;
-            if (i >= N || j >= N) continue;
-            const double w = p.alpha * acc[u][v];
-            if constexpr (MODE == kNsT) {
-                const double d = w - (i == j ? 1.0 : 0.0);
-                r2 = fma(d, d, r2);
-                p.C[(size_t)i * N + j] = (i == j ? 1.5 : 0.0) - 0.5 * w;
-            } else {
-                p.C[(size_t)i * N + j] = w;
-                if (p.Cf) p.Cf[(size_t)i * N + j] = (float)w;
-            }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int i = i0 + 16 * (wave >> 1) + (lane >> 4) + 4 * e, j = j0 + 16 * (wave & 1) + (lane & 15);
+        if (i >= N || j >= N) continue;
+        const double w = p.alpha * acc[e];
+        if constexpr (MODE == kNsT) {
+            const double d = w - (i == j ? 1.0 : 0.0);
+            r2 = fma(d, d, r2);
+            p.C[(size_t)i * N + j] = (i == j ? 1.5 : 0.0) - 0.5 * w;
+        } else {
+            p.C[(size_t)i * N + j] = w;
+            if (p.Cf) p.Cf[(size_t)i * N + j] = (float)w;
         }
+    }
     if constexpr (MODE == kNsT) {
         for (int off = 32; off > 0; off >>= 1) r2 += __shfl_xor(r2, off, 64);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r2;
@@ -453,40 +474,74 @@ __global__ void lr_sym_kernel(const double* T, double* B, int N, const DevState*
     B[e] = (i < r && j < r) ? 0.5 * (T[(size_t)i * N + j] + T[(size_t)j * N + i]) : (i == j ? 1.0 : 0.0);
 }
 
-// Newton-Schulz start: s = ||A||_F over the leading r x r block,
-// Y_0 = A / s there and the identity on the padded block (a fixed point of
-// the iteration), Z_0 = I (one workgroup).
+// Newton-Schulz start (one workgroup): the scale s is 1.25 times a
+// power-iteration estimate of lambda_max of the leading r x r block (8 steps
+// of x <- A x / ||A x|| from the normalised ones vector; ||A x|| approaches
+// lambda_max from below, so A / s keeps its spectrum inside the iteration's
+// (0, 2) convergence region as long as the estimate is above 0.63
+// lambda_max).  Y_0 = A / s there and the identity on the padded block (a
+// fixed point of the iteration), Z_0 = I.
+constexpr int kPowerSteps = 8;
+constexpr double kPowerMargin = 1.25;
+
 __global__ void __launch_bounds__(1024) lr_ns_init_kernel(const double* A, int N, double* Y0, double* Z0,
                                                           DevState* st, LrState* ls, int which)
 {
     if (st->done) return;
     __shared__ double red[16];
-    const int r = st->r;
-    double s = 0.0;
-    for (int e = threadIdx.x; e < N * N; e += 1024)
-        if (e / N < r && e % N < r) s = fma(A[e], A[e], s);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __shared__ double x[kMaxRLarge];
+    __shared__ double nrm;
+    const int r = st->r, tid = threadIdx.x;
+    auto block_sum = [&](double v) -> double {
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        __syncthreads();
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += red[w];
+        return t;
+    };
+    // non-finite entries make the estimate non-finite: reported below
+    for (int i = tid; i < r; i += 1024) x[i] = 1.0 / sqrt((double)r);
     __syncthreads();
-    double tot = 0.0;
-    for (int w = 0; w < 16; ++w) tot += red[w];
-    const double sc = sqrt(tot);
-    if (!(sc > 0.0) || !isfinite(sc)) {
-        if (threadIdx.x == 0) {
+    double lam = 0.0;
+    for (int it = 0; it < kPowerSteps; ++it) {
+        double y = 0.0;
+        if (tid < r) {   // y_i = sum_j A_ji x_j (A symmetric): coalesced over i
+            double y1 = 0.0, y2 = 0.0, y3 = 0.0;
+            int j = 0;
+            for (; j + 3 < r; j += 4) {
+                y = fma(A[(size_t)j * N + tid], x[j], y);
+                y1 = fma(A[(size_t)(j + 1) * N + tid], x[j + 1], y1);
+                y2 = fma(A[(size_t)(j + 2) * N + tid], x[j + 2], y2);
+                y3 = fma(A[(size_t)(j + 3) * N + tid], x[j + 3], y3);
+            }
+            for (; j < r; ++j) y = fma(A[(size_t)j * N + tid], x[j], y);
+            y = (y + y1) + (y2 + y3);
+        }
+        const double s2 = block_sum(tid < r ? y * y : 0.0);
+        lam = sqrt(s2);
+        if (!(lam > 0.0) || !isfinite(lam)) break;
+        if (tid < r) x[tid] = y / lam;
+        __syncthreads();
+    }
+    if (!(lam > 0.0) || !isfinite(lam)) {
+        if (tid == 0) {
             st->status = kErrNonFinite;
             st->iters = st->k - 1;
             st->done = 1;
         }
         return;
     }
+    const double sc = kPowerMargin * lam;
     const double inv = 1.0 / sc;
-    for (int e = threadIdx.x; e < N * N; e += 1024) {
+    for (int e = tid; e < N * N; e += 1024) {
         const int i = e / N, j = e % N;
         const double id = (i == j) ? 1.0 : 0.0;
         Y0[e] = (i < r && j < r) ? A[e] * inv : id;
         Z0[e] = id;
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         ls->ns_scale[which] = sc;
         ls->ns_done_at[which] = INT_MAX;
         ls->ns_used[which] = 0;
@@ -514,33 +569,16 @@ __global__ void __launch_bounds__(256) lr_ns_update_kernel(const double* Yc, con
     const double* A = blockIdx.z == 0 ? Yc : T;
     const double* B = blockIdx.z == 0 ? T : Zc;
     double* C = blockIdx.z == 0 ? Yn : Zn;
-    __shared__ double As[kT64][kT64 + 1], Bs[kT64][kT64 + 1];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    __shared__ double As[kT64][kT64K + 1], Bs[kT64K][kT64 + 1];
     const int i0 = blockIdx.y * kT64, j0 = blockIdx.x * kT64;
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (int k0 = 0; k0 < N; k0 += kT64) {
-        for (int e = threadIdx.x; e < kT64 * kT64; e += 256) {
-            const int a = e / kT64, b = e % kT64;
-            As[a][b] = (i0 + a < N && k0 + b < N) ? A[(size_t)(i0 + a) * N + k0 + b] : 0.0;
-            Bs[a][b] = (k0 + a < N && j0 + b < N) ? B[(size_t)(k0 + a) * N + j0 + b] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < kT64; ++kk) {
-            const double a0 = As[2 * ty][kk], a1 = As[2 * ty + 1][kk];
-            const double b0 = Bs[kk][2 * tx], b1 = Bs[kk][2 * tx + 1];
-            acc[0][0] = fma(a0, b0, acc[0][0]);
-            acc[0][1] = fma(a0, b1, acc[0][1]);
-            acc[1][0] = fma(a1, b0, acc[1][0]);
-            acc[1][1] = fma(a1, b1, acc[1][1]);
-        }
-        __syncthreads();
+    lr_f64x4 acc;
+    tile64(A, 0, B, 0, N, i0, j0, As, Bs, acc);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int i = i0 + 16 * (wave >> 1) + (lane >> 4) + 4 * e, j = j0 + 16 * (wave & 1) + (lane & 15);
+        if (i < N && j < N) C[(size_t)i * N + j] = acc[e];
     }
-    for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 2; ++v) {
-            const int i = i0 + 2 * ty + u, j = j0 + 2 * tx + v;
-            if (i < N && j < N) C[(size_t)i * N + j] = acc[u][v];
-        }
     if (last && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
         ls->ns_done_at[gate.which] = gate.iter;
         ls->ns_used[gate.which] = gate.iter + 1;
@@ -710,20 +748,36 @@ __global__ void __launch_bounds__(1024) lr_step_end_kernel(DevState* st, const d
 
 // ---------------------------------------------------------------------------
 // Extreme eigenvalues of the leading r x r block of a symmetric matrix:
-// Householder reduction to tridiagonal form (in `W`, N x N workspace), then
-// Sturm-sequence bisection for the smallest and largest eigenvalue.
+// Householder reduction to tridiagonal form (in `W`, r x r workspace; the
+// reflector v and the vector p of each step in LDS), then Sturm-sequence
+// multisection for the smallest and largest eigenvalue: every thread counts
+// the eigenvalues below its own point of the bracket, so each round shrinks
+// the bracket 1024-fold.
+__device__ int sturm_below(const double* d, const double* e2, int n, double x)
+{
+    // eigenvalues of the tridiagonal (d, e) below x: negative pivots of the
+    // LDL^T factorisation of T - x I
+    int c = 0;
+    double q = 1.0;
+    for (int i = 0; i < n; ++i) {
+        q = d[i] - x - ((i > 0) ? e2[i - 1] / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        c += (q < 0.0);
+    }
+    return c;
+}
+
 __global__ void __launch_bounds__(kEigTPB) lr_extreme_eig_kernel(const double* B, int N, int r, double* W,
                                                                  double* vec, DevState* st, int want_min,
                                                                  int want_max)
 {
     if (!st->done || st->status < 0 || st->exch_timeout) return;
+    double* part = vec;   // 16 x n partial sums of the tridiagonalisation's products
     __shared__ double red[kEigTPB / 64];
-    __shared__ double bc[2];
+    __shared__ double v[kMaxRLarge], p[kMaxRLarge], d[kMaxRLarge], e2[kMaxRLarge];
+    __shared__ double lohi[2];
+    __shared__ int bracket;
     const int tid = threadIdx.x, n = r;
-    double* v = vec;          // n
-    double* p = vec + n;      // n
-    double* d = vec + 2 * n;  // n
-    double* e = vec + 3 * n;  // n
     for (int x = tid; x < n * n; x += kEigTPB) W[x] = B[(size_t)(x / n) * N + x % n];
     __syncthreads();
     auto block_sum = [&](double s) -> double {
@@ -736,7 +790,7 @@ __global__ void __launch_bounds__(kEigTPB) lr_extreme_eig_kernel(const double* B
         return t;
     };
     for (int k = 0; k + 2 < n; ++k) {
-        const int len = n - k - 1;   // trailing block rows k+1 .. n-1
+        const int len = n - k - 1;   // trailing block: rows and columns k+1 .. n-1
         double s = 0.0;
         for (int i = tid; i < len; i += kEigTPB) {
             const double x = W[(size_t)(k + 1 + i) * n + k];
@@ -745,71 +799,116 @@ __global__ void __launch_bounds__(kEigTPB) lr_extreme_eig_kernel(const double* B
         const double nx = sqrt(block_sum(s));
         const double x0 = W[(size_t)(k + 1) * n + k];
         const double alpha = (x0 >= 0.0) ? -nx : nx;
-        // v = x - alpha e1, normalised (no reflection if x is already e1-aligned)
+        // v = (x - alpha e1) / ||x - alpha e1|| (no reflection if x is already along e1)
         const double v0 = x0 - alpha;
         const double vn2 = nx * nx - x0 * x0 + v0 * v0;
         const bool reflect = vn2 > 0.0 && nx > 0.0;
         const double vinv = reflect ? 1.0 / sqrt(vn2) : 0.0;
         for (int i = tid; i < len; i += kEigTPB) v[i] = (i == 0 ? v0 : W[(size_t)(k + 1 + i) * n + k]) * vinv;
-        if (tid == 0) { d[k] = W[(size_t)k * n + k]; e[k] = reflect ? alpha : x0; }
-        __syncthreads();
-        if (!reflect) continue;
-        // p = 2 A_sub v, column by column (A_sub is symmetric), so that at
-        // each j the threads read consecutive entries of one row
-        for (int i = tid; i < len; i += kEigTPB) {
-            const double* col = W + (size_t)(k + 1) * n + (k + 1 + i);
-            double q = 0.0;
-            for (int j = 0; j < len; ++j) q = fma(col[(size_t)j * n], v[j], q);
-            p[i] = 2.0 * q;
+        if (tid == 0) {
+            d[k] = W[(size_t)k * n + k];
+            const double ek = reflect ? alpha : x0;
+            e2[k] = ek * ek;
         }
         __syncthreads();
+        if (!reflect) continue;
+        // p = 2 A_sub v (A_sub symmetric): wavefront w sums the rows
+        // j = w, w + 16, ... for the columns i = lane + 64 c (consecutive
+        // lanes on consecutive entries of a row, every load independent);
+        // the 16 partial vectors go through `part` and are added in order
+        {
+            const int wv = tid >> 6, ln = tid & 63;
+            const int nch = (len + 63) >> 6;
+            double acc[kMaxRLarge / 64];
+#pragma unroll
+            for (int c = 0; c < kMaxRLarge / 64; ++c) acc[c] = 0.0;
+            for (int j = wv; j < len; j += kEigTPB / 64) {
+                const double* row = W + (size_t)(k + 1 + j) * n + (k + 1);
+                const double vj = v[j];
+#pragma unroll
+                for (int c = 0; c < kMaxRLarge / 64; ++c) {
+                    const int i = ln + 64 * c;
+                    if (c < nch && i < len) acc[c] = fma(row[i], vj, acc[c]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kMaxRLarge / 64; ++c) {
+                const int i = ln + 64 * c;
+                if (c < nch && i < len) part[(size_t)wv * n + i] = acc[c];
+            }
+            __syncthreads();
+            for (int i = tid; i < len; i += kEigTPB) {
+                double q = 0.0;
+                for (int w = 0; w < kEigTPB / 64; ++w) q += part[(size_t)w * n + i];
+                p[i] = 2.0 * q;
+            }
+            __syncthreads();
+        }
         double vp = 0.0;
         for (int i = tid; i < len; i += kEigTPB) vp = fma(v[i], p[i], vp);
         vp = block_sum(vp);
         for (int i = tid; i < len; i += kEigTPB) p[i] -= vp * v[i];   // w
         __syncthreads();
-        for (int x = tid; x < len * len; x += kEigTPB) {
-            const int i = x / len, j = x % len;
-            W[(size_t)(k + 1 + i) * n + (k + 1 + j)] -= v[i] * p[j] + p[i] * v[j];
+        // A_sub -= v w^T + w v^T: wavefront w on the rows i = w, w + 16, ...,
+        // consecutive lanes on consecutive columns
+        {
+            const int wv = tid >> 6, ln = tid & 63;
+            for (int i = wv; i < len; i += kEigTPB / 64) {
+                const double vi = v[i], wi = p[i];
+                double* row = W + (size_t)(k + 1 + i) * n + (k + 1);
+                for (int j = ln; j < len; j += 64) row[j] -= vi * p[j] + wi * v[j];
+            }
         }
         __syncthreads();
     }
-    if (tid != 0) return;
-    if (n >= 2) {
-        d[n - 2] = W[(size_t)(n - 2) * n + (n - 2)];
-        e[n - 2] = W[(size_t)(n - 1) * n + (n - 2)];
-    }
-    d[n - 1] = W[(size_t)(n - 1) * n + (n - 1)];
-    // Gershgorin interval
-    double lo = INFINITY, hi = -INFINITY;
-    for (int i = 0; i < n; ++i) {
-        const double rad = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
-        lo = fmin(lo, d[i] - rad);
-        hi = fmax(hi, d[i] + rad);
-    }
-    // number of eigenvalues below x (Sturm count of the LDL^T pivots)
-    auto below = [&](double x) -> int {
-        int c = 0;
-        double q = 1.0;
-        for (int i = 0; i < n; ++i) {
-            const double off = (i > 0) ? e[i - 1] * e[i - 1] / q : 0.0;
-            q = d[i] - x - off;
-            if (q == 0.0) q = -1e-300;
-            if (q < 0.0) ++c;
+    if (tid == 0) {
+        if (n >= 2) {
+            d[n - 2] = W[(size_t)(n - 2) * n + (n - 2)];
+            const double en = W[(size_t)(n - 1) * n + (n - 2)];
+            e2[n - 2] = en * en;
         }
-        return c;
-    };
-    auto kth = [&](int target) -> double {   // the eigenvalue with `target` eigenvalues below it
-        double a = lo, b = hi;
-        for (int it = 0; it < 200; ++it) {
-            const double mid = 0.5 * (a + b);
-            if (mid <= a || mid >= b) break;
-            if (below(mid) > target) b = mid; else a = mid;
+        d[n - 1] = W[(size_t)(n - 1) * n + (n - 1)];
+        // Gershgorin bracket of the whole spectrum
+        double lo = INFINITY, hi = -INFINITY;
+        for (int i = 0; i < n; ++i) {
+            const double rad = (i > 0 ? sqrt(e2[i - 1]) : 0.0) + (i + 1 < n ? sqrt(e2[i]) : 0.0);
+            lo = fmin(lo, d[i] - rad);
+            hi = fmax(hi, d[i] + rad);
+        }
+        const double pad = 1e-12 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+        lohi[0] = lo - pad;
+        lohi[1] = hi + pad;
+    }
+    __syncthreads();
+    // the eigenvalue with `target` eigenvalues below it, by multisection:
+    // thread t evaluates the count at a + (t + 1) (b - a) / (T + 1)
+    auto kth = [&](int target) -> double {
+        double a = lohi[0], b = lohi[1];
+        for (int round = 0; round < 8; ++round) {
+            const double h = (b - a) / (double)(kEigTPB + 1);
+            if (!(h > 0.0)) break;
+            if (tid == 0) bracket = kEigTPB;   // first point with more than `target` below
+            __syncthreads();
+            const double x = a + h * (double)(tid + 1);
+            if (sturm_below(d, e2, n, x) > target) atomicMin(&bracket, tid);
+            __syncthreads();
+            const int t = bracket;
+            const double na = (t == 0) ? a : a + h * (double)t;
+            const double nb = (t == kEigTPB) ? b : a + h * (double)(t + 1);
+            __syncthreads();
+            if (nb - na >= b - a) break;
+            a = na;
+            b = nb;
         }
         return 0.5 * (a + b);
     };
-    if (want_min) st->min_eig_B = kth(0);
-    if (want_max) st->max_eig_B = kth(n - 1);
+    double wmin = 0.0, wmax = 0.0;
+    if (want_min) wmin = kth(0);
+    if (want_max) wmax = kth(n - 1);
+    if (tid == 0) {
+        if (want_min) st->min_eig_B = wmin;
+        if (want_max) st->max_eig_B = wmax;
+    }
 }
 
 }  // namespace sfr
@@ -1080,7 +1179,7 @@ sfr_status lr_create(LrEngine** out, int m, int n, int r, int hist_len)
     da(&e->NT, RR);
     da(&e->nspart, (size_t)cdiv(R, kT64) * cdiv(R, kT64));
     da(&e->eigW, (size_t)r * r);
-    da(&e->eigv, (size_t)4 * r);
+    da(&e->eigv, (size_t)(kEigTPB / 64) * r);
     if (ok) ok = dev_alloc(e->allocs, e->bytes, (void**)&e->st, sizeof(DevState));
     if (ok) ok = dev_alloc(e->allocs, e->bytes, (void**)&e->ls, sizeof(LrState));
     da(&e->res_hist, (size_t)std::max(hist_len, kResHistMin) + 2);
