@@ -46,6 +46,7 @@ typedef enum {
     SFR_ERR_HANDLE = -6,     /* NULL or wrong-kind handle */
     SFR_ERR_SCRATCH = -7,    /* sfr_solve_noalloc: the problem needs more device workspace than
                                 its static scratch holds */
+    SFR_ERR_BUSY = -8,       /* sfr_queue_submit: every slot holds a problem in flight */
     SFR_WARN_MAXITER = 1,    /* max_iter reached before the tolerance */
     SFR_WARN_NOT_SPD = 2     /* returned B has a non-positive eigenvalue (eq. (8) is
                                 not guaranteed SPD away from the optimum, Appendix) */
@@ -268,6 +269,48 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
  */
 sfr_status sfr_tune_batch(sfr_handle h, const sfr_batch_item* items, int32_t count, int32_t* table,
                           void* hip_stream);
+
+/*
+ * Queue form of a batched handle (continuous batching).  Persistent kernels
+ * take problems one by one from a queue that the host appends to while they
+ * run, and retire each problem as soon as it is solved: a problem submitted
+ * while others are on the GPU starts as soon as a workgroup is free, and its
+ * result does not wait for any other problem.  Admission is by slot: each
+ * problem in flight holds one of the handle's `capacity` workspace slots
+ * (device memory allocated by sfr_create_batch), freed when its result is
+ * collected.  Each problem runs the iteration, stopping rule and outputs of
+ * sfr_solve_batch; problems with r <= 6 go to one kernel (the two-rows-per-
+ * wavefront form at the R = 6 bucket), the others to a second (the
+ * matrix-core form at the R = 16 bucket).  A problem's result depends only
+ * on the problem itself, not on what else is in flight.
+ *
+ * sfr_queue_start(h, grid_large, grid_small): launch the two persistent
+ *   kernels on two streams of the handle, with grid_large and grid_small
+ *   workgroups (0: three quarters and one quarter of the compute units).
+ *   Allocates pinned host memory for the queue the first time.  While the
+ *   queue runs, sfr_solve_batch and sfr_tune_batch return SFR_ERR_HANDLE.
+ * sfr_queue_submit(h, item, ticket): host only, never blocks.  Validates
+ *   the item (as sfr_solve_batch), takes a free slot, writes its descriptor
+ *   and appends it to its kernel's queue; *ticket receives the slot.
+ *   SFR_ERR_BUSY if every slot is in flight, SFR_ERR_ARG for an invalid item
+ *   (nothing submitted).  The item's output buffers must stay valid until
+ *   its result is collected.
+ * sfr_queue_poll(h, ticket, done, info, status): host only, never blocks.
+ *   *done = 1 once the problem is solved: its outputs are written, *info and
+ *   *status (the problem's sfr_status) are filled and the slot is free
+ *   again; else *done = 0.  An unused ticket gives SFR_ERR_ARG.
+ * sfr_queue_stop(h): close the queue, wait until every submitted problem is
+ *   solved and both kernels have ended.  Results not yet collected stay in
+ *   the handle until the next sfr_queue_start.
+ * A persistent kernel that finds no work for about a second ends by itself;
+ * submit and poll relaunch it when work is pending.  Errors: SFR_ERR_HANDLE
+ * (NULL or non-batched handle, queue not running / already running),
+ * SFR_ERR_DEVICE, SFR_ERR_NOMEM (sfr_queue_start).
+ */
+sfr_status sfr_queue_start(sfr_handle h, int32_t grid_large, int32_t grid_small);
+sfr_status sfr_queue_submit(sfr_handle h, const sfr_batch_item* item, int32_t* ticket);
+sfr_status sfr_queue_poll(sfr_handle h, int32_t ticket, int32_t* done, sfr_info* info, int32_t* status);
+sfr_status sfr_queue_stop(sfr_handle h);
 
 /*
  * FR-ADM without any device allocation, for callers that cannot allocate:

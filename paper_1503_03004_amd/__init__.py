@@ -8,5 +8,5 @@ hand-written HIP kernels for gfx950 behind the C ABI of include/sfr.h.  This pac
 from ._binding import (  # noqa: F401
     BatchSolver, Info, SFRError, Solver, lib, solve, solve_noalloc, solve_nys, status_string, tsvd,
     SFR_OK, SFR_ERR_ARG, SFR_ERR_NOMEM, SFR_ERR_DEVICE, SFR_ERR_RANK, SFR_ERR_NONFINITE,
-    SFR_ERR_HANDLE, SFR_ERR_SCRATCH, SFR_WARN_MAXITER, SFR_WARN_NOT_SPD, LIB_PATH,
+    SFR_ERR_HANDLE, SFR_ERR_SCRATCH, SFR_ERR_BUSY, SFR_WARN_MAXITER, SFR_WARN_NOT_SPD, LIB_PATH,
 )

@@ -21,6 +21,7 @@ SFR_ERR_RANK = -4
 SFR_ERR_NONFINITE = -5
 SFR_ERR_HANDLE = -6
 SFR_ERR_SCRATCH = -7
+SFR_ERR_BUSY = -8
 SFR_WARN_MAXITER = 1
 SFR_WARN_NOT_SPD = 2
 
@@ -118,6 +119,15 @@ def lib():
         L.sfr_solve_batch.restype = ctypes.c_int
         L.sfr_tune_batch.argtypes = [vp, ctypes.POINTER(sfr_batch_item), i32, ctypes.POINTER(ctypes.c_int32), vp]
         L.sfr_tune_batch.restype = ctypes.c_int
+        L.sfr_queue_start.argtypes = [vp, i32, i32]
+        L.sfr_queue_start.restype = ctypes.c_int
+        L.sfr_queue_submit.argtypes = [vp, ctypes.POINTER(sfr_batch_item), ctypes.POINTER(ctypes.c_int32)]
+        L.sfr_queue_submit.restype = ctypes.c_int
+        L.sfr_queue_poll.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(sfr_info),
+                                     ctypes.POINTER(ctypes.c_int32)]
+        L.sfr_queue_poll.restype = ctypes.c_int
+        L.sfr_queue_stop.argtypes = [vp]
+        L.sfr_queue_stop.restype = ctypes.c_int
         L.sfr_solve_noalloc.argtypes = [i64, i64, i32, d, d, d, ctypes.POINTER(sfr_options), vp, i64, vp, vp,
                                          vp, vp, i64, ctypes.POINTER(sfr_info), vp]
         L.sfr_solve_noalloc.restype = ctypes.c_int
@@ -353,6 +363,65 @@ class BatchSolver:
         if rc < 0 and (raise_on_error or rc in (SFR_ERR_ARG, SFR_ERR_HANDLE, SFR_ERR_DEVICE)):
             raise SFRError(rc, "sfr_solve_batch")
         return [(*keep[i], _info(int(st[i]), infos[i])) for i in range(count)]
+
+    # ---- queue form (continuous batching): persistent kernels fed while they run
+    def queue_start(self, grid_large=0, grid_small=0):
+        """Launch the persistent kernels (sfr_queue_start)."""
+        self._tickets = {}
+        rc = lib().sfr_queue_start(self._h, int(grid_large), int(grid_small))
+        if rc != SFR_OK:
+            raise SFRError(rc, "sfr_queue_start")
+
+    def queue_submit(self, M, r, lam, mu, tol, *, want_S=True, out=None):
+        """Append one problem (M a row-major float32 CUDA tensor).  Returns
+        its ticket, or None if every slot is in flight (SFR_ERR_BUSY).  The
+        output tensors are kept until the result is collected."""
+        import torch
+        if not (isinstance(M, torch.Tensor) and M.is_cuda and M.dtype == torch.float32 and M.dim() == 2):
+            raise TypeError("M must be a 2-D float32 CUDA (HIP) tensor")
+        if M.stride(1) != 1:
+            raise ValueError("M must be row-major (unit column stride)")
+        m, n = M.shape
+        if out is None:
+            U = torch.empty((m, r), dtype=torch.float32, device=M.device)
+            B = torch.empty((r, r), dtype=torch.float64, device=M.device)
+            V = torch.empty((n, r), dtype=torch.float32, device=M.device)
+            S = torch.empty((m, n), dtype=torch.float32, device=M.device) if want_S else None
+        else:
+            U, B, V, S = out
+            check_outputs(U, B, V, S, m, n, int(r), torch.float32, M.device)
+        it = sfr_batch_item()
+        it.m, it.n, it.r = m, n, int(r)
+        it.lam, it.mu, it.tol = float(lam), float(mu), float(tol)
+        it.M, it.ldm = M.data_ptr(), M.stride(0)
+        it.U, it.B, it.V = U.data_ptr(), B.data_ptr(), V.data_ptr()
+        it.S, it.lds = (S.data_ptr(), S.stride(0)) if S is not None else (None, 0)
+        t = ctypes.c_int32(-1)
+        rc = lib().sfr_queue_submit(self._h, ctypes.byref(it), ctypes.byref(t))
+        if rc == SFR_ERR_BUSY:
+            return None
+        if rc != SFR_OK:
+            raise SFRError(rc, "sfr_queue_submit")
+        self._tickets[t.value] = (M, U, B, V, S)
+        return t.value
+
+    def queue_poll(self, ticket):
+        """None while the problem is in flight, else (U, B, V, S, Info)."""
+        done = ctypes.c_int32(0)
+        info = sfr_info()
+        st = ctypes.c_int32(0)
+        rc = lib().sfr_queue_poll(self._h, int(ticket), ctypes.byref(done), ctypes.byref(info), ctypes.byref(st))
+        if rc != SFR_OK:
+            raise SFRError(rc, "sfr_queue_poll")
+        if not done.value:
+            return None
+        _, U, B, V, S = self._tickets.pop(ticket)
+        return U, B, V, S, _info(st.value, info)
+
+    def queue_stop(self):
+        rc = lib().sfr_queue_stop(self._h)
+        if rc != SFR_OK:
+            raise SFRError(rc, "sfr_queue_stop")
 
     VARIANTS = {0: "default", 1: "lane groups", 2: "one row per wavefront", 3: "two rows per wavefront",
                 4: "matrix cores"}

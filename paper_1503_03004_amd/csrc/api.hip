@@ -641,6 +641,7 @@ const char* sfr_status_string(sfr_status s)
     case SFR_ERR_NONFINITE: return "non-finite value in M or in the iteration";
     case SFR_ERR_HANDLE: return "invalid handle for this call";
     case SFR_ERR_SCRATCH: return "problem needs more device workspace than the static scratch holds";
+    case SFR_ERR_BUSY: return "no free slot: every slot of the queue holds a problem in flight";
     case SFR_WARN_MAXITER: return "max_iter reached before the tolerance";
     case SFR_WARN_NOT_SPD: return "returned B is not positive definite";
     }
@@ -696,6 +697,7 @@ sfr_status sfr_destroy(sfr_handle h)
 {
     if (!h) return SFR_OK;
     if (h->magic != 0x53465221u) return SFR_ERR_HANDLE;
+    if (h->batch) batch_queue_release(h);
     lr_destroy(h->lr);
     engine_destroy(h->main);
     engine_destroy(h->left);

@@ -69,7 +69,7 @@ __device__ inline float lane_bcast(float v, int l)
 // RW rows per wavefront per band (a band is 8 RW rows): two rows share each
 // V column read; one row keeps the larger ranks' band loop within registers.
 template <int R, int RW, bool NARROW, bool MF>
-__global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, BatchParams bp)
+__device__ __forceinline__ void batch_solve(BatchItemDev* it, const BatchParams& bp)
 {
     static_assert(R <= 16, "batched solver: r <= 16");
     static_assert(!MF || (!NARROW && R >= 8), "matrix-core form: wide problems, R >= 8");
@@ -80,7 +80,6 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
     constexpr int RP = (R + 3) / 4 * 4;   // rank padded to whole float4 groups
     constexpr int RC = RP / 4;
     constexpr int GS = NT / E;            // threads per G_Q entry
-    BatchItemDev* it = items + blockIdx.x;
     // the descriptor is read once (uniform: scalar loads) and its pointers
     // are held in registers for the whole solve
     const BatchItemDev d = *it;
@@ -727,18 +726,25 @@ __global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, Ba
     }
 }
 
+// One problem per workgroup (sfr_solve_batch).
+template <int R, int RW, bool NARROW, bool MF>
+__global__ void __launch_bounds__(kBTPB, 1) batch_kernel(BatchItemDev* items, BatchParams bp)
+{
+    batch_solve<R, RW, NARROW, MF>(items + blockIdx.x, bp);
+}
+
 // orth_err of one item: ||U^T U - I_r||_F and ||V^T V - I_r||_F of the
 // factors it wrote (FP64 sums over 64-row tiles staged in LDS, each Gram
 // entry owned by one thread and summed in row order).
 constexpr int kOrthRows = 64;
 
-__global__ void __launch_bounds__(256) batch_orth_kernel(BatchItemDev* items)
+__device__ void batch_orth_item(BatchItemDev* it)
 {
-    BatchItemDev* it = items + blockIdx.x;
     if (it->status < 0) return;
     __shared__ float tile[kOrthRows * 16];
     __shared__ double red[256];
     const int r = it->r, E = r * (r + 1) / 2, tid = threadIdx.x;
+    const int NT = blockDim.x;   // 256 or 512; entries and reductions use the first 256 threads
     int p = 0, q = 0;
     if (tid < E) {
         int e = tid;
@@ -753,13 +759,13 @@ __global__ void __launch_bounds__(256) batch_orth_kernel(BatchItemDev* items)
         for (int i0 = 0; i0 < rows; i0 += kOrthRows) {
             const int nr = min(kOrthRows, rows - i0);
             __syncthreads();
-            for (int e = tid; e < nr * r; e += 256) tile[e] = X[(int64_t)i0 * r + e];
+            for (int e = tid; e < nr * r; e += NT) tile[e] = X[(int64_t)i0 * r + e];
             __syncthreads();
             if (tid < E)
                 for (int i = 0; i < nr; ++i) g = fma((double)tile[i * r + p], (double)tile[i * r + q], g);
         }
         const double d = g - (p == q ? 1.0 : 0.0);
-        red[tid] = (tid < E) ? ((p == q) ? 1.0 : 2.0) * d * d : 0.0;
+        if (tid < 256) red[tid] = (tid < E) ? ((p == q) ? 1.0 : 2.0) * d * d : 0.0;
         __syncthreads();
         for (int h = 128; h > 0; h >>= 1) {
             if (tid < h) red[tid] += red[tid + h];
@@ -769,6 +775,95 @@ __global__ void __launch_bounds__(256) batch_orth_kernel(BatchItemDev* items)
         __syncthreads();
     }
     if (tid == 0) it->orth_err = fmax(dist[0], dist[1]);
+}
+
+__global__ void __launch_bounds__(256) batch_orth_kernel(BatchItemDev* items)
+{
+    batch_orth_item(items + blockIdx.x);
+}
+
+// Persistent form: the workgroups of one launch take problems one by one
+// from a queue that the host appends to while the kernel runs, and retire
+// each as soon as it is solved.  The host side (pinned, coherent memory):
+// the descriptors, the queue entries (entry -> slot) and `tail`; `closed`
+// asks the workgroups to leave once the queue is drained.  The device side:
+// `head`, the next entry to claim (compare-and-swap).  A workgroup that finds
+// no work for kQueueIdle polls leaves as well (the host relaunches when work
+// is pending and the kernel has ended), so every workgroup exits.
+constexpr uint32_t kQueueIdle = 1u << 18;
+
+template <int R, int RW, bool NARROW, bool MF>
+__global__ void __launch_bounds__(kBTPB, 1) batch_queue_kernel(BatchItemDev* items, BatchParams bp,
+                                                               BatchQueueDev* q, BatchQueueHost* hq, int32_t* done,
+                                                               int cap)
+{
+    __shared__ int s_slot;
+    __shared__ BatchItemDev sdesc;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            int slot = -1;
+            uint32_t polls = 0;
+            for (;;) {
+                const int tail = __hip_atomic_load(&hq->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                int h = __hip_atomic_load(&q->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (h < tail) {
+                    if (__hip_atomic_compare_exchange_strong(&q->head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)) {
+                        slot = __hip_atomic_load(&hq->order[h % cap], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                        break;
+                    }
+                    continue;
+                }
+                if (__hip_atomic_load(&hq->closed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+                if (++polls >= kQueueIdle) break;
+                __builtin_amdgcn_s_sleep(127);
+            }
+            s_slot = slot;
+        }
+        __syncthreads();
+        const int slot = s_slot;
+        __syncthreads();
+        if (slot < 0 || slot >= cap) break;
+        // The host rewrites a slot's descriptor between uses: it is read here
+        // word by word with system-scope loads into an LDS copy, solved from
+        // that copy, and the results are written back to the slot.
+        BatchItemDev* it = items + slot;
+        constexpr int DW = sizeof(BatchItemDev) / 4;
+        static_assert(DW <= kBTPB, "descriptor words per thread");
+        if (tid < DW)
+            reinterpret_cast<int32_t*>(&sdesc)[tid] =
+                __hip_atomic_load(reinterpret_cast<int32_t*>(it) + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __syncthreads();
+        batch_solve<R, RW, NARROW, MF>(&sdesc, bp);
+        __syncthreads();
+        __threadfence();   // this workgroup's U and V stores are visible to its reads below
+        batch_orth_item(&sdesc);
+        __syncthreads();
+        if (tid == 0) {
+            it->iters = sdesc.iters;
+            it->status = sdesc.status;
+            it->res = sdesc.res;
+            it->min_eig_B = sdesc.min_eig_B;
+            it->mu_final = sdesc.mu_final;
+            it->orth_err = sdesc.orth_err;
+            __threadfence_system();
+            __hip_atomic_store(&done[slot], sdesc.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batch_queue(BatchItemDev* items, const BatchParams& bp, BatchQueueDev* q, BatchQueueHost* hq,
+                              int32_t* done, int cap, int small, int grid, hipStream_t s)
+{
+    if (small)
+        hipLaunchKernelGGL((batch_queue_kernel<6, 2, false, false>), dim3(grid), dim3(kBTPB), 0, s, items, bp, q, hq,
+                           done, cap);
+    else
+        hipLaunchKernelGGL((batch_queue_kernel<16, 1, false, true>), dim3(grid), dim3(kBTPB), 0, s, items, bp, q, hq,
+                           done, cap);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_orth(BatchItemDev* items, int count, hipStream_t s)

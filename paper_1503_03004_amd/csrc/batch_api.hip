@@ -42,10 +42,9 @@ static bool item_valid(const sfr_ctx* h, const sfr_batch_item& it)
     return true;
 }
 
-// descriptor of the caller's item `it` in launch position `pos` (workspace slot pos)
-static void fill_desc(sfr_ctx* h, const sfr_batch_item& it, int32_t pos)
+// descriptor of the caller's item `it` for workspace slot `pos`
+static void build_desc(const sfr_ctx* h, const sfr_batch_item& it, int32_t pos, BatchItemDev& d)
 {
-    BatchItemDev& d = h->items_h[pos];
     memset(&d, 0, sizeof(d));
     d.m = (int32_t)it.m; d.n = (int32_t)it.n; d.r = it.r; d.ldy = (int32_t)h->ldy;
     d.lambda = it.lambda; d.mu0 = it.mu; d.tol = it.tol;
@@ -54,6 +53,12 @@ static void fill_desc(sfr_ctx* h, const sfr_batch_item& it, int32_t pos)
     d.S = static_cast<float*>(it.S); d.lds = it.lds;
     float* const* w = &h->slot_ws[(size_t)pos * 6];
     d.Y0 = w[0]; d.Y1 = w[1]; d.P0 = w[2]; d.P1 = w[3]; d.Q0 = w[4]; d.Q1 = w[5];
+}
+
+// descriptor of the caller's item `it` in launch position `pos` (workspace slot pos)
+static void fill_desc(sfr_ctx* h, const sfr_batch_item& it, int32_t pos)
+{
+    build_desc(h, it, pos, h->items_h[pos]);
 }
 
 }  // namespace sfr
@@ -132,7 +137,7 @@ sfr_status sfr_create_batch(sfr_handle* out, int32_t capacity, int64_t max_m, in
 sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t count, sfr_info* infos,
                            int32_t* statuses, void* hip_stream)
 {
-    if (!h || h->magic != 0x53465221u || !h->batch) return SFR_ERR_HANDLE;
+    if (!h || h->magic != 0x53465221u || !h->batch || h->qactive) return SFR_ERR_HANDLE;
     if (count < 0 || count > h->capacity || (count > 0 && !items)) return SFR_ERR_ARG;
     if (count == 0) return SFR_OK;
     // validate every item before any device work
@@ -211,7 +216,7 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
 sfr_status sfr_tune_batch(sfr_handle h, const sfr_batch_item* items, int32_t count, int32_t* table,
                           void* hip_stream)
 {
-    if (!h || h->magic != 0x53465221u || !h->batch) return SFR_ERR_HANDLE;
+    if (!h || h->magic != 0x53465221u || !h->batch || h->qactive) return SFR_ERR_HANDLE;
     if (count < 0 || count > h->capacity || (count > 0 && !items)) return SFR_ERR_ARG;
     for (int32_t i = 0; i < count; ++i)
         if (!item_valid(h, items[i])) return SFR_ERR_ARG;
@@ -272,6 +277,202 @@ sfr_status sfr_tune_batch(sfr_handle h, const sfr_batch_item* items, int32_t cou
     if (table) {
         for (int cls = 0; cls < 2; ++cls)
             for (int bi = 0; bi < kNumBatchBuckets; ++bi) table[cls * kNumBatchBuckets + bi] = h->variant[cls][bi];
+    }
+    return SFR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Queue form: persistent kernels fed while they run.
+namespace sfr {
+
+static bool queue_launch(sfr_ctx* h, int q)
+{
+    BatchParams bp;
+    bp.rho = h->prm.rho;
+    bp.mu_bar = h->prm.mu_bar;
+    bp.max_iter = h->prm.max_iter;
+    bp.fixed_iters = h->prm.fixed_iters;
+    return launch_batch_queue(h->qitems, bp, h->qdev + q, h->qhost[q], h->qdone, h->capacity, q, h->qgrid[q],
+                              h->qstream[q]) == hipSuccess;
+}
+
+// A persistent kernel leaves after a long idle spell; relaunch it when work
+// for it is pending and it has ended.
+static bool queue_keepalive(sfr_ctx* h, int q)
+{
+    if (h->qpending[q] == 0) return true;
+    const hipError_t e = hipStreamQuery(h->qstream[q]);
+    if (e == hipErrorNotReady) return true;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return queue_launch(h, q);
+}
+
+void batch_queue_release(sfr_ctx* h)
+{
+    if (h->qactive) {
+        for (int q = 0; q < 2; ++q) __atomic_store_n(&h->qhost[q]->closed, 1, __ATOMIC_RELEASE);
+        for (int q = 0; q < 2; ++q) (void)hipStreamSynchronize(h->qstream[q]);
+        h->qactive = false;
+    }
+    if (h->qitems) (void)hipHostFree(h->qitems);
+    if (h->qdone) (void)hipHostFree(h->qdone);
+    for (int q = 0; q < 2; ++q) {
+        if (h->qhost[q]) (void)hipHostFree(h->qhost[q]);
+        if (h->qstream[q]) (void)hipStreamDestroy(h->qstream[q]);
+        h->qhost[q] = nullptr;
+        h->qstream[q] = nullptr;
+    }
+    h->qitems = nullptr;
+    h->qdone = nullptr;
+}
+
+static void queue_free_host(sfr_ctx* h)
+{
+    if (h->qitems) (void)hipHostFree(h->qitems);
+    if (h->qdone) (void)hipHostFree(h->qdone);
+    for (int q = 0; q < 2; ++q) {
+        if (h->qhost[q]) (void)hipHostFree(h->qhost[q]);
+        if (h->qstream[q]) (void)hipStreamDestroy(h->qstream[q]);
+        h->qhost[q] = nullptr;
+        h->qstream[q] = nullptr;
+    }
+    h->qitems = nullptr;
+    h->qdone = nullptr;
+}
+
+}  // namespace sfr
+
+extern "C" {
+
+sfr_status sfr_queue_start(sfr_handle h, int32_t grid_large, int32_t grid_small)
+{
+    if (!h || h->magic != 0x53465221u || !h->batch || h->qactive) return SFR_ERR_HANDLE;
+    if (grid_large < 0 || grid_small < 0 || grid_large > 65536 || grid_small > 65536) return SFR_ERR_ARG;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return SFR_ERR_DEVICE;
+    }
+    const int cap = h->capacity;
+    if (!h->qitems) {
+        bool ok = hipHostMalloc((void**)&h->qitems, sizeof(BatchItemDev) * (size_t)cap, hipHostMallocCoherent) ==
+                      hipSuccess &&
+                  hipHostMalloc((void**)&h->qdone, sizeof(int32_t) * (size_t)cap, hipHostMallocCoherent) == hipSuccess;
+        for (int q = 0; q < 2 && ok; ++q)
+            ok = hipHostMalloc((void**)&h->qhost[q], sizeof(BatchQueueHost), hipHostMallocCoherent) == hipSuccess &&
+                 hipStreamCreateWithFlags(&h->qstream[q], hipStreamNonBlocking) == hipSuccess;
+        if (ok && !h->qdev) ok = dev_alloc(h->allocs, h->batch_bytes, (void**)&h->qdev, 2 * sizeof(BatchQueueDev));
+        if (!ok) {
+            (void)hipGetLastError();
+            queue_free_host(h);
+            return SFR_ERR_NOMEM;
+        }
+    }
+    memset(h->qitems, 0, sizeof(BatchItemDev) * (size_t)cap);
+    memset(h->qdone, 0, sizeof(int32_t) * (size_t)cap);
+    for (int q = 0; q < 2; ++q) memset(h->qhost[q], 0, sizeof(BatchQueueHost));
+    BatchQueueDev zero[2];
+    memset(zero, 0, sizeof(zero));
+    if (hipMemcpy(h->qdev, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return SFR_ERR_DEVICE;
+    }
+    h->qgrid[0] = grid_large > 0 ? grid_large : std::max(1, cus * 3 / 4);
+    h->qgrid[1] = grid_small > 0 ? grid_small : std::max(1, cus / 4);
+    h->qfree.clear();
+    for (int32_t s = cap - 1; s >= 0; --s) h->qfree.push_back(s);
+    h->qseq.assign((size_t)cap, 0);
+    h->qwhich.assign((size_t)cap, 0);
+    h->qpending[0] = h->qpending[1] = 0;
+    for (int q = 0; q < 2; ++q)
+        if (!queue_launch(h, q)) {
+            (void)hipGetLastError();
+            h->qhost[0]->closed = 1;
+            h->qhost[1]->closed = 1;
+            (void)hipStreamSynchronize(h->qstream[0]);
+            (void)hipStreamSynchronize(h->qstream[1]);
+            return SFR_ERR_DEVICE;
+        }
+    h->qactive = true;
+    return SFR_OK;
+}
+
+sfr_status sfr_queue_submit(sfr_handle h, const sfr_batch_item* item, int32_t* ticket)
+{
+    if (!h || h->magic != 0x53465221u || !h->batch || !h->qactive) return SFR_ERR_HANDLE;
+    if (!item || !ticket || !item_valid(h, *item)) return SFR_ERR_ARG;
+    if (h->qfree.empty()) return SFR_ERR_BUSY;
+    const int32_t slot = h->qfree.back();
+    h->qfree.pop_back();
+    const int q = (item->r <= 6) ? 1 : 0;
+    BatchItemDev d;
+    build_desc(h, *item, slot, d);
+    if (++h->qnext_seq <= 0) h->qnext_seq = 1;
+    d.seq = h->qnext_seq;
+    h->qitems[slot] = d;
+    h->qseq[slot] = d.seq;
+    h->qwhich[slot] = (int8_t)q;
+    BatchQueueHost* hq = h->qhost[q];
+    const int32_t t = __atomic_load_n(&hq->tail, __ATOMIC_RELAXED);
+    __atomic_store_n(&hq->order[t % h->capacity], slot, __ATOMIC_RELAXED);
+    __atomic_store_n(&hq->tail, t + 1, __ATOMIC_RELEASE);   // descriptor and entry before the tail
+    ++h->qpending[q];
+    *ticket = slot;
+    if (!queue_keepalive(h, q)) return SFR_ERR_DEVICE;
+    return SFR_OK;
+}
+
+sfr_status sfr_queue_poll(sfr_handle h, int32_t ticket, int32_t* done, sfr_info* info, int32_t* status)
+{
+    if (!h || h->magic != 0x53465221u || !h->batch || !h->qactive) return SFR_ERR_HANDLE;
+    if (!done || ticket < 0 || ticket >= h->capacity || h->qseq[ticket] == 0) return SFR_ERR_ARG;
+    *done = 0;
+    const int32_t seq = h->qseq[ticket];
+    if (__atomic_load_n(&h->qdone[ticket], __ATOMIC_ACQUIRE) != seq) {
+        if (!queue_keepalive(h, h->qwhich[ticket])) return SFR_ERR_DEVICE;
+        return SFR_OK;
+    }
+    const BatchItemDev& d = h->qitems[ticket];
+    sfr_status st = (sfr_status)d.status;
+    if (st == SFR_OK && !(d.min_eig_B > 0.0)) st = SFR_WARN_NOT_SPD;
+    if (d.status == 1) st = SFR_WARN_MAXITER;
+    if (status) *status = st;
+    if (info) {
+        memset(info, 0, sizeof(*info));
+        if (st >= 0) {
+            info->iters = d.iters;
+            info->converged = (d.status == SFR_OK) ? 1 : 0;
+            info->rel_residual = d.res;
+            info->min_eig_B = d.min_eig_B;
+            info->mu_final = d.mu_final;
+            info->mu0 = d.mu0;
+            info->orth_err = d.orth_err;
+        }
+    }
+    *done = 1;
+    --h->qpending[(int)h->qwhich[ticket]];
+    h->qseq[ticket] = 0;
+    h->qfree.push_back(ticket);
+    return SFR_OK;
+}
+
+sfr_status sfr_queue_stop(sfr_handle h)
+{
+    if (!h || h->magic != 0x53465221u || !h->batch || !h->qactive) return SFR_ERR_HANDLE;
+    // pending work is drained first (a kernel that left idle is relaunched)
+    bool ok = queue_keepalive(h, 0) && queue_keepalive(h, 1);
+    for (int q = 0; q < 2; ++q) __atomic_store_n(&h->qhost[q]->closed, 1, __ATOMIC_RELEASE);
+    for (int q = 0; q < 2; ++q) ok = (hipStreamSynchronize(h->qstream[q]) == hipSuccess) && ok;
+    h->qactive = false;
+    if (!ok) {
+        (void)hipGetLastError();
+        return SFR_ERR_DEVICE;
     }
     return SFR_OK;
 }

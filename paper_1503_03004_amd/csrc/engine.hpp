@@ -127,6 +127,20 @@ struct sfr_ctx {
     hipStream_t side = nullptr;             // second launch of a batch (narrow items)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     size_t batch_bytes = 0;
+    // queue form (sfr_queue_*): two persistent kernels (queue 0: r > 6 on
+    // the R = 16 matrix-core form; queue 1: r <= 6 on the R = 6 form)
+    bool qactive = false;
+    sfr::BatchItemDev* qitems = nullptr;         // pinned coherent: descriptors and results, per slot
+    int32_t* qdone = nullptr;                    // pinned coherent: per slot, the sequence number of the last solve
+    sfr::BatchQueueHost* qhost[2] = {nullptr, nullptr};   // pinned coherent
+    sfr::BatchQueueDev* qdev = nullptr;          // device: claim counters of the two queues
+    hipStream_t qstream[2] = {nullptr, nullptr};
+    int qgrid[2] = {0, 0};
+    std::vector<int32_t> qfree;                  // free slots
+    std::vector<int32_t> qseq;                   // per slot: sequence number in flight (0: free)
+    std::vector<int8_t> qwhich;                  // per slot: its queue
+    int32_t qnext_seq = 0;
+    int64_t qpending[2] = {0, 0};                // submitted and not yet retired, per queue
     std::vector<void*> allocs;
 };
 
@@ -193,4 +207,6 @@ template <typename T>
 sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, int64_t ldm,
                           const OutputSpec<T>& out, hipStream_t s, bool tsvd = false);
 sfr_status nys_setup(sfr_ctx* h);
+// Stop a batched handle's queue form (if running) and free its host buffers.
+void batch_queue_release(sfr_ctx* h);
 }  // namespace sfr

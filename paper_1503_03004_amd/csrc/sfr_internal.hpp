@@ -45,7 +45,7 @@ constexpr int kMaxGramPartials = 256;
 // Status codes mirrored from the public header (kept numerically equal).
 enum : int32_t {
     kOK = 0, kErrArg = -1, kErrNoMem = -2, kErrDevice = -3, kErrRank = -4,
-    kErrNonFinite = -5, kErrHandle = -6, kErrScratch = -7,
+    kErrNonFinite = -5, kErrHandle = -6, kErrScratch = -7, kErrBusy = -8,
     kWarnMaxIter = 1, kWarnNotSPD = 2
 };
 
@@ -204,6 +204,22 @@ struct BatchItemDev {
     int32_t iters, status;
     double res, min_eig_B, mu_final;
     double orth_err;                 // max(||U^T U - I||_F, ||V^T V - I||_F) of the written factors
+    int32_t seq, reserved;           // queue form: submission number, copied to the done flag
+};
+
+// Queue form of the batched solver (batch_queue_kernel): the claim counter
+// in device memory, and the host's side of the queue in pinned coherent
+// memory (the host writes it while the kernel runs).
+struct BatchQueueDev {
+    int32_t head;      // next entry to claim
+    int32_t pad[63];
+};
+constexpr int kQueueMaxCap = 65536;
+struct BatchQueueHost {
+    int32_t tail;      // entries submitted
+    int32_t closed;    // 1: leave once drained
+    int32_t pad[14];
+    int32_t order[kQueueMaxCap];   // entry e -> slot (ring of the handle's capacity)
 };
 
 struct BatchParams {
@@ -223,6 +239,10 @@ hipError_t launch_batch(BatchItemDev* items, int count, int R, bool narrow, int 
 // orth_err of every successful item of a batch (one workgroup per item),
 // from the factors it wrote.
 hipError_t launch_batch_orth(BatchItemDev* items, int count, hipStream_t s);
+// Persistent queue form: `grid` workgroups; small: the R = 6 two-rows form
+// (r <= 6), else the R = 16 matrix-core form (r <= 16).
+hipError_t launch_batch_queue(BatchItemDev* items, const BatchParams& bp, BatchQueueDev* q, BatchQueueHost* hq,
+                              int32_t* done, int cap, int small, int grid, hipStream_t s);
 
 // Host-side launchers (sweep.hip / small.hip / dense.hip).  The sweep takes
 // an optional start/stop event pair bound to its dispatch.

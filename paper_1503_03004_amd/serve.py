@@ -15,6 +15,10 @@ handles fit in a fraction of the free HBM reported by the runtime.  Requests
 beyond the handles' limits (n > 512, r > 16, m > max_m) are rejected at
 submission.
 
+QueueServer is the continuous form: persistent kernels take requests one by
+one while they run (no launch boundary), admission is by free slot and by
+free HBM at admission time.
+
 This module only schedules: all arithmetic runs in the HIP library.
 """
 from __future__ import annotations
@@ -175,6 +179,116 @@ class BatchServer:
         for s in self.solvers:
             s.close()
         self.solvers = []
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class QueueServer:
+    """Continuous batching on the queue form of a batched handle
+    (sfr_queue_*): persistent kernels take problems one by one while they
+    run, so a request is submitted the moment it arrives (if a workspace
+    slot and device memory are free), starts as soon as a workgroup is free,
+    and is collected as soon as it is solved -- no launch boundary, and no
+    wait for the slowest problem of a batch.
+
+    Admission: a request needs one of the handle's `capacity` workspace
+    slots (sized for the largest admissible problem, all of them cut to fit
+    `hbm_fraction` of the free HBM at construction) and, at admission time,
+    room in device memory for its outputs: the free HBM the runtime reports
+    is read before each round of admissions, and requests wait while it is
+    below `reserve_bytes`.  A request's latency is the time from its arrival
+    to the poll that collects its result.
+
+    This class only schedules: all arithmetic runs in the HIP library."""
+
+    def __init__(self, max_m: int, max_n: int = MAX_N, max_r: int = MAX_R, *, capacity: int = 1024,
+                 hbm_fraction: float = 0.5, reserve_bytes: int = 1 << 30, want_S: bool = True,
+                 grid_large: int = 0, grid_small: int = 0, rho: float = 1.5, mu_bar: float = 1e9,
+                 max_iter: int = 300):
+        import torch
+        if not (1 <= max_n <= MAX_N and 1 <= max_r <= MAX_R and max_m >= 1):
+            raise ValueError("batched limits: n <= 512, r <= 16")
+        free, _ = torch.cuda.mem_get_info()
+        fit = int(free * hbm_fraction) // slot_bytes(max_m, max_n)
+        if fit < 1:
+            raise MemoryError("not enough free device memory for one batched slot")
+        self.capacity = min(int(capacity), fit)
+        self.max_m, self.max_n, self.max_r = int(max_m), int(max_n), int(max_r)
+        self.want_S = want_S
+        self.reserve_bytes = int(reserve_bytes)
+        self.grid = (int(grid_large), int(grid_small))
+        self.solver = BatchSolver(self.capacity, max_m, max_n, max_r, rho=rho, mu_bar=mu_bar, max_iter=max_iter)
+        self.max_in_flight = 0
+        self.held_for_memory = 0
+
+    def admissible(self, req: Request) -> bool:
+        m, n = req.M.shape
+        return m <= self.max_m and n <= self.max_n and 1 <= req.r <= min(self.max_r, m, n)
+
+    def run(self, requests: list[Request]) -> float:
+        """Release the requests at their arrival times (seconds from now),
+        solve them all, and return the wall time of the run.  Each request
+        gets .start (submission), .done (collection, seconds from the start)
+        and .result = (U, B, V, S, Info)."""
+        import torch
+        for q in requests:
+            if not self.admissible(q):
+                raise ValueError("request beyond the server's limits")
+        order = sorted(range(len(requests)), key=lambda i: requests[i].arrival)
+        bs = self.solver
+        bs.queue_start(*self.grid)
+        waiting = collections.deque()
+        in_flight = {}
+        nxt = 0
+        remaining = len(requests)
+        t0 = time.perf_counter()
+        try:
+            while remaining:
+                now = time.perf_counter() - t0
+                while nxt < len(order) and requests[order[nxt]].arrival <= now:
+                    waiting.append(requests[order[nxt]])
+                    nxt += 1
+                progressed = False
+                if waiting:
+                    free, _ = torch.cuda.mem_get_info()
+                    if free < self.reserve_bytes:
+                        self.held_for_memory += 1
+                    else:
+                        while waiting:
+                            q = waiting[0]
+                            t = bs.queue_submit(q.M, q.r, q.lam, q.mu, q.tol, want_S=self.want_S)
+                            if t is None:
+                                break          # every slot in flight: wait for a retirement
+                            waiting.popleft()
+                            q.start = time.perf_counter() - t0
+                            in_flight[t] = q
+                            progressed = True
+                        self.max_in_flight = max(self.max_in_flight, len(in_flight))
+                for t in list(in_flight):
+                    res = bs.queue_poll(t)
+                    if res is not None:
+                        q = in_flight.pop(t)
+                        q.done = time.perf_counter() - t0
+                        q.result = res
+                        remaining -= 1
+                        progressed = True
+                if not progressed:
+                    nxt_t = requests[order[nxt]].arrival if nxt < len(order) else None
+                    wait = 5e-5 if nxt_t is None else min(5e-5, max(0.0, nxt_t - (time.perf_counter() - t0)))
+                    if wait > 0:
+                        time.sleep(wait)
+        finally:
+            bs.queue_stop()
+        return time.perf_counter() - t0
+
+    def close(self):
+        if self.solver is not None:
+            self.solver.close()
+        self.solver = None
 
     def __enter__(self):
         return self

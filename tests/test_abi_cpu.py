@@ -61,7 +61,7 @@ def test_struct_layouts_match_header(tmp_path):
 def test_status_strings_and_version():
     L = sfr.lib()
     assert L.sfr_version().decode().count(".") == 2
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, 1, 2):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, 1, 2):
         s = L.sfr_status_string(code).decode()
         assert s and s != "unknown status"
     assert L.sfr_status_string(99).decode() == "unknown status"
@@ -226,3 +226,17 @@ def test_noalloc_rejects_invalid_arguments_on_host():
     o = B._options("f32")
     o.struct_size = 3
     assert call(opt=o) == B.SFR_ERR_ARG
+
+
+def test_queue_entry_points_reject_bad_handles():
+    """The queue form's entry points check the handle on the host."""
+    L = sfr.lib()
+    info = B.sfr_info()
+    t = ctypes.c_int32(0)
+    d = ctypes.c_int32(0)
+    st = ctypes.c_int32(0)
+    item = B.sfr_batch_item()
+    assert L.sfr_queue_start(None, 0, 0) == B.SFR_ERR_HANDLE
+    assert L.sfr_queue_submit(None, ctypes.byref(item), ctypes.byref(t)) == B.SFR_ERR_HANDLE
+    assert L.sfr_queue_poll(None, 0, ctypes.byref(d), ctypes.byref(info), ctypes.byref(st)) == B.SFR_ERR_HANDLE
+    assert L.sfr_queue_stop(None) == B.SFR_ERR_HANDLE
