@@ -789,6 +789,30 @@ def serving(args):
         Lo = (ro[0].double() @ ro[1] @ ro[2].double().T).cpu().numpy()
         dL.append(rel(Lb, Lo))
         dS.append(rel(rb[3].double().cpu().numpy(), ro[3].double().cpu().numpy()))
+    # ---- the batched BF16 form (BF16 p and Q products while the residual is
+    # above 1e-3, FP32 after) on the same requests, one launch
+    bs16 = sfr.BatchSolver(len(one), 2048, 512, 16, bf16=True, bf16_tol=1e-3)
+    bs16.solve([(q.M, q.r, q.lam, q.mu, q.tol) for q in one], stream=stream)     # warm
+    torch.cuda.synchronize()
+    e0.record(stream)
+    res16 = bs16.solve([(q.M, q.r, q.lam, q.mu, q.tol) for q in one], stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    bf16_ms = e0.elapsed_time(e1)
+    bs16.close()
+    dL16 = []
+    for rb, r16 in zip(res, res16):
+        if rb[4].iters != r16[4].iters:
+            continue
+        Lb = (rb[0].double() @ rb[1] @ rb[2].double().T).cpu().numpy()
+        L16 = (r16[0].double() @ r16[1] @ r16[2].double().T).cpu().numpy()
+        dL16.append(max(rel(L16, Lb), rel(r16[3].double().cpu().numpy(), rb[3].double().cpu().numpy())))
+    bf16_batched = {"solves_per_s": len(one) / (bf16_ms * 1e-3), "launch_ms": bf16_ms, "requests": len(one),
+                    "same_iters_as_fp32_batched": len(dL16),
+                    "max_rel_diff_vs_fp32_batched": max(dL16) if dL16 else None,
+                    "note": "BF16 p and Q products while the residual > 1e-3 (matrix-core form, rank bucket >= 8), "
+                            "FP32 iterations after; same tol as the FP32 per-instance solves"}
+    print(f"[serving] batched BF16 form: {bf16_batched}", file=sys.stderr, flush=True)
     per_instance = {"solves_per_s": single_rate, "requests": len(one), "same_iters": same,
                     "max_rel_diff_L": max(dL) if dL else None, "max_rel_diff_S": max(dS) if dS else None,
                     "batched_one_launch_solves_per_s": len(one) / (launch_ms * 1e-3),
@@ -852,6 +876,7 @@ def serving(args):
         "slowest_request_alone_ms": slowest_alone_ms,
         "launch_server": launch_server,
         "per_instance_fp32": per_instance,
+        "bf16_batched": bf16_batched,
         "autotuned": {f"{'narrow' if k[0] else 'wide'} r<={k[1]}": v for k, v in tuned.items()},
         "median_iters": float(np.median(iters)),
         "failed": len(bad),

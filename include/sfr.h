@@ -222,9 +222,13 @@ typedef struct {
  * most max_m x max_n and rank max_r (FP32 only).
  *   1 <= capacity <= 65536; 1 <= max_n <= 512; 1 <= max_m <= 2^22;
  *   1 <= max_r <= min(16, max_m, max_n).
- *   opt (required): precision must be SFR_F32, nystrom_l 0 and the BF16
- *   fields 0; rho, mu_bar, max_iter and fixed_iters apply to every item
- *   (profile is ignored).
+ *   opt (required): precision must be SFR_F32 and nystrom_l 0; rho,
+ *   mu_bar, max_iter and fixed_iters apply to every item (profile is
+ *   ignored).  bf16, bf16_iters, bf16_tol: as for sfr_create, for the items
+ *   that run the matrix-core form (rank bucket 8 to 16): their p = X V and
+ *   Q = X^T P products take BF16 operands (FP32 accumulation) in the leading
+ *   iterations, up to bf16_iters and while the residual is above bf16_tol,
+ *   and FP32 iterations follow; other items are unaffected.
  * Each slot holds 2 Y buffers (max_m x max_n), 2 P (max_m x 16) and 2 Q
  * (max_n x 16) buffers in device memory; sfr_workspace_bytes reports the
  * total.  Returns SFR_ERR_NOMEM if it does not fit.

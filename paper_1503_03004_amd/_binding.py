@@ -307,13 +307,15 @@ class BatchSolver:
     FR-ADM problems (n <= 512, r <= 16) solved by one kernel launch, one
     workgroup per problem."""
 
-    def __init__(self, capacity, max_m, max_n, max_r, *, rho=1.5, mu_bar=1e9, max_iter=300, fixed_iters=0):
+    def __init__(self, capacity, max_m, max_n, max_r, *, rho=1.5, mu_bar=1e9, max_iter=300, fixed_iters=0,
+                 bf16=False, bf16_iters=0, bf16_tol=0.0):
         self.capacity, self.max_m, self.max_n, self.max_r = int(capacity), int(max_m), int(max_n), int(max_r)
         o = sfr_options()
         o.struct_size = ctypes.sizeof(sfr_options)
         o.precision = SFR_F32
         o.rho, o.mu_bar = float(rho), float(mu_bar)
         o.max_iter, o.fixed_iters = int(max_iter), int(fixed_iters)
+        o.bf16, o.bf16_iters, o.bf16_tol = (1 if bf16 else 0), int(bf16_iters), float(bf16_tol)
         self._h = ctypes.c_void_p(None)
         rc = lib().sfr_create_batch(ctypes.byref(self._h), self.capacity, self.max_m, self.max_n, self.max_r,
                                     ctypes.byref(o))

@@ -16,6 +16,7 @@
 // in HBM; nothing leaves the CU between iterations except those streams.
 // The iteration, its stopping rule and its outputs are those of the
 // single-problem engine (same kernels' arithmetic, FP32 streams).
+#include "mfma_bf16.hpp"
 #include "sfr_internal.hpp"
 #include "small_la.hpp"
 
@@ -164,6 +165,12 @@ __device__ __forceinline__ void batch_solve(BatchItemDev* it, const BatchParams&
         const float mup = (float)mu_prev;
         const float imup = (mode != 0) ? (float)(1.0 / mu_prev) : 0.f;
         const float imuc = (float)(1.0 / mu);
+        // BF16 operands for the p and Q products of this sweep (matrix-core
+        // form only): every sweep while the BF16 phase lasts, i.e. up to
+        // bf16_iters iterations and while the last residual is above bf16_tol
+        // (either 0: no limit of that kind)
+        const bool bfk = MF && bp.bf16 && (bp.bf16_iters <= 0 || k <= bp.bf16_iters) &&
+                         (bp.bf16_tol <= 0.0 || k <= 2 || res > bp.bf16_tol);
 
         // ---------------- sweep k ----------------
         float q[R];
@@ -436,8 +443,12 @@ __device__ __forceinline__ void batch_solve(BatchItemDev* it, const BatchParams&
                                     bf32x4{yn[0], yn[1], yn[2], yn[3]};
                         }
                         *reinterpret_cast<float4*>(Xw + lr * kMXP + 16 * u + 4 * lq) = make_float4(x[0], x[1], x[2], x[3]);
+                        if (bfk) {
+                            pacc = mfma_bf16(va2[u], x, pacc);
+                        } else {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) pacc = bmfma4(va2[u][e], x[e], pacc);
+                            for (int e = 0; e < 4; ++e) pacc = bmfma4(va2[u][e], x[e], pacc);
+                        }
                     }
                 }
                 acc2 += (double)rowacc;
@@ -458,11 +469,21 @@ __device__ __forceinline__ void batch_solve(BatchItemDev* it, const BatchParams&
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (wave + 8 * u < ntile) {
+                        if (bfk) {
+                            float a3[4], b3[4];
 #pragma unroll
-                        for (int s2 = 0; s2 < 4; ++s2) {
-                            const float a3 = Xw[(4 * s2 + lq) * kMXP + 16 * u + lr];
-                            const float b3 = PSA[(4 * s2 + lq) * 16 + lr];
-                            qacc[u] = bmfma4(a3, b3, qacc[u]);
+                            for (int s2 = 0; s2 < 4; ++s2) {
+                                a3[s2] = Xw[(4 * s2 + lq) * kMXP + 16 * u + lr];
+                                b3[s2] = PSA[(4 * s2 + lq) * 16 + lr];
+                            }
+                            qacc[u] = mfma_bf16(a3, b3, qacc[u]);
+                        } else {
+#pragma unroll
+                            for (int s2 = 0; s2 < 4; ++s2) {
+                                const float a3 = Xw[(4 * s2 + lq) * kMXP + 16 * u + lr];
+                                const float b3 = PSA[(4 * s2 + lq) * 16 + lr];
+                                qacc[u] = bmfma4(a3, b3, qacc[u]);
+                            }
                         }
                     }
                 }

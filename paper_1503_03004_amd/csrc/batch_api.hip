@@ -75,7 +75,10 @@ sfr_status sfr_create_batch(sfr_handle* out, int32_t capacity, int64_t max_m, in
     if (!opt || opt->struct_size != sizeof(sfr_options)) return SFR_ERR_ARG;
     sfr_options o = *opt;
     if (o.precision != SFR_F32 || o.nystrom_l != 0) return SFR_ERR_ARG;
-    if (o.bf16 != 0 || o.bf16_iters != 0 || o.bf16_tol != 0.0) return SFR_ERR_ARG;   // FP32 operands only
+    // BF16 operands for the p and Q products of the matrix-core form (rank
+    // buckets 8 to 16) in the leading iterations; FP32 iterations after
+    if (o.bf16_iters < 0 || o.bf16_iters > 100000 || !(o.bf16_tol >= 0.0) || o.bf16_tol > 1e300) return SFR_ERR_ARG;
+    if (o.bf16 == 0 && (o.bf16_iters != 0 || o.bf16_tol != 0.0)) return SFR_ERR_ARG;
     if (capacity < 1 || capacity > 65536) return SFR_ERR_ARG;
     if (max_m < 1 || max_m > (1 << 22) || max_n < 1 || max_n > 512) return SFR_ERR_ARG;
     if (max_r < 1 || max_r > 16 || max_r > max_m || max_r > max_n) return SFR_ERR_ARG;
@@ -95,6 +98,9 @@ sfr_status sfr_create_batch(sfr_handle* out, int32_t capacity, int64_t max_m, in
     h->prm.mu_bar = o.mu_bar;
     h->prm.max_iter = o.max_iter;
     h->prm.fixed_iters = o.fixed_iters;
+    h->prm.bf16 = o.bf16 != 0;
+    h->prm.bf16_iters = o.bf16_iters;
+    h->prm.bf16_tol = o.bf16_tol;
     h->ldy = (max_n + 3) / 4 * 4;
     const size_t ny = (size_t)max_m * h->ldy, np = (size_t)max_m * 16, nq = (size_t)max_n * 16;
     bool ok = dev_alloc(h->allocs, h->batch_bytes, (void**)&h->items_d, sizeof(BatchItemDev) * (size_t)capacity);
@@ -164,6 +170,9 @@ sfr_status sfr_solve_batch(sfr_handle h, const sfr_batch_item* items, int32_t co
     bp.mu_bar = h->prm.mu_bar;
     bp.max_iter = h->prm.max_iter;
     bp.fixed_iters = h->prm.fixed_iters;
+    bp.bf16 = h->prm.bf16 ? 1 : 0;
+    bp.bf16_iters = h->prm.bf16_iters;
+    bp.bf16_tol = h->prm.bf16_tol;
     const size_t bytes = sizeof(BatchItemDev) * (size_t)count;
     const int nn = count - nw;
     bool ok = hipMemcpyAsync(h->items_d, h->items_h, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
@@ -227,6 +236,9 @@ sfr_status sfr_tune_batch(sfr_handle h, const sfr_batch_item* items, int32_t cou
     bp.mu_bar = h->prm.mu_bar;
     bp.max_iter = h->prm.max_iter;
     bp.fixed_iters = kTuneIters;
+    bp.bf16 = 0;
+    bp.bf16_iters = 0;
+    bp.bf16_tol = 0.0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);
@@ -294,6 +306,9 @@ static bool queue_launch(sfr_ctx* h, int q)
     bp.mu_bar = h->prm.mu_bar;
     bp.max_iter = h->prm.max_iter;
     bp.fixed_iters = h->prm.fixed_iters;
+    bp.bf16 = h->prm.bf16 ? 1 : 0;
+    bp.bf16_iters = h->prm.bf16_iters;
+    bp.bf16_tol = h->prm.bf16_tol;
     return launch_batch_queue(h->qitems, bp, h->qdev + q, h->qhost[q], h->qdone, h->capacity, q, h->qgrid[q],
                               h->qstream[q]) == hipSuccess;
 }

@@ -225,6 +225,10 @@ struct BatchQueueHost {
 struct BatchParams {
     double rho, mu_bar;
     int32_t max_iter, fixed_iters;
+    // BF16-operand p and Q products (matrix-core form) for the leading
+    // iterations: up to bf16_iters and while the residual is above bf16_tol
+    int32_t bf16, bf16_iters;
+    double bf16_tol;
 };
 
 // Forms of the batched kernel's band loop (all exact; they differ in speed):

@@ -30,6 +30,7 @@
 //     Q stays in registers until the end.
 // HBM traffic per element: read M, read Y_{k-1}, write Y_k.
 #include "exchange.hpp"
+#include "mfma_bf16.hpp"
 #include "sfr_internal.hpp"
 
 #include <hip/hip_ext.h>
@@ -90,27 +91,6 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// BF16-operand form (FP32 accumulation): v_mfma_f32_16x16x16_bf16 takes four
-// consecutive K entries per lane where the FP32 instruction takes one, so the
-// four operands a lane feeds to four FP32 steps go to one BF16 instruction.
-// The K index is then visited in another order, the same for A and B, which
-// leaves the contraction unchanged.
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ short to_bf16(float x)
-{
-    // round to nearest, ties to even (finite inputs)
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
-
-__device__ __forceinline__ f32x4 mfma_bf16(const float (&a)[4], const float (&b)[4], f32x4 c)
-{
-    const bf16x4 av = {to_bf16(a[0]), to_bf16(a[1]), to_bf16(a[2]), to_bf16(a[3])};
-    const bf16x4 bv = {to_bf16(b[0]), to_bf16(b[1]), to_bf16(b[2]), to_bf16(b[3])};
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
-}
 
 // BF: the p and Q contractions take BF16 operands (FP32 accumulation); the
 // l reconstruction, M, Y and every stored value stay FP32.

@@ -132,7 +132,8 @@ def test_create_rejects_wrong_struct_size():
     ((4, 100, 64, 4), {"max_iter": -1}),
     ((4, 100, 64, 4), {"fixed_iters": -2}),
     ((4, 100, 64, 4), {"struct_size": 3}),
-    ((4, 100, 64, 4), {"bf16": 1}),       # the batched kernel takes FP32 operands only
+    ((4, 100, 64, 4), {"bf16_iters": 3}),                # BF16 fields without bf16
+    ((4, 100, 64, 4), {"bf16": 1, "bf16_tol": -1.0}),
 ])
 def test_create_batch_rejects_invalid_arguments(args, kw):
     o = B.sfr_options()

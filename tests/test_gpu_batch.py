@@ -313,3 +313,37 @@ def test_autotune_rejects_items_beyond_the_limits():
         with pytest.raises(sfr.SFRError) as e:
             bs.autotune([(torch.from_numpy(p["M"]).cuda(), 5, p["lam"], p["mu"], 1e-6)])
         assert e.value.code == sfr.SFR_ERR_ARG
+
+
+BF16_SHAPES = [(600, 300, 8), (900, 512, 16), (400, 200, 12), (1024, 260, 10)]
+
+
+def test_batched_bf16_every_iteration():
+    """Batched BF16 form, every iteration in BF16 (p = X V and Q = X^T P on
+    BF16 operands, FP32 accumulation, l in FP32): the unrefined result
+    within 1e-3 of the oracle at the same iteration count."""
+    probs = [make(m, n, r, seed=300 + i) for i, (m, n, r) in enumerate(BF16_SHAPES)]
+    with sfr.BatchSolver(len(probs), 1024, 512, 16, fixed_iters=12, bf16=True) as bs:
+        out = run_batch(bs, probs)
+    for p, g in zip(probs, out):
+        o = oracle.fradm(p["M"].astype(np.float64), p["r"], p["lam"], p["mu"], fixed_iters=12)
+        eL = rel(g["U"] @ g["B"] @ g["V"].T, o["U"] @ o["B"] @ o["V"].T)
+        eS = rel(g["S"], o["S"])
+        print(f"batched all-BF16 {p['M'].shape} r={p['r']}: errL {eL:.2e} errS {eS:.2e}")
+        assert eL <= 1e-3 and eS <= 1e-3
+        assert eL > 1e-6        # the BF16 operands are really in use
+
+
+def test_batched_bf16_head_then_fp32():
+    """Batched BF16 form with FP32 iterations after (BF16 while the residual
+    is above 1e-3), tolerance-driven to 1e-6: within one iteration of the
+    oracle's stop and within the FP32 bar of the oracle at the same count."""
+    probs = [make(m, n, r, seed=400 + i) for i, (m, n, r) in enumerate(BF16_SHAPES)]
+    with sfr.BatchSolver(len(probs), 1024, 512, 16, bf16=True, bf16_tol=1e-3) as bs:
+        out = run_batch(bs, probs, tol=1e-6)
+    for p, g in zip(probs, out):
+        Md = p["M"].astype(np.float64)
+        ot = oracle.fradm(Md, p["r"], p["lam"], p["mu"], tol=1e-6)
+        assert g["info"].status == sfr.SFR_OK
+        assert abs(g["info"].iters - ot["iters"]) <= 1, (g["info"].iters, ot["iters"])
+        check_vs_oracle(p, g, g["info"].iters, "batched BF16 head")
