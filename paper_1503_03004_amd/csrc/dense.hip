@@ -309,6 +309,7 @@ __global__ void __launch_bounds__(256) orth_partial_kernel(const DevState* st, c
                                                            int r, double* Up, int nu, double* Vp, int nv)
 {
     if (st && (!st->done || st->status < 0 || st->exch_timeout)) return;
+    __shared__ double acc_s[256];
     const bool isU = (int)blockIdx.x < nu;
     const int b = isU ? (int)blockIdx.x : (int)blockIdx.x - nu;
     const int nb = isU ? nu : nv;
@@ -318,12 +319,26 @@ __global__ void __launch_bounds__(256) orth_partial_kernel(const DevState* st, c
     double* out = (isU ? Up : Vp) + (size_t)b * E;
     const int per = (rows + nb - 1) / nb;
     const int i0 = b * per, i1 = min(rows, i0 + per);
-    for (int e = threadIdx.x; e < E; e += 256) {
-        int p, q;
-        tri_index(e, r, p, q);
-        double acc = 0.0;
-        for (int i = i0; i < i1; ++i) acc = fma((double)X[(int64_t)i * r + p], (double)X[(int64_t)i * r + q], acc);
-        out[e] = acc;
+    // every thread works: entry e = t % E over the rows of phase t / E
+    // (rows i0 + ph, i0 + ph + P, ...), the phases added in order after
+    const int P = E >= 256 ? 1 : 256 / E;
+    for (int e0 = 0; e0 < E; e0 += 256 / P) {
+        const int t = threadIdx.x;
+        const int e = e0 + t % (256 / P), ph = t / (256 / P);
+        double a = 0.0;
+        if (ph < P && e < E) {
+            int p, q;
+            tri_index(e, r, p, q);
+            for (int i = i0 + ph; i < i1; i += P) a = fma((double)X[(int64_t)i * r + p], (double)X[(int64_t)i * r + q], a);
+        }
+        acc_s[t] = a;
+        __syncthreads();
+        if (t < 256 / P && e0 + t < E) {
+            double s = 0.0;
+            for (int k = 0; k < P; ++k) s += acc_s[k * (256 / P) + t];
+            out[e0 + t] = s;
+        }
+        __syncthreads();
     }
 }
 
@@ -337,9 +352,22 @@ __global__ void __launch_bounds__(256) orth_final_kernel(const DevState* st, int
     for (int e = threadIdx.x; e < E; e += 256) {
         int p, q;
         tri_index(e, r, p, q);
+        // partials added in order, eight loads in flight at a time
         double gu = 0.0, gv = 0.0;
-        for (int b = 0; b < nu; ++b) gu += Up[(size_t)b * E + e];
-        for (int b = 0; b < nv; ++b) gv += Vp[(size_t)b * E + e];
+        for (int b0 = 0; b0 < nu; b0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = Up[(size_t)min(b0 + u, nu - 1) * E + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) gu += (b0 + u < nu) ? v[u] : 0.0;
+        }
+        for (int b0 = 0; b0 < nv; b0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = Vp[(size_t)min(b0 + u, nv - 1) * E + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) gv += (b0 + u < nv) ? v[u] : 0.0;
+        }
         const double w = (p == q) ? 1.0 : 2.0;
         const double du = gu - (p == q ? 1.0 : 0.0), dv = gv - (p == q ? 1.0 : 0.0);
         su += w * du * du;
@@ -358,12 +386,15 @@ __global__ void __launch_bounds__(256) orth_final_kernel(const DevState* st, int
     if (threadIdx.x == 0) *out = fmax(sqrt(red[0][0]), sqrt(red[1][0]));
 }
 
+// At most this many row blocks per factor: the final sum stays short.
+constexpr int kOrthParts = 32;
+
 template <typename T>
 hipError_t launch_orth(const DevState* st, const T* U, int m, const T* V, int n, int r, double* Up, int nu,
                        double* Vp, int nv, double* out, hipStream_t s)
 {
-    nu = std::max(1, std::min(nu, m));
-    nv = std::max(1, std::min(nv, n));
+    nu = std::max(1, std::min({nu, m, kOrthParts}));
+    nv = std::max(1, std::min({nv, n, kOrthParts}));
     hipLaunchKernelGGL(orth_partial_kernel<T>, dim3((unsigned)(nu + nv)), dim3(256), 0, s, st, U, m, V, n, r, Up,
                        nu, Vp, nv);
     hipLaunchKernelGGL(orth_final_kernel, dim3(1), dim3(256), 0, s, st, r, Up, nu, Vp, nv, out);
