@@ -163,14 +163,19 @@ static sfr_status configure(Engine& e)
     e.exch_words = std::max(exch_words_of(e, e.cfg[0]), exch_words_of(e, e.cfg[1]));
     // Gram launch shape.  Q: rows per workgroup such that each thread sums
     // about 32 cluster partials, with as many workgroups as that takes.
-    // P: at least kTPB / R rows per workgroup.
+    // P: one segment of the Gram kernel (kGramU kTPB / R rows) per workgroup.
     const int rows = kTPB / e.R;
     const int qrows = std::max(1, std::min(rows, (kTPB * 32) / (e.R * std::max(1, e.max_ncl))));
     e.nqb = std::max(1, std::min((e.ne + qrows - 1) / qrows, kMaxGramPartials));
     e.rows_q = (e.ne + e.nqb - 1) / e.nqb;
-    e.npb = std::max(1, std::min((e.m + rows - 1) / rows, kMaxGramPartials));
+    const int prows = (kGramU * kTPB) / e.R;
+    e.npb = std::max(1, std::min((e.m + prows - 1) / prows, kMaxGramPartials));
     e.rows_p = (e.m + e.npb - 1) / e.npb;
     e.E = e.R * (e.R + 1) / 2;
+    // the step kernel splits each of the 2E entries over nseg threads
+    const int nseg = (2 * e.E >= kStepTPB) ? 1 : kStepTPB / (2 * e.E);
+    e.gram_reduce = std::max(e.npb, e.nqb) > kStepPartialLoads * nseg;
+    if (step_prepare(e.R) != hipSuccess) return SFR_ERR_DEVICE;
     return SFR_OK;
 }
 
@@ -361,12 +366,14 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         g.m = e.m; g.n = e.ne; g.ncl = sc.ncl;
         g.rows_q = e.rows_q; g.nqb = e.nqb; g.rows_p = e.rows_p; g.npb = e.npb;
         HIPCHK(launch_gram<T>(g, e.R, s));
+        if (e.gram_reduce) HIPCHK(launch_gram_reduce(e.st, e.GQpart, e.nqb, e.GPpart, e.npb, e.E, s));
         StepArgs sa;
         sa.st = e.st;
-        sa.GPpart = e.GPpart; sa.npb = e.npb;
-        sa.GQpart = e.GQpart; sa.nqb = e.nqb;
+        sa.GPpart = e.GPpart; sa.npb = e.gram_reduce ? 1 : e.npb;
+        sa.GQpart = e.GQpart; sa.nqb = e.gram_reduce ? 1 : e.nqb;
         sa.dy2part = e.dy2part; sa.ndy = sc.grid;
         sa.res_hist = e.res_hist;
+        sa.ns_kappa = e.f64 ? kNsKappaF64 : kNsKappaF32;
         sa.dk_tau = e.f64 ? kDkTauF64 : kDkTauF32;
         HIPCHK(launch_step(sa, e.R, s));
         return SFR_OK;

@@ -35,6 +35,7 @@ struct Engine {
     int tag_stride = 0;
     int max_grid = 0, max_ncl = 0;
     int rows_q = 0, nqb = 0, rows_p = 0, npb = 0, E = 0;
+    bool gram_reduce = false;   // the Gram partials are summed before the step kernel
     int hist_len = 0;
     // workspace
     void* Y[2] = {nullptr, nullptr};

@@ -41,6 +41,11 @@ constexpr uint32_t kSpinLimit = 1u << 24;
 constexpr int kMaxDyPartials = 2048;
 // Upper bound on the Gram partials of one pass (one per Gram workgroup).
 constexpr int kMaxGramPartials = 256;
+// Threads of the step kernel.  It adds the Gram partials itself while each
+// of its threads has at most kStepPartialLoads of them to load (one round
+// of loads); beyond that a reduction kernel adds them first.
+constexpr int kStepTPB = 512;
+constexpr int kStepPartialLoads = 32;
 
 // Status codes mirrored from the public header (kept numerically equal).
 enum : int32_t {
@@ -134,22 +139,29 @@ struct GramArgs {
     int32_t npb;         // workgroups for P
 };
 
-// FP64 r x r step (one workgroup).
-// Relative off-diagonal size at which the Jacobi sweeps of the step's
-// inverse square roots stop, the rest being a second-order expansion with
-// relative error O(tau^3 r^2): about 1e-16 for FP64 solves; for FP32 solves
-// about 1e-11 r^2, far below the FP32 rounding of the m x n work (~1e-7),
-// and it saves about one sweep per decomposition.
+// Relative off-diagonal size at which the Jacobi sweeps of an inverse
+// square root stop, the rest being a second-order expansion with relative
+// error O(tau^3 r^2): about 1e-16 for FP64 solves; for FP32 solves about
+// 1e-11 r^2, far below the FP32 rounding of the m x n work (~1e-7).
 constexpr double kDkTauF64 = 4e-6;
 constexpr double kDkTauF32 = 2e-4;
+// The step kernel's Newton-Schulz inverse square roots are accurate to
+// about cond eps; above these bounds on the condition number of the Gram
+// products it takes the Jacobi path instead (result error ~1e-10 at the
+// FP64 bound, ~1e-6 at the FP32 one, against parity bars of 1e-9 and 1e-5).
+constexpr double kNsKappaF64 = 1e6;
+constexpr double kNsKappaF32 = 1e10;
 
+// FP64 r x r step (one workgroup).  It adds npb (nqb) partials of G_P
+// (G_Q); 1 once launch_gram_reduce has left the sums in partial 0.
 struct StepArgs {
     DevState* st;
     const double* GPpart; int32_t npb;
     const double* GQpart; int32_t nqb;
     const double* dy2part; int32_t ndy;
     double* res_hist;     // res_hist[k-1] = residual of iteration k
-    double dk_tau;        // kDkTauF64 or kDkTauF32
+    double ns_kappa;      // kNsKappaF64 or kNsKappaF32
+    double dk_tau;        // kDkTauF64 or kDkTauF32 (Jacobi path)
 };
 
 // The ping-pong buffers of one solve (P, Q: m x R, n x R; Y: m x n with
@@ -255,6 +267,10 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int R, int grid, size_t lds, hipS
                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 hipError_t launch_gram(const GramArgs<T>& a, int R, hipStream_t s);
+// Sum the nqb (npb) partials of each of the E entries of G_Q (G_P) into
+// partial 0, in a fixed order.
+hipError_t launch_gram_reduce(const DevState* st, double* GQpart, int nqb, double* GPpart, int npb, int E,
+                              hipStream_t s);
 template <typename T>
 size_t sweep_lds_bytes_c(int R, int lpr, int W, int c);
 template <typename T>
@@ -279,6 +295,9 @@ hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int tiles, int gr
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool bf16 = false);
 
 hipError_t launch_step(const StepArgs& a, int R, hipStream_t s);
+// Once per process and rank bucket before the first launch_step (the step
+// kernel's LDS size).
+hipError_t step_prepare(int R);
 hipError_t launch_final_small(DevState* st, int R, hipStream_t s);
 // Largest eigenvalue of the returned B into st->max_eig_B.
 hipError_t launch_max_eig(DevState* st, int R, hipStream_t s);

@@ -7,93 +7,136 @@
 //   B  = Sym(C1 B0 G_Q K C2)                                  (eq. (8))
 // and the next sweep rebuilds L rows as a_i = P_i (B0 C1 B).
 //
-// Inverse square roots come from the one-wavefront Jacobi eigendecomposition
-// of small_la.hpp, started from the eigenbasis found in the previous
-// iteration: the Grams change little from one iteration to the next, so one
-// or two sweeps suffice.
-#include "small_la.hpp"
+// The products run on the matrix cores and the inverse square roots by
+// Newton-Schulz (small_ns.hpp); Gram products too ill-conditioned for its
+// accuracy take the warm-started Jacobi eigendecompositions of small_la.hpp
+// (the eigenbases of the last such step are kept in the state).
+#include "small_ns.hpp"
 
 namespace sfr {
 
-// Workgroup size of the step kernel: the partial sums are latency bound,
-// so as many threads as the r x r algebra's register use allows (1024
-// threads leave 128 registers a lane, which buckets 5 and 12 and up exceed).
-// Up to R = 4 (2E <= 20 Gram entries) 256 threads already take every
-// partial in one round of loads, and the workgroup barriers cost less.
-template <int R>
-constexpr int step_tpb() { return R <= 4 ? 256 : ((R <= 10 && R != 5) ? 1024 : 512); }
-
-// The r x r matrices are held R x R (R the rank bucket, a compile-time
-// size) with an identity block on the padded indices: every product and
-// inverse square root below is then block diagonal and exact on the
-// leading r x r block, and the padded block is dropped when the transforms
-// are stored.
-template <int R>
-__global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
+// LDS of the step kernel: 14 RT x LDP matrices, the two Gram triangles and
+// their segment sums, the residual wave sums, the reduction slots and the
+// Jacobi scratch.
+struct StepLds {
+    size_t mats, tri, seg, red, cs, wbuf, total;
+};
+__host__ __device__ inline StepLds step_lds(int R)
 {
-    DevState* st = a.st;
-    if (st->done) return;
-    if (st->exch_timeout) {   // a sweep hit its wait bound: stop the solve
-        if (threadIdx.x == 0) st->done = 1;
-        return;
-    }
-    constexpr int TPB = step_tpb<R>();
-    // threads of the r x r algebra: one wavefront up to R = 12, the whole
-    // workgroup above (each Jacobi round then has >= 128 2x2 blocks)
-    constexpr int NT = (R >= 16) ? TPB : 64;
-    constexpr int E = R * (R + 1) / 2;
-    __shared__ double Gp[R * LDP], Gq[R * LDP], Bm[R * LDP], C1[R * LDP];
-    __shared__ double C2[R * LDP], Km[R * LDP], T1[R * LDP], T2[R * LDP];
-    __shared__ double Ev[R * LDP], Ev2[R * LDP];
-    __shared__ double seg[2 * E > TPB ? 2 * E : TPB];
-    __shared__ double tri[2][E];
-    __shared__ double red[TPB / 64];
-    __shared__ __align__(16) double cs[2 * 16];
-    __shared__ double wbuf[kMaxR];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r = st->r, k = st->k;
+    const int RT = R <= 16 ? 16 : 32;
+    const int E = R * (R + 1) / 2;
+    StepLds L;
+    size_t o = 0;
+    L.mats = o; o += sizeof(double) * 14 * (size_t)RT * LDP;
+    L.tri = o;  o += sizeof(double) * 2 * (size_t)E;
+    L.seg = o;  o += sizeof(double) * (size_t)(2 * E > kStepTPB ? 2 * E : kStepTPB);
+    L.red = o;  o += sizeof(double) * (kStepTPB / 64 + 12);
+    L.cs = o;   o += sizeof(double) * 2 * 16;
+    L.wbuf = o; o += sizeof(double) * kMaxR;
+    L.total = o;
+    return L;
+}
 
-    // ---- one round of loads: B0 and the two warm-start bases (wave 0, into
-    // registers), the residual partials and the Gram partials.  The Gram
-    // partials (upper triangles) are summed in a fixed order: thread w owns
-    // entry e of Gram g over the partials b = s, s + nseg, ... (segment s),
-    // then the nseg segment sums are added in order.
-    // Every load below is unconditional (indices are clamped into range and
-    // the surplus masked afterwards), so each thread has all of its loads in
-    // flight at once: one memory round trip for the lot.
-    constexpr int NPL = (R * R + NT - 1) / NT;
-    double rb[NPL], re1[NPL], re2[NPL];
-    if (tid < NT) {
+// The r x r matrices are held RT x RT (RT = 16 or 32 >= R, the rank
+// bucket) with an identity block on the padded indices: every product and
+// inverse square root is then block diagonal and exact on the leading r x r
+// block, and the padded block is dropped when the transforms are stored.
+template <int R>
+__global__ void __launch_bounds__(kStepTPB) step_kernel(StepArgs a)
+{
+    constexpr int NB = ns_nb<R>();
+    constexpr int RT = 16 * NB;
+    constexpr int TPB = kStepTPB;
+    // threads of the r x r algebra: one wavefront, or the whole workgroup
+    // (four wavefronts compute, the rest take part in the barriers)
+    constexpr int NT = (NB == 1) ? 64 : TPB;
+    constexpr int E = R * (R + 1) / 2;
+    constexpr int MS = RT * LDP;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const StepLds SL = step_lds(R);
+    double* mats = reinterpret_cast<double*>(smem + SL.mats);
+    double* Bm = mats;
+    double* Gp = mats + 1 * MS;
+    double* Gq = mats + 2 * MS;
+    double* X = mats + 3 * MS;
+    double* Am = mats + 4 * MS;
+    double* C = mats + 5 * MS;
+    double* Y0 = mats + 6 * MS;
+    double* Y1 = mats + 7 * MS;
+    double* Z0 = mats + 8 * MS;
+    double* Z1 = mats + 9 * MS;
+    double* Tm = mats + 10 * MS;
+    double* T1 = mats + 11 * MS;
+    double* R1 = mats + 12 * MS;
+    double* Km = mats + 13 * MS;
+    double* tri = reinterpret_cast<double*>(smem + SL.tri);
+    double* seg = reinterpret_cast<double*>(smem + SL.seg);
+    double* red = reinterpret_cast<double*>(smem + SL.red);
+    double* nsred = red + TPB / 64;
+    double* cs = reinterpret_cast<double*>(smem + SL.cs);
+    double* wbuf = reinterpret_cast<double*>(smem + SL.wbuf);
+
+    DevState* st = a.st;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const NsLane<NB> L;
+
+    // ---- one round of loads: the previous B (the algebra's lanes, their
+    // output block), the residual partials and the Gram partials.  Every
+    // load is unconditional (indices clamped into range, the surplus masked
+    // afterwards), so each thread has its loads in flight together.
+    double rb[4];
 #pragma unroll
-        for (int u = 0; u < NPL; ++u) {
-            const int e = min(tid + NT * u, R * R - 1);
-            const int i = e / R, j = e % R;
-            rb[u] = st->B[i * kMaxR + j];
-            re1[u] = st->E1[i * kMaxR + j];
-            re2[u] = st->E2[i * kMaxR + j];
-        }
-    }
+    for (int e = 0; e < 4; ++e) rb[e] = st->B[L.row(e) * kMaxR + L.col()];
     constexpr int DYU = (kMaxDyPartials + TPB - 1) / TPB;
     double dyv[DYU];
 #pragma unroll
     for (int u = 0; u < DYU; ++u) dyv[u] = a.dy2part[min(tid + u * TPB, a.ndy - 1)];
+    const int32_t done0 = st->done, tmo = st->exch_timeout;
+    const int r = st->r, k = st->k, tsvd = st->tsvd;
+    const int fixed_iters = st->fixed_iters, max_iter = st->max_iter;
+    const double mu = st->mu, mu_prev = st->mu_prev, nrmM = st->nrmM, tol = st->tol;
+    const double rho = st->rho, mu_bar = st->mu_bar;
+    if (done0) return;
+    if (tmo) {   // a sweep hit its wait bound: stop the solve
+        if (tid == 0) st->done = 1;
+        return;
+    }
+    // Gram partials of the 2E upper-triangle entries of (G_P, G_Q).  Summed
+    // already (one partial each): thread w takes entries w, w + TPB, ...
+    // Otherwise thread w owns entry e of one Gram over the partials
+    // b = s, s + nseg, ... (segment s), and the segment sums are added in
+    // segment order after the barrier.
+    const bool summed = a.npb == 1 && a.nqb == 1;
+    constexpr int EPT = (2 * E + TPB - 1) / TPB;
     constexpr int nseg = (2 * E >= TPB) ? 1 : TPB / (2 * E);
-    constexpr int PER = (kMaxGramPartials + nseg - 1) / nseg;   // partials per segment
-    constexpr int CH = PER < 32 ? PER : 32;                      // loads in flight
-    for (int w = tid; w < 2 * E * nseg; w += TPB) {
-        const int g = w / (E * nseg), rem = w % (E * nseg);
-        const int sg = rem / E, e = rem % E;
-        const double* part = g ? a.GQpart : a.GPpart;
-        const int count = g ? a.nqb : a.npb;
-        double s = 0.0;
-        for (int u0 = 0; u0 < PER; u0 += CH) {
-            double v[CH];
+    constexpr int PER = (kMaxGramPartials + nseg - 1) / nseg;
+    constexpr int CH = PER < 32 ? PER : 32;
+    if (summed) {
+        double gv[EPT];
 #pragma unroll
-            for (int u = 0; u < CH; ++u) v[u] = part[(size_t)min(sg + (u0 + u) * nseg, count - 1) * E + e];
-#pragma unroll
-            for (int u = 0; u < CH; ++u) s += (sg + (u0 + u) * nseg < count) ? v[u] : 0.0;
+        for (int u = 0; u < EPT; ++u) {
+            const int w = min(tid + u * TPB, 2 * E - 1);
+            gv[u] = (w < E) ? a.GPpart[w] : a.GQpart[w - E];
         }
-        seg[w] = s;
+#pragma unroll
+        for (int u = 0; u < EPT; ++u)
+            if (tid + u * TPB < 2 * E) tri[tid + u * TPB] = gv[u];
+    } else {
+        for (int w = tid; w < 2 * E * nseg; w += TPB) {
+            const int g = w / (E * nseg), rem = w % (E * nseg);
+            const int sg = rem / E, e = rem % E;
+            const double* part = g ? a.GQpart : a.GPpart;
+            const int count = g ? a.nqb : a.npb;
+            double sum = 0.0;
+            for (int u0 = 0; u0 * nseg < count; u0 += CH) {
+                double v[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) v[u] = part[(size_t)min(sg + (u0 + u) * nseg, count - 1) * E + e];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) sum += (sg + (u0 + u) * nseg < count) ? v[u] : 0.0;
+            }
+            seg[w] = sum;
+        }
     }
 
     // ---- convergence test of iteration k-1 (or ||M||_F on the first pass)
@@ -114,15 +157,15 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
             return;
         }
         if (tid == 0) st->nrmM = nrm;
-    } else if (!st->tsvd) {
-        const double res = sqrt(total) / (st->mu_prev * st->nrmM);
+    } else if (!tsvd) {
+        const double res = sqrt(total) / (mu_prev * nrmM);
         const int kdone = k - 1;
         bool stop = false;
         int32_t status = kOK;
         if (!isfinite(res)) { stop = true; status = kErrNonFinite; }
-        else if (st->fixed_iters > 0) { stop = kdone >= st->fixed_iters; }
-        else if (res <= st->tol) { stop = true; }
-        else if (kdone >= st->max_iter) { stop = true; status = kWarnMaxIter; }
+        else if (fixed_iters > 0) { stop = kdone >= fixed_iters; }
+        else if (res <= tol) { stop = true; }
+        else if (kdone >= max_iter) { stop = true; status = kWarnMaxIter; }
         if (tid == 0) {
             a.res_hist[kdone - 1] = res;
             st->res = res;
@@ -133,89 +176,100 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
         }
     }
 
-    // ---- Grams: add the segment sums
-    for (int w = tid; w < 2 * E; w += TPB) {
-        const int g = w / E, e = w % E;
-        double s = 0.0;
+    // ---- B_0, G_P and G_Q into LDS, identity on the padded indices
+    if (!summed) {
+        for (int w = tid; w < 2 * E; w += TPB) {
+            const int g = w / E, e = w % E;
+            double sum = 0.0;
 #pragma unroll
-        for (int sg = 0; sg < nseg; ++sg) s += seg[(g * nseg + sg) * E + e];
-        tri[g][e] = s;
+            for (int sg = 0; sg < nseg; ++sg) sum += seg[(g * nseg + sg) * E + e];
+            tri[w] = sum;
+        }
+        __syncthreads();
+    }
+    if (L.act) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Bm[L.row(e) * LDP + L.col()] = rb[e];
+    }
+    for (int e = tid; e < 2 * RT * RT; e += TPB) {
+        const int g = e / (RT * RT), ij = e % (RT * RT);
+        const int i = ij / RT, j = ij % RT;
+        const int x = i < j ? i : j, y = i < j ? j : i;
+        double v = (i == j) ? 1.0 : 0.0;
+        if (i < r && j < r) v = tri[g * E + x * R - x * (x - 1) / 2 + (y - x)];
+        (g ? Gq : Gp)[i * LDP + j] = v;
     }
     __syncthreads();
-    if (tid >= NT) return;
+    if constexpr (NB == 1) {
+        if (wave != 0) return;
+    }
 
-    // ---- the r x r algebra: NT threads from here on
-#pragma unroll
-    for (int u = 0; u < NPL; ++u) {
-        const int e = tid + NT * u;
-        if (e >= R * R) break;
-        const int i = e / R, j = e % R;
-        const int x = i < j ? i : j, y = i < j ? j : i;
-        const int t = x * R - x * (x - 1) / 2 + (y - x);   // upper-triangle index of (x, y)
-        const bool pad = (i >= r) || (j >= r);
-        Gp[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : tri[0][t];
-        Gq[i * LDP + j] = pad ? (i == j ? 1.0 : 0.0) : tri[1][t];
-        Bm[i * LDP + j] = rb[u];
-        Ev[i * LDP + j] = re1[u];
-        Ev2[i * LDP + j] = re2[u];
-    }
-    lsync<NT>();
-
-    if (!lstep_algebra<R, NT>(Gp, Gq, Bm, C1, C2, Km, T1, T2, Ev, Ev2, cs, wbuf, r, a.dk_tau)) {
-        if (tid == 0) { st->status = kErrRank; st->iters = k - 1; st->done = 1; }
-        return;
-    }
-    // only the R x R block changes; the rest keeps the values set at the
-    // start of the solve (zero, identity on the diagonal of B)
-#pragma unroll
-    for (int u = 0; u < NPL; ++u) {
-        const int e = tid + NT * u;
-        if (e >= R * R) break;
-        const int i = e / R, j = e % R;
-        const int g = i * kMaxR + j;
-        const bool in = (i < r) && (j < r);
-        const double tu = in ? Km[i * LDP + j] : 0.0;
-        const double tv = in ? Gp[i * LDP + j] : 0.0;
-        st->B[g] = in ? T2[i * LDP + j] : (i == j ? 1.0 : 0.0);
-        st->TU[g] = tu;
-        st->TUbar[g] = in ? T1[i * LDP + j] : 0.0;
-        st->TV[g] = tv;
-        st->TUf[g] = (float)tu;
-        st->TVf[g] = (float)tv;
-        st->E1[g] = Ev[i * LDP + j];
-        st->E2[g] = Ev2[i * LDP + j];
-    }
-    if (st->tsvd) {
-        // Alg. 4 stops after this step once B has settled:
-        // ||B_k - B_{k-1}||_F <= tol ||B_k||_F (or after fixed_iters steps)
-        double d2 = 0.0, n2 = 0.0;
-#pragma unroll
-        for (int u = 0; u < NPL; ++u) {
-            const int e = tid + NT * u;
+    // ---- the r x r algebra: Newton-Schulz, else the warm-started Jacobi
+    // path (which also decides rank loss); outputs left in LDS
+    const double *oB, *oTU, *oTUbar, *oTV;
+    if (ns_lstep<R>(Bm, Gp, Gq, X, Am, C, Y0, Y1, Z0, Z1, Tm, T1, R1, Km, nsred, r, a.ns_kappa)) {
+        oB = Y0; oTU = Am; oTUbar = T1; oTV = Gp;
+    } else {
+        // eigenbases of the last Jacobi step (identity at the start of a
+        // solve) into Z1 and Tm
+        const int t = lid<NT>();
+        for (int e = t; e < R * R; e += NT) {
             const int i = e / R, j = e % R;
-            if (e < R * R && i < r && j < r) {
-                const double bn = T2[i * LDP + j], bo = Bm[i * LDP + j];
+            Z1[i * LDP + j] = st->E1[i * kMaxR + j];
+            Tm[i * LDP + j] = st->E2[i * kMaxR + j];
+        }
+        lsync<NT>();
+        // C1 -> C, C2 -> Y1, T2 (the new B) -> Z0
+        if (!lstep_algebra<R, NT>(Gp, Gq, Bm, C, Y1, Km, T1, Z0, Z1, Tm, cs, wbuf, r, a.dk_tau)) {
+            if (tid == 0) { st->status = kErrRank; st->iters = k - 1; st->done = 1; }
+            return;
+        }
+        for (int e = t; e < R * R; e += NT) {
+            const int i = e / R, j = e % R;
+            st->E1[i * kMaxR + j] = Z1[i * LDP + j];
+            st->E2[i * kMaxR + j] = Tm[i * LDP + j];
+        }
+        oB = Z0; oTU = Km; oTUbar = T1; oTV = Gp;
+    }
+    // ---- the transforms: only the R x R block changes; the rest keeps the
+    // values set at the start of the solve (zero, identity on the diagonal of B)
+    double d2 = 0.0, n2 = 0.0;
+    if (L.act) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = L.row(e), j = L.col();
+            if (i >= R || j >= R) continue;
+            const int gi = i * kMaxR + j, li = i * LDP + j;
+            const bool in = (i < r) && (j < r);
+            const double bn = oB[li];
+            const double tv = in ? oTV[li] : 0.0;
+            const double tub = in ? oTUbar[li] : 0.0;
+            const double tuv = in ? oTU[li] : 0.0;
+            st->B[gi] = in ? bn : (i == j ? 1.0 : 0.0);
+            st->TU[gi] = tuv;
+            st->TUbar[gi] = tub;
+            st->TV[gi] = tv;
+            st->TUf[gi] = (float)tuv;
+            st->TVf[gi] = (float)tv;
+            if (in) {
+                const double bo = Bm[li];
                 d2 = fma(bn - bo, bn - bo, d2);
                 n2 = fma(bn, bn, n2);
             }
         }
-        d2 = wave_sum(d2);
-        n2 = wave_sum(n2);
-        if constexpr (NT > 64) {
-            // red[] (the residual reduction's, free now) holds the wave sums
-            if (lane == 0) { red[wave] = d2; seg[wave] = n2; }
-            __syncthreads();
-            d2 = 0.0; n2 = 0.0;
-#pragma unroll
-            for (int w = 0; w < NT / 64; ++w) { d2 += red[w]; n2 += seg[w]; }
-        }
+    }
+    if (tsvd) {
+        // Alg. 4 stops after this step once B has settled:
+        // ||B_k - B_{k-1}||_F <= tol ||B_k||_F (or after fixed_iters steps)
+        d2 = ns_sum<NB>(d2, nsred);
+        n2 = ns_sum<NB>(n2, nsred + 4);
         const double res = sqrt(d2 / n2);
         bool stop = false;
         int32_t status = kOK;
         if (!isfinite(res)) { stop = true; status = kErrNonFinite; }
-        else if (st->fixed_iters > 0) { stop = k >= st->fixed_iters; }
-        else if (res <= st->tol) { stop = true; }
-        else if (k >= st->max_iter) { stop = true; status = kWarnMaxIter; }
+        else if (fixed_iters > 0) { stop = k >= fixed_iters; }
+        else if (res <= tol) { stop = true; }
+        else if (k >= max_iter) { stop = true; status = kWarnMaxIter; }
         if (tid == 0) {
             a.res_hist[k - 1] = res;
             st->res = res;
@@ -225,10 +279,9 @@ __global__ void __launch_bounds__(step_tpb<R>()) step_kernel(StepArgs a)
         return;
     }
     if (tid == 0) {
-        const double mu = st->mu;
         st->mu_prev = mu;
-        const double nm = st->rho * mu;
-        st->mu = nm < st->mu_bar ? nm : st->mu_bar;
+        const double nm = rho * mu;
+        st->mu = nm < mu_bar ? nm : mu_bar;
         st->k = k + 1;
     }
 }
@@ -272,8 +325,9 @@ __global__ void __launch_bounds__(64) max_eig_kernel(DevState* st)
 
 hipError_t launch_step(const StepArgs& a, int R, hipStream_t s)
 {
+    const size_t lds = step_lds(R).total;
     switch (R) {
-#define CASE(rr) case rr: hipLaunchKernelGGL(step_kernel<rr>, dim3(1), dim3(step_tpb<rr>()), 0, s, a); break;
+#define CASE(rr) case rr: hipLaunchKernelGGL(step_kernel<rr>, dim3(1), dim3(kStepTPB), lds, s, a); break;
         SFR_R_LIST(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -281,9 +335,21 @@ hipError_t launch_step(const StepArgs& a, int R, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t step_prepare(int R)
+{
+    const int lds = (int)step_lds(R).total;
+    switch (R) {
+#define CASE(rr) \
+    case rr: return hipFuncSetAttribute(reinterpret_cast<const void*>(&step_kernel<rr>), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        SFR_R_LIST(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
 // Continue a stopped solve from its returned iterate K (the second phase of
 // a BF16 solve): every buffer of iterate K (Y_K, P_K, Q_K) and the state of
-// its step (transforms, B, mu, the warm-start bases) are intact, so this only
+// its step (transforms, B, mu) are intact, so this only
 // installs the new stopping rule, clears the stop and sets the next sweep to
 // K + 1.  A solve that stopped with an error, or with no iterations left in
 // the new rule, stays stopped.

@@ -667,6 +667,58 @@ __global__ void __launch_bounds__(kTPB) gram_kernel(GramArgs<T> a)
         for (int u = 0; u < EU; ++u)
             if (tid + u * kTPB < E) out[tid + u * kTPB] = acc[u];
     }
+
+}
+
+// Sum of the Gram partials: entry e of G_Q (e < E) or G_P (E <= e < 2E)
+// becomes the sum of its nqb or npb partials, added in a fixed order
+// (kGramSlices contiguous slices, the slice sums in slice order), written
+// over partial 0.  One workgroup per kGramRedEntries entries, every thread
+// with its (at most kMaxGramPartials / kGramSlices) loads in flight
+// together: the step kernel then reads one value per entry.
+constexpr int kGramRedEntries = 16;
+constexpr int kGramSlices = kTPB / kGramRedEntries;
+
+__global__ void __launch_bounds__(kTPB) gram_reduce_kernel(const DevState* st, double* GQpart, int nqb,
+                                                           double* GPpart, int npb, int E)
+{
+    if (st->done) return;
+    __shared__ double part[kGramSlices][kGramRedEntries];
+    const int tid = threadIdx.x;
+    const int el = tid % kGramRedEntries, sl = tid / kGramRedEntries;
+    const int w = blockIdx.x * kGramRedEntries + el;
+    const bool ok = w < 2 * E;
+    const bool isq = w < E;
+    double* base = isq ? GQpart : GPpart;
+    const int cnt = isq ? nqb : npb;
+    const int e = ok ? (isq ? w : w - E) : 0;
+    const int per = (cnt + kGramSlices - 1) / kGramSlices;
+    const int q0 = sl * per, q1 = min(cnt, q0 + per);
+    constexpr int CH = (kMaxGramPartials + kGramSlices - 1) / kGramSlices;
+    double s = 0.0;
+    for (int qb = q0; qb < q1; qb += CH) {
+        double v[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) v[u] = base[(size_t)min(qb + u, cnt - 1) * E + e];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) s += (qb + u < q1) ? v[u] : 0.0;
+    }
+    part[sl][el] = s;
+    __syncthreads();
+    if (sl == 0 && ok) {
+        double t = 0.0;
+#pragma unroll
+        for (int g = 0; g < kGramSlices; ++g) t += part[g][el];
+        base[e] = t;
+    }
+}
+
+hipError_t launch_gram_reduce(const DevState* st, double* GQpart, int nqb, double* GPpart, int npb, int E,
+                              hipStream_t s)
+{
+    const int grid = (2 * E + kGramRedEntries - 1) / kGramRedEntries;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid), dim3(kTPB), 0, s, st, GQpart, nqb, GPpart, npb, E);
+    return hipGetLastError();
 }
 
 #define SFR_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
