@@ -45,7 +45,7 @@ constexpr int kMaxGramPartials = 256;
 // of its threads has at most kStepPartialLoads of them to load (one round
 // of loads); beyond that a reduction kernel adds them first.
 constexpr int kStepTPB = 512;
-constexpr int kStepPartialLoads = 32;
+constexpr int kStepPartialLoads = 64;
 
 // Status codes mirrored from the public header (kept numerically equal).
 enum : int32_t {

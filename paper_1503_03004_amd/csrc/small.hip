@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kStepTPB) step_kernel(StepArgs a)
     constexpr int EPT = (2 * E + TPB - 1) / TPB;
     constexpr int nseg = (2 * E >= TPB) ? 1 : TPB / (2 * E);
     constexpr int PER = (kMaxGramPartials + nseg - 1) / nseg;
-    constexpr int CH = PER < 32 ? PER : 32;
+    constexpr int CH = PER < kStepPartialLoads ? PER : kStepPartialLoads;
     if (summed) {
         double gv[EPT];
 #pragma unroll
