@@ -807,9 +807,13 @@ def serving(args):
         Lb = (rb[0].double() @ rb[1] @ rb[2].double().T).cpu().numpy()
         L16 = (r16[0].double() @ r16[1] @ r16[2].double().T).cpu().numpy()
         dL16.append(max(rel(L16, Lb), rel(r16[3].double().cpu().numpy(), rb[3].double().cpu().numpy())))
+    d16 = np.array(dL16) if dL16 else np.zeros(0)
     bf16_batched = {"solves_per_s": len(one) / (bf16_ms * 1e-3), "launch_ms": bf16_ms, "requests": len(one),
                     "same_iters_as_fp32_batched": len(dL16),
                     "max_rel_diff_vs_fp32_batched": max(dL16) if dL16 else None,
+                    "median_rel_diff_vs_fp32_batched": float(np.median(d16)) if d16.size else None,
+                    "within_1e-5_of_fp32_batched": int((d16 <= 1e-5).sum()),
+                    "within_1e-3_of_fp32_batched": int((d16 <= 1e-3).sum()),
                     "note": "BF16 p and Q products while the residual > 1e-3 (matrix-core form, rank bucket >= 8), "
                             "FP32 iterations after; same tol as the FP32 per-instance solves"}
     print(f"[serving] batched BF16 form: {bf16_batched}", file=sys.stderr, flush=True)

@@ -24,6 +24,15 @@
  *    warning (> 0: outputs valid).  Arguments are validated on the host
  *    before any device work.
  *  - A handle serves one solve at a time; distinct handles are independent.
+ *    Handles may be driven from several host threads on several streams.
+ *    Solves whose rows are split over several cooperating workgroups (wide
+ *    rows: n above about 1000 columns at r <= 10, above 512 at larger r)
+ *    need all of those workgroups resident at once, so within one process
+ *    such solves run one after the other (a process-wide lock, held until
+ *    the solve's stream has drained); other solves run beside them.  Their
+ *    waits are bounded: if the device is held by another process's kernels
+ *    or by a running queue (sfr_queue_start) for too long, the solve
+ *    returns SFR_ERR_DEVICE with its outputs untouched.
  */
 #ifndef SFR_H
 #define SFR_H

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 namespace sfr {
@@ -100,7 +101,8 @@ static sfr_status configure_sweep(const Engine& e, SweepCfg& sc, bool mfma)
 
     int bpc = 0;
     hipError_t herr = sc.mfma ? sweep_mfma_prepare(e.R, sc.tiles, sc.lds, &bpc)
-                              : (e.f64 ? sweep_prepare<double>(e.R, sc.lds, &bpc) : sweep_prepare<float>(e.R, sc.lds, &bpc));
+                              : (e.f64 ? sweep_prepare<double>(e.R, sc.lpr, sc.W, sc.lds, &bpc)
+                                       : sweep_prepare<float>(e.R, sc.lpr, sc.W, sc.lds, &bpc));
     if (herr != hipSuccess || bpc < 1) return SFR_ERR_DEVICE;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SFR_ERR_DEVICE;
@@ -242,6 +244,30 @@ void engine_destroy(Engine& e)
         }                                          \
     } while (0)
 
+// Solves whose sweeps run in clusters (c > 1) hold this lock for their whole
+// run.  Cluster members wait on each other's partial row products, so all of
+// them must be resident at once; a plain launch gives that while no other
+// kernel whose workgroups wait on one another holds compute units, since
+// every other kernel drains and frees its slots.  Two such solves of one
+// process (handles driven from two host threads on two streams) therefore
+// run one after the other; solves without cluster waits run beside them.
+// The guard waits for its stream before it lets go, so a solve that returns
+// early on an error leaves no cluster kernel queued behind the lock.
+static std::mutex g_cluster_solve;
+
+struct ClusterGuard {
+    std::unique_lock<std::mutex> lk;
+    hipStream_t s;
+    ClusterGuard(bool waits, hipStream_t s_) : lk(g_cluster_solve, std::defer_lock), s(s_)
+    {
+        if (waits) lk.lock();
+    }
+    ~ClusterGuard()
+    {
+        if (lk.owns_lock()) (void)hipStreamSynchronize(s);
+    }
+};
+
 // Iterate Alg. 1 on the engine's shape and write the outputs of the
 // returned iterate.  M: device, row-major, ldm.  A fixed iteration count is
 // queued in one go; a tolerance-driven solve is queued in batches of 8 with
@@ -252,6 +278,7 @@ template <typename T>
 sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, int64_t ldm,
                           const OutputSpec<T>& out, hipStream_t s, bool tsvd)
 {
+    ClusterGuard guard(e.cfg[0].c > 1 || e.cfg[1].c > 1, s);
     const bool aligned = ((uintptr_t)M % 16 == 0) && (ldm % e.vec == 0) && (e.ne == e.n);
     const T* Mk = M;
     int64_t ldk = ldm;

@@ -279,8 +279,11 @@ template <typename T>
 int sweep_max_width(int R);   // widest column slice the sweep's column pass holds
 // Exchange slots cycled by a cluster (bands in flight between its members).
 constexpr int kExchSlots = 8;
+// Set the dynamic LDS limit of the sweep kernel that launch_sweep takes for
+// rank bucket R, lpr lanes per row and W-column slices, and report its
+// occupancy.
 template <typename T>
-hipError_t sweep_prepare(int R, size_t lds, int* blocks_per_cu);
+hipError_t sweep_prepare(int R, int lpr, int W, size_t lds, int* blocks_per_cu);
 
 // Matrix-core sweep (sweep_mfma.hip): FP32, R <= 32, member slices of
 // sweep_mfma_width(R, tiles) columns, 16-row bands, 512-thread workgroups.

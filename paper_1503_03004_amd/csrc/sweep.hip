@@ -20,9 +20,14 @@
 //     so a member may run up to two bands ahead of the slowest one before
 //     it waits.  A member can then publish at most five bands ahead of one
 //     still reading, so eight exchange slots are cycled.
-//   * Column pass (phase 2): thread-owned columns accumulate
-//     Q_j += x_ij p_i from the LDS copy of x: Q = X^T X V with no second
-//     read of the data.
+//   * Column pass (phase 2): Q_j += x_ij p_i from the LDS copy of x:
+//     Q = X^T X V with no second read of the data.  For FP32 wide slices
+//     (rank buckets up to 10, slices of 512 or 1024 columns) it runs on the
+//     matrix cores: wave w owns 16-column tiles of its member's slice and
+//     adds X_tile^T (16 columns x 4 rows) . P (4 rows x 16 ranks) with
+//     v_mfma_f32_16x16x4_f32 (exact FP32 products, FP32 accumulation), H/4
+//     steps per band.  Otherwise thread-owned columns accumulate it on the
+//     vector ALU.
 // HBM traffic per element: read M, read Y_{k-1}, write Y_k.
 #include "exchange.hpp"
 #include "sfr_internal.hpp"
@@ -127,18 +132,37 @@ __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15)
 // and the number of band buffers of x and p.
 __host__ __device__ inline int sweep_lag(int c) { return c > 1 ? 2 : 1; }
 
+// Whether the column pass runs on the matrix cores: FP32, rank buckets up to
+// 10 (512-thread workgroups), slices of whole 16-column tiles per wave.
+template <typename T>
+__host__ __device__ inline bool sweep_mcol(int R, int lpr, int W, int tpb)
+{
+    return sizeof(T) == 4 && R <= 10 && tpb == 512 && W >= tpb && W % (16 * (tpb / 64)) == 0 &&
+           W / (16 * (tpb / 64)) <= 8 && lpr >= 32;
+}
+
+// Row pitch (elements) of the LDS copy of x: the matrix-core column pass
+// reads four rows of 16 consecutive columns per instruction, so its rows
+// are offset by 16 banks.
+template <typename T>
+__host__ __device__ inline int sweep_xpitch(int R, int lpr, int W, int tpb)
+{
+    return sweep_mcol<T>(R, lpr, W, tpb) ? W + 16 : W;
+}
+
 template <typename T>
 __host__ __device__ inline SweepLds sweep_lds(int R, int lpr, int W, int c, int tpb)
 {
     const int H = (tpb / 64) * (64 / lpr);
     const int HG = (W >= tpb) ? 1 : tpb / W;
     const int nbuf = sweep_lag(c) + 1;
+    const int XP = sweep_xpitch<T>(R, lpr, W, tpb);
     SweepLds L;
     size_t o = 0;
     L.tu = o; o = al16(o + sizeof(T) * R * R);
     L.tv = o; o = al16(o + sizeof(T) * R * R);
     L.vs = o; o = al16(o + sizeof(T) * (size_t)R * W);
-    L.xs = o; o = al16(o + sizeof(T) * nbuf * (size_t)H * W);
+    L.xs = o; o = al16(o + sizeof(T) * nbuf * (size_t)H * XP);
     L.ps = o; o = al16(o + sizeof(T) * nbuf * (size_t)H * R);
     L.gx = o; o = al16(o + (c > 1 ? sizeof(T) * (tpb / 64) * (size_t)c * R : 0));
     L.qred = o; o = al16(o + (W < tpb ? sizeof(T) * (size_t)HG * W * R : 0));
@@ -162,7 +186,11 @@ constexpr int sweep_cpt2()
     return (R > 16) ? 2 : (64 * 4 * Vec<T>::N + sweep_tpb<T, R>() - 1) / sweep_tpb<T, R>();
 }
 
-template <typename T, int R>
+typedef float sw_f32x4 __attribute__((ext_vector_type(4)));
+
+// MC: the matrix-core column pass (the host launches it exactly where
+// sweep_mcol holds).
+template <typename T, int R, bool MC>
 __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs<T> a)
 {
     DevState* st = const_cast<DevState*>(a.st);
@@ -177,6 +205,7 @@ __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lpr = a.lpr, nv = a.nv, W = a.W, c = a.c;
     const int rpw = 64 / lpr, H = NW * rpw;
+    const int XP = MC ? W + 16 : W;   // sweep_xpitch
     const int lag = sweep_lag(c), nbuf = lag + 1;
     const int li = lane % lpr, rg = lane / lpr, gbase = lane - li;
     const int g = blockIdx.x;
@@ -243,11 +272,18 @@ __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs
     const int cpt2 = (W >= TPB) ? (W + TPB - 1) / TPB : 1;
     const int HG = (W >= TPB) ? 1 : TPB / W;
     double acc2 = 0.0;
-    T Qacc[CPT2MAX][R];
+    // column-pass accumulators: thread-owned columns (vector ALU), or this
+    // lane's part of the wave's 16 x 16 Q tiles (matrix cores)
+    constexpr int QE = MC ? 1 : CPT2MAX;
+    constexpr int MT = MC ? 8 : 1;
+    T Qacc[QE][R];
 #pragma unroll
-    for (int e = 0; e < CPT2MAX; ++e)
+    for (int e = 0; e < QE; ++e)
 #pragma unroll
         for (int k = 0; k < R; ++k) Qacc[e][k] = T(0);
+    sw_f32x4 qm[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) qm[t] = sw_f32x4{0.f, 0.f, 0.f, 0.f};
 
     // Row-pass operands of the band being processed: all 2 * nv vectors of
     // a lane are issued together, one band ahead of their use.  Vectors out
@@ -366,7 +402,7 @@ __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) x[e] = T(0);
                 }
-                store_vec<T>(Xs + ((size_t)buf * H + h) * W + jj, x);
+                store_vec<T>(Xs + ((size_t)buf * H + h) * XP + jj, x);
 #pragma unroll
                 for (int k = 0; k < R; ++k)
 #pragma unroll
@@ -476,7 +512,22 @@ __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs
                 }
             }
             // ---------------- phase 2: column pass, Q += X^T p --------------
-            if (W >= TPB) {
+            if constexpr (MC) {
+                // lane (lr, lq) supplies A[lr][lq] = x[row 4 s + lq][column 16 t + lr]
+                // and B[lq][lr] = p[row 4 s + lq][rank lr]; it receives
+                // Q[column 16 t + 4 lq + e][rank lr]
+                const int lr = lane & 15, lq = lane >> 4;
+                const int tpw = W / (16 * NW);
+                const float* xb = reinterpret_cast<const float*>(Xs) + (size_t)buf * H * XP + wave * tpw * 16 + lr;
+                const float* pb = reinterpret_cast<const float*>(Ps) + (size_t)buf * H * R;
+                for (int s4 = 0; s4 < H; s4 += 4) {
+                    const float bv = (lr < R) ? pb[(s4 + lq) * R + lr] : 0.f;
+                    const float* xr = xb + (size_t)(s4 + lq) * XP;
+#pragma unroll
+                    for (int t = 0; t < MT; ++t)
+                        if (t < tpw) qm[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[16 * t], bv, qm[t], 0, 0, 0);
+                }
+            } else if (W >= TPB) {
                 for (int hh = 0; hh < H; ++hh) {
                     const T* xr = Xs + ((size_t)buf * H + hh) * W;
                     T pk[R];
@@ -508,7 +559,22 @@ __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs
     }
 
     // ---------------- write the column partials of this cluster -----------
-    if (W >= TPB) {
+    if constexpr (MC) {
+        const int lr = lane & 15, lq = lane >> 4;
+        const int tpw = W / (16 * NW);
+        if (lr < R) {
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+                if (t < tpw) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int jcol = c0 + (wave * tpw + t) * 16 + 4 * lq + e;
+                        if (jcol < n) a.Qpart[((size_t)cl * n + jcol) * R + lr] = qm[t][e];
+                    }
+                }
+            }
+        }
+    } else if (W >= TPB) {
 #pragma unroll
         for (int e = 0; e < CPT2MAX; ++e) {
             const int col = tid + e * TPB;
@@ -547,6 +613,16 @@ __global__ void __launch_bounds__((sweep_tpb<T, R>()), 1) sweep_kernel(SweepArgs
 
 #define SFR_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
 
+// Kernel of rank bucket R; MC: the matrix-core column pass (FP32, R <= 10).
+template <typename T, int R>
+static void* sweep_fn_r(bool mc)
+{
+    if constexpr (sizeof(T) == 4 && R <= 10) {
+        if (mc) return reinterpret_cast<void*>(&sweep_kernel<T, R, true>);
+    }
+    return reinterpret_cast<void*>(&sweep_kernel<T, R, false>);
+}
+
 template <typename T>
 size_t sweep_lds_bytes_c(int R, int lpr, int W, int c)
 {
@@ -576,14 +652,26 @@ int sweep_max_width(int R)
 }
 
 template <typename T>
-static void* sweep_fn(int R)
+static void* sweep_fn(int R, bool mc)
 {
     switch (R) {
-#define CASE(r) case r: return reinterpret_cast<void*>(&sweep_kernel<T, r>);
+#define CASE(r) case r: return sweep_fn_r<T, r>(mc);
         SFR_R_LIST(CASE)
 #undef CASE
     default: return nullptr;
     }
+}
+
+template <typename T, int R, bool MC>
+static hipError_t launch_sweep_r(const SweepArgs<T>& a, int grid, size_t lds, hipStream_t s, hipEvent_t ev0,
+                                 hipEvent_t ev1)
+{
+    if (ev0)
+        hipExtLaunchKernelGGL((sweep_kernel<T, R, MC>), dim3(grid), dim3(sweep_tpb<T, R>()), (uint32_t)lds, s, ev0,
+                              ev1, 0u, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<T, R, MC>), dim3(grid), dim3(sweep_tpb<T, R>()), lds, s, a);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -591,14 +679,13 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int R, int grid, size_t lds, hipS
                         hipEvent_t ev1)
 {
     switch (R) {
-#define CASE(r)                                                                                            \
-    case r:                                                                                                \
-        if (ev0)                                                                                         \
-            hipExtLaunchKernelGGL((sweep_kernel<T, r>), dim3(grid), dim3(sweep_tpb<T, r>()), (uint32_t)lds, \
-                                  s, ev0, ev1, 0u, a);                                                   \
-        else                                                                                             \
-            hipLaunchKernelGGL((sweep_kernel<T, r>), dim3(grid), dim3(sweep_tpb<T, r>()), lds, s, a);   \
-        return hipGetLastError();
+#define CASE(r)                                                                                   \
+    case r:                                                                                       \
+        if constexpr (sizeof(T) == 4 && r <= 10) {                                                \
+            if (sweep_mcol<T>(r, a.lpr, a.W, sweep_tpb<T, r>()))                                  \
+                return launch_sweep_r<T, r, true>(a, grid, lds, s, ev0, ev1);                     \
+        }                                                                                         \
+        return launch_sweep_r<T, r, false>(a, grid, lds, s, ev0, ev1);
         SFR_R_LIST(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -606,9 +693,9 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int R, int grid, size_t lds, hipS
 }
 
 template <typename T>
-hipError_t sweep_prepare(int R, size_t lds, int* blocks_per_cu)
+hipError_t sweep_prepare(int R, int lpr, int W, size_t lds, int* blocks_per_cu)
 {
-    void* fn = sweep_fn<T>(R);
+    void* fn = sweep_fn<T>(R, sweep_mcol<T>(R, lpr, W, sweep_threads<T>(R)));
     if (!fn) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -625,7 +712,7 @@ template int sweep_threads<float>(int);
 template int sweep_threads<double>(int);
 template int sweep_max_width<float>(int);
 template int sweep_max_width<double>(int);
-template hipError_t sweep_prepare<float>(int, size_t, int*);
-template hipError_t sweep_prepare<double>(int, size_t, int*);
+template hipError_t sweep_prepare<float>(int, int, int, size_t, int*);
+template hipError_t sweep_prepare<double>(int, int, int, size_t, int*);
 
 }  // namespace sfr

@@ -178,8 +178,10 @@ def test_full_size_8000_fp32_tolerance_driven():
 
 def test_two_handles_on_two_streams():
     """Distinct handles are independent: two solves whose sweeps run in
-    clusters (c > 1 column slices) overlap on two streams from two host
-    threads, and each result is bitwise the result of the same solve alone."""
+    clusters (c > 1 column slices) are driven from two host threads on two
+    streams (the library runs such solves one at a time, so every cluster's
+    members are resident together), and each result is bitwise the result
+    of the same solve alone."""
     shapes = [(1500, 4096, 10, 31), (1200, 5000, 6, 32)]
     insts = [workloads.planted(m, n, r, seed=sd, frac=0.08, kind="uniform", scale=30.0, dtype=np.float32)
              for (m, n, r, sd) in shapes]
