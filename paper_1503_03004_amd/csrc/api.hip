@@ -49,8 +49,11 @@ static size_t lds_of(int R, int lpr, int W, int c) { return sweep_lds_bytes_c<T>
 
 // Pick the row-pass shape (lanes per row, vectors per lane), the cluster
 // size and the grid of one sweep kernel for an m x ne problem.
+static sfr_status configure_grid(const Engine& e, SweepCfg& sc);
+
 static sfr_status configure_sweep(const Engine& e, SweepCfg& sc, bool mfma)
 {
+    bool rb_forced = false;
     const int vec = e.vec;
     sc.mfma = mfma ? 1 : 0;
     const int nvec = (e.ne + vec - 1) / vec;
@@ -77,6 +80,16 @@ static sfr_status configure_sweep(const Engine& e, SweepCfg& sc, bool mfma)
         sc.tiles = (e.R == 16 && e.ne >= sweep_mfma_width(16, 8)) ? 8 : 0;
         const int mw = sweep_mfma_width(e.R, sc.tiles);
         sc.lpr = 64; sc.nv = 4; sc.c = (e.ne + mw - 1) / mw;
+        // wide clusters of the 4-tile forms exchange by reduce-then-broadcast
+        // (SFR_EXCH=gather or =reduce in the environment forces one form
+        // where both exist; they give bitwise the same result)
+        const char* ex = getenv("SFR_EXCH");
+        const bool rb_ok = sweep_mfma_rb_supported(e.R, sc.tiles) && sc.c > 1;
+        bool rb = rb_ok && sc.c >= kRbMinMembers;
+        if (ex && strcmp(ex, "gather") == 0) rb = false;
+        if (ex && strcmp(ex, "reduce") == 0) rb = rb_ok;
+        rb_forced = ex && (strcmp(ex, "gather") == 0 || strcmp(ex, "reduce") == 0);
+        sc.rb = rb ? 1 : 0;
     } else if (best_lpr > 0) {
         sc.lpr = best_lpr; sc.nv = best_nv; sc.c = 1;
     } else {
@@ -92,15 +105,32 @@ static sfr_status configure_sweep(const Engine& e, SweepCfg& sc, bool mfma)
         }
         sc.c = (e.ne + 64 * vec * sc.nv - 1) / (64 * vec * sc.nv);
     }
+    sfr_status fs = configure_grid(e, sc);
+    // Reduce-then-broadcast puts two dependent waits on each band; with few
+    // bands per cluster (the l x n blocks of FR-Nys) the pipeline never
+    // fills and all-gather is the faster form.
+    if (fs == SFR_OK && sc.rb && !rb_forced && sc.nbl_max < kRbMinBands) {
+        sc.rb = 0;
+        fs = configure_grid(e, sc);
+    }
+    return fs;
+}
+
+// Slice width, band height, LDS size and grid of a sweep whose kernel form
+// (vector or matrix-core, lanes per row, tiles, exchange form) and cluster
+// width are chosen.
+static sfr_status configure_grid(const Engine& e, SweepCfg& sc)
+{
+    const int vec = e.vec;
     sc.W = sc.mfma ? sweep_mfma_width(e.R, sc.tiles) : sc.lpr * vec * sc.nv;
     const int tpb = e.f64 ? sweep_threads<double>(e.R) : sweep_threads<float>(e.R);
     sc.H = sc.mfma ? 16 : (tpb / 64) * (64 / sc.lpr);
     sc.nbands = (e.m + sc.H - 1) / sc.H;
-    if (sc.mfma) sc.lds = sweep_mfma_lds_bytes(e.R, sc.tiles);
+    if (sc.mfma) sc.lds = sweep_mfma_lds_bytes(e.R, sc.tiles, sc.rb != 0);
     else sc.lds = e.f64 ? lds_of<double>(e.R, sc.lpr, sc.W, sc.c) : lds_of<float>(e.R, sc.lpr, sc.W, sc.c);
 
     int bpc = 0;
-    hipError_t herr = sc.mfma ? sweep_mfma_prepare(e.R, sc.tiles, sc.lds, &bpc)
+    hipError_t herr = sc.mfma ? sweep_mfma_prepare(e.R, sc.tiles, sc.rb != 0, sc.lds, &bpc)
                               : (e.f64 ? sweep_prepare<double>(e.R, sc.lpr, sc.W, sc.lds, &bpc)
                                        : sweep_prepare<float>(e.R, sc.lpr, sc.W, sc.lds, &bpc));
     if (herr != hipSuccess || bpc < 1) return SFR_ERR_DEVICE;
@@ -136,7 +166,11 @@ static sfr_status configure_sweep(const Engine& e, SweepCfg& sc, bool mfma)
 
 static size_t exch_words_of(const Engine& e, const SweepCfg& sc)
 {
-    return (sc.c > 1) ? (size_t)sc.ncl * kExchSlots * sc.c * sc.H * e.R * (e.esz / 4) : 0;
+    if (sc.c <= 1) return 0;
+    const size_t partial = (size_t)sc.ncl * kExchSlots * sc.c * sc.H * e.R * (e.esz / 4);
+    // reduce-then-broadcast: the owners' sums follow the partials
+    const size_t reduced = sc.rb ? (size_t)sc.ncl * kExchSlots * sc.H * e.R : 0;
+    return partial + reduced;
 }
 
 // The matrix-core sweep takes FP32 problems with at least one full member
@@ -379,7 +413,7 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         hipEvent_t ev0 = timed ? e.prof_ev[2 * (k - 3)] : nullptr;
         hipEvent_t ev1 = timed ? e.prof_ev[2 * (k - 3) + 1] : nullptr;
         if constexpr (sizeof(T) == 4) {
-            if (sc.mfma) HIPCHK(launch_sweep_mfma(a, e.R, sc.tiles, sc.grid, sc.lds, s, ev0, ev1, bf));
+            if (sc.mfma) HIPCHK(launch_sweep_mfma(a, e.R, sc.tiles, sc.rb != 0, sc.grid, sc.lds, s, ev0, ev1, bf));
             else HIPCHK(launch_sweep<T>(a, e.R, sc.grid, sc.lds, s, ev0, ev1));
         } else {
             HIPCHK(launch_sweep<T>(a, e.R, sc.grid, sc.lds, s, ev0, ev1));

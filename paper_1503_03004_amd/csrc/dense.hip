@@ -304,12 +304,18 @@ __device__ __forceinline__ void tri_index(int e, int r, int& p, int& q)
     q = p + e;
 }
 
+// Rows of a block are staged through LDS in chunks of kOrthChunk (one
+// coalesced load of the chunk's contiguous r-wide rows), then thread t adds
+// the products of its entries t, t + 256, ... (r <= 32: at most three) over
+// the chunk's rows, in row order.
+constexpr int kOrthChunk = 128;
+
 template <typename T>
 __global__ void __launch_bounds__(256) orth_partial_kernel(const DevState* st, const T* U, int m, const T* V, int n,
                                                            int r, double* Up, int nu, double* Vp, int nv)
 {
     if (st && (!st->done || st->status < 0 || st->exch_timeout)) return;
-    __shared__ double acc_s[256];
+    __shared__ double xs[kOrthChunk * kMaxR];
     const bool isU = (int)blockIdx.x < nu;
     const int b = isU ? (int)blockIdx.x : (int)blockIdx.x - nu;
     const int nb = isU ? nu : nv;
@@ -319,27 +325,38 @@ __global__ void __launch_bounds__(256) orth_partial_kernel(const DevState* st, c
     double* out = (isU ? Up : Vp) + (size_t)b * E;
     const int per = (rows + nb - 1) / nb;
     const int i0 = b * per, i1 = min(rows, i0 + per);
-    // every thread works: entry e = t % E over the rows of phase t / E
-    // (rows i0 + ph, i0 + ph + P, ...), the phases added in order after
-    const int P = E >= 256 ? 1 : 256 / E;
-    for (int e0 = 0; e0 < E; e0 += 256 / P) {
-        const int t = threadIdx.x;
-        const int e = e0 + t % (256 / P), ph = t / (256 / P);
-        double a = 0.0;
-        if (ph < P && e < E) {
-            int p, q;
-            tri_index(e, r, p, q);
-            for (int i = i0 + ph; i < i1; i += P) a = fma((double)X[(int64_t)i * r + p], (double)X[(int64_t)i * r + q], a);
-        }
-        acc_s[t] = a;
+    const int t = threadIdx.x;
+    constexpr int EU = (kMaxR * (kMaxR + 1) / 2 + 255) / 256;
+    int pp[EU], qq[EU];
+    double a[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+        a[u] = 0.0;
+        pp[u] = 0;
+        qq[u] = 0;
+        if (t + 256 * u < E) tri_index(t + 256 * u, r, pp[u], qq[u]);
+    }
+    for (int c0 = i0; c0 < i1; c0 += kOrthChunk) {
+        const int cnt = min(kOrthChunk, i1 - c0) * r;
+        const T* src = X + (int64_t)c0 * r;
+        for (int k = t; k < cnt; k += 256) xs[k] = (double)src[k];
         __syncthreads();
-        if (t < 256 / P && e0 + t < E) {
-            double s = 0.0;
-            for (int k = 0; k < P; ++k) s += acc_s[k * (256 / P) + t];
-            out[e0 + t] = s;
+        const int nr = cnt / r;
+#pragma unroll
+        for (int u = 0; u < EU; ++u) {
+            if (t + 256 * u < E) {
+                const double* xp = xs + pp[u];
+                const double* xq = xs + qq[u];
+                double acc = a[u];
+                for (int i = 0; i < nr; ++i) acc = fma(xp[i * r], xq[i * r], acc);
+                a[u] = acc;
+            }
         }
         __syncthreads();
     }
+#pragma unroll
+    for (int u = 0; u < EU; ++u)
+        if (t + 256 * u < E) out[t + 256 * u] = a[u];
 }
 
 __global__ void __launch_bounds__(256) orth_final_kernel(const DevState* st, int r, const double* Up, int nu,
@@ -393,6 +410,7 @@ template <typename T>
 hipError_t launch_orth(const DevState* st, const T* U, int m, const T* V, int n, int r, double* Up, int nu,
                        double* Vp, int nv, double* out, hipStream_t s)
 {
+    if (r < 1 || r > kMaxR) return hipErrorInvalidValue;
     nu = std::max(1, std::min({nu, m, kOrthParts}));
     nv = std::max(1, std::min({nv, n, kOrthParts}));
     hipLaunchKernelGGL(orth_partial_kernel<T>, dim3((unsigned)(nu + nv)), dim3(256), 0, s, st, U, m, V, n, r, Up,

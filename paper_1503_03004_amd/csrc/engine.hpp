@@ -13,6 +13,7 @@ namespace sfr {
 struct SweepCfg {
     int mfma = 0;   // 1: the matrix-core sweep (sweep_mfma.hip), else sweep.hip
     int tiles = 0;  // matrix-core sweep: 16-column tiles per wavefront (0: the bucket's default form)
+    int rb = 0;     // matrix-core sweep: reduce-then-broadcast cluster exchange (else all-gather)
     int lpr = 64, nv = 1, W = 0, c = 1, cpx = 1, xcd_local = 1, ncl = 8, grid = 8, H = 4, nbands = 0, nbl_max = 0;
     size_t lds = 0;
 };

@@ -279,6 +279,12 @@ template <typename T>
 int sweep_max_width(int R);   // widest column slice the sweep's column pass holds
 // Exchange slots cycled by a cluster (bands in flight between its members).
 constexpr int kExchSlots = 8;
+// Clusters of at least this many members exchange by reduce-then-broadcast
+// in the matrix-core sweep's 4-tile forms (all-gather reads 16 R c words a
+// band per member, reduce-then-broadcast about 16 R + c).
+constexpr int kRbMinMembers = 12;
+// ... and at least this many bands per cluster (each band then waits twice).
+constexpr int kRbMinBands = 8;
 // Set the dynamic LDS limit of the sweep kernel that launch_sweep takes for
 // rank bucket R, lpr lanes per row and W-column slices, and report its
 // occupancy.
@@ -290,12 +296,15 @@ hipError_t sweep_prepare(int R, int lpr, int W, size_t lds, int* blocks_per_cu);
 // tiles: 16-column tiles per wavefront, 0 for the bucket's default form; 8
 // selects the wide form of the R = 16 bucket (1024-column slices).
 bool sweep_mfma_supported(int R);
-size_t sweep_mfma_lds_bytes(int R, int tiles);
+// rb: the reduce-then-broadcast exchange (4-tile forms, R > 12), whose
+// reduced words follow the partial words in the exchange buffer.
+bool sweep_mfma_rb_supported(int R, int tiles);
+size_t sweep_mfma_lds_bytes(int R, int tiles, bool rb);
 int sweep_mfma_width(int R, int tiles);
-hipError_t sweep_mfma_prepare(int R, int tiles, size_t lds, int* blocks_per_cu);
+hipError_t sweep_mfma_prepare(int R, int tiles, bool rb, size_t lds, int* blocks_per_cu);
 // bf16: the contractions take BF16 operands (FP32 accumulation)
-hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int tiles, int grid, size_t lds, hipStream_t s,
-                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool bf16 = false);
+hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int tiles, bool rb, int grid, size_t lds,
+                             hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool bf16 = false);
 
 hipError_t launch_step(const StepArgs& a, int R, hipStream_t s);
 // Once per process and rank bucket before the first launch_step (the step

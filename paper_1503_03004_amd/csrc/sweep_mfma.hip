@@ -24,8 +24,15 @@
 //     wave's p partial (4 MFMA); each 16-byte load of the next band goes
 //     out as soon as its tile has been consumed.
 //   * The 8 waves' p partials are added in LDS; with c > 1 members of a
-//     cluster exchange them through tagged words (exchange.hpp), one band
-//     behind the row pass.
+//     cluster exchange them through tagged words (exchange.hpp).  Two forms:
+//     all-gather (every member reads every member's partials of a band, one
+//     band behind the row pass), and, for wide clusters of the 4-tile form,
+//     reduce-then-broadcast: the band's (row, rank) entries are dealt out
+//     to the members round-robin, each member adds the c partials of the
+//     entries it owns (one band behind) and publishes the sums, and every
+//     member reads the sums back (two bands behind).  A member then reads
+//     about 16 R + c words a band instead of 16 R c; both forms add the
+//     partials in member order, so they give bitwise the same P.
 //   * Column pass: Q += X^T P from the wave's own x tile (4 MFMA per tile);
 //     Q stays in registers until the end.
 // HBM traffic per element: read M, read Y_{k-1}, write Y_k.
@@ -63,24 +70,33 @@ struct MShape {
 };
 
 struct MfmaLds {
-    size_t tu, xw, pw, ps, red, total;
+    size_t tu, xw, pw, ps, rb, red, total;
 };
 
-template <int R, int TW = 0>
+// Largest cluster of the reduce-then-broadcast form (members resident at
+// once: at most two workgroups per CU of 256 CUs).
+constexpr int kRbMaxC = 512;
+
+// RB: reduce-then-broadcast exchange (column pass two bands behind the row
+// pass, three band buffers of x and P); else all-gather (one band behind).
+template <int R, int TW = 0, bool RB = false>
 __host__ __device__ inline MfmaLds mfma_lds()
 {
     using S = MShape<R, TW>;
+    constexpr int NBUF = RB ? 3 : 2;
     auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
     MfmaLds L;
     size_t o = 0;
     L.tu = o; o = al(o + sizeof(float) * R * R);
-    // x tiles: per wave, two band buffers of 16 rows; the V slice
+    // x tiles: per wave, NBUF band buffers of 16 rows; the V slice
     // (WIDTH x R floats) is staged here during the prologue
-    size_t xw = sizeof(float) * (size_t)kMW8 * 2 * kMH * S::XP;
+    size_t xw = sizeof(float) * (size_t)kMW8 * NBUF * kMH * S::XP;
     const size_t vst = sizeof(float) * (size_t)S::WIDTH * R;
     L.xw = o; o = al(o + (xw > vst ? xw : vst));
     L.pw = o; o = al(o + sizeof(float) * kMW8 * 256 * S::RT);
-    L.ps = o; o = al(o + sizeof(float) * 2 * 256 * S::RT);
+    L.ps = o; o = al(o + sizeof(float) * NBUF * 256 * S::RT);
+    // partials of the owned entries of a band (at most 16 R + c - 1)
+    L.rb = o; o = al(o + (RB ? sizeof(float) * (size_t)(kMH * R + kRbMaxC) : 0));
     L.red = o; o = al(o + sizeof(double) * kMW8);
     L.total = o;
     return L;
@@ -93,11 +109,13 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c)
 
 
 // BF: the p and Q contractions take BF16 operands (FP32 accumulation); the
-// l reconstruction, M, Y and every stored value stay FP32.
-template <int R, bool BF, int TW = 0>
+// l reconstruction, M, Y and every stored value stay FP32.  RB: the
+// reduce-then-broadcast exchange (the host takes it only with c > 1).
+template <int R, bool BF, int TW = 0, bool RB = false>
 __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a)
 {
     using SH = MShape<R, TW>;
+    constexpr int LAG = RB ? 2 : 1, NBUF = LAG + 1;
     constexpr int RT = SH::RT, S1 = SH::S1, kMTiles = SH::TPW, kMCols = SH::COLS;
     constexpr int kMWidth = SH::WIDTH, kMXP = SH::XP;
     constexpr int PT = 256 * RT;      // (row, padded rank) entries of one band
@@ -131,13 +149,14 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
     int32_t* tflag = &st->exch_timeout;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    const MfmaLds L = mfma_lds<R, TW>();
+    const MfmaLds L = mfma_lds<R, TW, RB>();
     float* TUs = reinterpret_cast<float*>(smem + L.tu);
     float* Xall = reinterpret_cast<float*>(smem + L.xw);
-    float* Xw = Xall + (size_t)wave * 2 * kMH * kMXP;
+    float* Xw = Xall + (size_t)wave * NBUF * kMH * kMXP;
     float* PW = reinterpret_cast<float*>(smem + L.pw);
     float* PS = reinterpret_cast<float*>(smem + L.ps);
     double* red = reinterpret_cast<double*>(smem + L.red);
+    float* RED1 = reinterpret_cast<float*>(smem + L.rb);
 
     // ---- prologue: TU, and V_j = Q_j TV for this member's columns
     float* Vst = Xall;   // kMWidth x R, row j - c0
@@ -215,8 +234,8 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
         for (int t = 0; t < kMTiles; ++t) issue_load(0, t);
     }
 
-    for (int j = 0; j <= nbl; ++j) {
-        const int buf = j & 1;
+    for (int j = 0; j < nbl + LAG; ++j) {
+        const int buf = j % NBUF;
         if (j < nbl) {
             // ---------------- row pass over band j ----------------
             const int i = (cl + j * ncl) * kMH + lr;
@@ -317,7 +336,48 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
                 publish<float>(a.exch + ((((size_t)cl * kExchSlots + slot) * c + q) * kMH + prow_) * R + prk, s, tag);
             }
         }
-        if (j >= 1 && c > 1 && tid < PT) {
+        if constexpr (RB) {
+            // (1) the entries of band j - 1 this member owns: entry
+            // e = row * R + rank goes to member e mod c; thread t loads the
+            // partial of member t mod c for its owned entry t / c
+            const int EN = kMH * R;
+            const int nown = (q < EN) ? (EN - q + c - 1) / c : 0;
+            const bool red_now = (c > 1) && (j >= 1) && (j - 1 < nbl);
+            const int jb1 = j - 1;
+            const uint32_t tag1 = kiter * (uint32_t)a.nbl_max + (uint32_t)jb1 + 1u;
+            const int slot1 = jb1 & (kExchSlots - 1);
+            if (red_now) {
+                const unsigned long long* pbase = a.exch + ((size_t)cl * kExchSlots + slot1) * c * EN;
+                for (int t = tid; t < nown * c; t += kMTPB) {
+                    const int u = t / c, q0 = t - u * c;
+                    const unsigned long long* src = pbase + (size_t)q0 * EN + (q + u * c);
+                    unsigned long long w = peek_word(src);
+                    if ((uint32_t)(w >> 32) != tag1) w = spin_word(src, tag1, tflag);
+                    RED1[t] = __uint_as_float((uint32_t)(w & 0xffffffffull));
+                }
+            }
+            __syncthreads();
+            unsigned long long* rbase = a.exch + (size_t)a.ncl * kExchSlots * c * EN;
+            if (red_now && tid < nown) {
+                float sr = 0.f;
+                for (int q0 = 0; q0 < c; ++q0) sr += RED1[tid * c + q0];   // member order
+                publish<float>(rbase + ((size_t)cl * kExchSlots + slot1) * EN + (q + tid * c), sr, tag1);
+            }
+            // (2) the sums of band j - 2, from their owners
+            if (c > 1 && j >= 2 && tid < PT) {
+                const int jb2 = j - 2;
+                const uint32_t tag2 = kiter * (uint32_t)a.nbl_max + (uint32_t)jb2 + 1u;
+                const int slot2 = jb2 & (kExchSlots - 1);
+                float sv = 0.f;
+                if (prk < R) {
+                    const unsigned long long* src = rbase + ((size_t)cl * kExchSlots + slot2) * EN + prow_ * R + prk;
+                    unsigned long long w = peek_word(src);
+                    if ((uint32_t)(w >> 32) != tag2) w = spin_word(src, tag2, tflag);
+                    sv = __uint_as_float((uint32_t)(w & 0xffffffffull));
+                }
+                PS[(jb2 % NBUF) * PT + tid] = sv;
+            }
+        } else if (j >= 1 && c > 1 && tid < PT) {
             // gather the members' partials of band j - 1, added in member order
             const int jb = j - 1;
             const uint32_t tag = kiter * (uint32_t)a.nbl_max + (uint32_t)jb + 1u;
@@ -344,13 +404,13 @@ __global__ void __launch_bounds__(kMTPB, 1) sweep_mfma_kernel(SweepArgs<float> a
                     }
                 }
             }
-            PS[(jb & 1) * PT + tid] = s;
+            PS[(jb % NBUF) * PT + tid] = s;
         }
         __syncthreads();
-        if (j >= 1) {
-            // ---------------- column pass over band j - 1 ----------------
-            const int jb = j - 1;
-            const int bb = jb & 1;
+        if (j >= LAG) {
+            // ---------------- column pass over band j - LAG ----------------
+            const int jb = j - LAG;
+            const int bb = jb % NBUF;
             const int i0 = (cl + jb * ncl) * kMH;
             if (q == 0) {
                 for (int e = tid; e < kMH * R; e += kMTPB) {
@@ -427,10 +487,29 @@ bool sweep_mfma_supported(int R)
 
 // tiles = 8 selects the wide form of the R = 16 bucket; 0 the default form.
 static bool wide16(int R, int tiles) { return R == 16 && tiles == 8; }
+// 16-column tiles per wavefront of the default form of bucket R.
+static int MShape_tpw(int R) { return R <= 12 ? 8 : 4; }
 
-size_t sweep_mfma_lds_bytes(int R, int tiles)
+// The reduce-then-broadcast exchange exists for the 4-tile forms (R > 12;
+// the 8-tile forms have no room for a third band buffer in LDS).
+#define SFR_MFMA_RB_LIST(X) X(16) X(20) X(24) X(32)
+
+bool sweep_mfma_rb_supported(int R, int tiles)
+{
+    return !wide16(R, tiles) && MShape_tpw(R) == 4 && sweep_mfma_supported(R);
+}
+
+size_t sweep_mfma_lds_bytes(int R, int tiles, bool rb)
 {
     if (wide16(R, tiles)) return mfma_lds<16, 8>().total;
+    if (rb) {
+        switch (R) {
+#define CASE(r) case r: return mfma_lds<r, 0, true>().total;
+            SFR_MFMA_RB_LIST(CASE)
+#undef CASE
+        default: return 0;
+        }
+    }
     switch (R) {
 #define CASE(r) case r: return mfma_lds<r>().total;
         SFR_MFMA_R_LIST(CASE)
@@ -450,11 +529,22 @@ int sweep_mfma_width(int R, int tiles)
     }
 }
 
-static void* sweep_mfma_fn(int R, int tiles, bool bf16)
+static void* sweep_mfma_fn(int R, int tiles, bool bf16, bool rb)
 {
     if (wide16(R, tiles))
         return bf16 ? reinterpret_cast<void*>(&sweep_mfma_kernel<16, true, 8>)
                     : reinterpret_cast<void*>(&sweep_mfma_kernel<16, false, 8>);
+    if (rb) {
+        switch (R) {
+#define CASE(r)                                                                             \
+    case r:                                                                                 \
+        return bf16 ? reinterpret_cast<void*>(&sweep_mfma_kernel<r, true, 0, true>)         \
+                    : reinterpret_cast<void*>(&sweep_mfma_kernel<r, false, 0, true>);
+            SFR_MFMA_RB_LIST(CASE)
+#undef CASE
+        default: return nullptr;
+        }
+    }
     switch (R) {
 #define CASE(r)                                                                             \
     case r:                                                                                 \
@@ -466,33 +556,49 @@ static void* sweep_mfma_fn(int R, int tiles, bool bf16)
     }
 }
 
-hipError_t sweep_mfma_prepare(int R, int tiles, size_t lds, int* blocks_per_cu)
+hipError_t sweep_mfma_prepare(int R, int tiles, bool rb, size_t lds, int* blocks_per_cu)
 {
     // both operand forms share the launch shape and LDS size
     for (int bf = 1; bf >= 0; --bf) {
-        void* fn = sweep_mfma_fn(R, tiles, bf != 0);
+        void* fn = sweep_mfma_fn(R, tiles, bf != 0, rb);
         if (!fn) return hipErrorInvalidValue;
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, sweep_mfma_fn(R, tiles, false), kMTPB, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, sweep_mfma_fn(R, tiles, false, rb), kMTPB,
+                                                        lds);
 }
 
-hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int tiles, int grid, size_t lds, hipStream_t s,
-                             hipEvent_t ev0, hipEvent_t ev1, bool bf16)
+hipError_t launch_sweep_mfma(const SweepArgs<float>& a, int R, int tiles, bool rb, int grid, size_t lds,
+                             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool bf16)
 {
-#define LAUNCH_TW(r, BF, TW)                                                                                \
+#define LAUNCH_TW(r, BF, TW, RBF)                                                                           \
     if (ev0)                                                                                                \
-        hipExtLaunchKernelGGL((sweep_mfma_kernel<r, BF, TW>), dim3(grid), dim3(kMTPB), (uint32_t)lds, s, ev0,  \
-                              ev1, 0u, a);                                                                  \
+        hipExtLaunchKernelGGL((sweep_mfma_kernel<r, BF, TW, RBF>), dim3(grid), dim3(kMTPB), (uint32_t)lds, s, \
+                              ev0, ev1, 0u, a);                                                             \
     else                                                                                                    \
-        hipLaunchKernelGGL((sweep_mfma_kernel<r, BF, TW>), dim3(grid), dim3(kMTPB), lds, s, a);
-#define LAUNCH(r, BF) LAUNCH_TW(r, BF, 0)
+        hipLaunchKernelGGL((sweep_mfma_kernel<r, BF, TW, RBF>), dim3(grid), dim3(kMTPB), lds, s, a);
+#define LAUNCH(r, BF) LAUNCH_TW(r, BF, 0, false)
+    if (rb) {
+        switch (R) {
+#define CASE(r)                           \
+    case r:                               \
+        if (bf16) {                       \
+            LAUNCH_TW(r, true, 0, true)   \
+        } else {                          \
+            LAUNCH_TW(r, false, 0, true)  \
+        }                                 \
+        return hipGetLastError();
+            SFR_MFMA_RB_LIST(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (wide16(R, tiles)) {
         if (bf16) {
-            LAUNCH_TW(16, true, 8)
+            LAUNCH_TW(16, true, 8, false)
         } else {
-            LAUNCH_TW(16, false, 8)
+            LAUNCH_TW(16, false, 8, false)
         }
         return hipGetLastError();
     }
