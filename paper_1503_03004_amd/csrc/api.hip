@@ -354,6 +354,12 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
     h.k = 1; h.done = 0; h.status = 0;
     h.mu = mu0; h.mu_prev = mu0;
     h.tsvd = tsvd ? 1 : 0;
+    // A fixed-count FR-ADM solve that returns S stops with the step of its
+    // last iteration K: the S pass of the outputs also takes the residual
+    // of iteration K, which would otherwise need sweep K + 1 (a pass over
+    // M and both Y buffers that the returned iterate does not use).
+    const bool stop_in_step = (fixed1 > 0) && !two_phase && !tsvd && (out.S != nullptr);
+    h.stop_after = stop_in_step ? fixed1 : 0;
     for (int i = 0; i < kMaxR; ++i) {
         h.E1[i * kMaxR + i] = 1.0;
         h.E2[i * kMaxR + i] = 1.0;
@@ -378,7 +384,7 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
     // still contracts: late in a solve (large mu) L hardly moves and S
     // absorbs the residual, so FP32 iterations there do not remove an error
     // in L.
-    const int limit = (fixed1 > 0 ? fixed1 : max1) + (tsvd ? 0 : 1);
+    const int limit = (fixed1 > 0 ? fixed1 : max1) + ((tsvd || stop_in_step) ? 0 : 1);
     const int batch = 8;
     // Profiling: start/stop events bound to every general sweep (k >= 3).
     if (p.profile) {
@@ -531,7 +537,10 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         la.lam = p.lambda;
         la.mu = 1.0;
         la.min_eig = out.min_eig ? 1 : 0;
-        HIPCHK(launch_lowrank_pass<T>(la, e.R, s));
+        la.rpart = stop_in_step ? e.rpart : nullptr;
+        int parts = 0;
+        HIPCHK(launch_lowrank_pass<T>(la, e.R, s, &parts));
+        if (stop_in_step) HIPCHK(launch_res_final(e.st, e.rpart, parts, e.res_hist, s));
     } else if (out.min_eig) {
         HIPCHK(launch_final_small(e.st, e.R, s));
     }

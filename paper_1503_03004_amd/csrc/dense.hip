@@ -176,7 +176,12 @@ __global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
     __shared__ T Ab[kLowrankRows * R];
     for (int e = tid; e < (i1 - i0) * R; e += 256) Ab[e] = A[(int64_t)i0 * R + e];
     __syncthreads();
-    if (j >= n) return;
+    // ||Y_{K+1} - Y_K||^2 of this thread's elements (a.rpart: the residual of
+    // the returned iterate, in the sweep's clamp form Y_{K+1} = clamp(mu_K R))
+    const bool want_res = (a.rpart != nullptr) && (mode == 0);
+    const T muT = (T)mu, lamT = (T)lam;
+    double racc = 0.0;
+    if (j < n) {
     // this thread's VEC columns of Vt stay in registers for the whole band
     T vk[R][VEC];
 #pragma unroll
@@ -214,6 +219,11 @@ __global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
                     const T Rr = mv[u][e] - l + yv[u][e] * imu;
                     const T a = Rr - t, b = Rr + t;
                     out[e] = (a > T(0) ? a : T(0)) + (b < T(0) ? b : T(0));
+                    if (want_res && full && j + e < n) {
+                        const T y = fmin(fmax(muT * Rr, -lamT), lamT);
+                        const double dy = (double)(y - yv[u][e]);
+                        racc = fma(dy, dy, racc);
+                    }
                 } else {
                     out[e] = mv[u][e] - l;
                 }
@@ -221,6 +231,47 @@ __global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
             if (full) vstore<T, VEC>(S + (int64_t)(i + u) * lds + j, out);
         }
     }
+    }
+    if (want_res) {
+        // workgroup sum in a fixed order: wavefronts by shuffles, then the
+        // four wavefront sums in order
+        __shared__ double rred[4];
+        for (int off = 32; off > 0; off >>= 1) racc += __shfl_xor(racc, off, 64);
+        if ((tid & 63) == 0) rred[tid >> 6] = racc;
+        __syncthreads();
+        if (tid == 0)
+            a.rpart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = (rred[0] + rred[1]) + (rred[2] + rred[3]);
+    }
+}
+
+int lowrank_res_parts(int m, int n)
+{
+    return ((n + 255) / 256) * ((m + kLowrankRows - 1) / kLowrankRows);
+}
+
+__global__ void __launch_bounds__(256) res_final_kernel(DevState* st, const double* rpart, int count,
+                                                        double* res_hist)
+{
+    if (!st->done || st->status < 0 || st->exch_timeout || st->stop_after <= 0) return;
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int e = t; e < count; e += 256) s += rpart[e];
+    red[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < 256; ++w) tot += red[w];
+        const double res = sqrt(tot) / (st->mu_prev * st->nrmM);
+        st->res = res;
+        if (st->iters >= 1) res_hist[st->iters - 1] = res;
+    }
+}
+
+hipError_t launch_res_final(DevState* st, const double* rpart, int count, double* res_hist, hipStream_t s)
+{
+    hipLaunchKernelGGL(res_final_kernel, dim3(1), dim3(256), 0, s, st, rpart, count, res_hist);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -234,9 +285,10 @@ hipError_t launch_factors(const DevState* st, const PingPong<T>& pp, int m, int 
 }
 
 template <typename T, int VEC>
-static hipError_t lowrank_dispatch(const LowrankArgs<T>& a, int R, hipStream_t s)
+static hipError_t lowrank_dispatch(const LowrankArgs<T>& a, int R, hipStream_t s, int* parts)
 {
     dim3 grid((unsigned)((a.n + 256 * VEC - 1) / (256 * VEC)), (unsigned)((a.m + a.rows_per_blk - 1) / a.rows_per_blk));
+    if (parts) *parts = (int)(grid.x * grid.y);
     switch (R) {
 #define CASE(rr)                                                                               \
     case rr: hipLaunchKernelGGL((lowrank_pass_kernel<T, VEC, rr>), grid, dim3(256), 0, s, a); \
@@ -252,7 +304,7 @@ static hipError_t lowrank_dispatch(const LowrankArgs<T>& a, int R, hipStream_t s
 // Vector paths need n, ldm, ldy, lds multiples of VEC and 16-byte aligned
 // bases (both Y buffers when they are picked on the device).
 template <typename T>
-hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s)
+hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s, int* parts)
 {
     constexpr int V = 16 / sizeof(T);
     a.rows_per_blk = kLowrankRows;
@@ -260,8 +312,8 @@ hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s)
     bool ys = a.st ? (al(a.pp.Y[0]) && al(a.pp.Y[1])) : (!a.Y || al(a.Y));
     const bool vec = (a.n % V == 0) && (a.ldm % V == 0) && (a.lds % V == 0) && al(a.M) && al(a.S) &&
                      (a.ldy % V == 0) && ys;
-    if (vec) return lowrank_dispatch<T, V>(a, R, s);
-    return lowrank_dispatch<T, 1>(a, R, s);
+    if (vec) return lowrank_dispatch<T, V>(a, R, s, parts);
+    return lowrank_dispatch<T, 1>(a, R, s, parts);
 }
 
 // Alg. 3: C = Mt[:, 0:l] (m x l), Rb = Mt[0:l, :] (l x n) with row i of the
@@ -426,7 +478,7 @@ hipError_t launch_orth(const DevState* st, const T* U, int m, const T* V, int n,
     template hipError_t launch_copy_pad<T>(const T*, int64_t, T*, int64_t, int, int, hipStream_t);          \
     template hipError_t launch_factors<T>(const DevState*, const PingPong<T>&, int, int, int, int, T*, T*,    \
                                           double*, hipStream_t);                                             \
-    template hipError_t launch_lowrank_pass<T>(LowrankArgs<T>, int, hipStream_t);                            \
+    template hipError_t launch_lowrank_pass<T>(LowrankArgs<T>, int, hipStream_t, int*);                            \
     template hipError_t launch_nys_gather<T>(const T*, int64_t, const int64_t*, int, int, int, T*, T*,       \
                                              hipStream_t);
 INST(float)

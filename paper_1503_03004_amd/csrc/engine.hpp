@@ -45,6 +45,7 @@ struct Engine {
     void* Q[2] = {nullptr, nullptr};
     void* Qpart = nullptr;
     double* dy2part = nullptr;
+    double* rpart = nullptr;     // residual partials of the S pass (fixed-count solves)
     unsigned long long* exch = nullptr;
     size_t exch_words = 0;
     double* GQpart = nullptr;
@@ -179,6 +180,7 @@ bool engine_buffers(Engine& e, bool pad, Get&& get)
         if (!(e.Q[b] = get((size_t)e.ne * e.R * e.esz))) return false;
     if (!(e.Qpart = get((size_t)e.max_ncl * e.ne * e.R * e.esz))) return false;
     if (!(e.dy2part = static_cast<double*>(get(sizeof(double) * (size_t)e.max_grid)))) return false;
+    if (!(e.rpart = static_cast<double*>(get(sizeof(double) * (size_t)lowrank_res_parts(e.m, e.n))))) return false;
     if (e.exch_words && !(e.exch = static_cast<unsigned long long*>(get(8 * e.exch_words)))) return false;
     if (!(e.GQpart = static_cast<double*>(get(sizeof(double) * (size_t)e.nqb * e.E)))) return false;
     if (!(e.GPpart = static_cast<double*>(get(sizeof(double) * (size_t)e.npb * e.E)))) return false;

@@ -70,6 +70,8 @@ struct DevState {
     int32_t iters;      // completed iterations once done
     int32_t exch_timeout;  // set if a cluster exchange wait hit its bound
     int32_t tsvd;       // 1: FixedRankOptFull (Alg. 4) on X = M, stop on the change of B
+    int32_t stop_after; // > 0: the step of this iteration ends the solve (a fixed-count FR-ADM solve
+                        // whose last residual is taken by the S pass instead of one more sweep)
     double nrmM;        // ||M||_F
     double mu;          // mu_k used by the next sweep's L-step input
     double mu_prev;     // mu_{k-1} used by the next sweep's S/Y step
@@ -192,7 +194,16 @@ struct LowrankArgs {
     int m, n, mode, rows_per_blk;
     int min_eig;   // with st: also write min eig(B) into the state
     double lam, mu;
+    double* rpart; // with st, FR-ADM: per-workgroup ||Y_{K+1} - Y_K||^2 of the returned iterate, or nullptr
 };
+
+// Partials of the returned iterate's residual held by the S pass: one per
+// workgroup of its grid (at most this many for an m x n pass).
+int lowrank_res_parts(int m, int n);
+// Residual ||M - L_{K+1} - S_{K+1}||_F / ||M||_F = ||Y_{K+1} - Y_K||_F / (mu_K ||M||_F)
+// of a solve stopped by stop_after, from the S pass's partials (fixed order):
+// into the state and res_hist[K - 1].
+hipError_t launch_res_final(DevState* st, const double* rpart, int count, double* res_hist, hipStream_t s);
 
 // One problem of a batched solve (batch.hip): the caller's arguments, the
 // slot's workspace and, on return, its results.  Device memory.
@@ -326,7 +337,7 @@ template <typename T>
 hipError_t launch_factors(const DevState* st, const PingPong<T>& pp, int m, int n, int r, int R, T* U, T* V,
                           double* B, hipStream_t s);
 template <typename T>
-hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s);
+hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s, int* parts = nullptr);
 // max(||U^T U - I_r||_F, ||V^T V - I_r||_F) of stored factors U (m x r) and
 // V (n x r), accumulated in FP64, into *out.  Up (nu x r(r+1)/2) and Vp
 // (nv x r(r+1)/2) receive the partial Grams of nu and nv row blocks.  With

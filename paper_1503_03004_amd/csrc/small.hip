@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(kStepTPB) step_kernel(StepArgs a)
     for (int u = 0; u < DYU; ++u) dyv[u] = a.dy2part[min(tid + u * TPB, a.ndy - 1)];
     const int32_t done0 = st->done, tmo = st->exch_timeout;
     const int r = st->r, k = st->k, tsvd = st->tsvd;
-    const int fixed_iters = st->fixed_iters, max_iter = st->max_iter;
+    const int fixed_iters = st->fixed_iters, max_iter = st->max_iter, stop_after = st->stop_after;
     const double mu = st->mu, mu_prev = st->mu_prev, nrmM = st->nrmM, tol = st->tol;
     const double rho = st->rho, mu_bar = st->mu_bar;
     if (done0) return;
@@ -283,6 +283,12 @@ __global__ void __launch_bounds__(kStepTPB) step_kernel(StepArgs a)
         const double nm = rho * mu;
         st->mu = nm < mu_bar ? nm : mu_bar;
         st->k = k + 1;
+        // a fixed-count solve ends with this step: its returned iterate is
+        // iteration k, whose residual the S pass takes
+        if (stop_after > 0 && k >= stop_after) {
+            st->iters = k;
+            st->done = 1;
+        }
     }
 }
 

@@ -318,3 +318,33 @@ def test_both_exchange_forms_bitwise(monkeypatch, m, n, r, fixed, bf16):
     if not bf16:   # BF16 operands: the two forms are compared with each other only
         o = oracle.fradm(Md, r, inst.lam, mu0, fixed_iters=fixed)
         compare(out["reduce"], o, "f32", f"reduce-then-broadcast {m}x{n} r={r}")
+
+
+@pytest.mark.parametrize("precision,fixed", [("f32", 9), ("f64", 7), ("f32", 1)])
+def test_fixed_count_residual_from_the_S_pass(precision, fixed):
+    """A fixed-count solve that returns S ends with the step of its last
+    iteration K and takes iteration K's residual ||M - L - S||_F / ||M||_F in
+    the pass that writes S; without S it comes from one more sweep.  Both
+    match the oracle's residual of iteration K (residual identity of the dual
+    update, ||M - L - S|| = ||Y_{K+1} - Y_K|| / mu_K), and the factors of the
+    two solves are bitwise the same."""
+    m, n, r = (900, 1300, 8) if precision == "f32" else (300, 260, 6)
+    dt = np.float32 if precision == "f32" else np.float64
+    inst = workloads.planted(m, n, r, seed=5, frac=0.1, kind="uniform", scale=30.0, dtype=dt)
+    Md = inst.M.astype(np.float64)
+    mu0 = workloads.default_mu0(Md)
+    o = oracle.fradm(Md, r, inst.lam, mu0, fixed_iters=fixed)
+    Mt = torch.from_numpy(np.ascontiguousarray(inst.M)).cuda()
+    with sfr.Solver(m, n, r, inst.lam, mu0, 1e-7, precision=precision, fixed_iters=fixed) as s:
+        U1, B1, V1, S1, i1 = s.solve(Mt)
+        U2, B2, V2, S2, i2 = s.solve(Mt, want_S=False)
+        torch.cuda.synchronize()
+    assert S2 is None and i1.iters == i2.iters == fixed
+    assert torch.equal(U1, U2) and torch.equal(B1, B2) and torch.equal(V1, V2)
+    # a reported figure, not an output: relative 1e-4 in FP32 (its terms are
+    # FP32 differences of Y, rounding floor about 3e-8 of ||M||), 1e-9 in FP64
+    bar, floor = (1e-4, 3e-8) if precision == "f32" else (1e-9, 1e-15)
+    print(f"{precision} K={fixed}: residual from the S pass {i1.rel_residual:.6e}, from sweep K + 1 "
+          f"{i2.rel_residual:.6e}, oracle {o['res']:.6e}")
+    for info in (i1, i2):
+        assert abs(info.rel_residual - o["res"]) <= bar * o["res"] + floor, (info.rel_residual, o["res"])
