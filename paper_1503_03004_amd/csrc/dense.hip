@@ -362,11 +362,77 @@ __device__ __forceinline__ void tri_index(int e, int r, int& p, int& q)
 // the chunk's rows, in row order.
 constexpr int kOrthChunk = 128;
 
+// Small ranks (r <= kOrthSmallR): thread t accumulates all r(r+1)/2 entries
+// over rows t, t + 256, ... of the block in registers, eight rows' loads in
+// flight at a time; the block then adds the 256 thread sums of each entry
+// (wavefront shuffles, then the four wavefront sums in order).  Tall
+// factors (the 262144 x 3 photometric U) stream at full width this way.
+constexpr int kOrthSmallR = 8;
+
+template <typename T>
+__device__ void orth_block_small(const T* X, int r, int i0, int i1, double* out)
+{
+    constexpr int RM = kOrthSmallR, EM = RM * (RM + 1) / 2, RU = 8;
+    double acc[EM];
+#pragma unroll
+    for (int e = 0; e < EM; ++e) acc[e] = 0.0;
+    const int t = threadIdx.x;
+    for (int i = i0 + t; i < i1; i += 256 * RU) {
+        double x[RU][RM];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int iu = i + 256 * u;
+#pragma unroll
+            for (int p = 0; p < RM; ++p) x[u][p] = (iu < i1 && p < r) ? (double)X[(int64_t)iu * r + p] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            int e = 0;
+#pragma unroll
+            for (int p = 0; p < RM; ++p)
+#pragma unroll
+                for (int q = p; q < RM; ++q) {
+                    acc[e] = fma(x[u][p], x[u][q], acc[e]);
+                    ++e;
+                }
+        }
+    }
+    __shared__ double wsum[4][EM];
+    const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+        double v = acc[e];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) wsum[wave][e] = v;
+    }
+    __syncthreads();
+    // entry e of the packed triangle of an r x r Gram (p <= q < r) from the
+    // RM x RM layout of the accumulators
+    if (t < r * (r + 1) / 2) {
+        int p, q, e = t;
+        p = 0;
+        while (e >= r - p) { e -= r - p; ++p; }
+        q = p + e;
+        const int em = p * RM - p * (p - 1) / 2 + (q - p);
+        out[t] = (wsum[0][em] + wsum[1][em]) + (wsum[2][em] + wsum[3][em]);
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) orth_partial_kernel(const DevState* st, const T* U, int m, const T* V, int n,
                                                            int r, double* Up, int nu, double* Vp, int nv)
 {
     if (st && (!st->done || st->status < 0 || st->exch_timeout)) return;
+    if (r <= kOrthSmallR) {
+        const bool isU = (int)blockIdx.x < nu;
+        const int b = isU ? (int)blockIdx.x : (int)blockIdx.x - nu;
+        const int nb = isU ? nu : nv;
+        const int rows = isU ? m : n;
+        const int per = (rows + nb - 1) / nb;
+        const int i0 = b * per, i1 = min(rows, i0 + per);
+        orth_block_small<T>(isU ? U : V, r, i0, i1, (isU ? Up : Vp) + (size_t)b * (r * (r + 1) / 2));
+        return;
+    }
     __shared__ double xs[kOrthChunk * kMaxR];
     const bool isU = (int)blockIdx.x < nu;
     const int b = isU ? (int)blockIdx.x : (int)blockIdx.x - nu;
