@@ -15,6 +15,10 @@
 
 namespace sfr {
 
+// Rank buckets up to this take the Jacobi route directly (the step's
+// Newton-Schulz products cost the same 16 x 16 tiles at every rank).
+constexpr int kStepJacobiMaxR = 4;
+
 // LDS of the step kernel: 14 RT x LDP matrices, the two Gram triangles and
 // their segment sums, the residual wave sums, the reduction slots and the
 // Jacobi scratch.
@@ -207,7 +211,13 @@ __global__ void __launch_bounds__(kStepTPB) step_kernel(StepArgs a)
     // ---- the r x r algebra: Newton-Schulz, else the warm-started Jacobi
     // path (which also decides rank loss); outputs left in LDS
     const double *oB, *oTU, *oTUbar, *oTV;
-    if (ns_lstep<R>(Bm, Gp, Gq, X, Am, C, Y0, Y1, Z0, Z1, Tm, T1, R1, Km, nsred, r, a.ns_kappa)) {
+    // Newton-Schulz works on 16 x 16 tiles whatever the rank; up to
+    // kStepJacobiMaxR the warm-started eigendecompositions of the R x R
+    // Grams are the cheaper route (262144 x 48, r = 3: 13 against 28 us)
+    bool use_ns = false;
+    if constexpr (R > kStepJacobiMaxR)
+        use_ns = ns_lstep<R>(Bm, Gp, Gq, X, Am, C, Y0, Y1, Z0, Z1, Tm, T1, R1, Km, nsred, r, a.ns_kappa);
+    if (use_ns) {
         oB = Y0; oTU = Am; oTUbar = T1; oTV = Gp;
     } else {
         // eigenbases of the last Jacobi step (identity at the start of a
