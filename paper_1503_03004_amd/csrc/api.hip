@@ -446,15 +446,16 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         return SFR_OK;
     };
     // One phase: iterations k0 .. lim, queued in one go (fixed rule) or in
-    // batches of 8 with one batch running ahead of the host's check of the
-    // previous one.  *K receives the returned iterate when the host knows
-    // it (fixed rule: lim - 1; polled: from the state), else -1.
+    // batches of up to 8 with one batch running ahead of the host's check of
+    // the previous one, cut at the forecast stop (StopForecast).  *K
+    // receives the returned iterate when the host knows it (fixed rule:
+    // lim - 1; polled: from the state), else -1.
     auto run_phase = [&](int k0, int lim, bool bf, bool fixed_rule, bool timed_ok, int* K) -> sfr_status {
         *K = -1;
         int k = k0;
         int launched_batches = 0, checked_batches = 0;   // this phase's poll slots
-        auto enqueue_batch = [&](void) -> sfr_status {
-            for (int b = 0; b < batch && k <= lim; ++b, ++k) {
+        auto enqueue_batch = [&](int count) -> sfr_status {
+            for (int b = 0; b < count && k <= lim; ++b, ++k) {
                 const sfr_status es = enqueue_iter(k, bf, timed_ok);
                 if (es != SFR_OK) return es;
             }
@@ -469,19 +470,24 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         sfr_status es;
         if (fixed_rule) {
             while (k <= lim) {
-                es = enqueue_batch();
+                es = enqueue_batch(batch);
                 if (es != SFR_OK) return es;
             }
             *K = lim - 1;   // if the phase failed instead, what follows returns at once
             return SFR_OK;
         }
-        es = enqueue_batch();
+        StopForecast fc;
+        es = enqueue_batch(batch);
         if (es != SFR_OK) return es;
         for (;;) {
             if (k <= lim) {
-                es = enqueue_batch();
-                if (es != SFR_OK) return es;
+                const int count = fc.size(k, batch, checked_batches == launched_batches);
+                if (count > 0) {
+                    es = enqueue_batch(count);
+                    if (es != SFR_OK) return es;
+                }
             }
+            if (checked_batches == launched_batches) return SFR_OK;   // k > lim: reported below
             const int slot = checked_batches & 1;
             // without poll events (an engine that owns no host objects) the
             // whole stream is waited for, which covers this batch's snapshot
@@ -493,7 +499,7 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
                 if (ph.done && ph.status >= 0 && !ph.exch_timeout) *K = ph.iters;
                 return SFR_OK;
             }
-            if (checked_batches == launched_batches && k > lim) return SFR_OK;   // reported below
+            fc.observe(ph);
         }
     };
     int bulk_iters = -1;

@@ -5,9 +5,53 @@
 #include "sfr.h"
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 namespace sfr {
+
+// Host forecast of where a tolerance-driven solve stops, from the state
+// snapshots the host reads between batches of queued iterations.  Once mu
+// grows by rho per iteration the residual falls about geometrically, so the
+// last two snapshots give its rate and the iteration at which it reaches
+// tol.  The forecast only sizes the batches queued ahead of the host's
+// checks, so that few iterations run after the stop (they return at once
+// but still cost their launches); the device decides the stop, and a full
+// batch is queued again whenever none is in flight and it has not stopped.
+struct StopForecast {
+    int idx = 0;        // iteration of the last snapshot's residual (0: none)
+    double res = 0.0;
+    int last = 0;       // forecast: last iteration to queue (0: no forecast)
+
+    void observe(const DevState& ph)
+    {
+        // FR-ADM tests iteration k - 1 in step k, Alg. 4 iteration k;
+        // ph.k is the next step's index
+        const int i = ph.tsvd ? ph.k - 1 : ph.k - 2;
+        const double r = ph.res;
+        if (i < 1 || !(r > 0.0) || !std::isfinite(r)) {
+            idx = 0;
+            last = 0;
+            return;
+        }
+        last = 0;
+        if (idx >= 1 && i > idx && r < res && ph.tol > 0.0) {
+            const double rate = std::log(r / res) / (double)(i - idx);   // < 0
+            const double more = std::ceil(std::log(ph.tol / r) / rate);
+            if (std::isfinite(more) && more < 1e6)
+                last = i + (int)std::max(0.0, more) + (ph.tsvd ? 0 : 1);
+        }
+        idx = i;
+        res = r;
+    }
+    // iterations to queue from k on, at most `batch`; idle: none in flight
+    int size(int k, int batch, bool idle) const
+    {
+        if (last == 0) return batch;
+        if (last >= k) return std::min(batch, last - k + 1);
+        return idle ? batch : 0;
+    }
+};
 
 // Launch shape of one sweep kernel on the engine's problem.
 struct SweepCfg {

@@ -1309,10 +1309,13 @@ static sfr_status lr_iterate(LrEngine& e, const Params& p, double mu0, const flo
             if (es != SFR_OK) return es;
         }
     } else {
+        // batches of up to 4, one running ahead of the host's check, cut at
+        // the forecast stop
         const int batch = 4;
         int k = 1, launched = 0, checked = 0;
-        auto enqueue_batch = [&]() -> sfr_status {
-            for (int j = 0; j < batch && k <= limit; ++j, ++k) {
+        StopForecast fc;
+        auto enqueue_batch = [&](int count) -> sfr_status {
+            for (int j = 0; j < count && k <= limit; ++j, ++k) {
                 const sfr_status es = lr_enqueue_iter(e, k, M, ldm, tsvd, s);
                 if (es != SFR_OK) return es;
             }
@@ -1322,18 +1325,22 @@ static sfr_status lr_iterate(LrEngine& e, const Params& p, double mu0, const flo
             ++launched;
             return SFR_OK;
         };
-        sfr_status es = enqueue_batch();
+        sfr_status es = enqueue_batch(batch);
         if (es != SFR_OK) return es;
         for (;;) {
             if (k <= limit) {
-                es = enqueue_batch();
-                if (es != SFR_OK) return es;
+                const int count = fc.size(k, batch, checked == launched);
+                if (count > 0) {
+                    es = enqueue_batch(count);
+                    if (es != SFR_OK) return es;
+                }
             }
+            if (checked == launched) break;   // k > limit
             const int slot = checked & 1;
             LRCHK(hipEventSynchronize(e.poll_ev[slot]));
             ++checked;
             if (e.host_poll[slot].done) break;
-            if (checked == launched && k > limit) break;
+            fc.observe(e.host_poll[slot]);
         }
     }
     LRCHK(hipMemcpyAsync(e.host_state, e.st, offsetof(DevState, B), hipMemcpyDeviceToHost, s));
