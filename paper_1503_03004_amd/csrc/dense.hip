@@ -4,6 +4,9 @@
 #include "sfr_internal.hpp"
 #include "small_la.hpp"
 
+#include <stdlib.h>
+#include <string.h>
+
 #include <algorithm>
 
 namespace sfr {
@@ -244,6 +247,149 @@ __global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
     }
 }
 
+// Matrix-core form of the FP32 pass (R >= 8).  The rank-R term of a tile of
+// 16 rows x 16 columns is one matrix-core product over K = R (padded to a
+// multiple of 4), taken transposed, D = Vt_tile A_tile^T, so that lane
+// (c, g) = (lane % 16, lane / 16) of a wavefront receives row c, columns
+// 4g .. 4g + 3 of the tile: exactly the M, Y and S elements it then reads
+// and writes as one 16-byte vector each.  A wavefront owns 64 columns (four
+// tiles, whose Vt operands stay in registers) of the workgroup's 64-row band
+// and walks it 16 rows at a time, the next rows' loads in flight.  After l
+// the arithmetic per element is that of lowrank_pass_kernel.
+typedef float dn_f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kLrmCols = 256;   // columns of a matrix-core workgroup (four wavefronts x 64)
+
+template <int R>
+__global__ void __launch_bounds__(256) lowrank_mfma_kernel(LowrankArgs<float> a)
+{
+    constexpr int KS = (R + 3) / 4;           // 4-deep steps of K
+    constexpr int AP = 4 * KS;                // padded row-factor pitch in LDS
+    constexpr int NST = kLowrankRows / 16;    // 16-row steps of the band
+    const float* M = a.M;
+    const int64_t ldm = a.ldm, ldy = a.ldy, lds = a.lds;
+    const int m = a.m, n = a.n, mode = a.mode;
+    float* S = a.S;
+    const float* Y = a.Y;
+    const float* A = a.A;
+    const float* Vt = a.Vt;
+    double mu = a.mu;
+    const double lam = a.lam;
+    if (a.st) {
+        // FR-ADM: the returned iterate K picks the buffers (see factors_kernel)
+        const DevState* st = a.st;
+        if (!st->done || st->status < 0 || st->exch_timeout) return;
+        const int K = st->iters;
+        Y = (K >= 2) ? a.pp.Y[K & 1] : nullptr;
+        A = a.pp.P[(K + 1) & 1];
+        Vt = a.pp.Q[(K + 1) & 1];
+        mu = st->mu_prev;
+        if (a.min_eig && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 64) {
+            __shared__ double Aw[R * LDP], Ew[R * LDP];
+            __shared__ __align__(16) double csw[2 * 16];
+            const double w = wmin_eig<R>(st->B, kMaxR, st->r, Aw, Ew, csw);
+            if (threadIdx.x == 0) a.st->min_eig_B = w;
+        }
+    }
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 15, g = lane >> 4;
+    const int i0 = blockIdx.y * kLowrankRows;
+    const int i1 = min(m, i0 + kLowrankRows);
+    const int jw = blockIdx.x * kLrmCols + wave * 64;
+    // the band's row factors, zero past rank R and past the band's last row
+    __shared__ float Ab[kLowrankRows * AP];
+    for (int e = tid; e < kLowrankRows * AP; e += 256) {
+        const int ii = e / AP, k = e % AP;
+        Ab[e] = (i0 + ii < i1 && k < R) ? A[(int64_t)(i0 + ii) * R + k] : 0.f;
+    }
+    // Vt operands of the wavefront's four tiles: column jw + 16 t + c, rank 4 s + g
+    float va[4][KS];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int col = jw + 16 * t + c;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int k = 4 * s + g;
+            va[t][s] = (col < n && k < R) ? Vt[(int64_t)col * R + k] : 0.f;
+        }
+    }
+    __syncthreads();
+    const float th = (float)(lam / mu), imu = (float)(1.0 / mu);
+    const bool want_res = (a.rpart != nullptr) && (mode == 0);
+    const float muT = (float)mu, lamT = (float)lam;
+    const bool use_y = (mode == 0) && (Y != nullptr);
+    double racc = 0.0;
+    // n is a multiple of 4: a lane's four columns of a tile are all in range or all out
+    bool cok[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) cok[t] = jw + 16 * t + 4 * g < n;
+    dn_f32x4 mv[2][4], yv[2][4];
+    auto issue = [&](int stp, int b) {
+        const int row = i0 + 16 * stp + c;
+        const bool rok = row < i1;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int col = jw + 16 * t + 4 * g;
+            const bool ok = rok && cok[t];
+            mv[b][t] = dn_f32x4{0.f, 0.f, 0.f, 0.f};
+            yv[b][t] = dn_f32x4{0.f, 0.f, 0.f, 0.f};
+            if (ok) {
+                mv[b][t] = *reinterpret_cast<const dn_f32x4*>(M + (int64_t)row * ldm + col);
+                if (use_y) yv[b][t] = *reinterpret_cast<const dn_f32x4*>(Y + (int64_t)row * ldy + col);
+            }
+        }
+    };
+    issue(0, 0);
+#pragma unroll
+    for (int stp = 0; stp < NST; ++stp) {
+        const int b = stp & 1;
+        if (stp + 1 < NST) issue(stp + 1, b ^ 1);
+        float vb[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) vb[s] = Ab[(16 * stp + c) * AP + 4 * s + g];
+        dn_f32x4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            acc[t] = dn_f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(va[t][s], vb[s], acc[t], 0, 0, 0);
+        }
+        const int row = i0 + 16 * stp + c;
+        const bool rok = row < i1;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const bool ok = rok && cok[t];
+            dn_f32x4 out;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float l = acc[t][e];
+                if (mode == 0) {
+                    const float Rr = mv[b][t][e] - l + yv[b][t][e] * imu;
+                    const float lo = Rr - th, hi = Rr + th;
+                    out[e] = (lo > 0.f ? lo : 0.f) + (hi < 0.f ? hi : 0.f);
+                    if (want_res && ok) {
+                        const float y = fminf(fmaxf(muT * Rr, -lamT), lamT);
+                        const double dy = (double)(y - yv[b][t][e]);
+                        racc = fma(dy, dy, racc);
+                    }
+                } else {
+                    out[e] = mv[b][t][e] - l;
+                }
+            }
+            if (ok) *reinterpret_cast<dn_f32x4*>(S + (int64_t)row * lds + jw + 16 * t + 4 * g) = out;
+        }
+    }
+    if (want_res) {
+        // workgroup sum in a fixed order: wavefronts by shuffles, then the
+        // four wavefront sums in order
+        __shared__ double rred[4];
+        for (int off = 32; off > 0; off >>= 1) racc += __shfl_xor(racc, off, 64);
+        if (lane == 0) rred[wave] = racc;
+        __syncthreads();
+        if (tid == 0)
+            a.rpart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = (rred[0] + rred[1]) + (rred[2] + rred[3]);
+    }
+}
+
 int lowrank_res_parts(int m, int n)
 {
     return ((n + 255) / 256) * ((m + kLowrankRows - 1) / kLowrankRows);
@@ -301,8 +447,33 @@ static hipError_t lowrank_dispatch(const LowrankArgs<T>& a, int R, hipStream_t s
     return hipGetLastError();
 }
 
+static hipError_t lowrank_mfma_dispatch(const LowrankArgs<float>& a, int R, hipStream_t s, int* parts)
+{
+    dim3 grid((unsigned)((a.n + kLrmCols - 1) / kLrmCols), (unsigned)((a.m + kLowrankRows - 1) / kLowrankRows));
+    if (parts) *parts = (int)(grid.x * grid.y);
+    switch (R) {
+#define CASE(rr)                                                                           \
+    case rr: hipLaunchKernelGGL((lowrank_mfma_kernel<rr>), grid, dim3(256), 0, s, a); \
+        break;
+        CASE(8) CASE(10) CASE(12) CASE(16) CASE(20) CASE(24) CASE(32)
+#undef CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Rank buckets that take the matrix-core FP32 pass (SFR_SPASS=vector keeps
+// the vector form for every bucket).
+static bool lowrank_mfma_bucket(int R)
+{
+    const char* v = getenv("SFR_SPASS");
+    const bool off = v != nullptr && strcmp(v, "vector") == 0;
+    return !off && (R == 8 || R == 10 || R == 12 || R == 16 || R == 20 || R == 24 || R == 32);
+}
+
 // Vector paths need n, ldm, ldy, lds multiples of VEC and 16-byte aligned
-// bases (both Y buffers when they are picked on the device).
+// bases (both Y buffers when they are picked on the device); so does the
+// matrix-core form (FP32, rank buckets from 8).
 template <typename T>
 hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s, int* parts)
 {
@@ -312,6 +483,9 @@ hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s, int* part
     bool ys = a.st ? (al(a.pp.Y[0]) && al(a.pp.Y[1])) : (!a.Y || al(a.Y));
     const bool vec = (a.n % V == 0) && (a.ldm % V == 0) && (a.lds % V == 0) && al(a.M) && al(a.S) &&
                      (a.ldy % V == 0) && ys;
+    if constexpr (sizeof(T) == 4) {
+        if (vec && lowrank_mfma_bucket(R)) return lowrank_mfma_dispatch(a, R, s, parts);
+    }
     if (vec) return lowrank_dispatch<T, V>(a, R, s, parts);
     return lowrank_dispatch<T, 1>(a, R, s, parts);
 }

@@ -348,3 +348,19 @@ def test_fixed_count_residual_from_the_S_pass(precision, fixed):
           f"{i2.rel_residual:.6e}, oracle {o['res']:.6e}")
     for info in (i1, i2):
         assert abs(info.rel_residual - o["res"]) <= bar * o["res"] + floor, (info.rel_residual, o["res"])
+
+
+@pytest.mark.parametrize("spass", ["mfma", "vector"])
+@pytest.mark.parametrize("m,n,r", [(301, 212, 8), (1037, 700, 10), (77, 3004, 12), (260, 1024, 16),
+                                   (500, 68, 20), (130, 904, 24), (150, 1500, 32)])
+def test_both_fp32_S_passes(monkeypatch, spass, m, n, r):
+    """The FP32 pass that writes the returned S (and, for a fixed count, the
+    last residual) in its two forms, selected by SFR_SPASS: the rank-r term
+    on the matrix cores (rank buckets from 8) or on the vector ALU.  Ragged
+    row bands (m not a multiple of 16 or 64) and column tiles (n a multiple
+    of 4 only); S and the residual against the oracle."""
+    monkeypatch.setenv("SFR_SPASS", spass)
+    inst = workloads.planted(m, n, r, seed=m + 3 * n + r, frac=0.08, kind="uniform", scale=30.0, dtype=np.float32)
+    g, o = case(inst, "f32", 5)
+    compare(g, o, "f32", f"S pass {spass} {m}x{n} r={r}")
+    assert abs(g["info"].rel_residual - o["res"]) <= 1e-4 * o["res"] + 3e-8, (g["info"].rel_residual, o["res"])

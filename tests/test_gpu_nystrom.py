@@ -45,13 +45,17 @@ def gpu_nys(M, r, l, perm, lam, mu_l, mu_t, precision, **opts):
                     S=S.double().cpu().numpy(), info=info)
 
 
-@pytest.mark.parametrize("m,n,r,l,precision", [
-    (600, 500, 5, 40, "f64"),
-    (2000, 1500, 10, 40, "f32"),
-    (900, 1300, 4, 30, "f32"),     # l not a multiple of the vector width
-    (300, 2600, 6, 24, "f32"),     # wide top block: clusters of column slices
+@pytest.mark.parametrize("m,n,r,l,precision,spass", [
+    (600, 500, 5, 40, "f64", "mfma"),
+    (2000, 1500, 10, 40, "f32", "mfma"),
+    (2000, 1500, 10, 40, "f32", "vector"),   # the dense S = M - L pass on the vector ALU
+    (900, 1300, 4, 30, "f32", "mfma"),     # l not a multiple of the vector width
+    (300, 2600, 6, 24, "f32", "mfma"),     # wide top block: clusters of column slices
+    (1100, 1300, 20, 80, "f32", "mfma"),   # the r = 20 bucket of the dense S pass on the matrix cores
+    (1100, 1300, 20, 80, "f32", "vector"),
 ])
-def test_nystrom_parity(m, n, r, l, precision):
+def test_nystrom_parity(monkeypatch, m, n, r, l, precision, spass):
+    monkeypatch.setenv("SFR_SPASS", spass)
     inst = workloads.planted(m, n, r, seed=m + n, frac=0.07, kind="laplace", scale=20.0)
     M = inst.M.astype(np.float64 if precision == "f64" else np.float32)
     Md = M.astype(np.float64)
