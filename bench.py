@@ -261,13 +261,8 @@ def main():
             return U_, B_, V_, None, inf_
         return solver.solve(M, out=out, stream=stream)
 
-    # ---- warmup: W untimed iterations
-    if args.warmup > 0:
-        with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=args.warmup, **bf_fixed) as w:
-            run(w)
-    torch.cuda.synchronize()
-
-    # ---- timed: exactly K iterations (plus the output pass writing U, B, V, S)
+    # ---- the timed handle and its outputs are set up first, so that the
+    # warm-up runs right before the timed solve
     K = args.steps
     solver = sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K, **bf_fixed)
     U = torch.empty((m, r), dtype=tdt, device=dev)
@@ -276,7 +271,14 @@ def main():
     S = torch.empty((m, n), dtype=tdt, device=dev)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+
+    # ---- warmup: W untimed iterations (a handle of their own)
+    if args.warmup > 0:
+        with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=args.warmup, **bf_fixed) as w:
+            run(w)
     torch.cuda.synchronize()
+
+    # ---- timed: exactly K iterations (plus the output pass writing U, B, V, S)
     ev0.record(stream)
     _, _, _, _, info = run(solver, out=(U, Bm, V, S), stream=stream)
     ev1.record(stream)
