@@ -10,14 +10,20 @@
 // The products run on the matrix cores and the inverse square roots by
 // Newton-Schulz (small_ns.hpp); Gram products too ill-conditioned for its
 // accuracy take the warm-started Jacobi eigendecompositions of small_la.hpp
-// (the eigenbases of the last such step are kept in the state).
+// (the eigenbases of the last such step are kept in the state).  The
+// smallest rank buckets take the Jacobi route directly, with the matrices in
+// registers up to R = 3 (small_reg.hpp).
 #include "small_ns.hpp"
+#include "small_reg.hpp"
 
 namespace sfr {
 
 // Rank buckets up to this take the Jacobi route directly (the step's
 // Newton-Schulz products cost the same 16 x 16 tiles at every rank).
 constexpr int kStepJacobiMaxR = 4;
+// Rank buckets up to this run that route in registers (small_reg.hpp); at
+// R = 4 the copies of the matrices no longer fit a lane's registers.
+constexpr int kStepRegMaxR = 3;
 
 // LDS of the step kernel: 14 RT x LDP matrices, the two Gram triangles and
 // their segment sums, the residual wave sums, the reduction slots and the
@@ -219,6 +225,41 @@ __global__ void __launch_bounds__(kStepTPB) step_kernel(StepArgs a)
         use_ns = ns_lstep<R>(Bm, Gp, Gq, X, Am, C, Y0, Y1, Z0, Z1, Tm, T1, R1, Km, nsred, r, a.ns_kappa);
     if (use_ns) {
         oB = Y0; oTU = Am; oTUbar = T1; oTV = Gp;
+    } else if constexpr (R <= kStepRegMaxR) {
+        // the warm-started Jacobi route with every lane holding the whole
+        // step in registers (small_reg.hpp); the eigenbases of the last step
+        // (identity at the start of a solve) come from the state
+        RMat<R> rGp, rGq, rB0, rE1, rE2;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                rGp.v[i][j] = Gp[i * LDP + j];
+                rGq.v[i][j] = Gq[i * LDP + j];
+                rB0.v[i][j] = Bm[i * LDP + j];
+                rE1.v[i][j] = st->E1[i * kMaxR + j];
+                rE2.v[i][j] = st->E2[i * kMaxR + j];
+            }
+        RMat<R> rB, rTU, rTUbar, rTV;
+        if (!rm_lstep<R>(rGp, rGq, rB0, rE1, rE2, r, a.dk_tau, rB, rTU, rTUbar, rTV)) {
+            if (tid == 0) { st->status = kErrRank; st->iters = k - 1; st->done = 1; }
+            return;
+        }
+        // lane i R + j publishes entry (i, j) of the outputs (every lane holds them all)
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if (lane == i * R + j) {
+                    Z0[i * LDP + j] = rB.v[i][j];
+                    Km[i * LDP + j] = rTU.v[i][j];
+                    T1[i * LDP + j] = rTUbar.v[i][j];
+                    Gp[i * LDP + j] = rTV.v[i][j];
+                    st->E1[i * kMaxR + j] = rE1.v[i][j];
+                    st->E2[i * kMaxR + j] = rE2.v[i][j];
+                }
+        wsync();
+        oB = Z0; oTU = Km; oTUbar = T1; oTV = Gp;
     } else {
         // eigenbases of the last Jacobi step (identity at the start of a
         // solve) into Z1 and Tm
