@@ -33,6 +33,12 @@
  *    waits are bounded: if the device is held by another process's kernels
  *    or by a running queue (sfr_queue_start) for too long, the solve
  *    returns SFR_ERR_DEVICE with its outputs untouched.
+ *  - Kernel forms can be forced through the environment, read when a handle
+ *    is created (SFR_SWEEP, SFR_EXCH) or when a pass is launched (SFR_SPASS):
+ *    SFR_SWEEP=vector|mfma picks the FP32 sweep kernel, SFR_EXCH=gather|reduce
+ *    the cluster exchange of the matrix-core sweep, SFR_SPASS=vector keeps
+ *    the returned-S pass off the matrix cores.  Every form computes the same
+ *    iteration; the default is chosen per shape.
  */
 #ifndef SFR_H
 #define SFR_H
