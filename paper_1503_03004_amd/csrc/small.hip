@@ -221,10 +221,27 @@ __global__ void __launch_bounds__(kStepTPB) step_kernel(StepArgs a)
     // kStepJacobiMaxR the warm-started eigendecompositions of the R x R
     // Grams are the cheaper route (262144 x 48, r = 3: 13 against 28 us)
     bool use_ns = false;
-    if constexpr (R > kStepJacobiMaxR)
+    if constexpr (R > kStepJacobiMaxR && NB == 1) {
+        // one wavefront, every matrix in registers; the outputs go to LDS at
+        // the lane's own entries, which the stores below read back
+        f64x4 bn, tu, tub, tv;
+        f64x4 b0 = {rb[0], rb[1], rb[2], rb[3]};
+        use_ns = ns1_lstep(b0, Gp, Gq, X, r, a.ns_kappa, bn, tu, tub, tv);
+        if (use_ns) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int li = L.row(e) * LDP + L.col();
+                Y0[li] = bn[e];
+                Am[li] = tu[e];
+                T1[li] = tub[e];
+                C[li] = tv[e];
+            }
+        }
+    } else if constexpr (R > kStepJacobiMaxR) {
         use_ns = ns_lstep<R>(Bm, Gp, Gq, X, Am, C, Y0, Y1, Z0, Z1, Tm, T1, R1, Km, nsred, r, a.ns_kappa);
+    }
     if (use_ns) {
-        oB = Y0; oTU = Am; oTUbar = T1; oTV = Gp;
+        oB = Y0; oTU = Am; oTUbar = T1; oTV = (NB == 1) ? C : Gp;
     } else if constexpr (R <= kStepRegMaxR) {
         // the warm-started Jacobi route with every lane holding the whole
         // step in registers (small_reg.hpp); the eigenbases of the last step

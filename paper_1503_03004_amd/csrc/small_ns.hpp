@@ -362,4 +362,156 @@ __device__ bool ns_lstep(double* Bm, double* Gp, double* Gq, double* X, double* 
     return true;
 }
 
+
+// ---- register form for one wavefront (NB = 1, R <= 16) ----------------
+// A 16 x 16 matrix X is held as the lane's four entries X[g + 4e][c]
+// (c = lane % 16, g = lane / 16): the output layout of the f64 matrix-core
+// step.  That layout is also the step's B-operand layout, and read as the A
+// operand it gives X^T (chunk kc takes A[c][4 kc + g]).  So ns_tmm(X, Y) =
+// X^T Y takes both operands from registers, which is X Y whenever X is
+// symmetric: every product of the step is arranged that way (a symmetric
+// left factor, or a left factor whose transpose is at hand), and only the
+// two symmetrisations of Z pass through LDS.
+__device__ __forceinline__ f64x4 ns_tmm(const f64x4& x, const f64x4& y)
+{
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kc], y[kc], acc, 0, 0, 0);
+    return acc;
+}
+
+// The lane's entries of V^T, through the LDS scratch S (16 x LDP doubles).
+__device__ __forceinline__ f64x4 ns_tile_t(const f64x4& v, double* S)
+{
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) S[(g + 4 * e) * LDP + c] = v[e];
+    wsync();
+    f64x4 t;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t[e] = S[c * LDP + g + 4 * e];
+    wsync();
+    return t;
+}
+
+// C = A^{-1/2} by Newton-Schulz as ns_invsqrt, in registers.  a: the lane's
+// entries of the symmetric A (the padded block is taken as identity).
+// Returns false under the same conditions as ns_invsqrt.
+__device__ inline bool ns1_invsqrt(const f64x4& a, f64x4& cout, double* S, int r, double kappa_max)
+{
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+    f64x4 w, id;
+    bool in[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int i = g + 4 * e;
+        in[e] = (i < r) && (c < r);
+        id[e] = (i == c) ? 1.0 : 0.0;
+        w[e] = in[e] ? a[e] : id[e];
+    }
+    // s = ||A^4||_F^{1/4} (leading block) >= lambda_max
+    const f64x4 s2 = ns_tmm(w, w);
+    const f64x4 s4 = ns_tmm(s2, s2);
+    double f = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (in[e]) f = fma(s4[e], s4[e], f);
+    f = ns_wave_sum(f);
+    const double s = sqrt(sqrt(sqrt(f))) * (1.0 + 1e-12);
+    if (!(s > 0.0) || !isfinite(s)) return false;
+    const double is = 1.0 / s;
+    // Y_0 = A / s (identity on the padded block), Z_0 = I, W_0 = Y_0
+    f64x4 y, z = id;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) y[e] = in[e] ? w[e] * is : w[e];
+    w = y;
+    // The iterates are symmetric only up to rounding.  Reading Z and Y
+    // transposed as left factors keeps the iteration's accuracy, but T must
+    // enter T Z as itself (with T^T the iteration stalls or drifts once cond(A)
+    // passes about 1e3), so its transpose is formed too, from W^T = Y^T Z:
+    // the same products in the same order as W = Z^T Y.
+    f64x4 wt = y;
+    double prev = INFINITY;
+    bool ok = false;
+    for (int it = 0; it < kNsCap; ++it) {
+        if (it > 0) {
+            w = ns_tmm(z, y);    // W = Z^T Y
+            wt = ns_tmm(y, z);   // W^T
+        }
+        f64x4 t, tt;
+        double d2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            t[e] = fma(-0.5, w[e], 1.5 * id[e]);
+            tt[e] = fma(-0.5, wt[e], 1.5 * id[e]);
+            const double d = w[e] - id[e];
+            if (in[e]) d2 = fma(d, d, d2);
+        }
+        const f64x4 yn = ns_tmm(y, t);    // Y^T T
+        const f64x4 zn = ns_tmm(tt, z);   // T Z
+        d2 = ns_wave_sum(d2);
+        if (!(d2 < prev)) break;   // not finite, or no longer contracting
+        prev = d2;
+        y = yn;
+        z = zn;
+        if (prev <= kNsTol * kNsTol) {
+            ok = true;
+            break;
+        }
+    }
+    if (!ok) return false;
+    // C = Sym(Z) / sqrt(s)
+    const f64x4 zt = ns_tile_t(z, S);
+    const double rs = sqrt(is);
+    double z2 = 0.0;
+    f64x4 cv;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double zz = 0.5 * (z[e] + zt[e]);
+        if (in[e]) z2 = fma(zz, zz, z2);
+        cv[e] = in[e] ? zz * rs : id[e];
+    }
+    z2 = ns_wave_sum(z2);
+    if (!(z2 < kappa_max)) return false;
+    cout = cv;
+    return true;
+}
+
+// ns_lstep for one wavefront with every matrix in registers.  b0: the lane's
+// entries of B_0; Gp, Gq: the Grams in LDS (read only); S: LDS scratch.  On
+// success bn = B, tu = B_0 C1 B (row factor transform), tubar = B_0 C1 (U
+// transform), tv = K C2 (V transform), as the lane's entries.  Uniform.
+__device__ inline bool ns1_lstep(const f64x4& b0, const double* Gp, const double* Gq, double* S, int r,
+                                 double kappa_max, f64x4& bn, f64x4& tu, f64x4& tubar, f64x4& tv)
+{
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+    f64x4 gp, gq;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        gp[e] = Gp[(g + 4 * e) * LDP + c];
+        gq[e] = Gq[(g + 4 * e) * LDP + c];
+    }
+    // A1 = B_0 G_P B_0, symmetrised: B_0 (G_P B_0) and (G_P B_0)^T B_0
+    const f64x4 x1 = ns_tmm(gp, b0);
+    const f64x4 a1 = 0.5 * (ns_tmm(b0, x1) + ns_tmm(x1, b0));
+    f64x4 c1;
+    if (!ns1_invsqrt(a1, c1, S, r, kappa_max)) return false;
+    const f64x4 t1 = ns_tmm(b0, c1);   // B_0 C1
+    const f64x4 r1 = ns_tmm(c1, b0);   // C1 B_0 = T1^T
+    // K = Sym(T1 B_0): T1 B_0 = R1^T B_0 and its transpose B_0 R1
+    const f64x4 kk = 0.5 * (ns_tmm(r1, b0) + ns_tmm(b0, r1));
+    // A2 = K G_Q K, symmetrised
+    const f64x4 x2 = ns_tmm(gq, kk);
+    const f64x4 a2 = 0.5 * (ns_tmm(kk, x2) + ns_tmm(x2, kk));
+    f64x4 c2;
+    if (!ns1_invsqrt(a2, c2, S, r, kappa_max)) return false;
+    tv = ns_tmm(kk, c2);                // K C2
+    // B = Sym(C1 B_0 G_Q TV) = Sym(T1^T X3), X3 = G_Q TV
+    const f64x4 x3 = ns_tmm(gq, tv);
+    bn = 0.5 * (ns_tmm(t1, x3) + ns_tmm(x3, t1));
+    tubar = t1;
+    tu = ns_tmm(r1, bn);                // R1^T B = T1 B
+    return true;
+}
+
 }  // namespace sfr
