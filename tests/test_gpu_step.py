@@ -106,3 +106,23 @@ def test_graded_rank_20_fp64_jacobi_path():
     eL, eS = rel(L, o["U"] @ o["B"] @ o["V"].T), rel(S, o["S"])
     print(f"r=20 cond(L) 40 FP64: L {eL:.2e} S {eS:.2e}")
     assert eL <= 1e-9 and eS <= 1e-9
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 7, 9, 11, 14, 16])
+def test_each_rank_bucket_fp64(r):
+    """Every route of the one-wavefront step against the oracle in FP64: the
+    register Jacobi form (r <= 3), the LDS Jacobi form (r = 4) and the
+    register Newton-Schulz form (5 <= r <= 16), including ranks below their
+    bucket (7 -> 8, 9 -> 10, 11 -> 12, 14 -> 16: an identity block pads the
+    16 x 16 matrices inside the bucket too)."""
+    m, n = 260, 230
+    Md = graded(m, n, r, 8.0, seed=40 + r)
+    lam = 1.0 / np.sqrt(max(m, n))
+    mu0 = workloads.default_mu0(Md)
+    L, S, info = solve(Md, r, lam, mu0, "f64", fixed_iters=10)
+    assert info.iters == 10
+    o = oracle.fradm(Md, r, lam, mu0, fixed_iters=10)
+    eL, eS = rel(L, o["U"] @ o["B"] @ o["V"].T), rel(S, o["S"])
+    print(f"r={r} FP64: L {eL:.2e} S {eS:.2e}, orth {info.orth_err:.1e}")
+    assert eL <= 1e-9 and eS <= 1e-9
+    assert info.orth_err <= 1e-12
