@@ -36,9 +36,11 @@
  *  - Kernel forms can be forced through the environment, read when a handle
  *    is created (SFR_SWEEP, SFR_EXCH) or when a pass is launched (SFR_SPASS):
  *    SFR_SWEEP=vector|mfma picks the FP32 sweep kernel, SFR_EXCH=gather|reduce
- *    the cluster exchange of the matrix-core sweep, SFR_SPASS=vector keeps
- *    the returned-S pass off the matrix cores.  Every form computes the same
- *    iteration; the default is chosen per shape.
+ *    the cluster exchange of the matrix-core sweep, SFR_SPASS=vector|mfma
+ *    keeps the returned-S pass in its column-tile form (vector ALU, or the
+ *    matrix cores where the rank allows) also for rows of at most 256
+ *    columns.  Every form computes the same iteration; the default is chosen
+ *    per shape.
  */
 #ifndef SFR_H
 #define SFR_H

@@ -247,6 +247,140 @@ __global__ void __launch_bounds__(256) lowrank_pass_kernel(LowrankArgs<T> a)
     }
 }
 
+// Narrow rows (n <= kNarrowCols, 16-byte vectors).  The column-tile form
+// above keeps one column vector per thread, so for narrow matrices all but
+// n / VEC of its 256 threads idle (262144 x 48: 12 of 256).  Here thread t
+// takes column vector t mod CPV (CPV = n / VEC vectors a row) of the band's
+// rows t div CPV, t div CPV + RPP, ... (RPP = 256 div CPV rows at a time),
+// with the M (and Y) loads of up to kNarrowInFlight rows in flight together.
+// The arithmetic per element is that of lowrank_pass_kernel.
+constexpr int kNarrowCols = 256;
+constexpr int kNarrowRows = 128;      // rows of a workgroup's band
+constexpr int kNarrowInFlight = 8;
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) lowrank_narrow_kernel(LowrankArgs<T> a)
+{
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int NR = kNarrowInFlight;
+    const T* M = a.M;
+    const int64_t ldm = a.ldm, ldy = a.ldy, lds = a.lds;
+    const int m = a.m, n = a.n, mode = a.mode;
+    T* S = a.S;
+    const T* Y = a.Y;
+    const T* A = a.A;
+    const T* Vt = a.Vt;
+    double mu = a.mu;
+    const double lam = a.lam;
+    if (a.st) {
+        // FR-ADM: the returned iterate K picks the buffers (see factors_kernel)
+        const DevState* st = a.st;
+        if (!st->done || st->status < 0 || st->exch_timeout) return;
+        const int K = st->iters;
+        Y = (K >= 2) ? a.pp.Y[K & 1] : nullptr;
+        A = a.pp.P[(K + 1) & 1];
+        Vt = a.pp.Q[(K + 1) & 1];
+        mu = st->mu_prev;
+        if (a.min_eig && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 64) {
+            __shared__ double Aw[R * LDP], Ew[R * LDP];
+            __shared__ __align__(16) double csw[2 * 16];
+            const double w = wmin_eig<R>(st->B, kMaxR, st->r, Aw, Ew, csw);
+            if (threadIdx.x == 0) a.st->min_eig_B = w;
+        }
+    }
+    const int tid = threadIdx.x;
+    const int cpv = n / VEC;                    // the host takes this form for n % VEC == 0, n <= kNarrowCols
+    const int rpp = 256 / cpv;
+    const int cv = tid % cpv, rr = tid / cpv;
+    const bool tact = rr < rpp;
+    const int j = cv * VEC;
+    const int i0 = blockIdx.y * kNarrowRows;
+    const int i1 = min(m, i0 + kNarrowRows);
+    __shared__ T Ab[kNarrowRows * R];
+    for (int e = tid; e < (i1 - i0) * R; e += 256) Ab[e] = A[(int64_t)i0 * R + e];
+    T vk[R][VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+#pragma unroll
+        for (int k = 0; k < R; ++k) vk[k][e] = Vt[(int64_t)(j + e) * R + k];
+    __syncthreads();
+    const T t = (T)(lam / mu), imu = (T)(1.0 / mu);
+    const bool want_res = (a.rpart != nullptr) && (mode == 0);
+    const bool use_y = (mode == 0) && (Y != nullptr);
+    const T muT = (T)mu, lamT = (T)lam;
+    double racc = 0.0;
+    if (tact) {
+        for (int ib = i0 + rr; ib < i1; ib += NR * rpp) {
+            T mv[NR][VEC], yv[NR][VEC];
+#pragma unroll
+            for (int u = 0; u < NR; ++u) {
+                const int i = ib + u * rpp;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) { mv[u][e] = T(0); yv[u][e] = T(0); }
+                if (i < i1) {
+                    vload<T, VEC>(M + (int64_t)i * ldm + j, mv[u]);
+                    if (use_y) vload<T, VEC>(Y + (int64_t)i * ldy + j, yv[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NR; ++u) {
+                const int i = ib + u * rpp;
+                if (i >= i1) break;
+                T av[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k) av[k] = Ab[(i - i0) * R + k];
+                T out[VEC];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    T l = 0;
+#pragma unroll
+                    for (int k = 0; k < R; ++k) l = fma(av[k], vk[k][e], l);
+                    if (mode == 0) {
+                        const T Rr = mv[u][e] - l + yv[u][e] * imu;
+                        const T lo = Rr - t, hi = Rr + t;
+                        out[e] = (lo > T(0) ? lo : T(0)) + (hi < T(0) ? hi : T(0));
+                        if (want_res) {
+                            const T y = fmin(fmax(muT * Rr, -lamT), lamT);
+                            const double dy = (double)(y - yv[u][e]);
+                            racc = fma(dy, dy, racc);
+                        }
+                    } else {
+                        out[e] = mv[u][e] - l;
+                    }
+                }
+                vstore<T, VEC>(S + (int64_t)i * lds + j, out);
+            }
+        }
+    }
+    if (want_res) {
+        // workgroup sum in a fixed order: wavefronts by shuffles, then the
+        // four wavefront sums in order
+        __shared__ double rred[4];
+        for (int off = 32; off > 0; off >>= 1) racc += __shfl_xor(racc, off, 64);
+        if ((tid & 63) == 0) rred[tid >> 6] = racc;
+        __syncthreads();
+        if (tid == 0)
+            a.rpart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = (rred[0] + rred[1]) + (rred[2] + rred[3]);
+    }
+}
+
+template <typename T>
+static hipError_t lowrank_narrow_dispatch(const LowrankArgs<T>& a, int R, hipStream_t s, int* parts)
+{
+    dim3 grid(1u, (unsigned)((a.m + kNarrowRows - 1) / kNarrowRows));
+    if (parts) *parts = (int)(grid.x * grid.y);
+    switch (R) {
+#define CASE(rr)                                                                                \
+    case rr: hipLaunchKernelGGL((lowrank_narrow_kernel<T, rr>), grid, dim3(256), 0, s, a); \
+        break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(8) CASE(10) CASE(12) CASE(16) CASE(20) CASE(24)
+        CASE(32)
+#undef CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // Matrix-core form of the FP32 pass (R >= 8).  The rank-R term of a tile of
 // 16 rows x 16 columns is one matrix-core product over K = R (padded to a
 // multiple of 4), taken transposed, D = Vt_tile A_tile^T, so that lane
@@ -471,9 +605,17 @@ static bool lowrank_mfma_bucket(int R)
     return !off && (R == 8 || R == 10 || R == 12 || R == 16 || R == 20 || R == 24 || R == 32);
 }
 
+// Narrow matrices take the row-packed form (SFR_SPASS=vector or =mfma keeps
+// the column-tile forms, to test them).
+static bool lowrank_narrow_ok()
+{
+    const char* v = getenv("SFR_SPASS");
+    return v == nullptr || strcmp(v, "narrow") == 0 || strcmp(v, "auto") == 0;
+}
+
 // Vector paths need n, ldm, ldy, lds multiples of VEC and 16-byte aligned
-// bases (both Y buffers when they are picked on the device); so does the
-// matrix-core form (FP32, rank buckets from 8).
+// bases (both Y buffers when they are picked on the device); so do the
+// row-packed narrow form and the matrix-core form (FP32, rank buckets from 8).
 template <typename T>
 hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s, int* parts)
 {
@@ -483,6 +625,7 @@ hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s, int* part
     bool ys = a.st ? (al(a.pp.Y[0]) && al(a.pp.Y[1])) : (!a.Y || al(a.Y));
     const bool vec = (a.n % V == 0) && (a.ldm % V == 0) && (a.lds % V == 0) && al(a.M) && al(a.S) &&
                      (a.ldy % V == 0) && ys;
+    if (vec && a.n <= kNarrowCols && lowrank_narrow_ok()) return lowrank_narrow_dispatch<T>(a, R, s, parts);
     if constexpr (sizeof(T) == 4) {
         if (vec && lowrank_mfma_bucket(R)) return lowrank_mfma_dispatch(a, R, s, parts);
     }

@@ -350,15 +350,17 @@ def test_fixed_count_residual_from_the_S_pass(precision, fixed):
         assert abs(info.rel_residual - o["res"]) <= bar * o["res"] + floor, (info.rel_residual, o["res"])
 
 
-@pytest.mark.parametrize("spass", ["mfma", "vector"])
+@pytest.mark.parametrize("spass", ["mfma", "vector", "narrow"])
 @pytest.mark.parametrize("m,n,r", [(301, 212, 8), (1037, 700, 10), (77, 3004, 12), (260, 1024, 16),
-                                   (500, 68, 20), (130, 904, 24), (150, 1500, 32)])
+                                   (500, 68, 20), (130, 904, 24), (150, 1500, 32), (333, 48, 3), (1000, 8, 2)])
 def test_both_fp32_S_passes(monkeypatch, spass, m, n, r):
     """The FP32 pass that writes the returned S (and, for a fixed count, the
-    last residual) in its two forms, selected by SFR_SPASS: the rank-r term
-    on the matrix cores (rank buckets from 8) or on the vector ALU.  Ragged
-    row bands (m not a multiple of 16 or 64) and column tiles (n a multiple
-    of 4 only); S and the residual against the oracle."""
+    last residual) in its forms, selected by SFR_SPASS: the rank-r term on the
+    matrix cores (rank buckets from 8), on the vector ALU with one column
+    vector per thread, or (n <= 256) the row-packed form that gives every
+    thread a column vector of several rows.  Ragged row bands (m not a
+    multiple of 16, 64 or 128) and column tiles (n a multiple of 4 only); S and
+    the residual against the oracle."""
     monkeypatch.setenv("SFR_SPASS", spass)
     inst = workloads.planted(m, n, r, seed=m + 3 * n + r, frac=0.08, kind="uniform", scale=30.0, dtype=np.float32)
     g, o = case(inst, "f32", 5)
