@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-config4", action="store_true",
                     help="large_fp32: skip the 40000^2 FR-Nys / full FR-ADM figures in the default line")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="large_fp32: skip the 400^2 FP64, photometric and serving figures in the default line")
     ap.add_argument("--all-cores-iters", type=int, default=2,
                     help="large_fp32: oracle iterations per process in the all-cores CPU leg (0: skip)")
     ap.add_argument("--oracle-iters", type=int, default=12, help="oracle iterations timed on the host (about 1 s each)")
@@ -209,192 +211,198 @@ def main():
     if args.workload == "large_rank":
         return large_rank(args)
 
-    t0 = time.time()
-    tsvd = args.workload == "tsvd_fp32"
-    if args.workload in ("large_fp32", "tsvd_fp32"):
-        rk = args.rank or 10
-        inst = workloads.large_fp32(seed=args.seed, r=rk)
-        precision, esz, tol = "f32", 4, 1e-6
-        desc = f"FR-ADM, m=n=8000, r={rk}, FP32, 10% outliers U[-100,100]"
-        if tsvd:
-            tol = 1e-6
-            desc = f"FixedRankOptFull (Alg. 4) rank-{rk} TSVD of the same 8000x8000 FP32 matrix"
-    elif args.workload == "plain_fp64":
-        inst = workloads.plain_fp64(seed=args.seed)
-        precision, esz, tol = "f64", 8, 1e-7
-        desc = "FR-ADM, m=n=400, r=5, FP64, 5% outliers U[-50,50]"
-    else:
-        inst = workloads.photometric(seed=args.seed)
-        precision, esz, tol = "f32", 4, 1e-6
-        desc = "FR-ADM, photometric stereo shape m=262144 x n=48, r=3, FP32"
-    m, n = inst.M.shape
-    r = inst.r
-    mu0 = workloads.default_mu0(inst.M)
-    # BF16 head (FP32 FR-ADM only): fixed-count solves take BF16 for their
-    # first --bf16-iters iterations, tolerance-driven ones until --bf16-tol
-    bf_fixed, bf_tol = {}, {}
-    if args.bf16_iters > 0:
-        if precision != "f32" or tsvd:
-            print("bench.py: --bf16-iters applies to FP32 FR-ADM workloads", file=sys.stderr)
-            sys.exit(2)
-        bf_fixed = dict(bf16=True, bf16_iters=args.bf16_iters)
-        bf_tol = dict(bf16=True, bf16_tol=args.bf16_tol)
-    tdt = torch.float64 if precision == "f64" else torch.float32
-    M = torch.from_numpy(np.ascontiguousarray(inst.M)).to(device=dev, dtype=tdt)
-    torch.cuda.synchronize()
-    print(f"[bench] workload {args.workload} {m}x{n} r={r} ready in {time.time() - t0:.1f}s", file=sys.stderr,
-          flush=True)
-
-    stream = torch.cuda.current_stream()
-    if args.calibrate_copy:
-        # a plain copy kernel of known size: reads and writes 256 MiB each
-        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    def run(solver, out=None, stream=None):
-        """One solve: FR-ADM (U, B, V, S, info) or Alg. 4 (U, B, V, None, info)."""
-        if tsvd:
-            U_, B_, V_, inf_ = solver.tsvd(M, out=None if out is None else out[:3], stream=stream)
-            return U_, B_, V_, None, inf_
-        return solver.solve(M, out=out, stream=stream)
-
-    # ---- the timed handle and its outputs are set up first, so that the
-    # warm-up runs right before the timed solve
-    K = args.steps
-    solver = sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K, **bf_fixed)
-    U = torch.empty((m, r), dtype=tdt, device=dev)
-    Bm = torch.empty((r, r), dtype=torch.float64, device=dev)
-    V = torch.empty((n, r), dtype=tdt, device=dev)
-    S = torch.empty((m, n), dtype=tdt, device=dev)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-
-    # ---- warmup: W untimed iterations (a handle of their own)
-    if args.warmup > 0:
-        with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=args.warmup, **bf_fixed) as w:
-            run(w)
-    torch.cuda.synchronize()
-
-    # ---- timed: exactly K iterations (plus the output pass writing U, B, V, S)
-    ev0.record(stream)
-    _, _, _, _, info = run(solver, out=(U, Bm, V, S), stream=stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    assert info.iters == K, info
-    value = K / (ms / 1e3)
-    solver.close()
-    # ---- the same K iterations again with HIP events bound to every sweep
-    # dispatch (kept out of the run above: the events cost a few us a launch)
-    with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K, profile=True,
-                    **bf_fixed) as sp:
-        _, _, _, _, pinfo = run(sp, out=(U, Bm, V, S), stream=stream)
-    torch.cuda.synchronize()
-    sweep_ms = pinfo.sweep_ms
-    print(f"[bench] {K} iterations in {ms:.3f} ms; sweep {sweep_ms * 1e3:.1f} us avg over {pinfo.sweeps_timed}",
-          file=sys.stderr, flush=True)
-
-    bytes_per_el = (1 if tsvd else 3) * esz  # read M (, read Y_{k-1}, write Y_k)
-    alg_bytes = bytes_per_el * m * n
-    achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
-    copy_gbs = copy_bandwidth_gbs(dev)
-    print(f"[bench] plain device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
-    # the committed counters were taken on the default configuration only
-    default_cfg = (not args.rank or args.rank == 10) and not bf_fixed
-    traffic = measured_traffic(args.workload) if default_cfg else None
-    sweep_name = "sweep_mfma_kernel" if (bf_fixed or r > 10 or tsvd) else "sweep_kernel"
-
-    # ---- full tolerance-driven solves: solves/s and latency percentiles
-    lat = []
-    solve_iters = None
-    Ls = None
-    with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, max_iter=300, **bf_tol) as s2:
-        for i in range(max(1, args.solves)):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            U2, B2, V2, S2, inf2 = run(s2, stream=stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            lat.append(e0.elapsed_time(e1))
-            solve_iters = inf2.iters
-        rec_err = None
-        if inst.L0 is not None and not tsvd:
-            rows = np.random.default_rng(1).choice(m, min(m, 256), replace=False)
-            Lr = (U2.double()[rows] @ B2 @ V2.double().T).cpu().numpy()
-            rec_err = rel(Lr, inst.L0[rows].astype(np.float64))
-    lat = np.array(lat)
-    print(f"[bench] tolerance-driven solve: {solve_iters} iterations, p50 {np.percentile(lat, 50):.2f} ms",
-          file=sys.stderr, flush=True)
-
-    # ---- FP64 oracle on the same input: host rate and parity of the first iterations
-    cpu = None
-    parity = None
-    if not args.no_cpu_baseline:
-        import oracle
-        Md = inst.M.astype(np.float64)
-        oi = args.oracle_iters
-        t1 = time.perf_counter()
-        if tsvd:
-            Uo, Bo, Vo, _ = oracle.fr_full(Md, np.eye(m, r), np.eye(r), np.eye(n, r), oi)
-            o = {"U": Uo, "B": Bo, "V": Vo, "S": None}
+    def single(args):
+        """One FR-ADM / Alg. 4 workload: the timed fixed-count solve, the
+        tolerance-driven solves and (unless --no-cpu-baseline) the oracle leg."""
+        t0 = time.time()
+        tsvd = args.workload == "tsvd_fp32"
+        if args.workload in ("large_fp32", "tsvd_fp32"):
+            rk = args.rank or 10
+            inst = workloads.large_fp32(seed=args.seed, r=rk)
+            precision, esz, tol = "f32", 4, 1e-6
+            desc = f"FR-ADM, m=n=8000, r={rk}, FP32, 10% outliers U[-100,100]"
+            if tsvd:
+                tol = 1e-6
+                desc = f"FixedRankOptFull (Alg. 4) rank-{rk} TSVD of the same 8000x8000 FP32 matrix"
+        elif args.workload == "plain_fp64":
+            inst = workloads.plain_fp64(seed=args.seed)
+            precision, esz, tol = "f64", 8, 1e-7
+            desc = "FR-ADM, m=n=400, r=5, FP64, 5% outliers U[-50,50]"
         else:
-            o = oracle.fradm(Md, r, inst.lam, mu0, fixed_iters=oi)
-        tc = time.perf_counter() - t1
-        cpu = {"value": oi / tc, "unit": "iters/s", "cores": 1, "kind": "oracle", "host": host_info(),
-               "sample": f"{oi} {'Alg. 4 steps' if tsvd else 'FR-ADM iterations'} of the same {m}x{n} r={r} "
-                         f"input, FP64, one thread ({tc:.1f} s)"}
-        # a BF16 head of the same share of the iterations as in the timed run
-        bf_par = dict(bf_fixed, bf16_iters=max(1, (args.bf16_iters * oi) // K)) if bf_fixed else {}
-        with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=oi, **bf_par) as s3:
-            U3, B3, V3, S3, _ = run(s3)
+            inst = workloads.photometric(seed=args.seed)
+            precision, esz, tol = "f32", 4, 1e-6
+            desc = "FR-ADM, photometric stereo shape m=262144 x n=48, r=3, FP32"
+        m, n = inst.M.shape
+        r = inst.r
+        mu0 = workloads.default_mu0(inst.M)
+        # BF16 head (FP32 FR-ADM only): fixed-count solves take BF16 for their
+        # first --bf16-iters iterations, tolerance-driven ones until --bf16-tol
+        bf_fixed, bf_tol = {}, {}
+        if args.bf16_iters > 0:
+            if precision != "f32" or tsvd:
+                print("bench.py: --bf16-iters applies to FP32 FR-ADM workloads", file=sys.stderr)
+                sys.exit(2)
+            bf_fixed = dict(bf16=True, bf16_iters=args.bf16_iters)
+            bf_tol = dict(bf16=True, bf16_tol=args.bf16_tol)
+        tdt = torch.float64 if precision == "f64" else torch.float32
+        M = torch.from_numpy(np.ascontiguousarray(inst.M)).to(device=dev, dtype=tdt)
         torch.cuda.synchronize()
-        rows = np.random.default_rng(2).choice(m, min(m, 128), replace=False)
-        Lg = (U3.double()[rows] @ B3 @ V3.double().T).cpu().numpy()
-        Lo = o["U"][rows] @ o["B"] @ o["V"].T
-        parity = {"iterations": oi, **({"bf16_iters": bf_par["bf16_iters"]} if bf_par else {}),
-                  "rel_err_L": rel(Lg, Lo),
-                  "rel_err_S": None if tsvd else rel(S3.double()[rows].cpu().numpy(), o["S"][rows]),
-                  "rows_sampled": int(rows.size)}
-        print(f"[bench] oracle {oi} iterations in {tc:.1f} s; parity {parity}", file=sys.stderr, flush=True)
+        print(f"[bench] workload {args.workload} {m}x{n} r={r} ready in {time.time() - t0:.1f}s", file=sys.stderr,
+              flush=True)
 
-    out = {
-        "metric": "iters/s & solves/s at rel-err<=1e-5 vs FP64 oracle; %HBM roofline; p50/p99",
-        "value": value,
-        "unit": "iters/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": ms / K,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "bf16-operands+f32" if bf_fixed else precision,
-        "data": "synthetic",
-        "config": {"workload": desc, "m": m, "n": n, "r": r, "lambda": inst.lam, "mu0": mu0,
-                   "rho": 1.5, "mu_bar": 1e9, "seed": args.seed,
-                   **({"bf16_iters": args.bf16_iters, "bf16_tol": args.bf16_tol} if bf_fixed else {})},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-                     "kernel": sweep_name, "sweep_us": sweep_ms * 1e3,
-                     "alg_bytes_per_launch": alg_bytes},
-        "cpu_baseline": cpu,
-        "solves_per_s": 1e3 / float(np.mean(lat)),
-        "solve_iters": solve_iters,
-        "solve_tol": tol,
-        "p50_ms": float(np.percentile(lat, 50)),
-        "p99_ms": float(np.percentile(lat, 99)),
-        "parity_vs_oracle": parity,
-        "recovery_rel_err_L": rec_err,
-        "paper_context": ("Appendix, Alg. 4 (FixedRankOptFull): Q-linear convergence to the TSVD; the paper "
-                          "prints no timing for this shape") if tsvd else
-                         ("Table 1, FR-ADM 8000^2 r=10 (outliers in [-1,1]): 28 iterations in 27.42 s "
-                          "(~1.0 it/s) on a 3.2 GHz desktop CPU; not the same workload"),
-    }
+        stream = torch.cuda.current_stream()
+        if args.calibrate_copy:
+            # a plain copy kernel of known size: reads and writes 256 MiB each
+            src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        def run(solver, out=None, stream=None):
+            """One solve: FR-ADM (U, B, V, S, info) or Alg. 4 (U, B, V, None, info)."""
+            if tsvd:
+                U_, B_, V_, inf_ = solver.tsvd(M, out=None if out is None else out[:3], stream=stream)
+                return U_, B_, V_, None, inf_
+            return solver.solve(M, out=out, stream=stream)
+
+        # ---- the timed handle and its outputs are set up first, so that the
+        # warm-up runs right before the timed solve
+        K = args.steps
+        solver = sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K, **bf_fixed)
+        U = torch.empty((m, r), dtype=tdt, device=dev)
+        Bm = torch.empty((r, r), dtype=torch.float64, device=dev)
+        V = torch.empty((n, r), dtype=tdt, device=dev)
+        S = torch.empty((m, n), dtype=tdt, device=dev)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+
+        # ---- warmup: W untimed iterations (a handle of their own)
+        if args.warmup > 0:
+            with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=args.warmup, **bf_fixed) as w:
+                run(w)
+        torch.cuda.synchronize()
+
+        # ---- timed: exactly K iterations (plus the output pass writing U, B, V, S)
+        ev0.record(stream)
+        _, _, _, _, info = run(solver, out=(U, Bm, V, S), stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        assert info.iters == K, info
+        value = K / (ms / 1e3)
+        solver.close()
+        # ---- the same K iterations again with HIP events bound to every sweep
+        # dispatch (kept out of the run above: the events cost a few us a launch)
+        with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=K, profile=True,
+                        **bf_fixed) as sp:
+            _, _, _, _, pinfo = run(sp, out=(U, Bm, V, S), stream=stream)
+        torch.cuda.synchronize()
+        sweep_ms = pinfo.sweep_ms
+        print(f"[bench] {K} iterations in {ms:.3f} ms; sweep {sweep_ms * 1e3:.1f} us avg over {pinfo.sweeps_timed}",
+              file=sys.stderr, flush=True)
+
+        bytes_per_el = (1 if tsvd else 3) * esz  # read M (, read Y_{k-1}, write Y_k)
+        alg_bytes = bytes_per_el * m * n
+        achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
+        copy_gbs = copy_bandwidth_gbs(dev)
+        print(f"[bench] plain device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+        # the committed counters were taken on the default configuration only
+        default_cfg = (not args.rank or args.rank == 10) and not bf_fixed
+        traffic = measured_traffic(args.workload) if default_cfg else None
+        sweep_name = "sweep_mfma_kernel" if (bf_fixed or r > 10 or tsvd) else "sweep_kernel"
+
+        # ---- full tolerance-driven solves: solves/s and latency percentiles
+        lat = []
+        solve_iters = None
+        Ls = None
+        with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, max_iter=300, **bf_tol) as s2:
+            for i in range(max(1, args.solves)):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                U2, B2, V2, S2, inf2 = run(s2, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                lat.append(e0.elapsed_time(e1))
+                solve_iters = inf2.iters
+            rec_err = None
+            if inst.L0 is not None and not tsvd:
+                rows = np.random.default_rng(1).choice(m, min(m, 256), replace=False)
+                Lr = (U2.double()[rows] @ B2 @ V2.double().T).cpu().numpy()
+                rec_err = rel(Lr, inst.L0[rows].astype(np.float64))
+        lat = np.array(lat)
+        print(f"[bench] tolerance-driven solve: {solve_iters} iterations, p50 {np.percentile(lat, 50):.2f} ms",
+              file=sys.stderr, flush=True)
+
+        # ---- FP64 oracle on the same input: host rate and parity of the first iterations
+        cpu = None
+        parity = None
+        if not args.no_cpu_baseline:
+            import oracle
+            Md = inst.M.astype(np.float64)
+            oi = args.oracle_iters
+            t1 = time.perf_counter()
+            if tsvd:
+                Uo, Bo, Vo, _ = oracle.fr_full(Md, np.eye(m, r), np.eye(r), np.eye(n, r), oi)
+                o = {"U": Uo, "B": Bo, "V": Vo, "S": None}
+            else:
+                o = oracle.fradm(Md, r, inst.lam, mu0, fixed_iters=oi)
+            tc = time.perf_counter() - t1
+            cpu = {"value": oi / tc, "unit": "iters/s", "cores": 1, "kind": "oracle", "host": host_info(),
+                   "sample": f"{oi} {'Alg. 4 steps' if tsvd else 'FR-ADM iterations'} of the same {m}x{n} r={r} "
+                             f"input, FP64, one thread ({tc:.1f} s)"}
+            # a BF16 head of the same share of the iterations as in the timed run
+            bf_par = dict(bf_fixed, bf16_iters=max(1, (args.bf16_iters * oi) // K)) if bf_fixed else {}
+            with sfr.Solver(m, n, r, inst.lam, mu0, tol, precision=precision, fixed_iters=oi, **bf_par) as s3:
+                U3, B3, V3, S3, _ = run(s3)
+            torch.cuda.synchronize()
+            rows = np.random.default_rng(2).choice(m, min(m, 128), replace=False)
+            Lg = (U3.double()[rows] @ B3 @ V3.double().T).cpu().numpy()
+            Lo = o["U"][rows] @ o["B"] @ o["V"].T
+            parity = {"iterations": oi, **({"bf16_iters": bf_par["bf16_iters"]} if bf_par else {}),
+                      "rel_err_L": rel(Lg, Lo),
+                      "rel_err_S": None if tsvd else rel(S3.double()[rows].cpu().numpy(), o["S"][rows]),
+                      "rows_sampled": int(rows.size)}
+            print(f"[bench] oracle {oi} iterations in {tc:.1f} s; parity {parity}", file=sys.stderr, flush=True)
+
+        out = {
+            "metric": "iters/s & solves/s at rel-err<=1e-5 vs FP64 oracle; %HBM roofline; p50/p99",
+            "value": value,
+            "unit": "iters/s",
+            "n_gpus": 1,
+            "steps": K,
+            "warmup": args.warmup,
+            "ms_per_step": ms / K,
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "bf16-operands+f32" if bf_fixed else precision,
+            "data": "synthetic",
+            "config": {"workload": desc, "m": m, "n": n, "r": r, "lambda": inst.lam, "mu0": mu0,
+                       "rho": 1.5, "mu_bar": 1e9, "seed": args.seed,
+                       **({"bf16_iters": args.bf16_iters, "bf16_tol": args.bf16_tol} if bf_fixed else {})},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                         "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                         "kernel": sweep_name, "sweep_us": sweep_ms * 1e3,
+                         "alg_bytes_per_launch": alg_bytes},
+            "cpu_baseline": cpu,
+            "solves_per_s": 1e3 / float(np.mean(lat)),
+            "solve_iters": solve_iters,
+            "solve_tol": tol,
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "parity_vs_oracle": parity,
+            "recovery_rel_err_L": rec_err,
+            "paper_context": ("Appendix, Alg. 4 (FixedRankOptFull): Q-linear convergence to the TSVD; the paper "
+                              "prints no timing for this shape") if tsvd else
+                             ("Table 1, FR-ADM 8000^2 r=10 (outliers in [-1,1]): 28 iterations in 27.42 s "
+                              "(~1.0 it/s) on a 3.2 GHz desktop CPU; not the same workload"),
+        }
+        return out, default_cfg
+
+    out, default_cfg = single(args)
     default_line = args.workload == "large_fp32" and default_cfg
     if default_line and not args.no_cpu_baseline and args.all_cores_iters > 0:
         procs = max(1, min(16, os.cpu_count() or 1))
@@ -407,6 +415,28 @@ def main():
         out["config4_nystrom"] = {k: c4[k] for k in ("config", "value", "unit", "ms_per_step", "nys_iters",
                                                      "nys_rel_err_vs_L0", "full_fradm", "parity_vs_oracle",
                                                      "cpu_baseline", "roofline")}
+    if default_line and not args.no_other_configs:
+        # the other workloads of the metric, each measured here as its own
+        # --workload run measures it (compact keys; the full lines come from
+        # bench.py --workload plain_fp64 | photometric | serving)
+        keep = ("config", "value", "unit", "ms_per_step", "dtype", "solves_per_s", "solve_iters", "p50_ms",
+                "p99_ms", "parity_vs_oracle", "recovery_rel_err_L", "cpu_baseline")
+        for wl, key in (("plain_fp64", "config1_fp64_400"), ("photometric", "config3_photometric")):
+            torch.cuda.empty_cache()
+            sub = argparse.Namespace(**vars(args))
+            sub.workload, sub.rank, sub.bf16_iters = wl, 0, 0
+            o, _ = single(sub)
+            out[key] = {k: o.get(k) for k in keep}
+            out[key]["roofline"] = {k: o["roofline"].get(k) for k in ("bound", "achieved", "peak", "unit", "frac",
+                                                                        "kernel", "sweep_us")}
+        torch.cuda.empty_cache()
+        sub = argparse.Namespace(**vars(args))
+        sub.workload, sub.requests = "serving", min(args.requests, 2000)
+        o = serving_measure(sub)
+        out["config5_serving"] = {k: o.get(k) for k in ("config", "value", "unit", "p50_ms", "p99_ms",
+                                                         "saturated_solves_per_s", "slowest_request_alone_ms",
+                                                         "failed", "failed_queue", "parity_vs_oracle",
+                                                         "cpu_baseline", "roofline")}
     print(json.dumps(out), flush=True)
 
 
@@ -659,6 +689,10 @@ def large_rank(args):
 
 
 def serving(args):
+    print(json.dumps(serving_measure(args)), flush=True)
+
+
+def serving_measure(args):
     """Serving workload: a Poisson stream of independent decompositions
     (m U[64, 2048], n U[32, 512], r U{2..16}, 5-15 % outliers U[-50, 50],
     FP32, tol 1e-6 on the relative residual) through the continuous-batching
@@ -888,7 +922,7 @@ def serving(args):
         "failed": len(bad),
         "parity_vs_oracle": parity,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":
