@@ -524,9 +524,20 @@ __global__ void __launch_bounds__(256) lowrank_mfma_kernel(LowrankArgs<float> a)
     }
 }
 
+// Rows of a column-tile workgroup's band: kLowrankRows, or fewer (down to 8)
+// for small m, so that a small matrix still spreads over the device.
+static int lowrank_band_rows(int m)
+{
+    if (m >= 64 * kLowrankRows) return kLowrankRows;
+    const int rows = (m + 63) / 64;
+    return std::max(8, std::min(kLowrankRows, (rows + 7) / 8 * 8));
+}
+
 int lowrank_res_parts(int m, int n)
 {
-    return ((n + 255) / 256) * ((m + kLowrankRows - 1) / kLowrankRows);
+    // the most workgroups any form of the pass launches (column tiles of 256
+    // columns at the smallest band)
+    return ((n + 255) / 256) * ((m + 7) / 8);
 }
 
 __global__ void __launch_bounds__(256) res_final_kernel(DevState* st, const double* rpart, int count,
@@ -620,7 +631,7 @@ template <typename T>
 hipError_t launch_lowrank_pass(LowrankArgs<T> a, int R, hipStream_t s, int* parts)
 {
     constexpr int V = 16 / sizeof(T);
-    a.rows_per_blk = kLowrankRows;
+    a.rows_per_blk = lowrank_band_rows(a.m);
     auto al = [](const void* p) { return ((uintptr_t)p % 16) == 0; };
     bool ys = a.st ? (al(a.pp.Y[0]) && al(a.pp.Y[1])) : (!a.Y || al(a.Y));
     const bool vec = (a.n % V == 0) && (a.ldm % V == 0) && (a.lds % V == 0) && al(a.M) && al(a.S) &&
