@@ -227,6 +227,7 @@ sfr_status engine_plan(Engine& e, int m, int n, int r, bool f64, int hist_len)
     sfr_status cs = configure(e);
     if (cs != SFR_OK) return cs;
     e.ldy = e.ne;
+    e.first = first_sweep_plan(e);
     return SFR_OK;
 }
 
@@ -398,6 +399,11 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
     // one iteration: sweep k, Gram reduction, FP64 step.  bf: BF16-operand
     // contractions (matrix-core sweep); timed_ok: HIP events bound to the
     // sweep's dispatch when profiling.
+    // The first sweep starts from V_0 = I_{n x r}: where its shape allows,
+    // first.hip takes it without the row products and the exchange
+    // (SFR_FIRST=sweep keeps the general sweep, to test both).
+    const char* first_env = getenv("SFR_FIRST");
+    const FirstPlan fp = (first_env && strcmp(first_env, "sweep") == 0) ? FirstPlan() : e.first;
     auto enqueue_iter = [&](int k, bool bf, bool timed_ok) -> sfr_status {
         SweepArgs<T> a;
         a.st = e.st;
@@ -418,7 +424,13 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         const bool timed = timed_ok && p.profile && k >= 3 && k <= limit;
         hipEvent_t ev0 = timed ? e.prof_ev[2 * (k - 3)] : nullptr;
         hipEvent_t ev1 = timed ? e.prof_ev[2 * (k - 3) + 1] : nullptr;
-        if constexpr (sizeof(T) == 4) {
+        const bool first = (k == 1) && fp.ok;
+        int ncl_k = sc.ncl, ndy_k = sc.grid;
+        if (first) {
+            HIPCHK(launch_first_sweep<T>(a, e.R, fp, s));
+            ncl_k = fp.gy;
+            ndy_k = fp.gx * fp.gy;
+        } else if constexpr (sizeof(T) == 4) {
             if (sc.mfma) HIPCHK(launch_sweep_mfma(a, e.R, sc.tiles, sc.rb != 0, sc.grid, sc.lds, s, ev0, ev1, bf));
             else HIPCHK(launch_sweep<T>(a, e.R, sc.grid, sc.lds, s, ev0, ev1));
         } else {
@@ -430,7 +442,7 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         g.Qnext = static_cast<T*>(e.Q[k & 1]);
         g.Pnext = static_cast<const T*>(e.P[k & 1]);
         g.GQpart = e.GQpart; g.GPpart = e.GPpart;
-        g.m = e.m; g.n = e.ne; g.ncl = sc.ncl;
+        g.m = e.m; g.n = e.ne; g.ncl = ncl_k;
         g.rows_q = e.rows_q; g.nqb = e.nqb; g.rows_p = e.rows_p; g.npb = e.npb;
         HIPCHK(launch_gram<T>(g, e.R, s));
         if (e.gram_reduce) HIPCHK(launch_gram_reduce(e.st, e.GQpart, e.nqb, e.GPpart, e.npb, e.E, s));
@@ -438,7 +450,7 @@ sfr_status engine_iterate(Engine& e, const Params& p, double mu0, const T* M, in
         sa.st = e.st;
         sa.GPpart = e.GPpart; sa.npb = e.gram_reduce ? 1 : e.npb;
         sa.GQpart = e.GQpart; sa.nqb = e.gram_reduce ? 1 : e.nqb;
-        sa.dy2part = e.dy2part; sa.ndy = sc.grid;
+        sa.dy2part = e.dy2part; sa.ndy = ndy_k;
         sa.res_hist = e.res_hist;
         sa.ns_kappa = e.f64 ? kNsKappaF64 : kNsKappaF32;
         sa.dk_tau = e.f64 ? kDkTauF64 : kDkTauF32;

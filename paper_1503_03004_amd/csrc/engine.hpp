@@ -64,6 +64,13 @@ struct SweepCfg {
 
 struct LrEngine;   // large-rank FR-ADM engine (lr.hip)
 
+// Launch shape of the first sweep (first.hip): column slices gx, row groups gy
+// of `rows` rows (gy column partials of Q, gx gy partials of ||M||^2).
+struct FirstPlan {
+    bool ok = false;
+    int gx = 0, gy = 0, rows = 0;
+};
+
 // Residual history entries every engine holds at least: the mu_0 estimate
 // (Alg. 4 on M) runs up to 60 steps whatever the handle's max_iter.
 constexpr int kResHistMin = 64;
@@ -81,6 +88,7 @@ struct Engine {
     int max_grid = 0, max_ncl = 0;
     int rows_q = 0, nqb = 0, rows_p = 0, npb = 0, E = 0;
     bool gram_reduce = false;   // the Gram partials are summed before the step kernel
+    FirstPlan first;            // the first sweep's shape (first.hip), if it applies
     int hist_len = 0;
     // workspace
     void* Y[2] = {nullptr, nullptr};
@@ -203,6 +211,10 @@ sfr_status lr_solve(LrEngine* e, const Params& prm, bool mu_auto, const float* M
 sfr_status lr_tsvd(LrEngine* e, const Params& prm, const float* M, int64_t ldm, float* U, double* B, float* V,
                    sfr_info* info, hipStream_t s);
 
+FirstPlan first_sweep_plan(const Engine& e);
+template <typename T>
+hipError_t launch_first_sweep(const SweepArgs<T>& a, int R, const FirstPlan& f, hipStream_t s);
+
 // Shape of an engine (sizes, rank bucket, launch configurations); no
 // device memory is touched.
 sfr_status engine_plan(Engine& e, int m, int n, int r, bool f64, int hist_len);
@@ -222,8 +234,10 @@ bool engine_buffers(Engine& e, bool pad, Get&& get)
         if (!(e.P[b] = get((size_t)e.m * e.R * e.esz))) return false;
     for (int b = 0; b < 2; ++b)
         if (!(e.Q[b] = get((size_t)e.ne * e.R * e.esz))) return false;
-    if (!(e.Qpart = get((size_t)e.max_ncl * e.ne * e.R * e.esz))) return false;
-    if (!(e.dy2part = static_cast<double*>(get(sizeof(double) * (size_t)e.max_grid)))) return false;
+    const int nqp = std::max(e.max_ncl, e.first.ok ? e.first.gy : 0);
+    const int ndy = std::max(e.max_grid, e.first.ok ? e.first.gx * e.first.gy : 0);
+    if (!(e.Qpart = get((size_t)nqp * e.ne * e.R * e.esz))) return false;
+    if (!(e.dy2part = static_cast<double*>(get(sizeof(double) * (size_t)ndy)))) return false;
     if (!(e.rpart = static_cast<double*>(get(sizeof(double) * (size_t)lowrank_res_parts(e.m, e.n))))) return false;
     if (e.exch_words && !(e.exch = static_cast<unsigned long long*>(get(8 * e.exch_words)))) return false;
     if (!(e.GQpart = static_cast<double*>(get(sizeof(double) * (size_t)e.nqb * e.E)))) return false;

@@ -366,3 +366,21 @@ def test_both_fp32_S_passes(monkeypatch, spass, m, n, r):
     g, o = case(inst, "f32", 5)
     compare(g, o, "f32", f"S pass {spass} {m}x{n} r={r}")
     assert abs(g["info"].rel_residual - o["res"]) <= 1e-4 * o["res"] + 3e-8, (g["info"].rel_residual, o["res"])
+
+
+@pytest.mark.parametrize("first", ["kernel", "sweep"])
+@pytest.mark.parametrize("m,n,r,precision,fixed", [(300, 1100, 10, "f32", 1), (300, 1100, 10, "f32", 6),
+                                                   (257, 2048, 4, "f32", 5), (130, 1500, 32, "f32", 4),
+                                                   (97, 4100, 16, "f32", 3), (200, 600, 5, "f64", 1),
+                                                   (200, 600, 5, "f64", 7), (1037, 1024, 12, "f64", 3)])
+def test_first_sweep_both_forms(monkeypatch, first, m, n, r, precision, fixed):
+    """The first sweep starts from V_0 = I: with P = M[:, :r] it needs only
+    Q = M^T P and ||M||_F (SFR_FIRST unset), or the general sweep runs it
+    (SFR_FIRST=sweep); both against the oracle, from one iteration on (wide
+    rows, ragged row groups)."""
+    if first == "sweep":
+        monkeypatch.setenv("SFR_FIRST", "sweep")
+    dt = np.float32 if precision == "f32" else np.float64
+    inst = workloads.planted(m, n, r, seed=m + n + 7 * r, frac=0.08, kind="uniform", scale=30.0, dtype=dt)
+    g, o = case(inst, precision, fixed)
+    compare(g, o, precision, f"first {first} {m}x{n} r={r} {precision} K={fixed}")
