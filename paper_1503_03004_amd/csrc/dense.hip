@@ -849,6 +849,68 @@ __global__ void __launch_bounds__(256) orth_final_kernel(const DevState* st, int
     if (threadIdx.x == 0) *out = fmax(sqrt(red[0][0]), sqrt(red[1][0]));
 }
 
+// Small ranks (r <= kOrthSmallR, at most 72 entries of the two Grams): up to
+// kOrthPartsSmall row blocks per factor, so that tall factors spread over the
+// device.  Thread t sums slice t / W of the partials of entry t mod W
+// (W = 2E: the U entries, then the V entries), its loads in flight together;
+// the slice sums are added in slice order and the entries' squared
+// deviations from I in a fixed tree.
+constexpr int kOrthPartsSmall = 256;
+
+__global__ void __launch_bounds__(256) orth_final_small_kernel(const DevState* st, int r, const double* Up, int nu,
+                                                               const double* Vp, int nv, double* out)
+{
+    if (st && (!st->done || st->status < 0 || st->exch_timeout)) return;
+    __shared__ double part[256];
+    __shared__ double dev[2][256];
+    constexpr int CH = 32;
+    const int E = r * (r + 1) / 2, W = 2 * E;   // W <= 72
+    const int S = 256 / W;
+    const int t = threadIdx.x;
+    const int sl = t / W, w = t % W;
+    double g = 0.0;
+    if (sl < S) {
+        const bool isU = w < E;
+        const int e = isU ? w : w - E;
+        const int cnt = isU ? nu : nv;
+        const double* base = isU ? Up : Vp;
+        const int per = (cnt + S - 1) / S;
+        const int b0 = sl * per, b1 = min(cnt, b0 + per);
+        for (int bb = b0; bb < b1; bb += CH) {
+            double v[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) v[u] = base[(size_t)min(bb + u, cnt - 1) * E + e];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) g += (bb + u < b1) ? v[u] : 0.0;
+        }
+    }
+    part[t] = g;
+    __syncthreads();
+    double cu = 0.0, cv = 0.0;
+    if (t < W) {
+        double gw = 0.0;
+        for (int q = 0; q < S; ++q) gw += part[q * W + t];
+        const bool isU = t < E;
+        int p, q;
+        tri_index(isU ? t : t - E, r, p, q);
+        const double d = gw - (p == q ? 1.0 : 0.0);
+        const double c = (p == q ? 1.0 : 2.0) * d * d;
+        cu = isU ? c : 0.0;
+        cv = isU ? 0.0 : c;
+    }
+    dev[0][t] = cu;
+    dev[1][t] = cv;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            dev[0][t] += dev[0][t + h];
+            dev[1][t] += dev[1][t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) *out = fmax(sqrt(dev[0][0]), sqrt(dev[1][0]));
+}
+
 // At most this many row blocks per factor: the final sum stays short.
 constexpr int kOrthParts = 32;
 
@@ -857,11 +919,16 @@ hipError_t launch_orth(const DevState* st, const T* U, int m, const T* V, int n,
                        double* Vp, int nv, double* out, hipStream_t s)
 {
     if (r < 1 || r > kMaxR) return hipErrorInvalidValue;
-    nu = std::max(1, std::min({nu, m, kOrthParts}));
-    nv = std::max(1, std::min({nv, n, kOrthParts}));
+    const bool small = r <= kOrthSmallR;
+    const int parts = small ? kOrthPartsSmall : kOrthParts;
+    nu = std::max(1, std::min({nu, m, parts}));
+    nv = std::max(1, std::min({nv, n, parts}));
     hipLaunchKernelGGL(orth_partial_kernel<T>, dim3((unsigned)(nu + nv)), dim3(256), 0, s, st, U, m, V, n, r, Up,
                        nu, Vp, nv);
-    hipLaunchKernelGGL(orth_final_kernel, dim3(1), dim3(256), 0, s, st, r, Up, nu, Vp, nv, out);
+    if (small)
+        hipLaunchKernelGGL(orth_final_small_kernel, dim3(1), dim3(256), 0, s, st, r, Up, nu, Vp, nv, out);
+    else
+        hipLaunchKernelGGL(orth_final_kernel, dim3(1), dim3(256), 0, s, st, r, Up, nu, Vp, nv, out);
     return hipGetLastError();
 }
 

@@ -76,6 +76,20 @@ def test_orth_err_reported(precision):
         assert abs(info.orth_err - want) <= 1e-12 + 1e-9 * want
 
 
+@pytest.mark.parametrize("m,n,r", [(60000, 48, 3), (9000, 600, 8), (700, 1300, 10)])
+def test_orth_err_tall_and_wide(m, n, r):
+    """orth_err on tall factors (many row blocks per factor, up to 256 for
+    r <= 8) and on the r > 8 form, FP32 against numpy."""
+    inst = workloads.planted(m, n, r, seed=m + r, frac=0.08, kind="uniform", scale=30.0, dtype=np.float32)
+    mu0 = workloads.default_mu0(inst.M.astype(np.float64))
+    Mt = torch.from_numpy(inst.M).cuda()
+    with sfr.Solver(m, n, r, inst.lam, mu0, 1e-6, precision="f32", fixed_iters=6) as s:
+        U, B, V, S, info = s.solve(Mt)
+    want = orth_np(U.cpu().numpy(), V.cpu().numpy())
+    print(f"{m}x{n} r={r}: orth_err {info.orth_err:.3e} numpy {want:.3e}")
+    assert abs(info.orth_err - want) <= 1e-12 + 1e-9 * want and info.orth_err <= 1e-5
+
+
 def test_orth_err_nystrom_and_batch():
     inst = workloads.planted(900, 700, 4, seed=5, frac=0.06, kind="uniform", scale=20.0, dtype=np.float32)
     Md = inst.M.astype(np.float64)
