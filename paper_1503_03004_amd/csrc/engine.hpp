@@ -68,6 +68,7 @@ struct LrEngine;   // large-rank FR-ADM engine (lr.hip)
 // of `rows` rows (gy column partials of Q, gx gy partials of ||M||^2).
 struct FirstPlan {
     bool ok = false;
+    bool narrow = false;   // fewer than 256 vectors a row: rows packed into a workgroup
     int gx = 0, gy = 0, rows = 0;
 };
 

@@ -372,12 +372,16 @@ def test_both_fp32_S_passes(monkeypatch, spass, m, n, r):
 @pytest.mark.parametrize("m,n,r,precision,fixed", [(300, 1100, 10, "f32", 1), (300, 1100, 10, "f32", 6),
                                                    (257, 2048, 4, "f32", 5), (130, 1500, 32, "f32", 4),
                                                    (97, 4100, 16, "f32", 3), (200, 600, 5, "f64", 1),
-                                                   (200, 600, 5, "f64", 7), (1037, 1024, 12, "f64", 3)])
+                                                   (200, 600, 5, "f64", 7), (1037, 1024, 12, "f64", 3),
+                                                   (333, 48, 3, "f32", 1), (1000, 200, 6, "f32", 5),
+                                                   (400, 400, 5, "f64", 4), (5000, 80, 20, "f32", 3),
+                                                   (3, 50, 2, "f64", 2)])
 def test_first_sweep_both_forms(monkeypatch, first, m, n, r, precision, fixed):
     """The first sweep starts from V_0 = I: with P = M[:, :r] it needs only
     Q = M^T P and ||M||_F (SFR_FIRST unset), or the general sweep runs it
     (SFR_FIRST=sweep); both against the oracle, from one iteration on (wide
-    rows, ragged row groups)."""
+    rows, and narrow rows packed several to a workgroup; ragged row
+    groups)."""
     if first == "sweep":
         monkeypatch.setenv("SFR_FIRST", "sweep")
     dt = np.float32 if precision == "f32" else np.float64
