@@ -34,7 +34,9 @@
  *    or by a running queue (sfr_queue_start) for too long, the solve
  *    returns SFR_ERR_DEVICE with its outputs untouched.
  *  - Kernel forms can be forced through the environment, read when a handle
- *    is created (SFR_SWEEP, SFR_EXCH) or when a pass is launched (SFR_SPASS):
+ *    is created (SFR_SWEEP, SFR_EXCH), when a solve starts (SFR_FIRST) or when
+ *    a pass is launched (SFR_SPASS): SFR_FIRST=sweep runs the first iteration
+ *    through the general sweep instead of the one-pass form for V_0 = I;
  *    SFR_SWEEP=vector|mfma picks the FP32 sweep kernel, SFR_EXCH=gather|reduce
  *    the cluster exchange of the matrix-core sweep, SFR_SPASS=vector|mfma
  *    keeps the returned-S pass in its column-tile form (vector ALU, or the
