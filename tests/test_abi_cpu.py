@@ -241,3 +241,18 @@ def test_queue_entry_points_reject_bad_handles():
     assert L.sfr_queue_submit(None, ctypes.byref(item), ctypes.byref(t)) == B.SFR_ERR_HANDLE
     assert L.sfr_queue_poll(None, 0, ctypes.byref(d), ctypes.byref(info), ctypes.byref(st)) == B.SFR_ERR_HANDLE
     assert L.sfr_queue_stop(None) == B.SFR_ERR_HANDLE
+
+
+@pytest.mark.parametrize("argv, env", [(["--gpus", "2"], {}), (["--gpus", "8"], {}), ([], {"WORLD_SIZE": "2"})])
+def test_bench_refuses_more_than_one_gpu(argv, env):
+    # the bench is a one-GPU measurement: a multi-GPU request exits with a
+    # message, before any device work
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    e = dict(os.environ, **env)
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), *argv], cwd=root, env=e,
+                       capture_output=True, text=True, timeout=60)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+    assert p.stdout == ""
